@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the constrained multilevel partitioner on one MI355X.
+
+One step = one full hgp_partition_device call (coarsening + refinement +
+connectivity) on a device-resident synthetic spiking-network hypergraph.
+Prints one JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--workload rand64k]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the derived LDS-atomic peak
+HBM_PEAK_GBS = 8000.0
+CUS, CLOCK_GHZ, LDS_ATOMIC_LANES_PER_CLK = 256, 2.4, 32
+LDS_ATOMIC_PEAK_TOPS = CUS * CLOCK_GHZ * 1e9 * LDS_ATOMIC_LANES_PER_CLK / 1e12
+
+# Algorithmic cost model per kernel class: (bound, bytes or ops per unit).
+# rate / propose: one LDS read-modify-write per unit (pin-pair visit, part-table
+# entry visit); the pin-streaming kernels: compulsory HBM bytes per pin.
+COST = {
+    "rate": ("alu", 1.0),
+    "propose": ("alu", 1.0),
+    "part_table": ("hbm", 16.0),
+    "seq_events": ("hbm", 4.0),
+    "contract": ("hbm", 16.0),
+    "incidence": ("hbm", 8.0),
+    "sort": ("hbm", 32.0),
+    "match": ("hbm", 20.0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample_n: int, mu: float, omega: int, delta: int):
+    import oracle
+    from paper_2604_14411_amd import synth
+
+    threads = os.cpu_count() or 1
+    oracle.set_threads(threads)
+    g = synth.random_snn(sample_n, mu, 2, 1, 16)
+    t = time.perf_counter()
+    rc, _, res, _ = oracle.partition(g, omega, delta)
+    dt = time.perf_counter() - t
+    assert rc == 0
+    return dict(value=g.n_pins / dt, unit="pins/s", cores=threads, kind="oracle",
+                sample=f"CPU oracle, whole partition of a reduced random SNN from the same generator: "
+                       f"n={sample_n}, |T_v|~Poisson({mu:g})+1, w in [1,16], seed 2, Omega={omega}, Delta={delta}; "
+                       f"{g.n_pins} pins, {res['n_levels']} levels, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rand64k")
+    ap.add_argument("--cpu-sample-n", type=int, default=3072)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_14411_amd import hgp
+    from paper_2604_14411_amd.synth.configs import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    g = w.make()
+    log(f"[bench] workload {w.name}: {w.note}; n={g.n_nodes} pins={g.n_pins}")
+    ctx = hgp.Context(0)
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out)
+        log(f"[bench] warmup {i}: {time.perf_counter() - t:.3f} s levels={res['n_levels']} "
+            f"rounds={res['n_rounds']} parts={res['n_parts']} conn={res['connectivity']}")
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, flags=hgp.FLAG_TIME_KERNELS)
+        results.append(res)
+        log(f"[bench] step {i}: levels={res['n_levels']} rounds={res['n_rounds']} conn={res['connectivity']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    value = g.n_pins * args.steps / elapsed
+
+    # per-kernel-class totals over the timed steps
+    agg = {}
+    for res in results:
+        for name, k in res["kernels"].items():
+            a = agg.setdefault(name, dict(ms=0.0, launches=0, units=0))
+            a["ms"] += k["ms"]
+            a["launches"] += k["launches"]
+            a["units"] += k["units"]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
+        if a["launches"]:
+            log(f"[bench] kernel {name:11s} {a['ms'] / args.steps:9.2f} ms/step  launches/step "
+                f"{a['launches'] / args.steps:8.1f}  avg {a['ms'] / a['launches'] * 1e3:9.1f} us  "
+                f"units/step {a['units'] / args.steps:.3e}")
+    dom = max(agg, key=lambda k: agg[k]["ms"])
+    a = agg[dom]
+    bound, per_unit = COST[dom]
+    avg_s = a["ms"] / a["launches"] / 1e3
+    units_per_launch = a["units"] / a["launches"]
+    if bound == "hbm":
+        achieved = per_unit * units_per_launch / avg_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=None)
+    else:
+        achieved = per_unit * units_per_launch / avg_s / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=LDS_ATOMIC_PEAK_TOPS, unit="TOP/s",
+                    frac=achieved / LDS_ATOMIC_PEAK_TOPS, traffic=None)
+    roof.update(kernel=dom, avg_launch_us=avg_s * 1e6, launches_per_step=a["launches"] / args.steps,
+                units_per_launch=units_per_launch, share_of_step=a["ms"] / args.steps / ms_step)
+
+    line = dict(metric="pins/s (sum |e| per second), whole constrained multilevel partition",
+                value=value, unit="pins/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32",
+                data="synthetic",
+                config=dict(workload=w.name, description=w.note, n_nodes=g.n_nodes, pins=g.n_pins,
+                            sum_e_sq=g.sum_sq(), omega=w.omega, delta=w.delta, max_refine_rounds=8,
+                            levels=results[-1]["n_levels"], rounds=results[-1]["n_rounds"],
+                            n_parts=results[-1]["n_parts"], connectivity=results[-1]["connectivity"]),
+                roofline=roof)
+    if not args.no_cpu_baseline:
+        log(f"[bench] cpu baseline (oracle) on a reduced sample n={args.cpu_sample_n} ...")
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, 191.0 if w.name == "rand64k" else 127.0, w.omega,
+                                            w.delta)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,538 @@
+// Coarsening kernels (Sec. III): canonical input, incidence transpose,
+// constrained candidate rating (Eq. 2), pseudo-forest matching, contraction.
+#include "coarsen.hpp"
+
+namespace hgp {
+
+constexpr int SEG_NT = 256;
+
+// ---------------------------------------------------------------------------
+// input validation + canonical level 0
+// ---------------------------------------------------------------------------
+__global__ void k_check_offsets(const int32_t *__restrict__ off, int32_t E, int32_t *err) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0 && off[0] != 0) atomicOr(err, kErrCsr);
+  if (e < E) {
+    const int32_t a = off[e], b = off[e + 1];
+    if (b < a) atomicOr(err, kErrCsr);
+    else if (b - a > kSegCap) atomicOr(err, kErrBigHedge);
+  }
+}
+
+__global__ void k_check_weights(const int32_t *__restrict__ hw, int32_t E, const int32_t *__restrict__ nw,
+                                int32_t N, int32_t *err, unsigned long long *sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long a = 0, b = 0;
+  if (i < E) {
+    const int32_t x = hw ? hw[i] : 1;
+    if (x < 1) atomicOr(err, kErrWeight);
+    else a = (unsigned long long)x;
+  }
+  if (i < N) {
+    const int32_t x = nw ? nw[i] : 1;
+    if (x < 1) atomicOr(err, kErrWeight);
+    else b = (unsigned long long)x;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if (lane_id() == 0) {
+    if (a) atomicAdd(&sums[0], a);
+    if (b) atomicAdd(&sums[1], b);
+  }
+}
+
+// One workgroup per hedge: tag destinations, sort pins by id, reject
+// out-of-range pins, duplicates and bad source counts.
+__global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                  const int32_t *__restrict__ nsrc, int32_t N, int32_t *err,
+                                                  uint32_t *__restrict__ hpin) {
+  __shared__ uint32_t key[kSegCap];
+  const int e = blockIdx.x;
+  const int b = off[e];
+  const int len = off[e + 1] - b;
+  if (len <= 0) return;
+  const int ns = nsrc ? nsrc[e] : 1;
+  if (threadIdx.x == 0 && (ns < 0 || ns > len)) atomicOr(err, kErrNsrc);
+  const int np = next_pow2(len);
+  for (int i = threadIdx.x; i < np; i += SEG_NT) {
+    uint32_t k = 0xffffffffu;
+    if (i < len) {
+      const int32_t v = pins[b + i];
+      if (v < 0 || v >= N) {
+        atomicOr(err, kErrPin);
+        k = 0xfffffffeu;
+      } else {
+        k = ((uint32_t)v << 1) | (i >= ns ? 1u : 0u);
+      }
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  block_bitonic_sort<uint32_t, SEG_NT>(key, np);
+  for (int i = threadIdx.x; i < len; i += SEG_NT) {
+    const uint32_t k = key[i];
+    if (i + 1 < len && (key[i + 1] >> 1) == (k >> 1)) atomicOr(err, kErrDup);
+    hpin[b + i] = (k >> 1) | ((k & 1u) << 31);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// incidence transpose: I(n) with the destination flag, |in(n)|
+// ---------------------------------------------------------------------------
+__global__ void k_degrees(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
+                          int32_t *__restrict__ deg, int32_t *__restrict__ indeg) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= E) return;
+  for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
+    const uint32_t x = hpin[j];
+    atomicAdd(&deg[x & kIdMask], 1);
+    if (x & kDst) atomicAdd(&indeg[x & kIdMask], 1);
+  }
+}
+
+__global__ void k_scatter_inc(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
+                              const int32_t *__restrict__ ioff, int32_t *__restrict__ fill,
+                              uint32_t *__restrict__ inc) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= E) return;
+  for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
+    const uint32_t x = hpin[j];
+    const uint32_t v = x & kIdMask;
+    const int p = atomicAdd(&fill[v], 1);
+    inc[ioff[v] + p] = (uint32_t)wid | (x & kDst);
+  }
+}
+
+// total(n) = sum of w(e) over I(n); feasibility of every node.
+__global__ void k_node_totals(const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
+                              const int32_t *__restrict__ hw, int32_t N, int32_t *__restrict__ total) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= N) return;
+  int64_t s = 0;
+  for (int i = ioff[wid] + lane_id(); i < ioff[wid + 1]; i += 64) s += hw[inc[i] & kIdMask];
+  s = wave_sum(s);
+  if (lane_id() == 0) total[wid] = (int32_t)s;
+}
+
+__global__ void k_feasible(const int32_t *__restrict__ size, const int32_t *__restrict__ indeg, int32_t N,
+                           int32_t omega, int32_t delta, int32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && (size[i] > omega || indeg[i] > delta)) atomicOr(err, kErrInfeasible);
+}
+
+// ---------------------------------------------------------------------------
+// rating + constrained selection (Eq. 2, Sec. III-A)
+// ---------------------------------------------------------------------------
+// One workgroup per node n.  The neighbour histogram lives in LDS as a dense
+// array over an id window [lo, lo+R); windows are swept until all ids are
+// covered.  Each counter packs hist (low hb bits) and c(n,m) = |in(n) n in(m)|
+// (high bits) in 32 bits when they fit, else a 64-bit (c << 32 | hist) pair.
+// A candidate is checked against Omega and Delta only when it would improve
+// the thread's running best, with |in(n) u in(m)| = |in(n)|+|in(m)|-c.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restrict__ ioff,
+                                             const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
+                                             const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+                                             const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
+                                             const int32_t *__restrict__ total, int32_t omega, int32_t delta,
+                                             int32_t words, int32_t *__restrict__ pair,
+                                             int64_t *__restrict__ score) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t red_h[NT / 64];
+  __shared__ int32_t red_m[NT / 64];
+  const int n = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = lane_id();
+  int best_m = -1;
+  int64_t best_h = 0;
+  const int64_t sn = size[n];
+  if (sn < omega) {
+    const uint32_t tot = (uint32_t)total[n];
+    const uint32_t din = (uint32_t)indeg[n];
+    const int hb = tot ? 32 - __clz(tot) : 0;
+    const int cb = din ? 32 - __clz(din) : 0;
+    const bool packed = hb + cb <= 32;
+    const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
+    const int R = packed ? words : (words >> 1);
+    const int i0 = ioff[n], i1 = ioff[n + 1];
+    uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
+    for (int lo = 0; lo < N; lo += R) {
+      const int span = min(R, N - lo);
+      const int zw = packed ? span : 2 * span;
+      for (int i = tid; i < zw; i += NT) lds[i] = 0u;
+      __syncthreads();
+      for (int i = i0 + w; i < i1; i += NT / 64) {
+        const uint32_t x = inc[i];
+        const int e = (int)(x & kIdMask);
+        const uint32_t ndst = x >> 31;
+        const uint32_t we = (uint32_t)hw[e];
+        const int b = hoff[e], en = hoff[e + 1];
+        for (int j = b + l; j < en; j += 64) {
+          const uint32_t y = hpin[j];
+          const int m = (int)(y & kIdMask);
+          const uint32_t rel = (uint32_t)(m - lo);
+          if (m != n && rel < (uint32_t)span) {
+            const uint32_t both = ndst & (y >> 31);
+            if (packed)
+              atomicAdd(&lds[rel], we + (both << hb));
+            else
+              atomicAdd((unsigned long long *)&lds64[rel], (unsigned long long)we | ((unsigned long long)both << 32));
+          }
+        }
+      }
+      __syncthreads();
+      for (int i = tid; i < span; i += NT) {
+        uint64_t h, c;
+        if (packed) {
+          const uint32_t v = lds[i];
+          if (!v) continue;
+          h = v & hmask;
+          c = (hb >= 32) ? 0 : (v >> hb);
+        } else {
+          const uint64_t v = lds64[i];
+          if (!v) continue;
+          h = v & 0xffffffffull;
+          c = v >> 32;
+        }
+        const int m = lo + i;
+        if ((int64_t)h > best_h || ((int64_t)h == best_h && m > best_m)) {
+          const int64_t un = (int64_t)din + indeg[m] - (int64_t)c;
+          if (sn + size[m] <= omega && un <= delta) {
+            best_h = (int64_t)h;
+            best_m = m;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // block argmax of (h, m)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t oh = __shfl_xor(best_h, o, 64);
+    const int om = __shfl_xor(best_m, o, 64);
+    if (oh > best_h || (oh == best_h && om > best_m)) {
+      best_h = oh;
+      best_m = om;
+    }
+  }
+  if (l == 0) {
+    red_h[w] = best_h;
+    red_m[w] = best_m;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < NT / 64; ++q)
+      if (red_h[q] > best_h || (red_h[q] == best_h && red_m[q] > best_m)) {
+        best_h = red_h[q];
+        best_m = red_m[q];
+      }
+    pair[n] = best_m;
+    score[n] = best_m < 0 ? 0 : best_h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// matching over the pairing pseudo-forest (Sec. III-A/B)
+// ---------------------------------------------------------------------------
+// best(p) as a packed (score << 32 | id) maximum over the nodes proposing p.
+__global__ void k_best(const int32_t *__restrict__ pair, const int64_t *__restrict__ score, int32_t N,
+                       unsigned long long *__restrict__ best) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int32_t p = pair[n];
+  if (p >= 0) atomicMax(&best[p], ((unsigned long long)score[n] << 32) | (unsigned long long)n);
+}
+
+// up(n): true on a 2-cycle, false without candidate or when n is not the
+// best proposer of pair(n), else the negation of up(pair(n)).  Each thread
+// follows the chain of "best proposer" links to a node whose value is
+// local; scores never decrease along the chain, so it ends (the walk is
+// capped at N steps; hitting the cap flags an internal error).
+__global__ void k_up(const int32_t *__restrict__ pair, const unsigned long long *__restrict__ best, int32_t N,
+                     uint8_t *__restrict__ up, int32_t *err) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int u = (int)n;
+  uint32_t parity = 0;
+  int r = -1;
+  for (int64_t step = 0; step <= N; ++step) {
+    const int p = pair[u];
+    if (p < 0) {
+      r = 0;
+      break;
+    }
+    if (pair[p] == u) {
+      r = 1;
+      break;
+    }
+    if ((int)(best[p] & 0xffffffffull) != u) {
+      r = 0;
+      break;
+    }
+    parity ^= 1u;
+    u = p;
+  }
+  if (r < 0) {
+    atomicOr(err, kErrInternal);
+    r = 0;
+  }
+  up[n] = (uint8_t)((uint32_t)r ^ parity);
+}
+
+__global__ void k_match(const int32_t *__restrict__ pair, const unsigned long long *__restrict__ best,
+                        const uint8_t *__restrict__ up, int32_t N, int32_t *__restrict__ match,
+                        int32_t *__restrict__ rep) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int m = (int)n;
+  if (up[n]) {
+    m = pair[n];
+  } else {
+    const unsigned long long b = best[n];
+    if (b) {
+      const int c = (int)(b & 0xffffffffull);
+      if (up[c]) m = c;
+    }
+  }
+  match[n] = m;
+  rep[n] = (m >= n) ? 1 : 0;
+}
+
+__global__ void k_gamma(const int32_t *__restrict__ match, int32_t N, int32_t *__restrict__ gamma) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int m = match[n];
+  if (m < n) gamma[n] = gamma[m];
+}
+
+// ---------------------------------------------------------------------------
+// contraction (Sec. III-B)
+// ---------------------------------------------------------------------------
+__global__ void k_cluster_size(const int32_t *__restrict__ match, const int32_t *__restrict__ gamma,
+                               const int32_t *__restrict__ size, int32_t N, int32_t *__restrict__ csize) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int m = match[n];
+  if (m >= n) csize[gamma[n]] = size[n] + (m != n ? size[m] : 0);
+}
+
+// One workgroup per hedge: map pins through `map`, sort (id << 1 | dst),
+// keep the last key of every id run (its low bit is the OR of the run's
+// destination flags), write the survivors at the hedge's old offset.
+__global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__ hoff,
+                                                     const uint32_t *__restrict__ hpin,
+                                                     const int32_t *__restrict__ map, uint32_t *__restrict__ out,
+                                                     int32_t *__restrict__ cnt) {
+  __shared__ uint32_t key[kSegCap];
+  __shared__ int32_t pos[kSegCap];
+  __shared__ int32_t tmp[SEG_NT / 64 + 1];
+  const int e = blockIdx.x;
+  const int b = hoff[e];
+  const int len = hoff[e + 1] - b;
+  if (len <= 0) {
+    if (threadIdx.x == 0) cnt[e] = 0;
+    return;
+  }
+  const int np = next_pow2(len);
+  for (int i = threadIdx.x; i < np; i += SEG_NT) {
+    uint32_t k = 0xffffffffu;
+    if (i < len) {
+      const uint32_t x = hpin[b + i];
+      k = ((uint32_t)map[x & kIdMask] << 1) | (x >> 31);
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  block_bitonic_sort<uint32_t, SEG_NT>(key, np);
+  for (int i = threadIdx.x; i < len; i += SEG_NT)
+    pos[i] = (i + 1 == len || (key[i + 1] >> 1) != (key[i] >> 1)) ? 1 : 0;
+  __syncthreads();
+  const int kept = block_exclusive_scan<int32_t, SEG_NT>(pos, len, tmp);
+  for (int i = threadIdx.x; i < len; i += SEG_NT) {
+    const bool last = (i + 1 == len || (key[i + 1] >> 1) != (key[i] >> 1));
+    if (last) {
+      const uint32_t k = key[i];
+      out[b + pos[i]] = (k >> 1) | ((k & 1u) << 31);
+    }
+  }
+  if (threadIdx.x == 0) cnt[e] = kept;
+}
+
+// Copy each hedge's survivors from the oversized layout to the packed one.
+__global__ void k_pack(const int32_t *__restrict__ old_off, const int32_t *__restrict__ new_off, int32_t E,
+                       const uint32_t *__restrict__ src, uint32_t *__restrict__ dst) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= E) return;
+  const int a = old_off[wid], b = new_off[wid], len = new_off[wid + 1] - b;
+  for (int j = lane_id(); j < len; j += 64) dst[b + j] = src[a + j];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+void launch_check_offsets(const int32_t *off, int32_t E, int32_t *err, hipStream_t s) {
+  k_check_offsets<<<div_up((int64_t)E + 1, 256), 256, 0, s>>>(off, E, err);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32_t N, int32_t *err,
+                          unsigned long long *sums, hipStream_t s) {
+  const int64_t m = E > N ? E : N;
+  if (m <= 0) return;
+  k_check_weights<<<div_up(m, 256), 256, 0, s>>>(hw, E, nw, N, err, sums);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
+                  uint32_t *hpin, hipStream_t s) {
+  if (E <= 0) return;
+  k_canon<<<E, SEG_NT, 0, s>>>(off, pins, nsrc, N, err, hpin);
+  HGP_LAUNCH_CHECK();
+}
+
+void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int32_t *ioff, uint32_t *inc,
+                     int32_t *indeg, int32_t *work, DevBuf &scan_tmp, hipStream_t s) {
+  KScope ks(5, s);
+  fill_i32(work, N, 0, s);
+  fill_i32(indeg, N, 0, s);
+  if (E > 0) {
+    k_degrees<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, work, indeg);
+    HGP_LAUNCH_CHECK();
+  }
+  scan_i32(work, ioff, N, ioff + N, scan_tmp, s);
+  fill_i32(work, N, 0, s);
+  if (E > 0) {
+    k_scatter_inc<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, ioff, work, inc);
+    HGP_LAUNCH_CHECK();
+  }
+}
+
+void launch_node_totals(const int32_t *ioff, const uint32_t *inc, const int32_t *hw, int32_t N, int32_t *total,
+                        hipStream_t s) {
+  if (N <= 0) return;
+  k_node_totals<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, total);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
+                     int32_t *err, hipStream_t s) {
+  if (N <= 0) return;
+  k_feasible<<<div_up(N, 256), 256, 0, s>>>(size, indeg, N, omega, delta, err);
+  HGP_LAUNCH_CHECK();
+}
+
+constexpr int RATE_NT = 512;
+constexpr int RATE_LDS_BYTES = 128 * 1024;
+
+void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
+                 int64_t *score, hipStream_t s) {
+  if (L.n <= 0) return;
+  // dense window: whole id range if it fits, else RATE_LDS_BYTES of counters
+  const int max_words = RATE_LDS_BYTES / 4;
+  int words = L.n <= max_words / 2 ? 2 * L.n : max_words;
+  words = (words + 1) & ~1;
+  const size_t bytes = (size_t)words * 4;
+  static bool attr_set = false;
+  if (!attr_set) {
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate<RATE_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                RATE_LDS_BYTES));
+    attr_set = true;
+  }
+  KScope ks(0, s);
+  k_rate<RATE_NT><<<L.n, RATE_NT, bytes, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
+                                              omega, delta, words, pair, score);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,
+                  int32_t *match, int32_t *gamma, int32_t *rep, int32_t *n_next_dev, int32_t *err,
+                  DevBuf &scan_tmp, hipStream_t s) {
+  if (N <= 0) return;
+  KScope ks(7, s);
+  add_units(7, N);
+  fill_i64(reinterpret_cast<int64_t *>(best), N, 0, s);
+  const int g = div_up(N, 256);
+  k_best<<<g, 256, 0, s>>>(pair, score, N, best);
+  HGP_LAUNCH_CHECK();
+  k_up<<<g, 256, 0, s>>>(pair, best, N, up, err);
+  HGP_LAUNCH_CHECK();
+  k_match<<<g, 256, 0, s>>>(pair, best, up, N, match, rep);
+  HGP_LAUNCH_CHECK();
+  scan_i32(rep, gamma, N, n_next_dev, scan_tmp, s);
+  k_gamma<<<g, 256, 0, s>>>(match, N, gamma);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
+                         hipStream_t s) {
+  if (N <= 0) return;
+  k_cluster_size<<<div_up(N, 256), 256, 0, s>>>(match, gamma, size, N, csize);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
+                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, DevBuf &scan_tmp, hipStream_t s) {
+  if (E <= 0) {
+    fill_i32(new_hoff, 1, 0, s);
+    return;
+  }
+  KScope ks(4, s);
+  k_contract<<<E, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt);
+  HGP_LAUNCH_CHECK();
+  scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);
+  k_pack<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, new_hoff, E, tmp_pins, new_hpin);
+  HGP_LAUNCH_CHECK();
+}
+
+__global__ void k_check_range(const int32_t *__restrict__ a, int64_t n, int32_t lo, int32_t hi, int32_t *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (a[i] < lo || a[i] >= hi)) atomicOr(err, kErrPin);
+}
+
+void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s) {
+  if (n <= 0) return;
+  k_check_range<<<div_up(n, 256), 256, 0, s>>>(a, n, lo, hi, err);
+  HGP_LAUNCH_CHECK();
+}
+
+// A canonical level: pin ids in [0, n), strictly ascending within a hedge.
+__global__ void k_check_level(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
+                              int32_t n, int32_t *err) {
+  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (wid >= E) return;
+  const int b = hoff[wid], en = hoff[wid + 1];
+  for (int j = b + lane_id(); j < en; j += 64) {
+    const int v = (int)(hpin[j] & kIdMask);
+    if (v >= n) atomicOr(err, kErrPin);
+    if (j > b && (int)(hpin[j - 1] & kIdMask) >= v) atomicOr(err, kErrDup);
+  }
+}
+
+void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t n, int32_t *err,
+                        hipStream_t s) {
+  if (E <= 0) return;
+  k_check_level<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, n, err);
+  HGP_LAUNCH_CHECK();
+}
+
+// Algorithmic units for kernel timing: sum |e|^2 and sum |e| * lambda(e).
+__global__ void k_units(const int32_t *__restrict__ hoff, const int32_t *__restrict__ lam, int32_t E,
+                        unsigned long long *acc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = 0;
+  if (e < E) {
+    const unsigned long long len = (unsigned long long)(hoff[e + 1] - hoff[e]);
+    v = lam ? len * (unsigned long long)lam[e] : len * len;
+  }
+  v = wave_sum(v);
+  if (lane_id() == 0 && v) atomicAdd(acc, v);
+}
+
+void launch_units(const int32_t *hoff, const int32_t *lam, int32_t E, unsigned long long *acc, hipStream_t s) {
+  if (E <= 0) return;
+  k_units<<<div_up(E, 256), 256, 0, s>>>(hoff, lam, E, acc);
+  HGP_LAUNCH_CHECK();
+}
+
+}  // namespace hgp

@@ -1,0 +1,103 @@
+// Host launchers of the coarsening and refinement kernels (internal).
+#pragma once
+
+#include "common.hpp"
+
+namespace hgp {
+
+// device error-flag bits
+constexpr int32_t kErrCsr = 1;         // offsets not monotone / not starting at 0
+constexpr int32_t kErrPin = 2;         // pin id out of range
+constexpr int32_t kErrDup = 4;         // duplicate pin within a hedge
+constexpr int32_t kErrNsrc = 8;        // n_src outside [0, |e|]
+constexpr int32_t kErrWeight = 16;     // weight < 1
+constexpr int32_t kErrInfeasible = 32; // node exceeding Omega or Delta on its own
+constexpr int32_t kErrBigHedge = 64;   // hedge larger than kSegCap pins
+constexpr int32_t kErrInternal = 128;  // internal consistency check
+
+// One hierarchy level resident on the device.
+struct LevelView {
+  int32_t n = 0;  // nodes
+  int32_t E = 0;  // hedges
+  const int32_t *hoff = nullptr;   // [E+1]
+  const uint32_t *hpin = nullptr;  // [P] id | dst << 31, ascending ids per hedge
+  const int32_t *ioff = nullptr;   // [n+1]
+  const uint32_t *inc = nullptr;   // [P] hedge | dst << 31 (any order within a node)
+  const int32_t *size = nullptr;   // [n]
+  const int32_t *indeg = nullptr;  // [n]
+  const int32_t *hw = nullptr;     // [E]
+};
+
+// --- coarsen.hip ---
+void launch_check_offsets(const int32_t *off, int32_t E, int32_t *err, hipStream_t s);
+void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32_t N, int32_t *err,
+                          unsigned long long *sums, hipStream_t s);
+void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
+                  uint32_t *hpin, hipStream_t s);
+void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int32_t *ioff, uint32_t *inc,
+                     int32_t *indeg, int32_t *work, DevBuf &scan_tmp, hipStream_t s);
+void launch_node_totals(const int32_t *ioff, const uint32_t *inc, const int32_t *hw, int32_t N, int32_t *total,
+                        hipStream_t s);
+void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
+                     int32_t *err, hipStream_t s);
+void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
+                 int64_t *score, hipStream_t s);
+void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,
+                  int32_t *match, int32_t *gamma, int32_t *rep, int32_t *n_next_dev, int32_t *err,
+                  DevBuf &scan_tmp, hipStream_t s);
+void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
+                         hipStream_t s);
+void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
+                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, DevBuf &scan_tmp, hipStream_t s);
+
+void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s);
+void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t n, int32_t *err,
+                        hipStream_t s);
+
+void launch_units(const int32_t *hoff, const int32_t *lam, int32_t E, unsigned long long *acc, hipStream_t s);
+
+// --- refine.hip ---
+struct RoundBufs {
+  // part table (oversized: one slot per pin, at the hedge's pin offset)
+  int2 *pt = nullptr;          // [P] (part, pins(p,e))
+  int32_t *ptin = nullptr;     // [P] pins_in(p,e)
+  int32_t *lam = nullptr;      // [E] entries per hedge
+  int32_t *psize = nullptr;    // [n_parts]
+  int32_t *pinb = nullptr;     // [n_parts]
+  int32_t *dest = nullptr;     // [n]
+  int32_t *gain = nullptr;     // [n]
+  int32_t *pos = nullptr;      // [n] 1-based sequence position, 0 if not moving
+  int32_t *flag = nullptr;     // [n] scratch
+  int32_t *seq = nullptr;      // [n]
+  uint64_t *keys = nullptr;    // [cap_events]
+  uint64_t *keys2 = nullptr;   // [cap_events]
+  int32_t *gp = nullptr;       // [n+1] in-sequence gain per position
+  int32_t *vdelta = nullptr;   // [n+1] violation deltas per position
+  int32_t *pcnt = nullptr;     // [n_parts+1] events per part -> offsets
+  int64_t *G = nullptr;        // [n+1]
+  int32_t *viol = nullptr;     // [n+1]
+  int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, applied, init_invalid
+  int64_t cap_events = 0;
+};
+
+void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, RoundBufs &B, int32_t *err,
+                       hipStream_t s);
+void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho, int32_t n_parts, int32_t omega,
+                    RoundBufs &B, hipStream_t s);
+// Builds the sequence; returns |S| (host sync).
+int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
+// In-sequence gains, validity, best prefix; returns (istar, Gstar) via host sync.
+void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta,
+                       int64_t S, RoundBufs &B, int32_t *err, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s,
+                       int64_t *istar, int64_t *gstar);
+void launch_apply(int32_t *rho, RoundBufs &B, int64_t istar, hipStream_t s);
+void launch_project(const int32_t *gamma, const int32_t *rho_coarse, int32_t n, int32_t *rho_fine, hipStream_t s);
+// Eq. 1 from a part table; result in *conn_dev (device int64).
+void launch_connectivity(const LevelView &L, const RoundBufs &B, int64_t *conn_dev, hipStream_t s);
+void launch_compact_parts(const int32_t *rho, int32_t n, int32_t n_parts, int32_t *used, int32_t *part_out,
+                          int32_t *np_dev, DevBuf &scan_tmp, hipStream_t s);
+
+void launch_cluster_size_sum(const int32_t *gamma, const int32_t *size, int32_t n, int32_t *out, hipStream_t s);
+void launch_widen(const int32_t *dest, const int32_t *gain, int32_t n, int32_t *d2, int64_t *g2, hipStream_t s);
+
+}  // namespace hgp

@@ -1,0 +1,834 @@
+// Host driver of the multilevel scheme (Sec. II-B) and the C-ABI of libhgp.
+#include <chrono>
+#include <cstring>
+#include <memory>
+
+#include "../../include/hgp.h"
+#include "coarsen.hpp"
+
+namespace hgp {
+
+static thread_local std::string g_last_error;
+
+struct Workspace {
+  DevBuf err, sums, scal2;
+  DevBuf hpin0, hoffA, hoffB, hpinA, hpinB, hoffR, hpinR, tmp_pins, cnt;
+  DevBuf ioff, inc, indeg, total, work;
+  DevBuf pair, score, best, up, match, rep;
+  DevBuf rhoA, rhoB, used, conn;
+  DevBuf pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, pcnt, G, viol, scal;
+  DevBuf scan_tmp, sort_tmp;
+  DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
+  DevBuf ones_e, ones_n;
+  std::vector<DevBuf> lv_size, lv_gamma, lv_Gamma;
+  std::vector<int32_t> lv_n;
+  KTimer timer;
+  DevBuf units_dev;
+
+  void clear_levels() {
+    for (auto &b : lv_size) b.release();
+    for (auto &b : lv_gamma) b.release();
+    for (auto &b : lv_Gamma) b.release();
+    lv_size.clear();
+    lv_gamma.clear();
+    lv_Gamma.clear();
+    lv_n.clear();
+  }
+
+  void release_all() {
+    DevBuf *all[] = {&err,  &sums,  &scal2,  &hpin0,  &hoffA,    &hoffB,  &hpinA,  &hpinB,   &hoffR,   &hpinR,
+                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work,   &pair,    &score,   &best,
+                     &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptin,    &lam,
+                     &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
+                     &vdelta, &pcnt, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
+                     &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
+    for (DevBuf *b : all) b->release();
+    units_dev.release();
+    timer.destroy();
+    clear_levels();
+  }
+};
+
+}  // namespace hgp
+
+struct hgp_ctx {
+  int device = 0;
+  hgp::Workspace ws;
+  ~hgp_ctx() { ws.release_all(); }
+};
+
+namespace hgp {
+
+template <class T>
+static T *need(DevBuf &b, int64_t n) {
+  b.reserve((size_t)(n > 0 ? n : 1) * sizeof(T));
+  return b.as<T>();
+}
+
+static int map_err(int32_t bits, const char **msg) {
+  if (bits & (kErrCsr | kErrPin | kErrNsrc)) {
+    *msg = (bits & kErrCsr) ? "hedge offsets are not monotone from 0"
+                            : (bits & kErrPin) ? "pin id out of range" : "n_src outside [0, |e|]";
+    return HGP_EBADCSR;
+  }
+  if (bits & kErrWeight) {
+    *msg = "hedge or node weight below 1";
+    return HGP_EINVAL;
+  }
+  if (bits & kErrDup) {
+    *msg = "duplicate pin within a hedge";
+    return HGP_EBADCSR;
+  }
+  if (bits & kErrBigHedge) {
+    *msg = "hedge with more than 4096 pins (unsupported)";
+    return HGP_EUNSUPPORTED;
+  }
+  if (bits & kErrInfeasible) {
+    *msg = "a node alone exceeds Omega or Delta";
+    return HGP_EINFEASIBLE;
+  }
+  if (bits & kErrInternal) {
+    *msg = "internal consistency check failed";
+    return HGP_EINTERNAL;
+  }
+  *msg = "";
+  return HGP_OK;
+}
+
+static int32_t read_i32(const int32_t *dptr, hipStream_t s) {
+  int32_t v = 0;
+  HGP_HIP(hipMemcpyAsync(&v, dptr, sizeof v, hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
+  const int32_t bits = read_i32(W.err.as<int32_t>(), s) & mask;
+  const char *msg = "";
+  const int rc = map_err(bits, &msg);
+  if (rc != HGP_OK) throw Error(rc, msg);
+}
+
+static void check_scalars(const hgp_hypergraph *g, int32_t omega, int32_t delta) {
+  if (!g) throw Error(HGP_EINVAL, "hypergraph is NULL");
+  if (g->n_nodes < 0 || g->n_hedges < 0) throw Error(HGP_EINVAL, "negative count");
+  if (omega < 1 || delta < 0) throw Error(HGP_EINVAL, "Omega < 1 or Delta < 0");
+  if (!g->hedge_off) throw Error(HGP_EINVAL, "hedge_off is NULL");
+  if (g->n_nodes >= (1 << 30)) throw Error(HGP_EUNSUPPORTED, "more than 2^30 - 1 nodes");
+}
+
+struct Ingest {
+  int64_t P = 0;
+  int64_t wsum_nodes = 0;
+  const int32_t *hw = nullptr;
+  const int32_t *nw = nullptr;
+  uint32_t *hpin0 = nullptr;
+};
+
+// Validate a device hypergraph (Sec. II-C layout) and build its canonical
+// level-0 pins: per hedge, ids ascending with the destination flag in bit 31.
+static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32_t delta, hipStream_t s) {
+  check_scalars(g, omega, delta);
+  Ingest I;
+  const int32_t N = g->n_nodes, E = g->n_hedges;
+  int32_t *err = need<int32_t>(W.err, 4);
+  fill_i32(err, 1, 0, s);
+  launch_check_offsets(g->hedge_off, E, err, s);
+  const int32_t P32 = read_i32(g->hedge_off + E, s);
+  check_err(W, s, kErrCsr | kErrBigHedge);
+  I.P = P32;
+  if (I.P > 0 && !g->pins) throw Error(HGP_EINVAL, "pins is NULL");
+  I.hpin0 = need<uint32_t>(W.hpin0, I.P);
+  unsigned long long *sums = need<unsigned long long>(W.sums, 2);
+  fill_i64(reinterpret_cast<int64_t *>(sums), 2, 0, s);
+  launch_check_weights(g->hedge_w, E, g->node_w, N, err, sums, s);
+  launch_canon(g->hedge_off, g->pins, g->n_src, E, N, err, I.hpin0, s);
+  unsigned long long hs[2] = {0, 0};
+  HGP_HIP(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, s));
+  check_err(W, s, kErrCsr | kErrPin | kErrNsrc | kErrWeight);
+  if (hs[0] > 2147483647ull || hs[1] > 2147483647ull)
+    throw Error(HGP_EUNSUPPORTED, "total hedge or node weight exceeds 2^31-1");
+  check_err(W, s);
+  I.wsum_nodes = (int64_t)hs[1];
+  if (g->hedge_w) {
+    I.hw = g->hedge_w;
+  } else {
+    int32_t *o = need<int32_t>(W.ones_e, E);
+    fill_i32(o, E, 1, s);
+    I.hw = o;
+  }
+  if (g->node_w) {
+    I.nw = g->node_w;
+  } else {
+    int32_t *o = need<int32_t>(W.ones_n, N);
+    fill_i32(o, N, 1, s);
+    I.nw = o;
+  }
+  return I;
+}
+
+// Incidence I(n) with destination flags, |in(n)| and total(n) of a level.
+// `size_cap` is the element capacity of the buffer behind `size` (checked).
+static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *hoff, const uint32_t *hpin,
+                           int64_t P, const int32_t *size, size_t size_cap, const int32_t *hw, hipStream_t s) {
+  if ((size_t)n > size_cap) throw Error(HGP_EINTERNAL, "node-size buffer smaller than the level");
+  int32_t *ioff = need<int32_t>(W.ioff, (int64_t)n + 1);
+  uint32_t *inc = need<uint32_t>(W.inc, P);
+  int32_t *indeg = need<int32_t>(W.indeg, n);
+  int32_t *work = need<int32_t>(W.work, n);
+  int32_t *total = need<int32_t>(W.total, n);
+  build_incidence(hoff, hpin, E, n, ioff, inc, indeg, work, W.scan_tmp, s);
+  add_units(HGP_K_INCIDENCE, P);
+  launch_node_totals(ioff, inc, hw, n, total, s);
+  LevelView L;
+  L.n = n;
+  L.E = E;
+  L.hoff = hoff;
+  L.hpin = hpin;
+  L.ioff = ioff;
+  L.inc = inc;
+  L.size = size;
+  L.indeg = indeg;
+  L.hw = hw;
+  return L;
+}
+
+static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32_t n_parts) {
+  RoundBufs B;
+  B.pt = need<int2>(W.pt, P);
+  B.ptin = need<int32_t>(W.ptin, P);
+  B.lam = need<int32_t>(W.lam, E);
+  B.psize = need<int32_t>(W.psize, n_parts);
+  B.pinb = need<int32_t>(W.pinb, n_parts);
+  B.dest = need<int32_t>(W.dest, n);
+  B.gain = need<int32_t>(W.gain, n);
+  B.pos = need<int32_t>(W.pos, n);
+  B.flag = need<int32_t>(W.flag, n);
+  B.seq = need<int32_t>(W.seq, n);
+  B.cap_events = 2 * P + 2 * (int64_t)n + 16;
+  B.keys = need<uint64_t>(W.keys, B.cap_events);
+  B.keys2 = need<uint64_t>(W.keys2, B.cap_events);
+  B.gp = need<int32_t>(W.gp, (int64_t)n + 1);
+  B.vdelta = need<int32_t>(W.vdelta, (int64_t)n + 1);
+  B.pcnt = need<int32_t>(W.pcnt, (int64_t)n_parts + 1);
+  B.G = need<int64_t>(W.G, (int64_t)n + 1);
+  B.viol = need<int32_t>(W.viol, (int64_t)n + 1);
+  B.scal = need<int64_t>(W.scal, 8);
+  return B;
+}
+
+struct RoundResult {
+  int64_t S = 0, istar = -1, gstar = 0;
+  bool applied = false;
+};
+
+// One refinement round (Sec. IV) on rho, in place.
+static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int32_t *rho, int32_t n_parts,
+                                int32_t omega, int32_t delta, hipStream_t s, RoundBufs *out_bufs = nullptr) {
+  RoundBufs B = round_bufs(W, L.n, L.E, P, n_parts);
+  int32_t *err = W.err.as<int32_t>();
+  launch_part_table(L, rho, n_parts, B, err, s);
+  add_units(HGP_K_PARTTABLE, P);
+  if (W.timer.on) launch_units(L.hoff, B.lam, L.E, W.units_dev.as<unsigned long long>() + HGP_K_PROPOSE, s);
+  launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s);
+  RoundResult R;
+  R.S = build_sequence(L, B, W.scan_tmp, W.sort_tmp, s);
+  if (R.S > 0) add_units(HGP_K_SEQEVENTS, P);
+  evaluate_sequence(L, rho, n_parts, omega, delta, R.S, B, err, W.scan_tmp, W.sort_tmp, s, &R.istar, &R.gstar);
+  check_err(W, s);
+  if (R.istar >= 0 && R.gstar > 0) {
+    launch_apply(rho, B, R.istar, s);
+    R.applied = true;
+  }
+  if (out_bufs) *out_bufs = B;
+  return R;
+}
+
+struct RunStats {
+  int64_t conn = 0;
+  int32_t n_parts = 0, n_levels = 0, n_rounds = 0;
+  double ms_coarsen = 0, ms_refine = 0;
+  double ms_kernel[HGP_NKERNEL] = {};
+  int64_t n_kernel[HGP_NKERNEL] = {};
+  int64_t units_kernel[HGP_NKERNEL] = {};
+};
+
+// Installs the context's kernel timer for the duration of one call.
+struct TimerGuard {
+  Workspace &W;
+  TimerGuard(Workspace &w, bool on, hipStream_t s) : W(w) {
+    W.timer.reset();
+    W.timer.on = on;
+    g_ktimer = &W.timer;
+    if (on) {
+      W.units_dev.reserve(HGP_NKERNEL * sizeof(int64_t));
+      fill_i64(W.units_dev.as<int64_t>(), HGP_NKERNEL, 0, s);
+    }
+  }
+  void collect(RunStats &st, hipStream_t s) {
+    if (!W.timer.on) return;
+    HGP_HIP(hipStreamSynchronize(s));
+    W.timer.resolve(st.ms_kernel, st.n_kernel);
+    int64_t dev[HGP_NKERNEL];
+    HGP_HIP(hipMemcpy(dev, W.units_dev.ptr, sizeof dev, hipMemcpyDeviceToHost));
+    for (int c = 0; c < HGP_NKERNEL; ++c) st.units_kernel[c] = W.timer.units[c] + dev[c];
+  }
+  ~TimerGuard() {
+    W.timer.on = false;
+    g_ktimer = nullptr;
+  }
+};
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// The multilevel scheme of Sec. II-B on a device hypergraph.  Coarsening
+// (Sec. III) repeats rate, match and contract until a matching leaves at most
+// T clusters (T = k, or ceil(sum w / Omega)) or matches nothing; those
+// clusters (or the nodes) are the initial parts.  Refinement (Sec. IV) then
+// runs from the coarsest level down, projecting through the cluster maps.
+// Coarse levels are not kept: level l is rebuilt from level 0 by the composed
+// cluster map when refinement reaches it.
+static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32_t delta,
+                              const hgp_options &opt, hipStream_t s, int32_t *part_out) {
+  RunStats st;
+  if (opt.k < 0 || opt.max_refine_rounds < 0) throw Error(HGP_EINVAL, "k < 0 or max_refine_rounds < 0");
+  const double t0 = now_ms();
+  Ingest I = ingest(W, g, omega, delta, s);
+  const int32_t N = g->n_nodes, E = g->n_hedges;
+  const int64_t P = I.P;
+  const int32_t *hoff0 = g->hedge_off;
+  const uint32_t *hpin0 = I.hpin0;
+  const int32_t *hw = I.hw;
+  W.clear_levels();
+  W.lv_size.emplace_back();
+  W.lv_n.push_back(N);
+  int32_t *size0 = need<int32_t>(W.lv_size[0], N);
+  if (N > 0)
+    HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
+  LevelView L = make_view(W, N, E, hoff0, hpin0, P, size0, W.lv_size[0].bytes / 4, hw, s);
+  launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
+  check_err(W, s);
+  st.n_levels = 1;
+  if (N == 0) {
+    // the single (empty) level still runs one refinement round that finds no move
+    st.n_rounds = opt.max_refine_rounds > 0 ? 1 : 0;
+    return st;
+  }
+  const int64_t T = opt.k > 0 ? (int64_t)opt.k : (I.wsum_nodes + omega - 1) / omega;
+  unsigned long long *units_dev = W.timer.on ? W.units_dev.as<unsigned long long>() : nullptr;
+
+  int32_t *pair = need<int32_t>(W.pair, N);
+  int64_t *score = need<int64_t>(W.score, N);
+  unsigned long long *best = need<unsigned long long>(W.best, N);
+  uint8_t *up = need<uint8_t>(W.up, N);
+  int32_t *match = need<int32_t>(W.match, N);
+  int32_t *rep = need<int32_t>(W.rep, N);
+  int32_t *nnext_dev = need<int32_t>(W.scal2, 4);
+  int32_t *rho = need<int32_t>(W.rhoA, N);
+  int32_t *rho2 = need<int32_t>(W.rhoB, N);
+  need<int32_t>(W.hoffA, (int64_t)E + 1);
+  need<int32_t>(W.hoffB, (int64_t)E + 1);
+  need<uint32_t>(W.hpinA, P);
+  need<uint32_t>(W.hpinB, P);
+  need<uint32_t>(W.tmp_pins, P);
+  need<int32_t>(W.cnt, E);
+
+  // ---- coarsening ----
+  int32_t n_parts = 0;
+  int lvl = 0;
+  const int32_t *cur_hoff = hoff0;
+  const uint32_t *cur_hpin = hpin0;
+  int64_t cur_P = P;
+  int ping = 0;
+  while (true) {
+    const int32_t n = L.n;
+    if (units_dev) launch_units(L.hoff, nullptr, E, units_dev + HGP_K_RATE, s);
+    launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s);
+    W.lv_gamma.emplace_back();
+    int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
+    launch_match(pair, score, n, best, up, match, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
+    const int32_t n_next = read_i32(nnext_dev, s);
+    check_err(W, s);
+    if (n_next == n) {
+      iota_i32(rho, n, s);
+      n_parts = n;
+      break;
+    }
+    if ((int64_t)n_next <= T) {
+      HGP_HIP(hipMemcpyAsync(rho, gam, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+      n_parts = n_next;
+      break;
+    }
+    W.lv_size.emplace_back();
+    W.lv_n.push_back(n_next);
+    int32_t *csize = need<int32_t>(W.lv_size[lvl + 1], n_next);
+    launch_cluster_size(match, gam, W.lv_size[lvl].as<int32_t>(), n, csize, s);
+    W.lv_Gamma.emplace_back();  // lv_Gamma[k]: level 0 -> level k+1
+    int32_t *Gm = need<int32_t>(W.lv_Gamma[lvl], N);
+    if (lvl == 0)
+      HGP_HIP(hipMemcpyAsync(Gm, gam, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    else
+      launch_project(W.lv_Gamma[lvl - 1].as<int32_t>(), gam, N, Gm, s);
+    int32_t *nh = ping ? W.hoffB.as<int32_t>() : W.hoffA.as<int32_t>();
+    uint32_t *npin = ping ? W.hpinB.as<uint32_t>() : W.hpinA.as<uint32_t>();
+    launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin,
+                    W.scan_tmp, s);
+    add_units(HGP_K_CONTRACT, cur_P);
+    cur_P = read_i32(nh + E, s);
+    cur_hoff = nh;
+    cur_hpin = npin;
+    ping ^= 1;
+    ++lvl;
+    L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, s);
+  }
+  const int Lmax = lvl;
+  st.n_levels = Lmax + 1;
+  HGP_HIP(hipStreamSynchronize(s));
+  const double t1 = now_ms();
+
+  // ---- refinement, coarsest level first ----
+  int rounds = 0;
+  LevelView V0;  // level 0, built by the last iteration
+  for (int lv = Lmax; lv >= 0; --lv) {
+    const int32_t n = W.lv_n[lv];
+    LevelView V;
+    int64_t Pl = 0;
+    if (lv == Lmax) {
+      V = L;
+      Pl = cur_P;
+    } else {
+      // rho_lv(v) = rho_{lv+1}(gamma_lv(v))
+      launch_project(W.lv_gamma[lv].as<int32_t>(), rho, n, rho2, s);
+      std::swap(rho, rho2);
+      const int32_t *h;
+      const uint32_t *p;
+      if (lv == 0) {
+        h = hoff0;
+        p = hpin0;
+        Pl = P;
+      } else {
+        int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
+        uint32_t *rp = need<uint32_t>(W.hpinR, P);
+        launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
+                        W.cnt.as<int32_t>(), rh, rp, W.scan_tmp, s);
+        add_units(HGP_K_CONTRACT, P);
+        Pl = read_i32(rh + E, s);
+        h = rh;
+        p = rp;
+      }
+      V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, s);
+    }
+    for (int r = 0; r < opt.max_refine_rounds; ++r) {
+      ++rounds;
+      RoundResult R = refine_round(W, V, Pl, rho, n_parts, omega, delta, s);
+      if (!R.applied) break;
+    }
+    if (lv == 0) V0 = V;
+  }
+  st.n_rounds = rounds;
+
+  // ---- output: Eq. 1 and compact part ids ----
+  {
+    if (V0.n != N || V0.hoff != hoff0 || V0.hpin != hpin0) throw Error(HGP_EINTERNAL, "level-0 view");
+    RoundBufs B = round_bufs(W, N, E, P, n_parts);
+    launch_part_table(V0, rho, n_parts, B, W.err.as<int32_t>(), s);
+    int64_t *conn = need<int64_t>(W.conn, 2);
+    launch_connectivity(V0, B, conn, s);
+    int32_t *used = need<int32_t>(W.used, (int64_t)n_parts + 1);
+    launch_compact_parts(rho, N, n_parts, used, part_out, reinterpret_cast<int32_t *>(conn + 1), W.scan_tmp, s);
+    int64_t h[2];
+    HGP_HIP(hipMemcpyAsync(h, conn, sizeof h, hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipStreamSynchronize(s));
+    check_err(W, s);
+    st.conn = h[0];
+    st.n_parts = (int32_t)(h[1] & 0xffffffff);
+  }
+  const double t2 = now_ms();
+  st.ms_coarsen = t1 - t0;
+  st.ms_refine = t2 - t1;
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// ABI plumbing
+// ---------------------------------------------------------------------------
+template <class F>
+static int guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return HGP_OK;
+  } catch (const Error &e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return HGP_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return HGP_EINTERNAL;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return HGP_EINTERNAL;
+  }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    HGP_HIP(hipGetDevice(&prev));
+    if (prev != dev) HGP_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+static hgp_options opts_or_default(const hgp_options *o) {
+  hgp_options d;
+  hgp_options_default(&d);
+  return o ? *o : d;
+}
+
+static void fill_result(hgp_result *res, const RunStats &st) {
+  if (!res) return;
+  std::memset(res, 0, sizeof *res);
+  res->connectivity = st.conn;
+  res->n_parts = st.n_parts;
+  res->n_levels = st.n_levels;
+  res->n_rounds = st.n_rounds;
+  res->ms_coarsen = st.ms_coarsen;
+  res->ms_refine = st.ms_refine;
+  for (int c = 0; c < HGP_NKERNEL; ++c) {
+    res->ms_kernel[c] = st.ms_kernel[c];
+    res->n_kernel[c] = st.n_kernel[c];
+    res->units_kernel[c] = st.units_kernel[c];
+  }
+}
+
+static LevelView level_view_from(Workspace &W, const hgp_level *lv, hipStream_t s, int64_t *P_out) {
+  if (!lv || lv->n_nodes < 0 || lv->n_hedges < 0 || !lv->hoff || !lv->size || !lv->hedge_w)
+    throw Error(HGP_EINVAL, "bad level");
+  if (lv->n_nodes >= (1 << 30)) throw Error(HGP_EUNSUPPORTED, "more than 2^30 - 1 nodes");
+  const int64_t P = read_i32(lv->hoff + lv->n_hedges, s);
+  if (P > 0 && !lv->hpin) throw Error(HGP_EINVAL, "bad level");
+  *P_out = P;
+  int32_t *err = need<int32_t>(W.err, 4);
+  fill_i32(err, 1, 0, s);
+  launch_check_offsets(lv->hoff, lv->n_hedges, err, s);
+  check_err(W, s);
+  launch_check_level(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), lv->n_hedges, lv->n_nodes, err, s);
+  check_err(W, s);
+  return make_view(W, lv->n_nodes, lv->n_hedges, lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), P,
+                   lv->size, (size_t)lv->n_nodes, lv->hedge_w, s);
+}
+
+}  // namespace hgp
+
+using namespace hgp;
+
+extern "C" {
+
+void hgp_options_default(hgp_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof *opt);
+  opt->k = 0;
+  opt->max_refine_rounds = 8;
+  opt->seed = 0;
+  opt->proposal = HGP_PLAIN;
+}
+
+const char *hgp_strerror(int code) {
+  switch (code) {
+    case HGP_OK: return "success";
+    case HGP_EINVAL: return "invalid argument";
+    case HGP_EBADCSR: return "malformed CSR hypergraph";
+    case HGP_EINFEASIBLE: return "infeasible: a node alone exceeds Omega or Delta";
+    case HGP_ENOMEM: return "out of memory";
+    case HGP_EDEVICE: return "HIP device error";
+    case HGP_EUNSUPPORTED: return "unsupported input";
+    case HGP_EINTERNAL: return "internal error";
+    default: return "unknown error";
+  }
+}
+
+const char *hgp_last_error(void) { return g_last_error.c_str(); }
+
+int hgp_ctx_create(hgp_ctx **ctx, int device) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  *ctx = nullptr;
+  return guarded([&] {
+    int count = 0;
+    HGP_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) throw Error(HGP_EINVAL, "no such device");
+    DeviceGuard dg(device);
+    HGP_HIP(hipFree(nullptr));
+    hgp_ctx *c = new hgp_ctx();
+    c->device = device;
+    *ctx = c;
+  });
+}
+
+void hgp_ctx_destroy(hgp_ctx *ctx) {
+  if (!ctx) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+int hgp_partition_device(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta,
+                         const hgp_options *opt, void *stream, int32_t *part_out, hgp_result *res) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g && g->n_nodes > 0 && !part_out) throw Error(HGP_EINVAL, "part_out is NULL");
+    const hgp_options o = opts_or_default(opt);
+    TimerGuard tg(ctx->ws, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+    RunStats st = run_partition(ctx->ws, g, omega, delta, o, s, part_out);
+    tg.collect(st, s);
+    HGP_HIP(hipStreamSynchronize(s));
+    fill_result(res, st);
+  });
+}
+
+int hgp_partition(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta, const hgp_options *opt,
+                  int32_t *part_out, hgp_result *res) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    check_scalars(g, omega, delta);
+    Workspace &W = ctx->ws;
+    const int32_t N = g->n_nodes, E = g->n_hedges;
+    if (N > 0 && !part_out) throw Error(HGP_EINVAL, "part_out is NULL");
+    for (int32_t e = 0; e < E; ++e)
+      if (g->hedge_off[e + 1] < g->hedge_off[e]) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
+    if (g->hedge_off[0] != 0) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
+    const int64_t P = g->hedge_off[E];
+    if (P > 0 && !g->pins) throw Error(HGP_EINVAL, "pins is NULL");
+    hipStream_t s = nullptr;
+    hgp_hypergraph d = *g;
+    int32_t *off = need<int32_t>(W.in_off, (int64_t)E + 1);
+    HGP_HIP(hipMemcpyAsync(off, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyHostToDevice, s));
+    d.hedge_off = off;
+    if (P > 0) {
+      int32_t *pp = need<int32_t>(W.in_pins, P);
+      HGP_HIP(hipMemcpyAsync(pp, g->pins, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
+      d.pins = pp;
+    }
+    if (g->n_src && E > 0) {
+      int32_t *q = need<int32_t>(W.in_nsrc, E);
+      HGP_HIP(hipMemcpyAsync(q, g->n_src, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
+      d.n_src = q;
+    }
+    if (g->hedge_w && E > 0) {
+      int32_t *q = need<int32_t>(W.in_hw, E);
+      HGP_HIP(hipMemcpyAsync(q, g->hedge_w, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
+      d.hedge_w = q;
+    }
+    if (g->node_w && N > 0) {
+      int32_t *q = need<int32_t>(W.in_nw, N);
+      HGP_HIP(hipMemcpyAsync(q, g->node_w, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s));
+      d.node_w = q;
+    }
+    int32_t *po = need<int32_t>(W.in_part, N);
+    const hgp_options o = opts_or_default(opt);
+    TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+    RunStats st = run_partition(W, &d, omega, delta, o, s, po);
+    tg.collect(st, s);
+    if (N > 0) HGP_HIP(hipMemcpyAsync(part_out, po, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipStreamSynchronize(s));
+    fill_result(res, st);
+  });
+}
+
+int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, void *stream,
+                            int64_t *out) {
+  if (!ctx || !out) {
+    g_last_error = "ctx or out is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (g && g->n_nodes > 0 && !part) throw Error(HGP_EINVAL, "part is NULL");
+    Workspace &W = ctx->ws;
+    Ingest I = ingest(W, g, 1, 0x7fffffff, s);
+    const int32_t N = g->n_nodes, E = g->n_hedges;
+    // part ids must be valid indices: bound them by the node count (ids >= 0 checked on device)
+    const int32_t np = N > 0 ? N : 1;
+    launch_check_range(part, N, 0, np, W.err.as<int32_t>(), s);
+    check_err(W, s);
+    LevelView V;
+    V.n = N;
+    V.E = E;
+    V.hoff = g->hedge_off;
+    V.hpin = I.hpin0;
+    V.hw = I.hw;
+    RoundBufs B = round_bufs(W, N, E, I.P, np);
+    launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
+    int64_t *conn = need<int64_t>(W.conn, 2);
+    launch_connectivity(V, B, conn, s);
+    HGP_HIP(hipMemcpyAsync(out, conn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int hgp_level_canonical(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta, void *stream,
+                        int32_t *hoff_out, int32_t *hpin_out) {
+  if (!ctx || !hoff_out) {
+    g_last_error = "ctx or hoff_out is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Workspace &W = ctx->ws;
+    Ingest I = ingest(W, g, omega, delta, s);
+    const int32_t N = g->n_nodes, E = g->n_hedges;
+    if (I.P > 0 && !hpin_out) throw Error(HGP_EINVAL, "hpin_out is NULL");
+    int32_t *size0 = need<int32_t>(W.rhoB, N);
+    if (N > 0) HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
+    LevelView L = make_view(W, N, E, g->hedge_off, I.hpin0, I.P, size0, W.rhoB.bytes / 4, I.hw, s);
+    launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
+    check_err(W, s);
+    HGP_HIP(hipMemcpyAsync(hoff_out, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyDeviceToDevice, s));
+    if (I.P > 0)
+      HGP_HIP(hipMemcpyAsync(hpin_out, I.hpin0, sizeof(int32_t) * (size_t)I.P, hipMemcpyDeviceToDevice, s));
+    HGP_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int hgp_level_rate(hgp_ctx *ctx, const hgp_level *lv, int32_t omega, int32_t delta, void *stream,
+                   int32_t *pair_out, int64_t *score_out) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (omega < 1 || delta < 0) throw Error(HGP_EINVAL, "Omega < 1 or Delta < 0");
+    if (lv && lv->n_nodes > 0 && (!pair_out || !score_out)) throw Error(HGP_EINVAL, "output is NULL");
+    int64_t P = 0;
+    LevelView L = level_view_from(ctx->ws, lv, s, &P);
+    launch_rate(L, ctx->ws.total.as<int32_t>(), omega, delta, pair_out, score_out, s);
+    HGP_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, void *stream,
+                    int32_t *match_out, int32_t *gamma_out, int32_t *n_next) {
+  if (!ctx || !n_next) {
+    g_last_error = "ctx or n_next is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n < 0) throw Error(HGP_EINVAL, "negative count");
+    if (n > 0 && (!pair || !score || !match_out || !gamma_out)) throw Error(HGP_EINVAL, "NULL array");
+    Workspace &W = ctx->ws;
+    if (n == 0) {
+      *n_next = 0;
+      return;
+    }
+    need<int32_t>(W.err, 4);
+    fill_i32(W.err.as<int32_t>(), 1, 0, s);
+    unsigned long long *best = need<unsigned long long>(W.best, n);
+    uint8_t *up = need<uint8_t>(W.up, n);
+    int32_t *rep = need<int32_t>(W.rep, n);
+    int32_t *nn = need<int32_t>(W.scal2, 4);
+    launch_check_range(pair, n, -1, n, W.err.as<int32_t>(), s);
+    check_err(W, s);
+    launch_match(pair, score, n, best, up, match_out, gamma_out, rep, nn, W.err.as<int32_t>(), W.scan_tmp, s);
+    *n_next = read_i32(nn, s);
+    check_err(W, s);
+  });
+}
+
+int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, int32_t n_next, void *stream,
+                       int32_t *hoff_out, int32_t *hpin_out, int32_t *size_out) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!lv || !hoff_out || lv->n_nodes < 0 || lv->n_hedges < 0 || n_next < 0) throw Error(HGP_EINVAL, "bad args");
+    if (lv->n_nodes > 0 && (!gamma || !size_out || !lv->size)) throw Error(HGP_EINVAL, "NULL array");
+    Workspace &W = ctx->ws;
+    const int32_t E = lv->n_hedges;
+    const int64_t P = read_i32(lv->hoff + E, s);
+    if (P > 0 && (!hpin_out || !lv->hpin)) throw Error(HGP_EINVAL, "NULL array");
+    int32_t *err = need<int32_t>(W.err, 4);
+    fill_i32(err, 1, 0, s);
+    launch_check_offsets(lv->hoff, E, err, s);
+    check_err(W, s);
+    launch_check_level(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, lv->n_nodes, err, s);
+    launch_check_range(gamma, lv->n_nodes, 0, n_next, err, s);
+    check_err(W, s);
+    uint32_t *tmp = need<uint32_t>(W.tmp_pins, P);
+    int32_t *cnt = need<int32_t>(W.cnt, E);
+    launch_contract(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, gamma, tmp, cnt, hoff_out,
+                    reinterpret_cast<uint32_t *>(hpin_out), W.scan_tmp, s);
+    // cluster sizes: sum of member sizes (atomics over the fine nodes)
+    fill_i32(size_out, n_next, 0, s);
+    launch_cluster_size_sum(gamma, lv->size, lv->n_nodes, size_out, s);
+    HGP_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int hgp_level_refine_round(hgp_ctx *ctx, const hgp_level *lv, const int32_t *rho, int32_t n_parts, int32_t omega,
+                           int32_t delta, void *stream, int32_t *pdest, int64_t *pgain, int32_t *seq, int64_t *gsum,
+                           int32_t *viol, int32_t *rho_out, int64_t *info) {
+  if (!ctx || !info) {
+    g_last_error = "ctx or info is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (omega < 1 || delta < 0 || n_parts < 0) throw Error(HGP_EINVAL, "bad scalar");
+    if (lv && lv->n_nodes > 0 && (!rho || !pdest || !pgain || !seq || !gsum || !viol || !rho_out))
+      throw Error(HGP_EINVAL, "NULL array");
+    Workspace &W = ctx->ws;
+    int64_t P = 0;
+    LevelView L = level_view_from(W, lv, s, &P);
+    const int32_t n = L.n;
+    launch_check_range(rho, n, 0, n_parts, W.err.as<int32_t>(), s);
+    check_err(W, s);
+    if (n > 0)
+      HGP_HIP(hipMemcpyAsync(rho_out, rho, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    RoundBufs B;
+    RoundResult R = refine_round(W, L, P, rho_out, n_parts, omega, delta, s, &B);
+    if (n > 0) {
+      launch_widen(B.dest, B.gain, n, pdest, pgain, s);
+      if (R.S > 0) HGP_HIP(hipMemcpyAsync(seq, B.seq, sizeof(int32_t) * (size_t)R.S, hipMemcpyDeviceToDevice, s));
+      HGP_HIP(hipMemcpyAsync(gsum, B.G, sizeof(int64_t) * (size_t)(R.S + 1), hipMemcpyDeviceToDevice, s));
+      HGP_HIP(hipMemcpyAsync(viol, B.viol, sizeof(int32_t) * (size_t)(R.S + 1), hipMemcpyDeviceToDevice, s));
+    }
+    HGP_HIP(hipStreamSynchronize(s));
+    info[0] = R.S;
+    info[1] = R.istar;
+    info[2] = R.gstar;
+    info[3] = R.applied ? 1 : 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// Device-wide primitives: exclusive scans, stable LSD radix sort, fills.
+#include "common.hpp"
+
+#include <cstdio>
+
+namespace hgp {
+
+void hip_fail(hipError_t e, const char *what, const char *file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  if (e == hipErrorOutOfMemory) throw Error(-4, buf);
+  throw Error(-5, buf);
+}
+
+thread_local KTimer *g_ktimer = nullptr;
+
+hipEvent_t KTimer::take() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    HGP_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+void KTimer::begin(hipStream_t s) {
+  pending = take();
+  HGP_HIP(hipEventRecord(pending, s));
+}
+
+void KTimer::end(int cls, hipStream_t s) {
+  hipEvent_t b = take();
+  HGP_HIP(hipEventRecord(b, s));
+  recs.push_back({cls, pending, b});
+}
+
+void KTimer::reset() {
+  used = 0;
+  recs.clear();
+  for (auto &u : units) u = 0;
+}
+
+void KTimer::resolve(double *ms, int64_t *cnt) {
+  for (const Rec &r : recs) {
+    float t = 0.f;
+    HGP_HIP(hipEventSynchronize(r.b));
+    HGP_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    cnt[r.cls] += 1;
+  }
+}
+
+void KTimer::destroy() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+  used = 0;
+  recs.clear();
+}
+
+void DevBuf::reserve(size_t need) {
+  if (need <= bytes) return;
+  release();
+  size_t b = need < 256 ? 256 : need;
+  b = (b + 255) & ~size_t(255);
+  hipError_t e = hipMalloc(&ptr, b);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    bytes = 0;
+    (void)hipGetLastError();
+    throw Error(-4, "device allocation of " + std::to_string(b) + " bytes failed");
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_fill(T *p, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_iota(int32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// scans
+// ---------------------------------------------------------------------------
+constexpr int SC_NT = 256;
+constexpr int SC_TILE = 4096;
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_tile_sum(const T *__restrict__ in, int64_t n, T *__restrict__ bsum) {
+  __shared__ T red[SC_NT / 64];
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  T s = 0;
+  for (int i = threadIdx.x; i < SC_TILE; i += SC_NT) {
+    const int64_t j = base + i;
+    if (j < n) s += in[j];
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T t = 0;
+    for (int w = 0; w < SC_NT / 64; ++w) t += red[w];
+    bsum[blockIdx.x] = t;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(SC_NT) void k_tile_scan(const T *in, T *out, int64_t n, const T *__restrict__ boff,
+                                                     T *total) {
+  __shared__ T tile[SC_TILE];
+  __shared__ T tmp[SC_NT / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  for (int i = threadIdx.x; i < SC_TILE; i += SC_NT) {
+    const int64_t j = base + i;
+    tile[i] = j < n ? in[j] : T(0);
+  }
+  __syncthreads();
+  T tot = block_exclusive_scan<T, SC_NT>(tile, SC_TILE, tmp);
+  const T off = boff ? boff[blockIdx.x] : T(0);
+  for (int i = threadIdx.x; i < SC_TILE; i += SC_NT) {
+    const int64_t j = base + i;
+    if (j < n) out[j] = tile[i] + off;
+  }
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
+}
+
+template <class T>
+static void scan_impl(const T *in, T *out, int64_t n, T *total, T *tmp, hipStream_t s) {
+  if (n <= 0) {
+    if (total) {
+      k_fill<T><<<1, 1, 0, s>>>(total, 1, T(0));
+      HGP_LAUNCH_CHECK();
+    }
+    return;
+  }
+  const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+  if (nb == 1) {
+    k_tile_scan<T><<<1, SC_NT, 0, s>>>(in, out, n, nullptr, total);
+    HGP_LAUNCH_CHECK();
+    return;
+  }
+  T *bsum = tmp;
+  k_tile_sum<T><<<(unsigned)nb, SC_NT, 0, s>>>(in, n, bsum);
+  HGP_LAUNCH_CHECK();
+  scan_impl<T>(bsum, bsum, nb, nullptr, tmp + ((nb + 63) & ~int64_t(63)), s);
+  k_tile_scan<T><<<(unsigned)nb, SC_NT, 0, s>>>(in, out, n, bsum, total);
+  HGP_LAUNCH_CHECK();
+}
+
+static size_t scan_tmp_elems(int64_t n) {
+  size_t t = 0;
+  while (n > SC_TILE) {
+    n = (n + SC_TILE - 1) / SC_TILE;
+    t += (size_t)((n + 63) & ~int64_t(63));
+  }
+  return t + 64;
+}
+
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, DevBuf &tmp, hipStream_t s) {
+  tmp.reserve(scan_tmp_elems(n) * sizeof(int32_t));
+  scan_impl<int32_t>(in, out, n, total, tmp.as<int32_t>(), s);
+}
+
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, DevBuf &tmp, hipStream_t s) {
+  tmp.reserve(scan_tmp_elems(n) * sizeof(int64_t));
+  scan_impl<int64_t>(in, out, n, total, tmp.as<int64_t>(), s);
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits, 4096-key tiles
+// ---------------------------------------------------------------------------
+constexpr int RS_NT = 256;
+constexpr int RS_ROUNDS = 16;
+constexpr int RS_TILE = RS_NT * RS_ROUNDS;
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                   int32_t *__restrict__ hist, int ntiles) {
+  __shared__ int32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t j = base + r * RS_NT + threadIdx.x;
+    if (j < n) atomicAdd(&cnt[(keys[j] >> shift) & 255u], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ vals, int64_t n, int shift,
+                                                      const int32_t *__restrict__ offs, int ntiles,
+                                                      uint64_t *__restrict__ okeys, uint32_t *__restrict__ ovals) {
+  __shared__ int32_t base[256];
+  __shared__ int32_t wcnt[RS_NT / 64][256];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
+    __syncthreads();
+    const int64_t j = tbase + r * RS_NT + tid;
+    const bool valid = j < n;
+    uint64_t key = valid ? keys[j] : 0;
+    uint32_t val = (valid && vals) ? vals[j] : 0u;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      match &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(match & lt);
+    const int cnt = __popcll(match);
+    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;  // last lane of the group publishes
+    __syncthreads();
+    if (valid) {
+      int pre = 0;
+      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      const int64_t pos = (int64_t)base[d] + pre + rank;
+      okeys[pos] = key;
+      if (vals) ovals[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
+    base[tid] += add;
+    __syncthreads();
+  }
+}
+
+void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
+                    DevBuf &tmp, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return;
+  const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+  const int64_t hn = 256LL * ntiles;
+  const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
+  const size_t need = hist_bytes + scan_tmp_elems(hn) * sizeof(int32_t);
+  tmp.reserve(need);
+  int32_t *hist = tmp.as<int32_t>();
+  int32_t *stmp = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
+  uint64_t *src = keys, *dst = alt;
+  uint32_t *vs = vals, *vd = valt;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += 8, ++passes) {
+    k_rs_hist<<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
+    HGP_LAUNCH_CHECK();
+    scan_impl<int32_t>(hist, hist, hn, nullptr, stmp, s);
+    k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+    HGP_LAUNCH_CHECK();
+    std::swap(src, dst);
+    std::swap(vs, vd);
+  }
+  if (passes & 1) {
+    HGP_HIP(hipMemcpyAsync(keys, src, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (vals) HGP_HIP(hipMemcpyAsync(vals, vs, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<int32_t><<<div_up(n, 256), 256, 0, s>>>(p, n, v);
+  HGP_LAUNCH_CHECK();
+}
+
+void fill_i64(int64_t *p, int64_t n, int64_t v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill<int64_t><<<div_up(n, 256), 256, 0, s>>>(p, n, v);
+  HGP_LAUNCH_CHECK();
+}
+
+void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_iota<<<div_up(n, 256), 256, 0, s>>>(p, n);
+  HGP_LAUNCH_CHECK();
+}
+
+}  // namespace hgp

@@ -1,0 +1,257 @@
+"""GPU path vs CPU oracle, end to end and step by step (through the C-ABI).
+
+Integer method: every comparison is exact.
+"""
+import hashlib
+import json
+import os
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2604_14411_amd import synth
+from paper_2604_14411_amd.synth import from_lists
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2604_14411_amd import hgp
+
+    assert torch.cuda.is_available()
+    c = hgp.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_partition(ctx, g, omega, delta, k=0, rounds=8):
+    from paper_2604_14411_amd import hgp
+
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    try:
+        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds)
+        return 0, parts.cpu().numpy(), res
+    except hgp.HgpError as e:
+        return e.code, None, None
+
+
+def _compare(ctx, g, omega, delta, k=0, rounds=8, label=""):
+    say(f"[parity] {label} n={g.n_nodes} E={g.n_hedges} P={g.n_pins} omega={omega} delta={delta} k={k} R={rounds}")
+    rc, ref, rres, _ = oracle.partition(g, omega, delta, k=k, max_rounds=rounds)
+    grc, got, gres = _gpu_partition(ctx, g, omega, delta, k, rounds)
+    assert grc == rc, (grc, rc)
+    if rc != 0:
+        return
+    assert np.array_equal(got, ref), "part ids differ"
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds"):
+        assert gres[key] == rres[key], (key, gres[key], rres[key])
+
+
+def _tiny(seed):
+    rng = random.Random(seed)
+    n = rng.randint(1, 14)
+    hedges, w, nw = brute.random_tiny(rng, n, rng.randint(0, 12), 6, wmax=6, node_wmax=rng.choice([1, 1, 3]))
+    return from_lists(n, hedges, w, nw), rng.randint(1, 9), rng.randint(0, 8), rng.choice([0, 0, 1, 3]), \
+        rng.choice([0, 1, 8])
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_tiny_random_end_to_end(ctx, seed):
+    g, omega, delta, k, rounds = _tiny(seed)
+    _compare(ctx, g, omega, delta, k, rounds, label=f"tiny seed={seed}")
+
+
+MEDIUM = [
+    ("rand300", lambda: synth.random_snn(300, 9.0, 101), 12, 60),
+    ("rand1500", lambda: synth.random_snn(1500, 24.0, 102), 64, 200),
+    ("rand4000", lambda: synth.random_snn(4000, 40.0, 103), 128, 600),
+    ("rand3000_tightD", lambda: synth.random_snn(3000, 30.0, 104), 1024, 120),
+    ("conv_small", lambda: synth.layered_conv(4, 6, 8, 8, 3, 0.1, 105), 64, 2000),
+    ("conv_wide", lambda: synth.layered_conv(5, 4, 10, 9, 5, 0.2, 106), 96, 500),
+]
+
+
+@pytest.mark.parametrize("name,make,omega,delta", MEDIUM, ids=[m[0] for m in MEDIUM])
+def test_medium_end_to_end(ctx, name, make, omega, delta):
+    _compare(ctx, make(), omega, delta, label=name)
+
+
+def test_host_entry_matches_device_entry(ctx):
+    from paper_2604_14411_amd import hgp
+
+    g = synth.random_snn(2000, 20.0, 7)
+    say("[parity] host entry rand2000")
+    p1, r1 = hgp.partition_host(ctx, g, 64, 300)
+    rc, p2, r2 = _gpu_partition(ctx, g, 64, 300)
+    assert rc == 0 and np.array_equal(p1, p2) and r1["connectivity"] == r2["connectivity"]
+
+
+def test_repeat_runs_identical(ctx):
+    g = synth.random_snn(2500, 30.0, 8)
+    outs = []
+    for i in range(3):
+        say(f"[determinism] run {i}")
+        rc, p, r = _gpu_partition(ctx, g, 80, 400)
+        assert rc == 0
+        outs.append((p.tobytes(), r["connectivity"]))
+    assert outs[0] == outs[1] == outs[2]
+
+
+def test_seed_does_not_change_plain_result(ctx):
+    from paper_2604_14411_amd import hgp
+
+    g = synth.random_snn(1200, 16.0, 9)
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    say("[seed] two seeds")
+    import ctypes
+
+    outs = []
+    for seed in (1, 987654321):
+        o = hgp.options(0, 8, seed)
+        import torch
+
+        out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
+        res = hgp.Result_t()
+        hgp._check(hgp.load().hgp_partition_device(ctx.handle, ctypes.byref(dg.struct()), 64, 256, ctypes.byref(o),
+                                                   hgp._stream(), out.data_ptr(), ctypes.byref(res)))
+        outs.append(out.cpu().numpy().tobytes())
+    assert outs[0] == outs[1]
+
+
+# --------------------------------------------------------------- step parity
+def _t(a, dt=None):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a) if dt is None else np.ascontiguousarray(a, dtype=dt)).to("cuda:0")
+
+
+STEP_CASES = [
+    ("rand1200", lambda: synth.random_snn(1200, 16.0, 21), 48, 220),
+    ("conv", lambda: synth.layered_conv(4, 5, 7, 7, 3, 0.1, 22), 40, 900),
+]
+
+
+@pytest.mark.parametrize("name,make,omega,delta", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_each_step_matches_oracle_trace(ctx, name, make, omega, delta):
+    from paper_2604_14411_amd import hgp
+
+    g = make()
+    rc, parts, res, tr = oracle.partition(g, omega, delta, trace=True)
+    assert rc == 0
+    hw = _t(g.hedge_w, np.int32)
+    # canonical level 0
+    say(f"[steps] {name} canonical")
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    hoff0, hpin0 = hgp.level_canonical(ctx, dg, omega, delta)
+    assert np.array_equal(hoff0.cpu().numpy(), tr.get(oracle.LV_HOFF, 0).astype(np.int32))
+    assert np.array_equal(hpin0.cpu().numpy(), tr.get(oracle.LV_HPIN, 0))
+    for l in range(tr.levels):
+        hoff = _t(tr.get(oracle.LV_HOFF, l), np.int32)
+        hpin = _t(tr.get(oracle.LV_HPIN, l), np.int32)
+        size = _t(tr.get(oracle.LV_SIZE, l), np.int32)
+        n = size.numel()
+        say(f"[steps] {name} level {l} rate n={n}")
+        pair, score = hgp.level_rate(ctx, n, hoff, hpin, size, hw, omega, delta)
+        assert np.array_equal(pair.cpu().numpy(), tr.get(oracle.LV_PAIR, l)), f"pair level {l}"
+        assert np.array_equal(score.cpu().numpy(), tr.get(oracle.LV_SCORE, l)), f"score level {l}"
+        say(f"[steps] {name} level {l} match")
+        match, gamma, n_next = hgp.level_match(ctx, pair, score)
+        assert np.array_equal(match.cpu().numpy(), tr.get(oracle.LV_MATCH, l)), f"match level {l}"
+        gam = tr.get(oracle.LV_GAMMA, l)
+        if gam is not None:
+            assert np.array_equal(gamma.cpu().numpy(), gam)
+        if l + 1 < tr.levels:
+            say(f"[steps] {name} level {l} contract")
+            h2, p2, s2 = hgp.level_contract(ctx, n, hoff, hpin, size, hw, gamma, n_next)
+            assert np.array_equal(h2.cpu().numpy(), tr.get(oracle.LV_HOFF, l + 1).astype(np.int32))
+            assert np.array_equal(p2.cpu().numpy(), tr.get(oracle.LV_HPIN, l + 1))
+            assert np.array_equal(s2.cpu().numpy(), tr.get(oracle.LV_SIZE, l + 1).astype(np.int32))
+    for r in range(tr.rounds):
+        info = [int(x) for x in tr.get(oracle.RD_INFO, r)]
+        l, S, istar, gstar, applied, n_parts = info
+        hoff = _t(tr.get(oracle.LV_HOFF, l), np.int32)
+        hpin = _t(tr.get(oracle.LV_HPIN, l), np.int32)
+        size = _t(tr.get(oracle.LV_SIZE, l), np.int32)
+        rho = _t(tr.get(oracle.RD_RHO, r), np.int32)
+        say(f"[steps] {name} round {r} level {l} S={S}")
+        out = hgp.level_refine_round(ctx, size.numel(), hoff, hpin, size, hw, rho, n_parts, omega, delta)
+        assert np.array_equal(out["dest"].cpu().numpy(), tr.get(oracle.RD_PDEST, r)), f"dest round {r}"
+        assert np.array_equal(out["gain"].cpu().numpy(), tr.get(oracle.RD_PGAIN, r)), f"gain round {r}"
+        assert out["S"] == S
+        assert np.array_equal(out["seq"].cpu().numpy(), tr.get(oracle.RD_SEQ, r)), f"seq round {r}"
+        assert np.array_equal(out["G"].cpu().numpy(), tr.get(oracle.RD_G, r)), f"G round {r}"
+        assert np.array_equal(out["viol"].cpu().numpy(), tr.get(oracle.RD_VIOL, r)), f"viol round {r}"
+        assert out["istar"] == istar and out["gstar"] == gstar and out["applied"] == bool(applied)
+        rho_after = tr.get(oracle.RD_RHO, r + 1) if r + 1 < tr.rounds and \
+            int(tr.get(oracle.RD_INFO, r + 1)[0]) == l else None
+        if rho_after is not None:
+            assert np.array_equal(out["rho"].cpu().numpy(), rho_after)
+
+
+# --------------------------------------------------------------- errors
+def test_error_codes(ctx):
+    from paper_2604_14411_amd import hgp
+
+    say("[errors]")
+    good = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 2])
+    cases = []
+    bad_off = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 2])
+    bad_off.hedge_off = np.array([0, 3, 2], dtype=np.int32)
+    cases.append((bad_off, hgp.EBADCSR))
+    bad_pin = from_lists(4, [([0], [1, 7]), ([3], [0])], [1, 2])
+    cases.append((bad_pin, hgp.EBADCSR))
+    dup = from_lists(4, [([0], [1, 1]), ([3], [0])], [1, 2])
+    cases.append((dup, hgp.EBADCSR))
+    badw = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 0])
+    cases.append((badw, hgp.EINVAL))
+    infeas = from_lists(4, [([0], [1, 2]), ([3], [1]), ([2], [1])], [1, 1, 1])
+    for g, want in cases:
+        rc, _, _ = _gpu_partition(ctx, g, 4, 4)
+        assert rc == want
+    rc, _, _ = _gpu_partition(ctx, infeas, 4, 1)
+    assert rc == hgp.EINFEASIBLE
+    rc, _, _ = _gpu_partition(ctx, good, 0, 4)
+    assert rc == hgp.EINVAL
+    rc, _, _ = _gpu_partition(ctx, good, 4, 4)
+    assert rc == 0
+
+
+def test_empty_inputs(ctx):
+    say("[empty]")
+    for n, hedges in [(0, []), (3, []), (3, [([], [])]), (5, [([0], []), ([1], [2])])]:
+        g = from_lists(n, hedges)
+        _compare(ctx, g, 2, 2, label=f"empty n={n} E={len(hedges)}")
+
+
+# --------------------------------------------------------------- full-size
+def test_rand16k_matches_oracle_golden(ctx):
+    path = os.path.join(HERE, "golden", "rand16k.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    gold = json.load(open(path))
+    from paper_2604_14411_amd.synth.configs import WORKLOADS
+
+    w = WORKLOADS["rand16k"]
+    g = w.make()
+    assert g.digest() == gold["input_sha256"]
+    say("[golden] rand16k")
+    rc, parts, res = _gpu_partition(ctx, g, w.omega, w.delta)
+    assert rc == 0
+    assert hashlib.sha256(np.ascontiguousarray(parts, dtype="<i4").tobytes()).hexdigest() == gold["parts_sha256"]
+    assert res["connectivity"] == gold["connectivity"]
+    assert res["n_parts"] == gold["n_parts"] and res["n_levels"] == gold["n_levels"]
+    assert res["n_rounds"] == gold["n_rounds"]
