@@ -18,9 +18,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the derived LDS-atomic peak
+# MI355X published HBM peak and the LDS-atomic peak derived from unit counts:
+# 256 CUs x 2.4 GHz x 16 atomic lanes per clock per CU
 HBM_PEAK_GBS = 8000.0
-CUS, CLOCK_GHZ, LDS_ATOMIC_LANES_PER_CLK = 256, 2.4, 32
+CUS, CLOCK_GHZ, LDS_ATOMIC_LANES_PER_CLK = 256, 2.4, 16
 LDS_ATOMIC_PEAK_TOPS = CUS * CLOCK_GHZ * 1e9 * LDS_ATOMIC_LANES_PER_CLK / 1e12
 
 # Algorithmic cost model per kernel class: (bound, bytes or ops per unit).

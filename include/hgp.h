@@ -67,7 +67,8 @@ typedef struct {
 #define HGP_PLAIN 0
 
 /* hgp_options.flags */
-#define HGP_FLAG_TIME_KERNELS 1 /* time kernel classes with HIP events on the call's stream */
+#define HGP_FLAG_TIME_KERNELS 1   /* time kernel classes with HIP events on the call's stream */
+#define HGP_FLAG_NO_INCREMENTAL 2 /* rate every level and propose every round from scratch (same result) */
 
 /* kernel classes reported in hgp_result.ms_kernel / n_kernel / units_kernel */
 #define HGP_K_RATE 0       /* candidate rating + selection; unit: pin-pair visit (sum |e|^2 per level) */

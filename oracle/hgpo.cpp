@@ -92,6 +92,13 @@ void build_incidence(Level &L, int32_t E) {
     }
 }
 
+/* Memory only: the incidence of a level is not needed while other levels run. */
+void drop_incidence(Level &L) {
+  std::vector<int64_t>().swap(L.ioff);
+  std::vector<int32_t>().swap(L.ihe);
+  std::vector<uint8_t>().swap(L.idst);
+}
+
 /* Eq. 1: sum over hedges of w(e) * (number of distinct parts among its pins
  * minus one).  A hedge with no pins contributes nothing. */
 int64_t connectivity_of(const Level &L, int32_t E, const std::vector<int32_t> &w, const std::vector<int32_t> &rho) {
@@ -675,6 +682,7 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
       }
       levels.emplace_back();
       contract(levels[(size_t)l], E, levels[(size_t)l].gamma, n_next, levels[(size_t)l + 1]);
+      drop_incidence(levels[(size_t)l]);  /* rebuilt when refinement returns to this level */
       ++l;
     }
     const int32_t Lmax = l;
@@ -684,6 +692,7 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
     int32_t rounds = 0;
     for (int32_t lv = Lmax; lv >= 0; --lv) {
       Level &L = levels[(size_t)lv];
+      if (L.ioff.empty()) build_incidence(L, E);
       if (lv < Lmax) {
         std::vector<int32_t> finer((size_t)L.n);
         for (int32_t v = 0; v < L.n; ++v) finer[v] = rho[L.gamma[v]];
@@ -696,6 +705,11 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
         if (!ro.applied) break;
       }
       if (trace) trace->put32(HGPO_LV_RHO1, lv, rho);
+      if (lv > 0) {
+        drop_incidence(L);
+        std::vector<int32_t>().swap(L.hpin);
+        std::vector<uint8_t>().swap(L.hdst);
+      }
     }
 
     /* output: renumber non-empty parts ascending */

@@ -77,41 +77,50 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
 }
 
 // ---------------------------------------------------------------------------
-// incidence transpose: I(n) with the destination flag, |in(n)|
+// incidence transpose: I(n) with the destination flag, |in(n)|, total(n)
 // ---------------------------------------------------------------------------
-__global__ void k_degrees(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
-                          int32_t *__restrict__ deg, int32_t *__restrict__ indeg) {
+// (node, hedge|dst) pairs in hedge order, then a stable radix sort by node:
+// every I(n) comes out ascending by hedge id, with no contended atomics.
+__global__ void k_expand(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
+                         uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= E) return;
   for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
     const uint32_t x = hpin[j];
-    atomicAdd(&deg[x & kIdMask], 1);
-    if (x & kDst) atomicAdd(&indeg[x & kIdMask], 1);
+    key[j] = x & kIdMask;
+    val[j] = (uint32_t)wid | (x & kDst);
   }
 }
 
-__global__ void k_scatter_inc(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
-                              const int32_t *__restrict__ ioff, int32_t *__restrict__ fill,
-                              uint32_t *__restrict__ inc) {
-  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wid >= E) return;
-  for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
-    const uint32_t x = hpin[j];
-    const uint32_t v = x & kIdMask;
-    const int p = atomicAdd(&fill[v], 1);
-    inc[ioff[v] + p] = (uint32_t)wid | (x & kDst);
-  }
+// ioff[v] = first position of node v in the sorted keys (P if none after).
+__global__ void k_offsets_from_sorted(const uint32_t *__restrict__ key, int64_t P, int32_t N,
+                                      int32_t *__restrict__ ioff) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > P) return;
+  const int64_t cur = j < P ? (int64_t)key[j] : (int64_t)N;
+  const int64_t prev = j > 0 ? (int64_t)key[j - 1] : -1;
+  for (int64_t v = prev + 1; v <= cur; ++v) ioff[v] = (int32_t)j;
 }
 
-// total(n) = sum of w(e) over I(n); feasibility of every node.
-__global__ void k_node_totals(const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
-                              const int32_t *__restrict__ hw, int32_t N, int32_t *__restrict__ total) {
+// |in(n)| and total(n) = sum of w(e) over I(n), one wave per node.
+__global__ void k_node_stats(const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
+                             const int32_t *__restrict__ hw, int32_t N, int32_t *__restrict__ indeg,
+                             int32_t *__restrict__ total) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= N) return;
   int64_t s = 0;
-  for (int i = ioff[wid] + lane_id(); i < ioff[wid + 1]; i += 64) s += hw[inc[i] & kIdMask];
+  int d = 0;
+  for (int i = ioff[wid] + lane_id(); i < ioff[wid + 1]; i += 64) {
+    const uint32_t x = inc[i];
+    s += hw[x & kIdMask];
+    d += (int)(x >> 31);
+  }
   s = wave_sum(s);
-  if (lane_id() == 0) total[wid] = (int32_t)s;
+  d = wave_sum(d);
+  if (lane_id() == 0) {
+    total[wid] = (int32_t)s;
+    indeg[wid] = d;
+  }
 }
 
 __global__ void k_feasible(const int32_t *__restrict__ size, const int32_t *__restrict__ indeg, int32_t N,
@@ -136,15 +145,17 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
                                              const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
                                              const int32_t *__restrict__ total, int32_t omega, int32_t delta,
                                              int32_t words, int32_t *__restrict__ pair,
-                                             int64_t *__restrict__ score) {
+                                             int64_t *__restrict__ score, unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t red_h[NT / 64];
   __shared__ int32_t red_m[NT / 64];
+  __shared__ int32_t tbl[NT / 64 * 192];
   const int n = blockIdx.x;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = lane_id();
   int best_m = -1;
   int64_t best_h = 0;
+  int64_t streamed = 0;
   const int64_t sn = size[n];
   if (sn < omega) {
     const uint32_t tot = (uint32_t)total[n];
@@ -161,25 +172,21 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
       const int zw = packed ? span : 2 * span;
       for (int i = tid; i < zw; i += NT) lds[i] = 0u;
       __syncthreads();
-      for (int i = i0 + w; i < i1; i += NT / 64) {
-        const uint32_t x = inc[i];
-        const int e = (int)(x & kIdMask);
-        const uint32_t ndst = x >> 31;
-        const uint32_t we = (uint32_t)hw[e];
-        const int b = hoff[e], en = hoff[e + 1];
-        for (int j = b + l; j < en; j += 64) {
-          const uint32_t y = hpin[j];
-          const int m = (int)(y & kIdMask);
-          const uint32_t rel = (uint32_t)(m - lo);
-          if (m != n && rel < (uint32_t)span) {
-            const uint32_t both = ndst & (y >> 31);
-            if (packed)
-              atomicAdd(&lds[rel], we + (both << hb));
-            else
-              atomicAdd((unsigned long long *)&lds64[rel], (unsigned long long)we | ((unsigned long long)both << 32));
-          }
-        }
-      }
+      streamed += stream_segments<NT / 64, 4, true, uint32_t>(
+          i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+          [&](uint32_t y, uint32_t info) {
+            const int m = (int)(y & kIdMask);
+            const uint32_t rel = (uint32_t)(m - lo);
+            if (m != n && rel < (uint32_t)span) {
+              const uint32_t we = info & kIdMask;
+              const uint32_t both = (info >> 31) & (y >> 31);
+              if (packed)
+                atomicAdd(&lds[rel], we + (both << hb));
+              else
+                atomicAdd((unsigned long long *)&lds64[rel],
+                          (unsigned long long)we | ((unsigned long long)both << 32));
+            }
+          });
       __syncthreads();
       for (int i = tid; i < span; i += NT) {
         uint64_t h, c;
@@ -206,6 +213,7 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
       __syncthreads();
     }
   }
+  add_wave_units(units, streamed);
   // block argmax of (h, m)
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -391,28 +399,27 @@ void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, 
   HGP_LAUNCH_CHECK();
 }
 
-void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int32_t *ioff, uint32_t *inc,
-                     int32_t *indeg, int32_t *work, DevBuf &scan_tmp, hipStream_t s) {
-  KScope ks(5, s);
-  fill_i32(work, N, 0, s);
-  fill_i32(indeg, N, 0, s);
-  if (E > 0) {
-    k_degrees<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, work, indeg);
-    HGP_LAUNCH_CHECK();
-  }
-  scan_i32(work, ioff, N, ioff + N, scan_tmp, s);
-  fill_i32(work, N, 0, s);
-  if (E > 0) {
-    k_scatter_inc<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, ioff, work, inc);
-    HGP_LAUNCH_CHECK();
-  }
+static int bits_of(int64_t x) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << b) <= x) ++b;
+  return b;
 }
 
-void launch_node_totals(const int32_t *ioff, const uint32_t *inc, const int32_t *hw, int32_t N, int32_t *total,
-                        hipStream_t s) {
-  if (N <= 0) return;
-  k_node_totals<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, total);
+void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
+                     int32_t *ioff, uint32_t *inc, int32_t *indeg, int32_t *total, uint32_t *tkey,
+                     uint32_t *tkey2, uint32_t *tval2, DevBuf &sort_tmp, hipStream_t s) {
+  KScope ks(5, s);
+  if (E > 0 && P > 0) {
+    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, inc);
+    HGP_LAUNCH_CHECK();
+    radix_sort_u32(tkey, tkey2, inc, tval2, P, bits_of(N > 0 ? N - 1 : 0), sort_tmp, s);
+  }
+  k_offsets_from_sorted<<<div_up(P + 1, 256), 256, 0, s>>>(tkey, P, N, ioff);
   HGP_LAUNCH_CHECK();
+  if (N > 0) {
+    k_node_stats<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
+    HGP_LAUNCH_CHECK();
+  }
 }
 
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
@@ -441,7 +448,7 @@ void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_
   }
   KScope ks(0, s);
   k_rate<RATE_NT><<<L.n, RATE_NT, bytes, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
-                                              omega, delta, words, pair, score);
+                                              omega, delta, words, pair, score, units_ptr(0));
   HGP_LAUNCH_CHECK();
 }
 
@@ -513,25 +520,6 @@ void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, in
                         hipStream_t s) {
   if (E <= 0) return;
   k_check_level<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, n, err);
-  HGP_LAUNCH_CHECK();
-}
-
-// Algorithmic units for kernel timing: sum |e|^2 and sum |e| * lambda(e).
-__global__ void k_units(const int32_t *__restrict__ hoff, const int32_t *__restrict__ lam, int32_t E,
-                        unsigned long long *acc) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = 0;
-  if (e < E) {
-    const unsigned long long len = (unsigned long long)(hoff[e + 1] - hoff[e]);
-    v = lam ? len * (unsigned long long)lam[e] : len * len;
-  }
-  v = wave_sum(v);
-  if (lane_id() == 0 && v) atomicAdd(acc, v);
-}
-
-void launch_units(const int32_t *hoff, const int32_t *lam, int32_t E, unsigned long long *acc, hipStream_t s) {
-  if (E <= 0) return;
-  k_units<<<div_up(E, 256), 256, 0, s>>>(hoff, lam, E, acc);
   HGP_LAUNCH_CHECK();
 }
 

@@ -34,10 +34,11 @@ void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32
                           unsigned long long *sums, hipStream_t s);
 void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
                   uint32_t *hpin, hipStream_t s);
-void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int32_t *ioff, uint32_t *inc,
-                     int32_t *indeg, int32_t *work, DevBuf &scan_tmp, hipStream_t s);
-void launch_node_totals(const int32_t *ioff, const uint32_t *inc, const int32_t *hw, int32_t N, int32_t *total,
-                        hipStream_t s);
+// Incidence I(n) (ascending hedge ids, destination flag in bit 31), |in(n)|
+// and total(n) of a level; tkey/tkey2/tval2 are P-element scratch.
+void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
+                     int32_t *ioff, uint32_t *inc, int32_t *indeg, int32_t *total, uint32_t *tkey,
+                     uint32_t *tkey2, uint32_t *tval2, DevBuf &sort_tmp, hipStream_t s);
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
                      int32_t *err, hipStream_t s);
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
@@ -54,7 +55,6 @@ void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int
 void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t n, int32_t *err,
                         hipStream_t s);
 
-void launch_units(const int32_t *hoff, const int32_t *lam, int32_t E, unsigned long long *acc, hipStream_t s);
 
 // --- refine.hip ---
 struct RoundBufs {
@@ -76,14 +76,18 @@ struct RoundBufs {
   int32_t *pcnt = nullptr;     // [n_parts+1] events per part -> offsets
   int64_t *G = nullptr;        // [n+1]
   int32_t *viol = nullptr;     // [n+1]
-  int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, applied, init_invalid
+  int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, init_invalid, heavy count
+  int32_t *heavy = nullptr;    // [E] hedges queued for the large-LDS event kernel
   int64_t cap_events = 0;
 };
 
 void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, RoundBufs &B, int32_t *err,
                        hipStream_t s);
+// Proposals for every node, or for list[0 .. *count) when list is non-null.
 void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho, int32_t n_parts, int32_t omega,
-                    RoundBufs &B, hipStream_t s);
+                    RoundBufs &B, hipStream_t s, const int32_t *list = nullptr, const int64_t *count = nullptr);
+void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, const int32_t *cdest,
+                        const int32_t *cgain, RoundBufs &B, int32_t *list, int64_t *cnt, hipStream_t s);
 // Builds the sequence; returns |S| (host sync).
 int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
 // In-sequence gains, validity, best prefix; returns (istar, Gstar) via host sync.

@@ -125,6 +125,92 @@ __device__ void block_bitonic_sort(K *s, int n) {
   }
 }
 
+// Make this wave's LDS writes visible to its other lanes (LDS operations of
+// one wave execute in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Streams, for the incidences i in [i0, i1) of one node (inc[i] = hedge |
+// dst << 31), every entry j of each hedge's segment [soff[e], soff[e] + len)
+// with len = soff[e+1] - soff[e] (LEN_FROM_END) or slen[e].  Each wave takes
+// 64 incidences at a time, loads their segment bounds and weights in one
+// round, then walks the concatenation of the 64 segments with every lane
+// busy and U loads in flight per lane: load(j) fetches entry j, apply(v, info)
+// consumes it with info = w(e) | (dst << 31).  tbl: 192 ints of LDS per wave.
+// Returns the number of entries this wave streamed (uniform across the wave).
+template <int NW, int U, bool LEN_FROM_END, class V, class Load, class Apply>
+__device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_t *__restrict__ inc,
+                                                   const int32_t *__restrict__ soff, const int32_t *__restrict__ slen,
+                                                   const int32_t *__restrict__ hw, int32_t *tbl, Load load,
+                                                   Apply apply) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  int64_t streamed = 0;
+  int32_t *t_end = tbl + w * 192;
+  int32_t *t_shift = t_end + 64;
+  uint32_t *t_info = reinterpret_cast<uint32_t *>(t_end + 128);
+  for (int base = i0 + w * 64; base < i1; base += NW * 64) {
+    const int idx = base + l;
+    int b = 0, len = 0;
+    uint32_t info = 0;
+    if (idx < i1) {
+      const uint32_t x = inc[idx];
+      const int e = (int)(x & kIdMask);
+      b = soff[e];
+      len = LEN_FROM_END ? soff[e + 1] - b : slen[e];
+      info = (uint32_t)hw[e] | (x & kDst);
+    }
+    const int incl = wave_inclusive_scan(len);
+    const int total = __shfl(incl, 63, 64);
+    t_end[l] = incl;
+    t_shift[l] = b - (incl - len);
+    t_info[l] = info;
+    wave_lds_sync();
+    // per-lane cursor over the 64 segments, its bounds cached in registers
+    int k = 0;
+    int k_end = t_end[0];
+    int k_shift = t_shift[0];
+    uint32_t k_info = t_info[0];
+    streamed += total;
+    for (int v0 = 0; v0 < total; v0 += 64 * U) {
+      int jj[U];
+      uint32_t ii[U];
+      V vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int v = v0 + u * 64 + l;
+        jj[u] = -1;
+        ii[u] = 0;
+        if (v < total) {
+          while (k_end <= v) {
+            ++k;
+            k_end = t_end[k];
+            k_shift = t_shift[k];
+            k_info = t_info[k];
+          }
+          jj[u] = v + k_shift;
+          ii[u] = k_info;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (jj[u] >= 0) vv[u] = load(jj[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (jj[u] >= 0) apply(vv[u], ii[u]);
+    }
+    wave_lds_sync();
+  }
+  return streamed;
+}
+
+// Adds a per-wave count to a device counter (one atomic per wave).
+__device__ __forceinline__ void add_wave_units(unsigned long long *units, int64_t v) {
+  if (units && lane_id() == 0 && v) atomicAdd(units, (unsigned long long)v);
+}
+
 __host__ __device__ inline int next_pow2(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -146,6 +232,7 @@ struct KTimer {
   std::vector<Rec> recs;
   hipEvent_t pending = nullptr;
   int64_t units[kNKClass] = {};
+  unsigned long long *units_dev = nullptr;  // device counters, one per class
   hipEvent_t take();
   void begin(hipStream_t s);
   void end(int cls, hipStream_t s);
@@ -169,6 +256,10 @@ struct KScope {
 inline void add_units(int cls, int64_t u) {
   if (g_ktimer && g_ktimer->on) g_ktimer->units[cls] += u;
 }
+// Device counter for kernels that count their own algorithmic units.
+inline unsigned long long *units_ptr(int cls) {
+  return (g_ktimer && g_ktimer->on && g_ktimer->units_dev) ? g_ktimer->units_dev + cls : nullptr;
+}
 
 // ---------------------------------------------------------------------------
 // Host-side primitives (prims.hip)
@@ -183,6 +274,9 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, DevBuf
 // `keys` on entry and exit (ping-pong through `alt`).  Optional uint32 values
 // travel with the keys (vals / valt).
 void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
+                    DevBuf &tmp, hipStream_t s);
+
+void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
                     DevBuf &tmp, hipStream_t s);
 
 // Fill / iota helpers.

@@ -5,6 +5,7 @@
 
 #include "../../include/hgp.h"
 #include "coarsen.hpp"
+#include "tail.hpp"
 
 namespace hgp {
 
@@ -13,10 +14,10 @@ static thread_local std::string g_last_error;
 struct Workspace {
   DevBuf err, sums, scal2;
   DevBuf hpin0, hoffA, hoffB, hpinA, hpinB, hoffR, hpinR, tmp_pins, cnt;
-  DevBuf ioff, inc, indeg, total, work;
+  DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2;
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
-  DevBuf pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, pcnt, G, viol, scal;
+  DevBuf heavy, pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, pcnt, G, viol, scal;
   DevBuf scan_tmp, sort_tmp;
   DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
   DevBuf ones_e, ones_n;
@@ -24,11 +25,17 @@ struct Workspace {
   std::vector<int32_t> lv_n;
   KTimer timer;
   DevBuf units_dev;
+  // incremental late levels
+  DevBuf tkA_key, tkA_cnt, tkA_kap, tkB_key, tkB_cnt, tkB_kap, rows, newc, row_slot, nflag, rerate, dev_cnt;
+  DevBuf split, cdest, cgain;
+  std::vector<DevBuf> lv_match;
 
   void clear_levels() {
     for (auto &b : lv_size) b.release();
     for (auto &b : lv_gamma) b.release();
     for (auto &b : lv_Gamma) b.release();
+    for (auto &b : lv_match) b.release();
+    lv_match.clear();
     lv_size.clear();
     lv_gamma.clear();
     lv_Gamma.clear();
@@ -37,13 +44,16 @@ struct Workspace {
 
   void release_all() {
     DevBuf *all[] = {&err,  &sums,  &scal2,  &hpin0,  &hoffA,    &hoffB,  &hpinA,  &hpinB,   &hoffR,   &hpinR,
-                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work,   &pair,    &score,   &best,
-                     &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptin,    &lam,
+                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2,   &pair,    &score,   &best,
+                     &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptin,    &lam, &heavy,
                      &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
                      &vdelta, &pcnt, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
+    DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain};
+    for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     clear_levels();
   }
@@ -175,11 +185,12 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   int32_t *ioff = need<int32_t>(W.ioff, (int64_t)n + 1);
   uint32_t *inc = need<uint32_t>(W.inc, P);
   int32_t *indeg = need<int32_t>(W.indeg, n);
-  int32_t *work = need<int32_t>(W.work, n);
   int32_t *total = need<int32_t>(W.total, n);
-  build_incidence(hoff, hpin, E, n, ioff, inc, indeg, work, W.scan_tmp, s);
+  uint32_t *tkey = need<uint32_t>(W.tkey, P);
+  uint32_t *tkey2 = need<uint32_t>(W.tkey2, P);
+  uint32_t *tval2 = need<uint32_t>(W.tval2, P);
+  build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, indeg, total, tkey, tkey2, tval2, W.sort_tmp, s);
   add_units(HGP_K_INCIDENCE, P);
-  launch_node_totals(ioff, inc, hw, n, total, s);
   LevelView L;
   L.n = n;
   L.E = E;
@@ -214,6 +225,7 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.G = need<int64_t>(W.G, (int64_t)n + 1);
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);
   B.scal = need<int64_t>(W.scal, 8);
+  B.heavy = need<int32_t>(W.heavy, E);
   return B;
 }
 
@@ -223,14 +235,28 @@ struct RoundResult {
 };
 
 // One refinement round (Sec. IV) on rho, in place.
+// Proposals carried from the next coarser level (see k_prop_gather).
+struct Carry {
+  const int32_t *match = nullptr;  // level match (n)
+  const int32_t *gamma = nullptr;  // level cluster map (n)
+};
+
 static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int32_t *rho, int32_t n_parts,
-                                int32_t omega, int32_t delta, hipStream_t s, RoundBufs *out_bufs = nullptr) {
+                                int32_t omega, int32_t delta, hipStream_t s, RoundBufs *out_bufs = nullptr,
+                                const Carry *carry = nullptr) {
   RoundBufs B = round_bufs(W, L.n, L.E, P, n_parts);
   int32_t *err = W.err.as<int32_t>();
   launch_part_table(L, rho, n_parts, B, err, s);
   add_units(HGP_K_PARTTABLE, P);
-  if (W.timer.on) launch_units(L.hoff, B.lam, L.E, W.units_dev.as<unsigned long long>() + HGP_K_PROPOSE, s);
-  launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s);
+  if (carry) {
+    int32_t *list = need<int32_t>(W.split, L.n);
+    int64_t *cnt = need<int64_t>(W.dev_cnt, 4);
+    launch_prop_gather(L.n, carry->match, carry->gamma, W.cdest.as<int32_t>(), W.cgain.as<int32_t>(), B, list, cnt,
+                       s);
+    launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s, list, cnt);
+  } else {
+    launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s);
+  }
   RoundResult R;
   R.S = build_sequence(L, B, W.scan_tmp, W.sort_tmp, s);
   if (R.S > 0) add_units(HGP_K_SEQEVENTS, P);
@@ -263,6 +289,9 @@ struct TimerGuard {
     if (on) {
       W.units_dev.reserve(HGP_NKERNEL * sizeof(int64_t));
       fill_i64(W.units_dev.as<int64_t>(), HGP_NKERNEL, 0, s);
+      W.timer.units_dev = W.units_dev.as<unsigned long long>();
+    } else {
+      W.timer.units_dev = nullptr;
     }
   }
   void collect(RunStats &st, hipStream_t s) {
@@ -317,7 +346,6 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     return st;
   }
   const int64_t T = opt.k > 0 ? (int64_t)opt.k : (I.wsum_nodes + omega - 1) / omega;
-  unsigned long long *units_dev = W.timer.on ? W.units_dev.as<unsigned long long>() : nullptr;
 
   int32_t *pair = need<int32_t>(W.pair, N);
   int64_t *score = need<int64_t>(W.score, N);
@@ -336,19 +364,49 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   need<int32_t>(W.cnt, E);
 
   // ---- coarsening ----
+  // Late levels that merge few pairs are rated incrementally (tail.hip):
+  // lists of the exact top candidates per node are carried between levels,
+  // new clusters are rated in full and offered to their neighbours.
+  const bool incremental = (opt.flags & HGP_FLAG_NO_INCREMENTAL) == 0;
   int32_t n_parts = 0;
   int lvl = 0;
   const int32_t *cur_hoff = hoff0;
   const uint32_t *cur_hpin = hpin0;
   int64_t cur_P = P;
   int ping = 0;
+  TopK tk_cur, tk_nxt;
+  tk_cur.key = need<uint64_t>(W.tkA_key, (int64_t)N * kTopK);
+  tk_cur.cnt = need<int32_t>(W.tkA_cnt, N);
+  tk_cur.kappa = need<uint64_t>(W.tkA_kap, N);
+  tk_nxt.key = need<uint64_t>(W.tkB_key, (int64_t)N * kTopK);
+  tk_nxt.cnt = need<int32_t>(W.tkB_cnt, N);
+  tk_nxt.kappa = need<uint64_t>(W.tkB_kap, N);
+  int32_t *newc = need<int32_t>(W.newc, N);
+  int32_t *row_slot = need<int32_t>(W.row_slot, N);
+  int32_t *nflag = need<int32_t>(W.nflag, N);
+  int32_t *rerate = need<int32_t>(W.rerate, N);
+  int64_t *dcnt = need<int64_t>(W.dev_cnt, 4);
+  bool have_pairs = false;  // pair/score of the current level already computed
+  bool lists_ok = false;    // tk_cur holds exact lists for the current level
+  bool tail = false;        // the previous matching merged few pairs
   while (true) {
     const int32_t n = L.n;
-    if (units_dev) launch_units(L.hoff, nullptr, E, units_dev + HGP_K_RATE, s);
-    launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s);
+    if (!have_pairs) {
+      if (incremental && tail && 2 * (int64_t)n <= kTopKMaxIds) {
+        launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, nullptr, nullptr, pair, score,
+                         tk_cur, s);
+        lists_ok = true;
+      } else {
+        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s);
+        lists_ok = false;
+      }
+    }
+    have_pairs = false;
     W.lv_gamma.emplace_back();
+    W.lv_match.emplace_back();
     int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
-    launch_match(pair, score, n, best, up, match, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
+    int32_t *lmatch = need<int32_t>(W.lv_match[lvl], n);
+    launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
     const int32_t n_next = read_i32(nnext_dev, s);
     check_err(W, s);
     if (n_next == n) {
@@ -361,10 +419,11 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       n_parts = n_next;
       break;
     }
+    const int32_t M = n - n_next;
     W.lv_size.emplace_back();
     W.lv_n.push_back(n_next);
     int32_t *csize = need<int32_t>(W.lv_size[lvl + 1], n_next);
-    launch_cluster_size(match, gam, W.lv_size[lvl].as<int32_t>(), n, csize, s);
+    launch_cluster_size(lmatch, gam, W.lv_size[lvl].as<int32_t>(), n, csize, s);
     W.lv_Gamma.emplace_back();  // lv_Gamma[k]: level 0 -> level k+1
     int32_t *Gm = need<int32_t>(W.lv_Gamma[lvl], N);
     if (lvl == 0)
@@ -382,6 +441,25 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     ping ^= 1;
     ++lvl;
     L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, s);
+    tail = (int64_t)M * kTailRatio <= (int64_t)n;
+    if (incremental && lists_ok && tail && 2 * (int64_t)n_next <= kTopKMaxIds &&
+        (int64_t)M * n_next <= kRowBudget) {
+      // rate level lvl incrementally from the lists of level lvl-1
+      int32_t *rows = need<int32_t>(W.rows, (int64_t)M * n_next);
+      launch_new_clusters(lmatch, gam, n, n_next, nflag, newc, row_slot, W.scan_tmp, s);
+      fill_i64(dcnt, 1, M, s);
+      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot, rows, pair, score, tk_nxt,
+                       s);
+      fill_i64(dcnt + 1, 1, 0, s);
+      launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, tk_nxt, pair, score, rerate, dcnt + 1, s);
+      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, nullptr, nullptr, pair,
+                       score, tk_nxt, s);
+      have_pairs = true;
+      lists_ok = true;
+    } else {
+      lists_ok = false;
+    }
+    std::swap(tk_cur, tk_nxt);
   }
   const int Lmax = lvl;
   st.n_levels = Lmax + 1;
@@ -389,8 +467,13 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const double t1 = now_ms();
 
   // ---- refinement, coarsest level first ----
+  // A level whose last round applied no move hands its proposals to the next
+  // finer level: only the nodes of split clusters are proposed again there.
   int rounds = 0;
   LevelView V0;  // level 0, built by the last iteration
+  bool carry_ok = false;
+  need<int32_t>(W.cdest, N);
+  need<int32_t>(W.cgain, N);
   for (int lv = Lmax; lv >= 0; --lv) {
     const int32_t n = W.lv_n[lv];
     LevelView V;
@@ -420,11 +503,32 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       }
       V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, s);
     }
+    bool last_applied = false;
+    int ran = 0;
     for (int r = 0; r < opt.max_refine_rounds; ++r) {
       ++rounds;
-      RoundResult R = refine_round(W, V, Pl, rho, n_parts, omega, delta, s);
-      if (!R.applied) break;
+      ++ran;
+      Carry c;
+      const bool use_carry = incremental && r == 0 && carry_ok && lv < Lmax;
+      if (use_carry) {
+        c.match = W.lv_match[lv].as<int32_t>();
+        c.gamma = W.lv_gamma[lv].as<int32_t>();
+      }
+      RoundBufs B;
+      RoundResult R = refine_round(W, V, Pl, rho, n_parts, omega, delta, s, &B, use_carry ? &c : nullptr);
+      last_applied = R.applied;
+      if (!R.applied) {
+        // the state is unchanged: these proposals hold for it
+        if (incremental && n > 0) {
+          HGP_HIP(hipMemcpyAsync(W.cdest.as<int32_t>(), B.dest, sizeof(int32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, s));
+          HGP_HIP(hipMemcpyAsync(W.cgain.as<int32_t>(), B.gain, sizeof(int32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, s));
+        }
+        break;
+      }
     }
+    carry_ok = ran > 0 && !last_applied;
     if (lv == 0) V0 = V;
   }
   st.n_rounds = rounds;

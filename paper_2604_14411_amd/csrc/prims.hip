@@ -186,7 +186,8 @@ constexpr int RS_NT = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_NT * RS_ROUNDS;
 
-__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+template <class K>
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                    int32_t *__restrict__ hist, int ntiles) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
@@ -194,16 +195,18 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t *__restrict__ 
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t j = base + r * RS_NT + threadIdx.x;
-    if (j < n) atomicAdd(&cnt[(keys[j] >> shift) & 255u], 1);
+    if (j < n) atomicAdd(&cnt[(uint32_t)(keys[j] >> shift) & 255u], 1);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *__restrict__ keys,
-                                                      const uint32_t *__restrict__ vals, int64_t n, int shift,
-                                                      const int32_t *__restrict__ offs, int ntiles,
-                                                      uint64_t *__restrict__ okeys, uint32_t *__restrict__ ovals) {
+// Stable scatter of one 4096-key tile: keys are ranked in tile order within
+// their digit using wave match masks (8 ballots) and per-wave digit counts.
+template <class K>
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                      int64_t n, int shift, const int32_t *__restrict__ offs,
+                                                      int ntiles, K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
   __shared__ int32_t base[256];
   __shared__ int32_t wcnt[RS_NT / 64][256];
   const int tid = threadIdx.x;
@@ -217,8 +220,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *__restrict
     __syncthreads();
     const int64_t j = tbase + r * RS_NT + tid;
     const bool valid = j < n;
-    uint64_t key = valid ? keys[j] : 0;
-    uint32_t val = (valid && vals) ? vals[j] : 0u;
+    const K key = valid ? keys[j] : K(0);
+    const uint32_t val = (valid && vals) ? vals[j] : 0u;
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
     uint64_t match = __ballot(valid);
 #pragma unroll
@@ -246,8 +249,9 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t *__restrict
   }
 }
 
-void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
-                    DevBuf &tmp, hipStream_t s) {
+template <class K>
+static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits, DevBuf &tmp,
+                            hipStream_t s) {
   if (n <= 1 || bits <= 0) return;
   const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
   const int64_t hn = 256LL * ntiles;
@@ -256,22 +260,32 @@ void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *val
   tmp.reserve(need);
   int32_t *hist = tmp.as<int32_t>();
   int32_t *stmp = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
-  uint64_t *src = keys, *dst = alt;
+  K *src = keys, *dst = alt;
   uint32_t *vs = vals, *vd = valt;
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    k_rs_hist<<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
+    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
     HGP_LAUNCH_CHECK();
     scan_impl<int32_t>(hist, hist, hn, nullptr, stmp, s);
-    k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+    k_rs_scatter<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
     HGP_LAUNCH_CHECK();
     std::swap(src, dst);
     std::swap(vs, vd);
   }
   if (passes & 1) {
-    HGP_HIP(hipMemcpyAsync(keys, src, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    HGP_HIP(hipMemcpyAsync(keys, src, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
     if (vals) HGP_HIP(hipMemcpyAsync(vals, vs, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   }
+}
+
+void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
+                    DevBuf &tmp, hipStream_t s) {
+  radix_sort_impl<uint64_t>(keys, alt, vals, valt, n, bits, tmp, s);
+}
+
+void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
+                    DevBuf &tmp, hipStream_t s) {
+  radix_sort_impl<uint32_t>(keys, alt, vals, valt, n, bits > 32 ? 32 : bits, tmp, s);
 }
 
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {

@@ -9,7 +9,7 @@ constexpr int PT_NT = 256;
 constexpr int PROP_NT = 256;
 constexpr int PROP_LDS_BYTES = 64 * 1024;
 
-enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4 };
+enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4, SC_HEAVY = 5 };
 
 __device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int n, uint32_t x) {
   int lo = 0, hi = n;
@@ -108,7 +108,8 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // ---------------------------------------------------------------------------
 // proposals (Eq. 3)
 // ---------------------------------------------------------------------------
-// One workgroup per node n in part p_s.  saving(n) is summed first by one
+// One workgroup per node n in part p_s (node list[t], or t when list is
+// null; grid-stride over *count nodes).  saving(n) is summed first by one
 // lookup of p_s per hedge; if it is zero no move can have positive gain
 // (loss >= 0) and the node is done.  Otherwise every part table entry of
 // every hedge of I(n) adds w(e) to conn[p] in LDS; then
@@ -116,109 +117,144 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // and the best part by (gain, id) among those with size(p)+size(n) <= Omega
 // is kept if gain > 0.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_propose(int32_t N, const int32_t *__restrict__ ioff,
+__global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list, const int64_t *__restrict__ count,
+                                                int32_t N, const int32_t *__restrict__ ioff,
                                                 const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
                                                 const int2 *__restrict__ pt, const int32_t *__restrict__ ptin,
                                                 const int32_t *__restrict__ lam, const int32_t *__restrict__ hw,
                                                 const int32_t *__restrict__ rho, const int32_t *__restrict__ size,
                                                 const int32_t *__restrict__ psize, const int32_t *__restrict__ total,
                                                 int32_t n_parts, int32_t omega, int32_t words,
-                                                int32_t *__restrict__ dest, int32_t *__restrict__ gain) {
+                                                int32_t *__restrict__ dest, int32_t *__restrict__ gain,
+                                                unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t conn[];
   __shared__ int64_t red[NT / 64];
   __shared__ int32_t redp[NT / 64];
   __shared__ int64_t s_saving;
-  const int n = blockIdx.x;
+  __shared__ int32_t tbl[NT / 64 * 192];
   const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
-  const int ps = rho[n];
-  const int i0 = ioff[n], i1 = ioff[n + 1];
-  // saving(n)
-  int64_t sav = 0;
-  for (int i = i0 + tid; i < i1; i += NT) {
-    const int e = (int)(inc[i] & kIdMask);
-    const int2 c = pt_lookup(pt, ptin, hoff[e], lam[e], ps);
-    if (c.x == 1) sav += hw[e];
-  }
-  sav = wave_sum(sav);
-  if (l == 0) red[w] = sav;
-  __syncthreads();
-  if (tid == 0) {
-    int64_t t = 0;
-    for (int q = 0; q < NT / 64; ++q) t += red[q];
-    s_saving = t;
-  }
-  __syncthreads();
-  const int64_t saving = s_saving;
-  int bp = -1;
-  int64_t bg = 0;
-  if (saving > 0) {
-    const int64_t tot = total[n];
-    const int64_t sn = size[n];
-    for (int lo = 0; lo < n_parts; lo += words) {
-      const int span = min(words, n_parts - lo);
-      for (int i = tid; i < span; i += NT) conn[i] = 0u;
-      __syncthreads();
-      for (int i = i0 + w; i < i1; i += NT / 64) {
-        const int e = (int)(inc[i] & kIdMask);
-        const uint32_t we = (uint32_t)hw[e];
-        const int b = hoff[e], en = b + lam[e];
-        for (int k = b + l; k < en; k += 64) {
-          const uint32_t rel = (uint32_t)(pt[k].x - lo);
-          if (rel < (uint32_t)span) atomicAdd(&conn[rel], we);
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < span; i += NT) {
-        const uint32_t c = conn[i];
-        if (!c) continue;
-        const int p = lo + i;
-        if (p == ps) continue;
-        const int64_t g = saving - tot + (int64_t)c;
-        if (g > 0 && (g > bg || (g == bg && p > bp)) && (int64_t)psize[p] + sn <= omega) {
-          bg = g;
-          bp = p;
-        }
-      }
-      __syncthreads();
+  const int64_t cnt_nodes = list ? *count : (int64_t)N;
+  int64_t streamed = 0;
+  for (int64_t t = blockIdx.x; t < cnt_nodes; t += gridDim.x) {
+    const int n = list ? list[t] : (int)t;
+    const int ps = rho[n];
+    const int i0 = ioff[n], i1 = ioff[n + 1];
+    // saving(n)
+    int64_t sav = 0;
+    for (int i = i0 + tid; i < i1; i += NT) {
+      const int e = (int)(inc[i] & kIdMask);
+      const int2 c = pt_lookup(pt, ptin, hoff[e], lam[e], ps);
+      if (c.x == 1) sav += hw[e];
     }
-  }
+    sav = wave_sum(sav);
+    if (l == 0) red[w] = sav;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t tt = 0;
+      for (int q = 0; q < NT / 64; ++q) tt += red[q];
+      s_saving = tt;
+    }
+    __syncthreads();
+    const int64_t saving = s_saving;
+    int bp = -1;
+    int64_t bg = 0;
+    if (saving > 0) {
+      const int64_t tot = total[n];
+      const int64_t sn = size[n];
+      for (int lo = 0; lo < n_parts; lo += words) {
+        const int span = min(words, n_parts - lo);
+        for (int i = tid; i < span; i += NT) conn[i] = 0u;
+        __syncthreads();
+        streamed += stream_segments<NT / 64, 4, false, int32_t>(
+            i0, i1, inc, hoff, lam, hw, tbl, [&](int j) { return pt[j].x; },
+            [&](int32_t p, uint32_t info) {
+              const uint32_t rel = (uint32_t)(p - lo);
+              if (rel < (uint32_t)span) atomicAdd(&conn[rel], info & kIdMask);
+            });
+        __syncthreads();
+        for (int i = tid; i < span; i += NT) {
+          const uint32_t c = conn[i];
+          if (!c) continue;
+          const int p = lo + i;
+          if (p == ps) continue;
+          const int64_t g = saving - tot + (int64_t)c;
+          if (g > 0 && (g > bg || (g == bg && p > bp)) && (int64_t)psize[p] + sn <= omega) {
+            bg = g;
+            bp = p;
+          }
+        }
+        __syncthreads();
+      }
+    }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const int64_t og = __shfl_xor(bg, o, 64);
-    const int op = __shfl_xor(bp, o, 64);
-    if (op >= 0 && (bp < 0 || og > bg || (og == bg && op > bp))) {
-      bg = og;
-      bp = op;
-    }
-  }
-  if (l == 0) {
-    red[w] = bg;
-    redp[w] = bp;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    for (int q = 1; q < NT / 64; ++q) {
-      const int op = redp[q];
-      const int64_t og = red[q];
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t og = __shfl_xor(bg, o, 64);
+      const int op = __shfl_xor(bp, o, 64);
       if (op >= 0 && (bp < 0 || og > bg || (og == bg && op > bp))) {
         bg = og;
         bp = op;
       }
     }
-    dest[n] = bp;
-    gain[n] = bp >= 0 ? (int32_t)bg : 0;
+    if (l == 0) {
+      red[w] = bg;
+      redp[w] = bp;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int q = 1; q < NT / 64; ++q) {
+        const int op = redp[q];
+        const int64_t og = red[q];
+        if (op >= 0 && (bp < 0 || og > bg || (og == bg && op > bp))) {
+          bg = og;
+          bp = op;
+        }
+      }
+      dest[n] = bp;
+      gain[n] = bp >= 0 ? (int32_t)bg : 0;
+    }
+    __syncthreads();
   }
+  add_wave_units(units, streamed);
 }
 
+constexpr int PROP_GRID = 8192;
+
 void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho, int32_t n_parts, int32_t omega,
-                    RoundBufs &B, hipStream_t s) {
+                    RoundBufs &B, hipStream_t s, const int32_t *list, const int64_t *count) {
   if (L.n <= 0) return;
   const int max_words = PROP_LDS_BYTES / 4;
   const int words = n_parts < max_words ? (n_parts > 0 ? n_parts : 1) : max_words;
   KScope ks(1, s);
-  k_propose<PROP_NT><<<L.n, PROP_NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, B.pt, B.ptin, B.lam, L.hw,
-                                                            rho, L.size, B.psize, total, n_parts, omega, words,
-                                                            B.dest, B.gain);
+  const int grid = list ? (L.n < PROP_GRID ? L.n : PROP_GRID) : L.n;
+  k_propose<PROP_NT><<<grid, PROP_NT, (size_t)words * 4, s>>>(list, count, L.n, L.ioff, L.inc, L.hoff, B.pt, B.ptin,
+                                                             B.lam, L.hw, rho, L.size, B.psize, total, n_parts, omega,
+                                                             words, B.dest, B.gain, units_ptr(1));
+  HGP_LAUNCH_CHECK();
+}
+
+// Proposals carried over from the next coarser level: a node whose cluster
+// was not split there keeps that cluster's proposal (same parts, sizes and
+// per-hedge part sets, hence the same Eq. 3 values); split nodes are queued.
+__global__ void k_prop_gather(int32_t n, const int32_t *__restrict__ match, const int32_t *__restrict__ gamma,
+                              const int32_t *__restrict__ cdest, const int32_t *__restrict__ cgain,
+                              int32_t *__restrict__ dest, int32_t *__restrict__ gain, int32_t *__restrict__ list,
+                              int64_t *__restrict__ cnt) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  if (match[v] == v) {
+    const int c = gamma[v];
+    dest[v] = cdest[c];
+    gain[v] = cgain[c];
+  } else {
+    list[atomicAdd((unsigned long long *)cnt, 1ull)] = (int32_t)v;
+  }
+}
+
+void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, const int32_t *cdest,
+                        const int32_t *cgain, RoundBufs &B, int32_t *list, int64_t *cnt, hipStream_t s) {
+  fill_i64(cnt, 1, 0, s);
+  if (n <= 0) return;
+  k_prop_gather<<<div_up(n, 256), 256, 0, s>>>(n, match, gamma, cdest, cgain, B.dest, B.gain, list, cnt);
   HGP_LAUNCH_CHECK();
 }
 
@@ -319,48 +355,38 @@ int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBu
 // (role 0 = source, 1 = destination).  Validity events use
 // part << 32 | position << 2 | type (type 0: inbound -1, 1: inbound +1,
 // 2: size change).
-template <int CAPEV>
-__global__ __launch_bounds__(PT_NT) void k_seq_events(const int32_t *__restrict__ hoff,
-                                                      const uint32_t *__restrict__ hpin,
-                                                      const int32_t *__restrict__ hw, const int32_t *__restrict__ rho,
-                                                      const int32_t *__restrict__ dest,
-                                                      const int32_t *__restrict__ pos, const int2 *__restrict__ pt,
-                                                      const int32_t *__restrict__ ptin,
-                                                      const int32_t *__restrict__ lam, int lo_moving, int hi_moving,
-                                                      int32_t *__restrict__ gp, uint64_t *__restrict__ ev,
-                                                      int32_t *__restrict__ pcnt, int64_t *__restrict__ scal,
-                                                      int32_t *err) {
-  __shared__ uint64_t key[CAPEV];
-  __shared__ int32_t dl[CAPEV];
-  __shared__ int32_t s_cnt;
-  __shared__ int32_t s_base;
-  __shared__ int32_t tmp[PT_NT / 64 + 1];
-  const int e = blockIdx.x;
+// Part table of the hedge staged in LDS (parts ascending; counts packed as
+// pins | pins_in << 16, both <= 4096).
+__device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t *sc, int len, int p) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sp[mid] < p) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < len && sp[lo] == p) return make_int2((int)(sc[lo] & 0xffffu), (int)(sc[lo] >> 16));
+  return make_int2(0, 0);
+}
+
+template <int CAPEV, int PTCAP>
+__device__ void seq_events_hedge(int e, int moving, const int32_t *__restrict__ hoff,
+                                 const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+                                 const int32_t *__restrict__ rho, const int32_t *__restrict__ dest,
+                                 const int32_t *__restrict__ pos, const int2 *__restrict__ pt,
+                                 const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int pshift,
+                                 int32_t *__restrict__ gp, uint64_t *__restrict__ ev, int32_t *__restrict__ pcnt,
+                                 int64_t *__restrict__ scal, uint64_t *key, int32_t *dl, int32_t *tmp,
+                                 int32_t *s_cnt, int64_t *s_base, int32_t *sp, uint32_t *sc) {
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  // count moving pins
-  int mine = 0;
-  for (int i = threadIdx.x; i < len; i += PT_NT) mine += pos[hpin[b + i] & kIdMask] > 0 ? 1 : 0;
-  mine = wave_sum(mine);
-  if (lane_id() == 0 && mine) atomicAdd(&s_cnt, mine);
-  __syncthreads();
-  const int moving = s_cnt;
-  if (moving <= lo_moving || moving > hi_moving) return;
-  if (2 * moving > CAPEV) {
-    if (threadIdx.x == 0) atomicOr(err, kErrInternal);
-    return;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) s_cnt = 0;
+  if (threadIdx.x == 0) *s_cnt = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < len; i += PT_NT) {
     const uint32_t x = hpin[b + i];
     const int v = (int)(x & kIdMask);
     const int q = pos[v];
     if (q > 0) {
-      const int slot = atomicAdd(&s_cnt, 2);
+      const int slot = atomicAdd(s_cnt, 2);
       const uint64_t d = x >> 31;
       key[slot] = ((uint64_t)(uint32_t)rho[v] << 32) | ((uint64_t)q << 2) | d;
       key[slot + 1] = ((uint64_t)(uint32_t)dest[v] << 32) | ((uint64_t)q << 2) | 2ull | d;
@@ -380,85 +406,151 @@ __global__ __launch_bounds__(PT_NT) void k_seq_events(const int32_t *__restrict_
   }
   __syncthreads();
   block_exclusive_scan<int32_t, PT_NT>(dl, nev, tmp);
-  // emit
-  if (threadIdx.x == 0) s_cnt = 0;
+  if (threadIdx.x == 0) *s_cnt = 0;
   __syncthreads();
   const int32_t we = hw[e];
-  const int pb = b, plen = lam[e];
-  // pass 1: gains + count inbound events; pass 2: write inbound events
-  int my_events = 0;
-  for (int i = threadIdx.x; i < nev; i += PT_NT) {
-    const uint64_t k = key[i];
-    const uint32_t part = (uint32_t)(k >> 32);
-    const int q = (int)((k >> 2) & 0x3fffffffull);
-    const bool is_dst_role = (k & 2ull) != 0;
-    // group start: first event of this part
-    int lo = 0, hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((uint32_t)(key[mid] >> 32) < part) lo = mid + 1;
-      else hi = mid;
-    }
-    const int32_t pre = dl[i] - dl[lo];
-    const int32_t pre_pins = (int32_t)(int16_t)(pre & 0xffff);
-    const int32_t pre_in = (pre - pre_pins) >> 16;
-    const int2 c0 = pt_lookup(pt, ptin, pb, plen, (int)part);
-    const int before = c0.x + pre_pins;
-    if (!is_dst_role && before == 1) atomicAdd(&gp[q], we);
-    if (is_dst_role && before == 0) atomicAdd(&gp[q], -we);
-    if (k & 1ull) {
-      const int bin = c0.y + pre_in;
-      if ((!is_dst_role && bin == 1) || (is_dst_role && bin == 0)) ++my_events;
+  const int plen = lam[e];
+  const bool staged = plen <= PTCAP;
+  if (staged) {
+    for (int i = threadIdx.x; i < plen; i += PT_NT) {
+      const int2 x = pt[b + i];
+      sp[i] = x.x;
+      sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
     }
   }
-  my_events = wave_sum(my_events);
-  if (lane_id() == 0 && my_events) atomicAdd(&s_cnt, my_events);
   __syncthreads();
-  if (threadIdx.x == 0) s_base = s_cnt ? (int32_t)atomicAdd((unsigned long long *)&scal[SC_EVENTS],
-                                                             (unsigned long long)s_cnt)
-                                       : 0;
-  __syncthreads();
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < nev; i += PT_NT) {
-    const uint64_t k = key[i];
-    if (!(k & 1ull)) continue;
-    const uint32_t part = (uint32_t)(k >> 32);
-    const int q = (int)((k >> 2) & 0x3fffffffull);
-    const bool is_dst_role = (k & 2ull) != 0;
-    int lo = 0, hi = i;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((uint32_t)(key[mid] >> 32) < part) lo = mid + 1;
-      else hi = mid;
+  // pass 1: gains, and count inbound events; pass 2: write inbound events
+  int my_events = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = threadIdx.x; i < nev; i += PT_NT) {
+      const uint64_t k = key[i];
+      if (pass == 1 && !(k & 1ull)) continue;
+      const uint32_t part = (uint32_t)(k >> 32);
+      const int q = (int)((k >> 2) & 0x3fffffffull);
+      const bool is_dst_role = (k & 2ull) != 0;
+      int lo = 0, hi = i;  // first event of this part
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((uint32_t)(key[mid] >> 32) < part) lo = mid + 1;
+        else hi = mid;
+      }
+      const int32_t pre = dl[i] - dl[lo];
+      const int32_t pre_pins = (int32_t)(int16_t)(pre & 0xffff);
+      const int32_t pre_in = (pre - pre_pins) >> 16;
+      const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, (int)part) : pt_lookup(pt, ptin, b, plen, (int)part);
+      if (pass == 0) {
+        const int before = c0.x + pre_pins;
+        if (!is_dst_role && before == 1) atomicAdd(&gp[q], we);
+        if (is_dst_role && before == 0) atomicAdd(&gp[q], -we);
+      }
+      if (k & 1ull) {
+        const int bin = c0.y + pre_in;
+        int type = -1;
+        if (!is_dst_role && bin == 1) type = 0;
+        if (is_dst_role && bin == 0) type = 1;
+        if (type >= 0) {
+          if (pass == 0) {
+            ++my_events;
+          } else {
+            const int64_t slot = *s_base + atomicAdd(s_cnt, 1);
+            ev[slot] = ((uint64_t)part << pshift) | ((uint64_t)q << 2) | (uint64_t)type;
+            atomicAdd(&pcnt[part], 1);
+          }
+        }
+      }
     }
-    const int32_t pre = dl[i] - dl[lo];
-    const int32_t pre_pins = (int32_t)(int16_t)(pre & 0xffff);
-    const int32_t pre_in = (pre - pre_pins) >> 16;
-    const int2 c0 = pt_lookup(pt, ptin, pb, plen, (int)part);
-    const int bin = c0.y + pre_in;
-    int type = -1;
-    if (!is_dst_role && bin == 1) type = 0;
-    if (is_dst_role && bin == 0) type = 1;
-    if (type >= 0) {
-      const int slot = s_base + atomicAdd(&s_cnt, 1);
-      ev[slot] = ((uint64_t)part << 32) | ((uint64_t)q << 2) | (uint64_t)type;
-      atomicAdd(&pcnt[part], 1);
+    if (pass == 0) {
+      my_events = wave_sum(my_events);
+      if (lane_id() == 0 && my_events) atomicAdd(s_cnt, my_events);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int c = *s_cnt;
+        *s_base = c ? (int64_t)atomicAdd((unsigned long long *)&scal[SC_EVENTS], (unsigned long long)c) : 0;
+        *s_cnt = 0;
+      }
+      __syncthreads();
     }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int count_moving(const uint32_t *__restrict__ hpin, const int32_t *__restrict__ pos,
+                                            int b, int len, int32_t *s_cnt) {
+  if (threadIdx.x == 0) *s_cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int i = threadIdx.x; i < len; i += PT_NT) mine += pos[hpin[b + i] & kIdMask] > 0 ? 1 : 0;
+  mine = wave_sum(mine);
+  if (lane_id() == 0 && mine) atomicAdd(s_cnt, mine);
+  __syncthreads();
+  const int m = *s_cnt;
+  __syncthreads();
+  return m;
+}
+
+constexpr int EV_LIGHT = 512;  // moving pins per hedge handled by the small-LDS kernel
+
+// One workgroup per hedge; hedges with more than EV_LIGHT moving pins are
+// queued for k_seq_events_heavy.
+__global__ __launch_bounds__(PT_NT) void k_seq_events_light(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int pshift,
+    int32_t *__restrict__ gp, uint64_t *__restrict__ ev, int32_t *__restrict__ pcnt, int64_t *__restrict__ scal,
+    int32_t *__restrict__ heavy) {
+  __shared__ uint64_t key[2 * EV_LIGHT];
+  __shared__ int32_t dl[2 * EV_LIGHT];
+  __shared__ int32_t sp[1024];
+  __shared__ uint32_t sc[1024];
+  __shared__ int32_t tmp[PT_NT / 64 + 1];
+  __shared__ int32_t s_cnt;
+  __shared__ int64_t s_base;
+  const int e = blockIdx.x;
+  const int moving = count_moving(hpin, pos, hoff[e], hoff[e + 1] - hoff[e], &s_cnt);
+  if (moving == 0) return;
+  if (moving > EV_LIGHT) {
+    if (threadIdx.x == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
+    return;
+  }
+  seq_events_hedge<2 * EV_LIGHT, 1024>(e, moving, hoff, hpin, hw, rho, dest, pos, pt, ptin, lam, pshift, gp, ev,
+                                       pcnt, scal, key, dl, tmp, &s_cnt, &s_base, sp, sc);
+}
+
+constexpr int EV_HEAVY_GRID = 512;
+
+__global__ __launch_bounds__(PT_NT) void k_seq_events_heavy(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int pshift,
+    int32_t *__restrict__ gp, uint64_t *__restrict__ ev, int32_t *__restrict__ pcnt, int64_t *__restrict__ scal,
+    const int32_t *__restrict__ heavy) {
+  __shared__ uint64_t key[2 * kSegCap];
+  __shared__ int32_t dl[2 * kSegCap];
+  __shared__ int32_t sp[kSegCap];
+  __shared__ uint32_t sc[kSegCap];
+  __shared__ int32_t tmp[PT_NT / 64 + 1];
+  __shared__ int32_t s_cnt;
+  __shared__ int64_t s_base;
+  const int64_t nh = scal[SC_HEAVY];
+  for (int64_t t = blockIdx.x; t < nh; t += gridDim.x) {
+    const int e = heavy[t];
+    const int moving = count_moving(hpin, pos, hoff[e], hoff[e + 1] - hoff[e], &s_cnt);
+    seq_events_hedge<2 * kSegCap, kSegCap>(e, moving, hoff, hpin, hw, rho, dest, pos, pt, ptin, lam, pshift, gp, ev,
+                                           pcnt, scal, key, dl, tmp, &s_cnt, &s_base, sp, sc);
   }
 }
 
 // size events: (p_s, i, size) and (p_d, i, size) for every move i
 __global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const int32_t *__restrict__ rho,
-                              const int32_t *__restrict__ dest, uint64_t *__restrict__ ev, int64_t base,
+                              const int32_t *__restrict__ dest, int pshift, uint64_t *__restrict__ ev, int64_t base,
                               int32_t *__restrict__ pcnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   const int v = seq[i];
   const uint64_t q = (uint64_t)(i + 1);
   const uint32_t ps = (uint32_t)rho[v], pd = (uint32_t)dest[v];
-  ev[base + 2 * i] = ((uint64_t)ps << 32) | (q << 2) | 2ull;
-  ev[base + 2 * i + 1] = ((uint64_t)pd << 32) | (q << 2) | 2ull;
+  ev[base + 2 * i] = ((uint64_t)ps << pshift) | (q << 2) | 2ull;
+  ev[base + 2 * i + 1] = ((uint64_t)pd << pshift) | (q << 2) | 2ull;
   atomicAdd(&pcnt[ps], 1);
   atomicAdd(&pcnt[pd], 1);
 }
@@ -478,7 +570,7 @@ __global__ void k_init_invalid(const int32_t *__restrict__ psize, const int32_t 
 __global__ void k_part_validity(const uint64_t *__restrict__ ev, const int32_t *__restrict__ poff, int32_t P,
                                 const int32_t *__restrict__ psize, const int32_t *__restrict__ pinb,
                                 const int32_t *__restrict__ seq, const int32_t *__restrict__ rho,
-                                const int32_t *__restrict__ size, int32_t omega, int32_t delta,
+                                const int32_t *__restrict__ size, int32_t omega, int32_t delta, uint64_t qmask,
                                 int32_t *__restrict__ vdelta) {
   const int p = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (p >= P) return;
@@ -496,7 +588,7 @@ __global__ void k_part_validity(const uint64_t *__restrict__ ev, const int32_t *
     int q = -1;
     if (act) {
       const uint64_t k = ev[i];
-      q = (int)((k >> 2) & 0x3fffffffull);
+      q = (int)((k >> 2) & qmask);
       const int type = (int)(k & 3ull);
       if (type == 0) di = -1;
       else if (type == 1) di = 1;
@@ -508,7 +600,7 @@ __global__ void k_part_validity(const uint64_t *__restrict__ ev, const int32_t *
     const int64_t cs = wave_inclusive_scan(ds) + run_size;
     const int64_t ci = wave_inclusive_scan(di) + run_inb;
     int qn = __shfl_down(q, 1, 64);
-    if (l == 63) qn = (i + 1 < en) ? (int)((ev[i + 1] >> 2) & 0x3fffffffull) : -1;
+    if (l == 63) qn = (i + 1 < en) ? (int)((ev[i + 1] >> 2) & qmask) : -1;
     const bool last = act && (i + 1 >= en || qn != q);
     const bool valid = cs <= omega && ci <= delta;
     const uint64_t lastmask = __ballot(last);
@@ -609,8 +701,6 @@ __global__ __launch_bounds__(FIN_NT) void k_finish(const int32_t *__restrict__ g
   }
 }
 
-constexpr int EV_LIGHT = 512;  // moving pins handled by the small-LDS variant
-
 void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta,
                        int64_t S, RoundBufs &B, int32_t *err, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s,
                        int64_t *istar, int64_t *gstar) {
@@ -619,13 +709,16 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   fill_i32(B.pcnt, (int64_t)n_parts + 1, 0, s);
   fill_i64(B.scal + SC_EVENTS, 1, 0, s);
   fill_i64(B.scal + SC_INVALID0, 1, 0, s);
+  const int posbits = bits_for(S);
+  const int pshift = posbits + 2;
+  fill_i64(B.scal + SC_HEAVY, 1, 0, s);
   if (S > 0 && L.E > 0) {
     KScope ks(3, s);
-    k_seq_events<2 * EV_LIGHT><<<L.E, PT_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam,
-                                                     0, EV_LIGHT, B.gp, B.keys, B.pcnt, B.scal, err);
+    k_seq_events_light<<<L.E, PT_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam, pshift,
+                                            B.gp, B.keys, B.pcnt, B.scal, B.heavy);
     HGP_LAUNCH_CHECK();
-    k_seq_events<2 * kSegCap><<<L.E, PT_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam,
-                                                    EV_LIGHT, kSegCap, B.gp, B.keys, B.pcnt, B.scal, err);
+    k_seq_events_heavy<<<EV_HEAVY_GRID, PT_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin,
+                                                       B.lam, pshift, B.gp, B.keys, B.pcnt, B.scal, B.heavy);
     HGP_LAUNCH_CHECK();
   }
   int64_t nin = 0;
@@ -634,7 +727,7 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   const int64_t nev = nin + 2 * S;
   if (nev > B.cap_events) throw Error(-7, "event buffer overflow");
   if (S > 0) {
-    k_size_events<<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, B.keys, nin, B.pcnt);
+    k_size_events<<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, pshift, B.keys, nin, B.pcnt);
     HGP_LAUNCH_CHECK();
   }
   k_init_invalid<<<div_up(n_parts > 0 ? n_parts : 1, 256), 256, 0, s>>>(B.psize, B.pinb, n_parts, omega, delta,
@@ -642,11 +735,12 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   HGP_LAUNCH_CHECK();
   int pbits = bits_for(n_parts > 0 ? n_parts - 1 : 0);
   if (pbits < 1) pbits = 1;
-  sort_keys(B.keys, B.keys2, nev, 32 + pbits, sort_tmp, s);
+  sort_keys(B.keys, B.keys2, nev, pshift + pbits, sort_tmp, s);
   scan_i32(B.pcnt, B.pcnt, (int64_t)n_parts + 1, nullptr, scan_tmp, s);
   if (n_parts > 0 && nev > 0) {
     k_part_validity<<<div_up((int64_t)n_parts * 64, 256), 256, 0, s>>>(B.keys, B.pcnt, n_parts, B.psize, B.pinb,
-                                                                        B.seq, rho, L.size, omega, delta, B.vdelta);
+                                                                        B.seq, rho, L.size, omega, delta,
+                                                                        (1ull << posbits) - 1ull, B.vdelta);
     HGP_LAUNCH_CHECK();
   }
   k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhgp.so")
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PLAIN = 0
 FLAG_TIME_KERNELS = 1
+FLAG_NO_INCREMENTAL = 2
 KERNEL_CLASSES = ["rate", "propose", "part_table", "seq_events", "contract", "incidence", "sort", "match"]
 
 

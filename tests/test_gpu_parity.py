@@ -38,12 +38,12 @@ def ctx():
     c.close()
 
 
-def _gpu_partition(ctx, g, omega, delta, k=0, rounds=8):
+def _gpu_partition(ctx, g, omega, delta, k=0, rounds=8, flags=0):
     from paper_2604_14411_amd import hgp
 
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     try:
-        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds)
+        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds, flags=flags)
         return 0, parts.cpu().numpy(), res
     except hgp.HgpError as e:
         return e.code, None, None
@@ -88,6 +88,32 @@ MEDIUM = [
 @pytest.mark.parametrize("name,make,omega,delta", MEDIUM, ids=[m[0] for m in MEDIUM])
 def test_medium_end_to_end(ctx, name, make, omega, delta):
     _compare(ctx, make(), omega, delta, label=name)
+
+
+INCR = [
+    ("rand2500_tail", lambda: synth.random_snn(2500, 30.0, 31), 1024, 400),
+    ("rand6000_tail", lambda: synth.random_snn(6000, 60.0, 32), 1024, 1500),
+    ("rand3000_omega", lambda: synth.random_snn(3000, 20.0, 33), 48, 100000),
+    ("conv_tail", lambda: synth.layered_conv(6, 8, 8, 8, 3, 0.1, 34), 256, 3000),
+]
+
+
+@pytest.mark.parametrize("name,make,omega,delta", INCR, ids=[c[0] for c in INCR])
+def test_incremental_late_levels_match_full_recompute(ctx, name, make, omega, delta):
+    from paper_2604_14411_amd import hgp
+
+    g = make()
+    say(f"[incremental] {name} full recompute")
+    rc1, p1, r1 = _gpu_partition(ctx, g, omega, delta, flags=hgp.FLAG_NO_INCREMENTAL)
+    say(f"[incremental] {name} incremental")
+    rc2, p2, r2 = _gpu_partition(ctx, g, omega, delta)
+    assert rc1 == rc2 == 0
+    assert np.array_equal(p1, p2)
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds"):
+        assert r1[key] == r2[key], key
+    say(f"[incremental] {name} oracle")
+    rc, ref, rres, _ = oracle.partition(g, omega, delta)
+    assert rc == 0 and np.array_equal(p2, ref) and rres["connectivity"] == r2["connectivity"]
 
 
 def test_host_entry_matches_device_entry(ctx):
