@@ -29,6 +29,7 @@ LDS_ATOMIC_PEAK_TOPS = CUS * CLOCK_GHZ * 1e9 * LDS_ATOMIC_LANES_PER_CLK / 1e12
 # entry visit); the pin-streaming kernels: compulsory HBM bytes per pin.
 COST = {
     "rate": ("alu", 1.0),
+    "rate_tail": ("alu", 1.0),
     "propose": ("alu", 1.0),
     "part_table": ("hbm", 16.0),
     "seq_events": ("hbm", 4.0),

@@ -79,7 +79,8 @@ typedef struct {
 #define HGP_K_INCIDENCE 5  /* incidence transpose; unit: pin */
 #define HGP_K_SORT 6       /* move / event sorts; unit: key */
 #define HGP_K_MATCH 7      /* pseudo-forest matching; unit: node */
-#define HGP_NKERNEL 8
+#define HGP_K_RATE_TAIL 8  /* late-level rating with top-K lists; unit: pin-pair visit */
+#define HGP_NKERNEL 9
 
 typedef struct {
   int32_t k;                 /* 0: coarsen to ceil(sum w / Omega) clusters (Sec. II-B); k > 0: to k */

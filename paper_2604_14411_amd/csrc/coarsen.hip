@@ -331,11 +331,11 @@ __global__ void k_cluster_size(const int32_t *__restrict__ match, const int32_t 
 __global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__ hoff,
                                                      const uint32_t *__restrict__ hpin,
                                                      const int32_t *__restrict__ map, uint32_t *__restrict__ out,
-                                                     int32_t *__restrict__ cnt) {
+                                                     int32_t *__restrict__ cnt, const int32_t *__restrict__ list) {
   __shared__ uint32_t key[kSegCap];
   __shared__ int32_t pos[kSegCap];
   __shared__ int32_t tmp[SEG_NT / 64 + 1];
-  const int e = blockIdx.x;
+  const int e = list[blockIdx.x];
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
   if (len <= 0) {
@@ -479,14 +479,18 @@ void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32
 }
 
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
-                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, DevBuf &scan_tmp, hipStream_t s) {
+                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
+                     hipStream_t s) {
   if (E <= 0) {
     fill_i32(new_hoff, 1, 0, s);
     return;
   }
   KScope ks(4, s);
-  k_contract<<<E, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt);
-  HGP_LAUNCH_CHECK();
+  launch_contract_wave(hoff, hpin, E, map, tmp_pins, cnt, s);
+  if (big.n > 0) {
+    k_contract<<<big.n, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, big.list);
+    HGP_LAUNCH_CHECK();
+  }
   scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);
   k_pack<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, new_hoff, E, tmp_pins, new_hpin);
   HGP_LAUNCH_CHECK();

@@ -15,6 +15,13 @@ constexpr int32_t kErrInfeasible = 32; // node exceeding Omega or Delta on its o
 constexpr int32_t kErrBigHedge = 64;   // hedge larger than kSegCap pins
 constexpr int32_t kErrInternal = 128;  // internal consistency check
 
+// Hedges longer than kWaveSegMax pins, handled by workgroup-per-hedge kernels.
+constexpr int kWaveSegMax = 1024;
+struct BigHedges {
+  const int32_t *list = nullptr;
+  int32_t n = 0;
+};
+
 // One hierarchy level resident on the device.
 struct LevelView {
   int32_t n = 0;  // nodes
@@ -26,6 +33,7 @@ struct LevelView {
   const int32_t *size = nullptr;   // [n]
   const int32_t *indeg = nullptr;  // [n]
   const int32_t *hw = nullptr;     // [E]
+  BigHedges big;                   // hedges longer than kWaveSegMax (a superset is fine)
 };
 
 // --- coarsen.hip ---
@@ -49,7 +57,14 @@ void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned
 void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
                          hipStream_t s);
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
-                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, DevBuf &scan_tmp, hipStream_t s);
+                     int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
+                     hipStream_t s);
+// --- seg.hip ---
+void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
+                          int32_t *cnt, hipStream_t s);
+void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
+                            int32_t *ptin, int32_t *lam, int32_t *pinb, hipStream_t s);
+void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s);
 
 void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s);
 void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t n, int32_t *err,

@@ -211,6 +211,48 @@ __device__ __forceinline__ void add_wave_units(unsigned long long *units, int64_
   if (units && lane_id() == 0 && v) atomicAdd(units, (unsigned long long)v);
 }
 
+// Bitonic sort (ascending) of 64*KPL keys held by one wave in registers; key
+// i = lane * KPL + j sits in k[j] of that lane.  Compare-exchange partners
+// closer than KPL are in the same lane, the others one xor-shuffle away.
+template <int KPL, class K>
+__device__ __forceinline__ void wave_bitonic_sort(K (&k)[KPL]) {
+  const int l = lane_id();
+#pragma unroll
+  for (int size = 2; size <= 64 * KPL; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= KPL) {
+        const int lx = stride / KPL;
+        const bool lower = (l & lx) == 0;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+          const bool asc = ((l * KPL + j) & size) == 0;
+          const K other = __shfl_xor(k[j], lx, 64);
+          k[j] = (lower == asc) ? (k[j] < other ? k[j] : other) : (k[j] < other ? other : k[j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+          const int p = j ^ stride;
+          if (p > j) {
+            const bool asc = ((l * KPL + j) & size) == 0;
+            const K a = k[j], b = k[p];
+            if ((a > b) == asc) {
+              k[j] = b;
+              k[p] = a;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class T>
+__device__ __forceinline__ T wave_exclusive_scan(T v) {
+  return wave_inclusive_scan(v) - v;
+}
+
 __host__ __device__ inline int next_pow2(int x) {
   int p = 1;
   while (p < x) p <<= 1;
@@ -220,7 +262,7 @@ __host__ __device__ inline int next_pow2(int x) {
 // ---------------------------------------------------------------------------
 // Optional per-kernel-class timing with HIP events (enabled per call).
 // ---------------------------------------------------------------------------
-constexpr int kNKClass = 8;
+constexpr int kNKClass = 9;
 struct KTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;

@@ -1,5 +1,7 @@
 // Host driver of the multilevel scheme (Sec. II-B) and the C-ABI of libhgp.
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -10,6 +12,15 @@
 namespace hgp {
 
 static thread_local std::string g_last_error;
+
+// HGP_LOG=1 prints one line per level and per refinement round to stderr.
+static bool log_on() {
+  static const bool on = [] {
+    const char *v = std::getenv("HGP_LOG");
+    return v && v[0] && v[0] != '0';
+  }();
+  return on;
+}
 
 struct Workspace {
   DevBuf err, sums, scal2;
@@ -27,7 +38,7 @@ struct Workspace {
   DevBuf units_dev;
   // incremental late levels
   DevBuf tkA_key, tkA_cnt, tkA_kap, tkB_key, tkB_cnt, tkB_kap, rows, newc, row_slot, nflag, rerate, dev_cnt;
-  DevBuf split, cdest, cgain;
+  DevBuf split, cdest, cgain, maxbits, biglist;
   std::vector<DevBuf> lv_match;
 
   void clear_levels() {
@@ -52,7 +63,7 @@ struct Workspace {
     for (DevBuf *b : all) b->release();
     units_dev.release();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     clear_levels();
@@ -178,9 +189,20 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
 }
 
 // Incidence I(n) with destination flags, |in(n)| and total(n) of a level.
+// Hedges of `hoff` longer than kWaveSegMax pins (list kept in W.biglist).
+static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStream_t s) {
+  BigHedges b;
+  int32_t *list = need<int32_t>(W.biglist, (int64_t)E + 1);
+  launch_big_hedges(hoff, E, list + 1, list, s);
+  b.n = read_i32(list, s);
+  b.list = list + 1;
+  return b;
+}
+
 // `size_cap` is the element capacity of the buffer behind `size` (checked).
 static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *hoff, const uint32_t *hpin,
-                           int64_t P, const int32_t *size, size_t size_cap, const int32_t *hw, hipStream_t s) {
+                           int64_t P, const int32_t *size, size_t size_cap, const int32_t *hw, const BigHedges &big,
+                           hipStream_t s) {
   if ((size_t)n > size_cap) throw Error(HGP_EINTERNAL, "node-size buffer smaller than the level");
   int32_t *ioff = need<int32_t>(W.ioff, (int64_t)n + 1);
   uint32_t *inc = need<uint32_t>(W.inc, P);
@@ -201,6 +223,7 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   L.size = size;
   L.indeg = indeg;
   L.hw = hw;
+  L.big = big;
   return L;
 }
 
@@ -270,6 +293,16 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
   return R;
 }
 
+// LDS words per id for the top-K rating of level L: 2 if the wide window fits,
+// 1 if every node's counters pack in 32 bits and the narrow window fits, else 0.
+static int topk_words_per_id(Workspace &W, const LevelView &L, hipStream_t s) {
+  if (2 * (int64_t)L.n <= kTopKMaxWords) return 2;
+  if ((int64_t)L.n > kTopKMaxWords) return 0;
+  int32_t *d = need<int32_t>(W.maxbits, 4);
+  launch_max_counter_bits(W.total.as<int32_t>(), L.indeg, L.n, d, s);
+  return read_i32(d, s) <= 32 ? 1 : 0;
+}
+
 struct RunStats {
   int64_t conn = 0;
   int32_t n_parts = 0, n_levels = 0, n_rounds = 0;
@@ -336,7 +369,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
   if (N > 0)
     HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
-  LevelView L = make_view(W, N, E, hoff0, hpin0, P, size0, W.lv_size[0].bytes / 4, hw, s);
+  const BigHedges big = find_big(W, hoff0, E, s);  // coarse hedges only shrink: valid for every level
+  LevelView L = make_view(W, N, E, hoff0, hpin0, P, size0, W.lv_size[0].bytes / 4, hw, big, s);
   launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
   check_err(W, s);
   st.n_levels = 1;
@@ -389,12 +423,16 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   bool have_pairs = false;  // pair/score of the current level already computed
   bool lists_ok = false;    // tk_cur holds exact lists for the current level
   bool tail = false;        // the previous matching merged few pairs
+  const char *path = "plain";
   while (true) {
     const int32_t n = L.n;
     if (!have_pairs) {
-      if (incremental && tail && 2 * (int64_t)n <= kTopKMaxIds) {
+      path = "plain";
+      const int wpi = (incremental && tail) ? topk_words_per_id(W, L, s) : 0;
+      if (wpi > 0) {
+        path = "topk";
         launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, nullptr, nullptr, pair, score,
-                         tk_cur, s);
+                         tk_cur, wpi, W.err.as<int32_t>(), s);
         lists_ok = true;
       } else {
         launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s);
@@ -409,6 +447,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
     const int32_t n_next = read_i32(nnext_dev, s);
     check_err(W, s);
+    if (log_on())
+      fprintf(stderr, "[hgp] level %d n=%d pins=%lld merged=%d rating=%s\n", lvl, n, (long long)cur_P, n - n_next,
+              path);
     if (n_next == n) {
       iota_i32(rho, n, s);
       n_parts = n;
@@ -432,7 +473,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       launch_project(W.lv_Gamma[lvl - 1].as<int32_t>(), gam, N, Gm, s);
     int32_t *nh = ping ? W.hoffB.as<int32_t>() : W.hoffA.as<int32_t>();
     uint32_t *npin = ping ? W.hpinB.as<uint32_t>() : W.hpinA.as<uint32_t>();
-    launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin,
+    launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
                     W.scan_tmp, s);
     add_units(HGP_K_CONTRACT, cur_P);
     cur_P = read_i32(nh + E, s);
@@ -440,22 +481,31 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     cur_hpin = npin;
     ping ^= 1;
     ++lvl;
-    L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, s);
+    L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s);
     tail = (int64_t)M * kTailRatio <= (int64_t)n;
-    if (incremental && lists_ok && tail && 2 * (int64_t)n_next <= kTopKMaxIds &&
-        (int64_t)M * n_next <= kRowBudget) {
+    const int wpi = (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget)
+                        ? topk_words_per_id(W, L, s)
+                        : 0;
+    if (wpi > 0) {
       // rate level lvl incrementally from the lists of level lvl-1
       int32_t *rows = need<int32_t>(W.rows, (int64_t)M * n_next);
       launch_new_clusters(lmatch, gam, n, n_next, nflag, newc, row_slot, W.scan_tmp, s);
       fill_i64(dcnt, 1, M, s);
       launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot, rows, pair, score, tk_nxt,
-                       s);
+                       wpi, W.err.as<int32_t>(), s);
       fill_i64(dcnt + 1, 1, 0, s);
       launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, tk_nxt, pair, score, rerate, dcnt + 1, s);
       launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, nullptr, nullptr, pair,
-                       score, tk_nxt, s);
+                       score, tk_nxt, wpi, W.err.as<int32_t>(), s);
       have_pairs = true;
       lists_ok = true;
+      path = "incremental";
+      if (log_on()) {
+        int64_t rr = 0;
+        HGP_HIP(hipMemcpyAsync(&rr, dcnt + 1, sizeof rr, hipMemcpyDeviceToHost, s));
+        HGP_HIP(hipStreamSynchronize(s));
+        fprintf(stderr, "[hgp]   level %d: %d new clusters rated, %lld nodes re-rated\n", lvl, M, (long long)rr);
+      }
     } else {
       lists_ok = false;
     }
@@ -495,13 +545,13 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
         uint32_t *rp = need<uint32_t>(W.hpinR, P);
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
-                        W.cnt.as<int32_t>(), rh, rp, W.scan_tmp, s);
+                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, s);
         add_units(HGP_K_CONTRACT, P);
         Pl = read_i32(rh + E, s);
         h = rh;
         p = rp;
       }
-      V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, s);
+      V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, big, s);
     }
     bool last_applied = false;
     int ran = 0;
@@ -517,6 +567,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       RoundBufs B;
       RoundResult R = refine_round(W, V, Pl, rho, n_parts, omega, delta, s, &B, use_carry ? &c : nullptr);
       last_applied = R.applied;
+      if (log_on())
+        fprintf(stderr, "[hgp] refine level %d round %d n=%d moves=%lld i*=%lld G=%lld applied=%d carried=%d\n", lv,
+                r, n, (long long)R.S, (long long)R.istar, (long long)R.gstar, R.applied ? 1 : 0, use_carry ? 1 : 0);
       if (!R.applied) {
         // the state is unchanged: these proposals hold for it
         if (incremental && n > 0) {
@@ -626,8 +679,9 @@ static LevelView level_view_from(Workspace &W, const hgp_level *lv, hipStream_t 
   check_err(W, s);
   launch_check_level(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), lv->n_hedges, lv->n_nodes, err, s);
   check_err(W, s);
+  const BigHedges big = find_big(W, lv->hoff, lv->n_hedges, s);
   return make_view(W, lv->n_nodes, lv->n_hedges, lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), P,
-                   lv->size, (size_t)lv->n_nodes, lv->hedge_w, s);
+                   lv->size, (size_t)lv->n_nodes, lv->hedge_w, big, s);
 }
 
 }  // namespace hgp
@@ -783,6 +837,8 @@ int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t
     V.hoff = g->hedge_off;
     V.hpin = I.hpin0;
     V.hw = I.hw;
+    V.size = I.nw;
+    V.big = find_big(W, g->hedge_off, E, s);
     RoundBufs B = round_bufs(W, N, E, I.P, np);
     launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
     int64_t *conn = need<int64_t>(W.conn, 2);
@@ -807,7 +863,8 @@ int hgp_level_canonical(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, in
     if (I.P > 0 && !hpin_out) throw Error(HGP_EINVAL, "hpin_out is NULL");
     int32_t *size0 = need<int32_t>(W.rhoB, N);
     if (N > 0) HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
-    LevelView L = make_view(W, N, E, g->hedge_off, I.hpin0, I.P, size0, W.rhoB.bytes / 4, I.hw, s);
+    const BigHedges big = find_big(W, g->hedge_off, E, s);
+    LevelView L = make_view(W, N, E, g->hedge_off, I.hpin0, I.P, size0, W.rhoB.bytes / 4, I.hw, big, s);
     launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
     check_err(W, s);
     HGP_HIP(hipMemcpyAsync(hoff_out, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyDeviceToDevice, s));
@@ -889,8 +946,9 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
     check_err(W, s);
     uint32_t *tmp = need<uint32_t>(W.tmp_pins, P);
     int32_t *cnt = need<int32_t>(W.cnt, E);
+    const BigHedges big = find_big(W, lv->hoff, E, s);
     launch_contract(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, gamma, tmp, cnt, hoff_out,
-                    reinterpret_cast<uint32_t *>(hpin_out), W.scan_tmp, s);
+                    reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, s);
     // cluster sizes: sum of member sizes (atomics over the fine nodes)
     fill_i32(size_out, n_next, 0, s);
     launch_cluster_size_sum(gamma, lv->size, lv->n_nodes, size_out, s);

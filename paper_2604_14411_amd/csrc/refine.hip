@@ -41,11 +41,12 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
                                                       const uint32_t *__restrict__ hpin,
                                                       const int32_t *__restrict__ rho, int2 *__restrict__ pt,
                                                       int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
-                                                      int32_t *__restrict__ pinb, int32_t *err) {
+                                                      int32_t *__restrict__ pinb, int32_t *err,
+                                                      const int32_t *__restrict__ list) {
   __shared__ uint32_t key[kSegCap];
   __shared__ int32_t first[kSegCap];
   __shared__ int32_t tmp[PT_NT / 64 + 1];
-  const int e = blockIdx.x;
+  const int e = list[blockIdx.x];
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
   if (len <= 0 || len > kSegCap) {
@@ -96,10 +97,13 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   KScope ks(2, s);
   add_units(2, 0);
   if (L.E > 0) {
-    k_part_table<<<L.E, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.pinb, err);
-    HGP_LAUNCH_CHECK();
+    launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.pinb, s);
+    if (L.big.n > 0) {
+      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.pinb, err, L.big.list);
+      HGP_LAUNCH_CHECK();
+    }
   }
-  if (L.n > 0) {
+  if (L.n > 0 && L.size) {
     k_part_size<<<div_up(L.n, 256), 256, 0, s>>>(rho, L.size, L.n, B.psize);
     HGP_LAUNCH_CHECK();
   }

@@ -1,0 +1,176 @@
+// Per-hedge kernels with one wave per hedge: the hedge's keys are sorted in
+// registers (wave_bitonic_sort) without workgroup barriers.  Hedges with more
+// than kWaveSegMax pins are left to the workgroup-per-hedge kernels, which run
+// over the list of such hedges.
+#include "coarsen.hpp"
+
+namespace hgp {
+
+__device__ __forceinline__ int lb_u32(const uint32_t *a, int n, uint32_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Coarse pins of one hedge (Sec. III-B): keys (map(v) << 1 | dst) sorted;
+// the last key of every id run survives, its low bit being the OR of the
+// run's destination flags.  Survivors go to out[b ..], their count to cnt[e].
+template <int KPL>
+__device__ __forceinline__ void contract_wave(int e, int b, int len, const uint32_t *__restrict__ hpin,
+                                              const int32_t *__restrict__ map, uint32_t *__restrict__ out,
+                                              int32_t *__restrict__ cnt) {
+  const int l = lane_id();
+  uint32_t k[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    uint32_t key = 0xffffffffu;
+    if (i < len) {
+      const uint32_t x = hpin[b + i];
+      key = ((uint32_t)map[x & kIdMask] << 1) | (x >> 31);
+    }
+    k[j] = key;
+  }
+  wave_bitonic_sort<KPL>(k);
+  const uint32_t next_lane_first = __shfl_down(k[0], 1, 64);
+  bool kept[KPL];
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    const uint32_t nx = (j + 1 < KPL) ? k[j + 1] : next_lane_first;
+    kept[j] = i < len && (i + 1 == len || (nx >> 1) != (k[j] >> 1));
+    c += kept[j] ? 1 : 0;
+  }
+  int pos = wave_exclusive_scan(c);
+  const int total = __shfl(pos + c, 63, 64);
+#pragma unroll
+  for (int j = 0; j < KPL; ++j)
+    if (kept[j]) out[b + pos++] = (k[j] >> 1) | ((k[j] & 1u) << 31);
+  if (l == 0) cnt[e] = total;
+}
+
+__global__ __launch_bounds__(256) void k_contract_wave(const int32_t *__restrict__ hoff,
+                                                       const uint32_t *__restrict__ hpin, int32_t E,
+                                                       const int32_t *__restrict__ map, uint32_t *__restrict__ out,
+                                                       int32_t *__restrict__ cnt) {
+  const int e = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (e >= E) return;
+  const int b = hoff[e], len = hoff[e + 1] - b;
+  if (len > kWaveSegMax) return;
+  if (len <= 64) contract_wave<1>(e, b, len, hpin, map, out, cnt);
+  else if (len <= 128) contract_wave<2>(e, b, len, hpin, map, out, cnt);
+  else if (len <= 256) contract_wave<4>(e, b, len, hpin, map, out, cnt);
+  else if (len <= 512) contract_wave<8>(e, b, len, hpin, map, out, cnt);
+  else contract_wave<16>(e, b, len, hpin, map, out, cnt);
+}
+
+// Part table of one hedge (Sec. IV-B): keys (rho(v) << 1 | dst) sorted; each
+// run of one part gives (part, pins(p,e)) and pins_in(p,e), written at the
+// hedge's pin offset; lam[e] = number of runs.  s: 64*KPL words of LDS.
+template <int KPL>
+__device__ __forceinline__ void part_table_wave(int e, int b, int len, const uint32_t *__restrict__ hpin,
+                                                const int32_t *__restrict__ rho, int2 *__restrict__ pt,
+                                                int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
+                                                int32_t *__restrict__ pinb, uint32_t *s) {
+  const int l = lane_id();
+  uint32_t k[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    uint32_t key = 0xffffffffu;
+    if (i < len) {
+      const uint32_t x = hpin[b + i];
+      key = ((uint32_t)rho[x & kIdMask] << 1) | (x >> 31);
+    }
+    k[j] = key;
+  }
+  wave_bitonic_sort<KPL>(k);
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) s[l * KPL + j] = k[j];
+  wave_lds_sync();
+  const uint32_t prev_lane_last = __shfl_up(k[KPL - 1], 1, 64);
+  bool first[KPL];
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    const uint32_t pv = (j > 0) ? k[j - 1] : prev_lane_last;
+    first[j] = i < len && (i == 0 || (pv >> 1) != (k[j] >> 1));
+    c += first[j] ? 1 : 0;
+  }
+  int r = wave_exclusive_scan(c);
+  const int runs = __shfl(r + c, 63, 64);
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    if (first[j]) {
+      const int i = l * KPL + j;
+      const uint32_t part = k[j] >> 1;
+      const int end = lb_u32(s, len, (part + 1) << 1);
+      const int dst0 = lb_u32(s, len, (part << 1) | 1u);
+      pt[b + r] = make_int2((int)part, end - i);
+      ptin[b + r] = end - dst0;
+      if (end > dst0) atomicAdd(&pinb[part], 1);
+      ++r;
+    }
+  }
+  if (l == 0) lam[e] = runs;
+  wave_lds_sync();
+}
+
+__global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restrict__ hoff,
+                                                         const uint32_t *__restrict__ hpin, int32_t E,
+                                                         const int32_t *__restrict__ rho, int2 *__restrict__ pt,
+                                                         int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
+                                                         int32_t *__restrict__ pinb) {
+  __shared__ uint32_t sbuf[4][kWaveSegMax];
+  const int w = threadIdx.x >> 6;
+  const int e = (int)(blockIdx.x * 4 + w);
+  if (e >= E) return;
+  const int b = hoff[e], len = hoff[e + 1] - b;
+  if (len > kWaveSegMax) return;
+  if (len == 0) {
+    if (lane_id() == 0) lam[e] = 0;
+    return;
+  }
+  uint32_t *s = sbuf[w];
+  if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+  else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+  else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+  else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+  else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+}
+
+void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
+                          int32_t *cnt, hipStream_t s) {
+  if (E <= 0) return;
+  k_contract_wave<<<div_up(E, 4), 256, 0, s>>>(hoff, hpin, E, map, out, cnt);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
+                            int32_t *ptin, int32_t *lam, int32_t *pinb, hipStream_t s) {
+  if (E <= 0) return;
+  k_part_table_wave<<<div_up(E, 4), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb);
+  HGP_LAUNCH_CHECK();
+}
+
+// Hedges longer than kWaveSegMax pins (fixed by level 0: coarse hedges only shrink).
+__global__ void k_big_hedges(const int32_t *__restrict__ hoff, int32_t E, int32_t *__restrict__ list,
+                             int32_t *__restrict__ count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < E && hoff[e + 1] - hoff[e] > kWaveSegMax) list[atomicAdd(count, 1)] = (int32_t)e;
+}
+
+void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s) {
+  fill_i32(count, 1, 0, s);
+  if (E <= 0) return;
+  k_big_hedges<<<div_up(E, 256), 256, 0, s>>>(hoff, E, list, count);
+  HGP_LAUNCH_CHECK();
+}
+
+}  // namespace hgp

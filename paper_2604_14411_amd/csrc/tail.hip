@@ -41,8 +41,8 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
                                                   const int32_t *__restrict__ row_slot, int32_t *__restrict__ rows,
                                                   int32_t *__restrict__ pair, int64_t *__restrict__ score,
                                                   uint64_t *__restrict__ tk_key, int32_t *__restrict__ tk_cnt,
-                                                  uint64_t *__restrict__ tk_kappa,
-                                                  unsigned long long *__restrict__ units) {
+                                                  uint64_t *__restrict__ tk_kappa, int32_t words,
+                                                  int32_t *err, unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t lds[];
   __shared__ int32_t tbl[NT / 64 * 192];
   __shared__ uint64_t red[NT / 64];
@@ -61,6 +61,10 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
     const bool packed = hb + cb <= 32;
     const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
     const int zw = packed ? N : 2 * N;
+    if (zw > words) {  // the window was sized for packed counters only
+      if (tid == 0) atomicOr(err, kErrInternal);
+      continue;
+    }
     for (int i = tid; i < zw; i += NT) lds[i] = 0u;
     __syncthreads();
     if (sn < omega) {
@@ -233,20 +237,22 @@ constexpr int TOPK_GRID = 2048;
 
 void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, const int32_t *list,
                       const int64_t *count, int64_t grid_nodes, const int32_t *row_slot, int32_t *rows, int32_t *pair,
-                      int64_t *score, TopK &tk, hipStream_t s) {
+                      int64_t *score, TopK &tk, int words_per_id, int32_t *err, hipStream_t s) {
   if (L.n <= 0 || grid_nodes <= 0) return;
-  KScope ks(0, s);
-  const size_t bytes = (size_t)2 * L.n * 4;
+  const int64_t words = (int64_t)words_per_id * L.n;
+  if (words > kTopKMaxWords) throw Error(-7, "top-K window exceeds LDS");
+  KScope ks(8, s);
+  const size_t bytes = (size_t)words * 4;
   static bool attr_set = false;
   if (!attr_set) {
     HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kTopKMaxIds * 8));
+                                kTopKMaxWords * 4));
     attr_set = true;
   }
   const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, bytes, s>>>(L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size,
                                                     L.indeg, total, omega, delta, row_slot, rows, pair, score, tk.key,
-                                                    tk.cnt, tk.kappa, units_ptr(0));
+                                                    tk.cnt, tk.kappa, (int32_t)words, err, units_ptr(8));
   HGP_LAUNCH_CHECK();
 }
 
@@ -254,10 +260,30 @@ void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gam
                         int32_t n_new, const int32_t *newc, const int32_t *rows, int32_t n_coarse, TopK &tk,
                         int32_t *pair, int64_t *score, int32_t *rerate, int64_t *rerate_cnt, hipStream_t s) {
   if (n_fine <= 0) return;
-  KScope ks(0, s);
+  KScope ks(8, s);
   k_rate_update<<<div_up(n_fine, 256), 256, 0, s>>>(n_fine, match, gamma, old_tk.key, old_tk.cnt, old_tk.kappa, n_new,
                                                     newc, rows, n_coarse, tk.key, tk.cnt, tk.kappa, pair, score,
                                                     rerate, rerate_cnt);
+  HGP_LAUNCH_CHECK();
+}
+
+__global__ void k_max_counter_bits(const int32_t *__restrict__ total, const int32_t *__restrict__ indeg, int32_t n,
+                                   int32_t *out) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  if (v < n) {
+    const uint32_t t = (uint32_t)total[v], d = (uint32_t)indeg[v];
+    b = (t ? 32 - __clz(t) : 0) + (d ? 32 - __clz(d) : 0);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) b = max(b, __shfl_xor(b, o, 64));
+  if (lane_id() == 0 && b) atomicMax(out, b);
+}
+
+void launch_max_counter_bits(const int32_t *total, const int32_t *indeg, int32_t n, int32_t *out, hipStream_t s) {
+  fill_i32(out, 1, 0, s);
+  if (n <= 0) return;
+  k_max_counter_bits<<<div_up(n, 256), 256, 0, s>>>(total, indeg, n, out);
   HGP_LAUNCH_CHECK();
 }
 

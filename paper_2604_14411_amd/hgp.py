@@ -18,7 +18,8 @@ OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, 
 PLAIN = 0
 FLAG_TIME_KERNELS = 1
 FLAG_NO_INCREMENTAL = 2
-KERNEL_CLASSES = ["rate", "propose", "part_table", "seq_events", "contract", "incidence", "sort", "match"]
+KERNEL_CLASSES = ["rate", "propose", "part_table", "seq_events", "contract", "incidence", "sort", "match",
+                  "rate_tail"]
 
 
 class HgpError(RuntimeError):
@@ -41,8 +42,8 @@ class Options_t(ctypes.Structure):
 class Result_t(ctypes.Structure):
     _fields_ = [("connectivity", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("n_rounds", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms_coarsen", ctypes.c_double),
-                ("ms_refine", ctypes.c_double), ("ms_kernel", ctypes.c_double * 8),
-                ("n_kernel", ctypes.c_int64 * 8), ("units_kernel", ctypes.c_int64 * 8)]
+                ("ms_refine", ctypes.c_double), ("ms_kernel", ctypes.c_double * 9),
+                ("n_kernel", ctypes.c_int64 * 9), ("units_kernel", ctypes.c_int64 * 9)]
 
 
 class Level_t(ctypes.Structure):

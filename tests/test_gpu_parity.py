@@ -281,3 +281,47 @@ def test_rand16k_matches_oracle_golden(ctx):
     assert res["connectivity"] == gold["connectivity"]
     assert res["n_parts"] == gold["n_parts"] and res["n_levels"] == gold["n_levels"]
     assert res["n_rounds"] == gold["n_rounds"]
+
+
+def _with_big_hedges(n, mu, n_big, big_len, seed):
+    """Random SNN plus a few hub hedges longer than one wave's sort capacity."""
+    import random as _r
+
+    g = synth.random_snn(n, mu, seed)
+    rng = _r.Random(seed)
+    hedges = []
+    for e in range(g.n_hedges):
+        b, en, ns = int(g.hedge_off[e]), int(g.hedge_off[e + 1]), int(g.n_src[e])
+        pins = [int(x) for x in g.pins[b:en]]
+        hedges.append((pins[:ns], pins[ns:]))
+    w = [int(x) for x in g.hedge_w]
+    for _ in range(n_big):
+        pins = rng.sample(range(n), big_len)
+        hedges.append((pins[:1], pins[1:]))
+        w.append(rng.randint(1, 16))
+    return from_lists(n, hedges, w)
+
+
+def test_hedges_longer_than_a_wave(ctx):
+    g = _with_big_hedges(2500, 20.0, 6, 1500, 41)
+    _compare(ctx, g, 64, 2000, label="big hedges")
+    from paper_2604_14411_amd import hgp
+
+    too_big = from_lists(5000, [([0], list(range(1, 4098)))])
+    rc, _, _ = _gpu_partition(ctx, too_big, 64, 4000)
+    assert rc == hgp.EUNSUPPORTED
+
+
+def test_connectivity_entry_point(ctx):
+    from paper_2604_14411_amd import hgp
+
+    g = _with_big_hedges(1500, 15.0, 2, 1200, 43)
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    rng = np.random.default_rng(5)
+    import torch
+
+    for k in (1, 7, 300, g.n_nodes):
+        part = rng.integers(0, k, size=g.n_nodes).astype(np.int32)
+        say(f"[connectivity] k={k}")
+        got = hgp.connectivity_device(ctx, dg, torch.as_tensor(part).to("cuda:0"))
+        assert got == oracle.connectivity(g, part)
