@@ -325,3 +325,23 @@ def test_connectivity_entry_point(ctx):
         say(f"[connectivity] k={k}")
         got = hgp.connectivity_device(ctx, dg, torch.as_tensor(part).to("cuda:0"))
         assert got == oracle.connectivity(g, part)
+
+
+def test_rand64k_matches_oracle_golden(ctx):
+    """The benchmark workload at full size: part ids and statistics bit-exact."""
+    path = os.path.join(HERE, "golden", "rand64k.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    gold = json.load(open(path))
+    from paper_2604_14411_amd.synth.configs import WORKLOADS
+
+    w = WORKLOADS["rand64k"]
+    g = w.make()
+    assert g.digest() == gold["input_sha256"]
+    say("[golden] rand64k")
+    rc, parts, res = _gpu_partition(ctx, g, w.omega, w.delta)
+    assert rc == 0
+    assert hashlib.sha256(np.ascontiguousarray(parts, dtype="<i4").tobytes()).hexdigest() == gold["parts_sha256"]
+    assert res["connectivity"] == gold["connectivity"]
+    assert res["n_parts"] == gold["n_parts"] and res["n_levels"] == gold["n_levels"]
+    assert res["n_rounds"] == gold["n_rounds"]
