@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libhgpo.so")
 
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 
-LV_HOFF, LV_HPIN, LV_SIZE, LV_PAIR, LV_SCORE, LV_MATCH, LV_GAMMA, LV_RHO0, LV_RHO1 = range(9)
+(LV_HOFF, LV_HPIN, LV_SIZE, LV_PAIR, LV_SCORE, LV_MATCH, LV_GAMMA, LV_RHO0, LV_RHO1, LV_COFF, LV_CAND, LV_CSCORE,
+ LV_FEAT, LV_PPAIR, LV_FALLBACK) = range(15)
+MLP_F, MLP_H, MLP_NFEAT = 16, 64, 10
 (RD_INFO, RD_RHO, RD_PDEST, RD_PGAIN, RD_SEQ, RD_GP, RD_G, RD_VIOL, RD_PTOFF, RD_PT, RD_PSIZE,
  RD_PINB) = range(20, 32)
 
@@ -31,7 +33,25 @@ class _HG(ctypes.Structure):
 
 class _Res(ctypes.Structure):
     _fields_ = [("connectivity", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("n_rounds", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("n_rounds", ctypes.c_int32), ("n_fallback", ctypes.c_int32)]
+
+
+class _MLP(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32), ("b3", ctypes.c_int32),
+                ("w1", ctypes.c_int32 * (MLP_F * MLP_H)), ("b1", ctypes.c_int32 * MLP_H),
+                ("w2", ctypes.c_int32 * (MLP_H * MLP_H)), ("b2", ctypes.c_int32 * MLP_H),
+                ("w3", ctypes.c_int32 * MLP_H)]
+
+
+def _mlp(q) -> _MLP:
+    """Packs an integer network given as a dict (k, r1, r2, b3, w1[16,64], b1[64], w2[64,64], b2[64], w3[64])."""
+    m = _MLP()
+    m.k, m.r1, m.r2, m.b3 = int(q["k"]), int(q["r1"]), int(q["r2"]), int(q["b3"])
+    for name, n in (("w1", MLP_F * MLP_H), ("b1", MLP_H), ("w2", MLP_H * MLP_H), ("b2", MLP_H), ("w3", MLP_H)):
+        a = np.ascontiguousarray(np.asarray(q[name]).reshape(-1), dtype=np.int32)
+        assert a.size == n, name
+        ctypes.memmove(getattr(m, name), a.ctypes.data, 4 * n)
+    return m
 
 
 _lib = None
@@ -56,6 +76,14 @@ def _load():
         lib.hgpo_partition.restype = ctypes.c_int
         lib.hgpo_partition.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_Res), ctypes.c_void_p]
+        lib.hgpo_partition_learned.restype = ctypes.c_int
+        lib.hgpo_partition_learned.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.POINTER(_MLP), ctypes.c_void_p,
+                                               ctypes.POINTER(_Res), ctypes.c_void_p]
+        lib.hgpo_mlp_score.restype = ctypes.c_int
+        lib.hgpo_mlp_score.argtypes = [ctypes.POINTER(_MLP), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.hgpo_qlog.restype = ctypes.c_int32
+        lib.hgpo_qlog.argtypes = [ctypes.c_int64]
         lib.hgpo_connectivity.restype = ctypes.c_int
         lib.hgpo_connectivity.argtypes = [ctypes.POINTER(_HG), ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         lib.hgpo_trace_new.restype = ctypes.c_void_p
@@ -132,6 +160,40 @@ def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace:
                             tr.ptr if tr else None)
     out = dict(connectivity=res.connectivity, n_parts=res.n_parts, n_levels=res.n_levels, n_rounds=res.n_rounds)
     return rc, parts[:g.n_nodes], out, tr
+
+
+def partition_learned(g, omega: int, delta: int, mlp, k: int = 0, max_rounds: int = 8, trace: bool = False):
+    """The oracle with the learned merge proposal (mlp: integer network dict).
+    Returns (rc, parts, result dict, Trace or None)."""
+    lib = _load()
+    keep = []
+    hg = _hg(g, keep)
+    m = _mlp(mlp)
+    parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
+    res = _Res()
+    tr = Trace() if trace else None
+    rc = lib.hgpo_partition_learned(ctypes.byref(hg), omega, delta, k, max_rounds, ctypes.byref(m),
+                                    parts.ctypes.data, ctypes.byref(res), tr.ptr if tr else None)
+    out = dict(connectivity=res.connectivity, n_parts=res.n_parts, n_levels=res.n_levels, n_rounds=res.n_rounds,
+               n_fallback=res.n_fallback)
+    return rc, parts[:g.n_nodes], out, tr
+
+
+def mlp_score(mlp, xq) -> np.ndarray:
+    """The integer network on rows of 16 input codes; returns int64 scores."""
+    lib = _load()
+    m = _mlp(mlp)
+    x = np.ascontiguousarray(xq, dtype=np.int32).reshape(-1, MLP_F)
+    out = np.zeros(max(len(x), 1), dtype=np.int64)
+    rc = lib.hgpo_mlp_score(ctypes.byref(m), x.ctypes.data if x.size else None, len(x), out.ctypes.data)
+    if rc != OK:
+        raise ValueError(f"hgpo_mlp_score rc={rc}")
+    return out[:len(x)]
+
+
+def qlog(f: int) -> int:
+    """The 8-bit feature code of f >= 0."""
+    return int(_load().hgpo_qlog(int(f)))
 
 
 def connectivity(g, part) -> int:

@@ -241,6 +241,219 @@ void match_pairs(const std::vector<int32_t> &pair, const std::vector<int64_t> &s
 }
 
 /*
+ * Learned merge proposal (an extension outside the paper's method; the
+ * definitions are stated in hgpo.h).  Everything is integer arithmetic.
+ */
+
+/* 8 * floor(log2(f+1)) + the three bits below the leading one of f+1, capped
+ * at 255. */
+int32_t qlog_code(int64_t f) {
+  const uint64_t v = (uint64_t)f + 1u;
+  int e = 63;
+  while (!((v >> e) & 1u)) --e;
+  const uint64_t t = e >= 3 ? (v >> (e - 3)) & 7u : (v << (3 - e)) & 7u;
+  const int64_t code = 8 * (int64_t)e + (int64_t)t;
+  return (int32_t)std::min<int64_t>(code, 255);
+}
+
+/* x / 2^r rounded to nearest, ties to even. */
+int64_t rshift_rne(int64_t x, int32_t r) {
+  if (r == 0) return x;
+  const int64_t q = x >> r; /* floor */
+  const int64_t rem = x - q * ((int64_t)1 << r);
+  const int64_t half = (int64_t)1 << (r - 1);
+  return (rem > half || (rem == half && (q & 1))) ? q + 1 : q;
+}
+
+int64_t clamp255(int64_t v) { return v < 0 ? 0 : (v > 255 ? 255 : v); }
+
+/* The fixed-point network: two hidden layers of 64 ReLU units (requantised
+ * to 0..255 by a rounded right shift) and a linear output. */
+int64_t mlp_forward(const hgpo_mlp &q, const int32_t *x) {
+  int64_t a1[HGPO_MLP_H], a2[HGPO_MLP_H];
+  for (int j = 0; j < HGPO_MLP_H; ++j) {
+    int64_t acc = q.b1[j];
+    for (int f = 0; f < HGPO_MLP_F; ++f) acc += (int64_t)x[f] * q.w1[f * HGPO_MLP_H + j];
+    a1[j] = clamp255(rshift_rne(acc, q.r1));
+  }
+  for (int k = 0; k < HGPO_MLP_H; ++k) {
+    int64_t acc = q.b2[k];
+    for (int j = 0; j < HGPO_MLP_H; ++j) acc += a1[j] * q.w2[j * HGPO_MLP_H + k];
+    a2[k] = clamp255(rshift_rne(acc, q.r2));
+  }
+  int64_t s = q.b3;
+  for (int k = 0; k < HGPO_MLP_H; ++k) s += a2[k] * q.w3[k];
+  return s;
+}
+
+bool mlp_ok(const hgpo_mlp *q) {
+  if (!q || q->k < 1 || q->r1 < 0 || q->r1 > 30 || q->r2 < 0 || q->r2 > 30) return false;
+  const int64_t bmax = (int64_t)1 << 22;
+  auto wok = [](int32_t v) { return v >= -255 && v <= 255; };
+  auto bok = [bmax](int32_t v) { return (int64_t)v >= -bmax && (int64_t)v <= bmax; };
+  for (int i = 0; i < HGPO_MLP_F * HGPO_MLP_H; ++i)
+    if (!wok(q->w1[i])) return false;
+  for (int i = 0; i < HGPO_MLP_H * HGPO_MLP_H; ++i)
+    if (!wok(q->w2[i])) return false;
+  for (int i = 0; i < HGPO_MLP_H; ++i)
+    if (!wok(q->w3[i]) || !bok(q->b1[i]) || !bok(q->b2[i])) return false;
+  return bok(q->b3);
+}
+
+/* A valid candidate m of n with hist(n,m) and c(n,m). */
+struct Cand {
+  int32_t m;
+  int64_t h;
+  int64_t c;
+};
+
+/* Codes of the features of the unordered pair {n, m} (see hgpo.h). */
+void pair_codes(const Level &L, int32_t level, int64_t omega, int64_t delta, int32_t n, const Cand &cd, int32_t *x) {
+  const int32_t a = std::min(n, cd.m), b = std::max(n, cd.m);
+  const int64_t uni = (int64_t)L.indeg[a] + L.indeg[b] - cd.c;
+  const int64_t f[HGPO_MLP_NFEAT] = {cd.h,
+                                     cd.c,
+                                     L.size[a],
+                                     L.size[b],
+                                     uni,
+                                     L.ioff[a + 1] - L.ioff[a],
+                                     L.ioff[b + 1] - L.ioff[b],
+                                     level,
+                                     omega - L.size[a] - L.size[b],
+                                     delta - uni};
+  for (int i = 0; i < HGPO_MLP_F; ++i) x[i] = i < HGPO_MLP_NFEAT ? qlog_code(f[i]) : 0;
+}
+
+/* The K best valid candidates of every node by (hist, id), descending, with
+ * the same hist / c / validity as rate_select (Eq. 2, Sec. III-A). */
+void rate_topk(const Level &L, const std::vector<int32_t> &w, int64_t omega, int64_t delta, int32_t K,
+               std::vector<std::vector<Cand>> &top) {
+  const int32_t N = L.n;
+  top.assign((size_t)N, {});
+#pragma omp parallel
+  {
+    std::vector<int64_t> hist((size_t)N, 0);
+    std::vector<int64_t> common((size_t)N, 0);
+    std::vector<uint8_t> seen((size_t)N, 0);
+    std::vector<int32_t> touched;
+    std::vector<Cand> valid;
+#pragma omp for schedule(dynamic, 64)
+    for (int32_t n = 0; n < N; ++n) {
+      touched.clear();
+      for (int64_t i = L.ioff[n]; i < L.ioff[n + 1]; ++i) {
+        const int32_t e = L.ihe[i];
+        const bool n_dst = L.idst[i] != 0;
+        for (int64_t j = L.hoff[e]; j < L.hoff[e + 1]; ++j) {
+          const int32_t m = L.hpin[j];
+          if (m == n) continue;
+          if (!seen[m]) {
+            seen[m] = 1;
+            touched.push_back(m);
+          }
+          hist[m] += w[e];
+          if (n_dst && L.hdst[j]) common[m] += 1;
+        }
+      }
+      valid.clear();
+      for (int32_t m : touched) {
+        if (L.size[n] + L.size[m] <= omega && (int64_t)L.indeg[n] + L.indeg[m] - common[m] <= delta)
+          valid.push_back({m, hist[m], common[m]});
+        hist[m] = 0;
+        common[m] = 0;
+        seen[m] = 0;
+      }
+      std::sort(valid.begin(), valid.end(),
+                [](const Cand &x, const Cand &y) { return x.h != y.h ? x.h > y.h : x.m > y.m; });
+      if ((int32_t)valid.size() > K) valid.resize((size_t)K);
+      top[n] = valid;
+    }
+  }
+}
+
+/* C(n) = topK(n) u {m : n in topK(m)}, ascending by id. */
+void symmetric_candidates(const std::vector<std::vector<Cand>> &top, std::vector<std::vector<Cand>> &cand) {
+  const int32_t N = (int32_t)top.size();
+  cand.assign((size_t)N, {});
+  for (int32_t n = 0; n < N; ++n)
+    for (const Cand &x : top[n]) {
+      cand[n].push_back(x);
+      cand[x.m].push_back({n, x.h, x.c});
+    }
+  for (auto &v : cand) {
+    std::sort(v.begin(), v.end(), [](const Cand &x, const Cand &y) { return x.m < y.m; });
+    v.erase(std::unique(v.begin(), v.end(), [](const Cand &x, const Cand &y) { return x.m == y.m; }), v.end());
+  }
+}
+
+/* One coarsening level with the learned proposal: top-K rating, symmetric
+ * candidate sets, network scores, pair(n) = argmax (score, id) over C(n),
+ * the matching of Sec. III-A on those pairs, and the plain fallback. */
+void learned_level(const Level &L, int32_t level, const std::vector<int32_t> &w, int64_t omega, int64_t delta,
+                   const hgpo_mlp &q, std::vector<int32_t> &pair, std::vector<int64_t> &score,
+                   std::vector<int32_t> &match, int32_t &n_fallback, hgpo_trace *trace) {
+  const int32_t N = L.n;
+  std::vector<std::vector<Cand>> top, cand;
+  rate_topk(L, w, omega, delta, q.k, top);
+  std::vector<int32_t> ppair((size_t)N, -1), pmatch;
+  std::vector<int64_t> pscore((size_t)N, 0);
+  for (int32_t n = 0; n < N; ++n)
+    if (!top[n].empty()) {
+      ppair[n] = top[n][0].m;
+      pscore[n] = top[n][0].h;
+    }
+  symmetric_candidates(top, cand);
+  std::vector<std::vector<int64_t>> cs((size_t)N);
+  pair.assign((size_t)N, -1);
+  score.assign((size_t)N, 0);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t n = 0; n < N; ++n) {
+    int32_t x[HGPO_MLP_F];
+    cs[n].resize(cand[n].size());
+    for (size_t i = 0; i < cand[n].size(); ++i) {
+      pair_codes(L, level, omega, delta, n, cand[n][i], x);
+      const int64_t s = mlp_forward(q, x);
+      cs[n][i] = s;
+      if (pair[n] < 0 || s > score[n] || (s == score[n] && cand[n][i].m > pair[n])) {
+        pair[n] = cand[n][i].m;
+        score[n] = s;
+      }
+    }
+  }
+  match_pairs(pair, score, match);
+  match_pairs(ppair, pscore, pmatch);
+  int64_t ml = 0, mp = 0;
+  for (int32_t n = 0; n < N; ++n) {
+    ml += match[n] > n;
+    mp += pmatch[n] > n;
+  }
+  const bool fb = 2 * ml < mp;
+  if (fb) {
+    match.swap(pmatch);
+    ++n_fallback;
+  }
+  if (trace) {
+    std::vector<int64_t> coff((size_t)N + 1, 0), csc;
+    std::vector<int32_t> cid, feat;
+    int32_t x[HGPO_MLP_F];
+    for (int32_t n = 0; n < N; ++n) {
+      for (size_t i = 0; i < cand[n].size(); ++i) {
+        cid.push_back(cand[n][i].m);
+        csc.push_back(cs[n][i]);
+        pair_codes(L, level, omega, delta, n, cand[n][i], x);
+        feat.insert(feat.end(), x, x + HGPO_MLP_F);
+      }
+      coff[(size_t)n + 1] = (int64_t)cid.size();
+    }
+    trace->put64(HGPO_LV_COFF, level, coff);
+    trace->put32(HGPO_LV_CAND, level, cid);
+    trace->put64(HGPO_LV_CSCORE, level, csc);
+    trace->put32(HGPO_LV_FEAT, level, feat);
+    trace->put32(HGPO_LV_PPAIR, level, ppair);
+    trace->put32(HGPO_LV_FALLBACK, level, std::vector<int32_t>{fb ? 1 : 0});
+  }
+}
+
+/*
  * Coarse hypergraph, Sec. III-B: N' = {{n, match(n)}}, gamma(n) = the rank of
  * the cluster's smaller member among all such representatives (ascending).
  * Every hedge keeps its id and weight; its pins become the set of clusters of
@@ -604,8 +817,8 @@ int hgpo_connectivity(const hgpo_hypergraph *g, const int32_t *part, int64_t *ou
  * max_rounds.  Output part ids are renumbered 0..n_parts-1 by ascending
  * initial-part id, skipping emptied parts.
  */
-int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
-                   int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                          const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
   int rc = validate(g, omega, delta, k, max_rounds);
   if (rc != HGPO_OK) return rc;
   if (!part_out && g->n_nodes > 0) return HGPO_EINVAL;
@@ -644,6 +857,7 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
     const int64_t T = k > 0 ? (int64_t)k : (wsum + omega - 1) / omega;
 
     /* coarsening */
+    int32_t n_fallback = 0;
     std::vector<int32_t> rho;
     int32_t n_parts = 0;
     int32_t l = 0;
@@ -651,8 +865,12 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
       Level &L = levels[(size_t)l];
       std::vector<int32_t> pair, match;
       std::vector<int64_t> score;
-      rate_select(L, w, omega, delta, pair, score);
-      match_pairs(pair, score, match);
+      if (!mlp) {
+        rate_select(L, w, omega, delta, pair, score);
+        match_pairs(pair, score, match);
+      } else {
+        learned_level(L, l, w, omega, delta, *mlp, pair, score, match, n_fallback, trace);
+      }
       int32_t M = 0;
       for (int32_t n = 0; n < L.n; ++n)
         if (match[n] > n) ++M;
@@ -725,12 +943,33 @@ int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32
       res->n_parts = np;
       res->n_levels = Lmax + 1;
       res->n_rounds = rounds;
-      res->pad = 0;
+      res->n_fallback = n_fallback;
     }
   } catch (const std::bad_alloc &) {
     return HGPO_ENOMEM;
   }
   return HGPO_OK;
 }
+
+int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                   int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+  return partition_impl(g, omega, delta, k, max_rounds, nullptr, part_out, res, trace);
+}
+
+int hgpo_partition_learned(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                           const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+  if (!mlp_ok(mlp)) return HGPO_EINVAL;
+  return partition_impl(g, omega, delta, k, max_rounds, mlp, part_out, res, trace);
+}
+
+int hgpo_mlp_score(const hgpo_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score) {
+  if (!mlp_ok(mlp) || n < 0 || (n > 0 && (!xq || !score))) return HGPO_EINVAL;
+  for (int64_t i = 0; i < n * HGPO_MLP_F; ++i)
+    if (xq[i] < 0 || xq[i] > 255) return HGPO_EINVAL;
+  for (int64_t i = 0; i < n; ++i) score[i] = mlp_forward(*mlp, xq + i * HGPO_MLP_F);
+  return HGPO_OK;
+}
+
+int32_t hgpo_qlog(int64_t f) { return f < 0 ? -1 : qlog_code(f); }
 
 }  // extern "C"

@@ -157,3 +157,26 @@ def from_lists(n_nodes: int, hedges, hedge_w=None, node_w=None) -> Hypergraph:
     nw = np.ones(n_nodes, dtype=np.int32) if node_w is None else np.asarray(node_w, dtype=np.int32)
     return Hypergraph(np.asarray(off, dtype=np.int32), np.asarray(pins, dtype=np.int32),
                       np.asarray(nsrc, dtype=np.int32), hw, nw)
+
+
+def random_int_mlp(seed: int, k: int = 8, r1: int = 7, r2: int = 9, wmax: int = 255, bmax: int = 4096) -> dict:
+    """Seeded random integer network for the learned merge proposal (test input):
+    weights uniform in [-wmax, wmax], biases in [-bmax, bmax], codes 10..15 of
+    the first layer zero (padding inputs)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.integers(-wmax, wmax + 1, size=(16, 64), dtype=np.int64)
+    w1[10:, :] = 0
+    return dict(k=int(k), r1=int(r1), r2=int(r2), b3=int(rng.integers(-bmax, bmax + 1)),
+                w1=w1.astype(np.int32),
+                b1=rng.integers(-bmax, bmax + 1, size=64).astype(np.int32),
+                w2=rng.integers(-wmax, wmax + 1, size=(64, 64)).astype(np.int32),
+                b2=rng.integers(-bmax, bmax + 1, size=64).astype(np.int32),
+                w3=rng.integers(-wmax, wmax + 1, size=64).astype(np.int32))
+
+
+def feature_codes(seed: int, n: int) -> np.ndarray:
+    """Seeded rows of 16 input codes in 0..255 (first 10 random, rest zero)."""
+    rng = np.random.default_rng(seed)
+    x = np.zeros((n, 16), dtype=np.int32)
+    x[:, :10] = rng.integers(0, 256, size=(n, 10))
+    return x

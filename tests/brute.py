@@ -267,3 +267,48 @@ def random_tiny(rng, n, n_hedges, max_pins, wmax=5, node_wmax=1):
 
 def combos(n):
     return itertools.combinations(range(n), 2)
+
+
+# ---------------------------------------------------------------------------
+# learned merge proposal (extension; the definitions are those of the oracle
+# header), restated with explicit sets
+# ---------------------------------------------------------------------------
+def qlog_closed(f: int) -> int:
+    """8 floor(log2(f+1)) + floor(8 (v / 2^e - 1)), v = f+1, e = floor(log2 v), capped at 255."""
+    v = f + 1
+    e = v.bit_length() - 1
+    return min(255, 8 * e + ((v - (1 << e)) * 8) // (1 << e))
+
+
+def candidates(L: Lvl, omega, delta, K):
+    """topK(n) by (hist, id) among valid m, and the symmetric sets
+    C(n) = topK(n) u {m : n in topK(m)} as {m: (hist, c)}."""
+    top = []
+    for n in range(L.n):
+        In = L.I(n)
+        nbrs = set()
+        for e in In:
+            nbrs |= set(L.hedges[e])
+        nbrs.discard(n)
+        valid = []
+        for m in nbrs:
+            hist = sum(L.w[e] for e in In if m in L.hedges[e])
+            c = len(L.inb(n) & L.inb(m))
+            if L.size[n] + L.size[m] <= omega and len(L.inb(n) | L.inb(m)) <= delta:
+                valid.append((hist, m, c))
+        valid.sort(key=lambda t: (t[0], t[1]), reverse=True)
+        top.append(valid[:K])
+    C = [dict() for _ in range(L.n)]
+    for n in range(L.n):
+        for hist, m, c in top[n]:
+            C[n][m] = (hist, c)
+            C[m][n] = (hist, c)
+    return top, C
+
+
+def pair_features(L: Lvl, level, omega, delta, n, m, hist, c):
+    a, b = min(n, m), max(n, m)
+    uni = len(L.inb(a) | L.inb(b))
+    f = [hist, c, L.size[a], L.size[b], uni, len(L.I(a)), len(L.I(b)), level, omega - L.size[a] - L.size[b],
+         delta - uni]
+    return [qlog_closed(x) for x in f] + [0] * 6
