@@ -5,7 +5,10 @@ One step = one full hgp_partition_device call (coarsening + refinement +
 connectivity) on a device-resident synthetic spiking-network hypergraph.
 Prints one JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--workload rand64k]
+    python bench.py [--steps K] [--warmup W] [--workload rand64k] [--mlp CHECKPOINT]
+
+With --mlp the timed steps use the learned merge proposal; the plain method
+is then timed on the same input too and the line reports both connectivities.
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ COST = {
     "incidence": ("hbm", 8.0),
     "sort": ("hbm", 32.0),
     "match": ("hbm", 20.0),
+    "mlp": ("hbm", 52.0),
 }
 
 
@@ -61,6 +65,50 @@ def cpu_baseline(sample_n: int, mu: float, omega: int, delta: int):
                        f"{g.n_pins} pins, {res['n_levels']} levels, {dt:.1f} s")
 
 
+def bench_batch(args):
+    """256 random SNNs (node counts log-uniform in [2048, 32768], |T_v| ~
+    Poisson(mu)+1 with mu uniform in [32, 256], w in [1,16], seeds 4000+g),
+    partitioned as one batch; the schedule is tuned once before timing."""
+    import numpy as np
+    import torch
+
+    from paper_2604_14411_amd import hgp, synth
+
+    t = time.perf_counter()
+    gs = [synth.random_snn_family(4000 + i)[0] for i in range(256)]
+    pins = sum(g.n_pins for g in gs)
+    log(f"[bench] batch of {len(gs)} graphs, {pins} pins, generated in {time.perf_counter() - t:.1f} s")
+    ctx = hgp.Context(0)
+    dgs = [hgp.DeviceHypergraph(g, "cuda:0") for g in gs]
+    outs = [torch.empty(max(g.n_nodes, 1), dtype=torch.int32, device="cuda:0") for g in gs]
+    om, de = [1024] * len(gs), [4096] * len(gs)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sched, tune_ms = hgp.batch_tune(ctx, dgs, om, de, outs=outs)
+    log(f"[bench] tuned schedule {sched} ({tune_ms:.0f} ms per batch) in {time.perf_counter() - t:.1f} s")
+    lat, done = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, res, ts, te = hgp.partition_batch_device(ctx, dgs, om, de, outs=outs)
+        lat.append(te - ts)
+        done.append(te)
+        log(f"[bench] batch step {i}: {te.max():.0f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat = np.concatenate(lat)
+    done = np.concatenate(done)
+    line = dict(metric="pins/s (sum |e| per second), batch of independent partitions", value=pins * args.steps / elapsed,
+                unit="pins/s", n_gpus=1, steps=args.steps, warmup=0, ms_per_step=1e3 * elapsed / args.steps,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
+                config=dict(workload="batch256", graphs=len(gs), pins=pins, omega=1024, delta=4096,
+                            schedule=sched, conn_sum=int(sum(r["connectivity"] for r in res))),
+                latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                                completion_p50=float(np.percentile(done, 50)),
+                                completion_p99=float(np.percentile(done, 99))))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +117,7 @@ def main():
     ap.add_argument("--workload", default="rand64k")
     ap.add_argument("--cpu-sample-n", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mlp", default=None, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path",
@@ -80,6 +129,9 @@ def main():
     from paper_2604_14411_amd import hgp
     from paper_2604_14411_amd.synth.configs import WORKLOADS
 
+    if args.workload == "batch256":
+        return bench_batch(args)
+
     w = WORKLOADS[args.workload]
     g = w.make()
     log(f"[bench] workload {w.name}: {w.note}; n={g.n_nodes} pins={g.n_pins}")
@@ -87,20 +139,36 @@ def main():
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
-    for i in range(args.warmup):
-        t = time.perf_counter()
-        _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out)
-        log(f"[bench] warmup {i}: {time.perf_counter() - t:.3f} s levels={res['n_levels']} "
-            f"rounds={res['n_rounds']} parts={res['n_parts']} conn={res['connectivity']}")
-    results = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, flags=hgp.FLAG_TIME_KERNELS)
-        results.append(res)
-        log(f"[bench] step {i}: levels={res['n_levels']} rounds={res['n_rounds']} conn={res['connectivity']}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+
+    def run(mlp, tag):
+        for i in range(args.warmup):
+            t = time.perf_counter()
+            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, mlp=mlp)
+            log(f"[bench] {tag} warmup {i}: {time.perf_counter() - t:.3f} s levels={res['n_levels']} "
+                f"rounds={res['n_rounds']} parts={res['n_parts']} conn={res['connectivity']}")
+        results = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, flags=hgp.FLAG_TIME_KERNELS, mlp=mlp)
+            results.append(res)
+            log(f"[bench] {tag} step {i}: levels={res['n_levels']} rounds={res['n_rounds']} "
+                f"conn={res['connectivity']} fallback={res['n_fallback']}")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, results
+
+    plain_cmp = None
+    if args.mlp:
+        from paper_2604_14411_amd.learn import load_checkpoint
+
+        q, _, ck = load_checkpoint(args.mlp)
+        pel, pres = run(None, "plain")
+        plain_cmp = dict(value=g.n_pins * args.steps / pel, ms_per_step=1e3 * pel / args.steps,
+                         connectivity=pres[-1]["connectivity"], n_parts=pres[-1]["n_parts"],
+                         levels=pres[-1]["n_levels"])
+        elapsed, results = run(q, "learned")
+    else:
+        elapsed, results = run(None, "plain")
     ms_step = 1e3 * elapsed / args.steps
     value = g.n_pins * args.steps / elapsed
 
@@ -140,8 +208,14 @@ def main():
                 config=dict(workload=w.name, description=w.note, n_nodes=g.n_nodes, pins=g.n_pins,
                             sum_e_sq=g.sum_sq(), omega=w.omega, delta=w.delta, max_refine_rounds=8,
                             levels=results[-1]["n_levels"], rounds=results[-1]["n_rounds"],
-                            n_parts=results[-1]["n_parts"], connectivity=results[-1]["connectivity"]),
+                            n_parts=results[-1]["n_parts"], connectivity=results[-1]["connectivity"],
+                proposal="learned" if args.mlp else "plain"),
                 roofline=roof)
+    if plain_cmp:
+        line["learned_vs_plain"] = dict(plain=plain_cmp, learned_connectivity=results[-1]["connectivity"],
+                                        conn_ratio=results[-1]["connectivity"] / max(plain_cmp["connectivity"], 1),
+                                        speed_ratio=value / plain_cmp["value"],
+                                        n_fallback=results[-1]["n_fallback"], checkpoint=os.path.basename(args.mlp))
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline (oracle) on a reduced sample n={args.cpu_sample_n} ...")
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, 191.0 if w.name == "rand64k" else 127.0, w.omega,

@@ -65,6 +65,7 @@ typedef struct {
 } hgp_hypergraph;
 
 #define HGP_PLAIN 0
+#define HGP_LEARNED 1 /* learned merge proposal (hgp_options.mlp) */
 
 /* hgp_options.flags */
 #define HGP_FLAG_TIME_KERNELS 1   /* time kernel classes with HIP events on the call's stream */
@@ -80,15 +81,54 @@ typedef struct {
 #define HGP_K_SORT 6       /* move / event sorts; unit: key */
 #define HGP_K_MATCH 7      /* pseudo-forest matching; unit: node */
 #define HGP_K_RATE_TAIL 8  /* late-level rating with top-K lists; unit: pin-pair visit */
-#define HGP_NKERNEL 9
+#define HGP_K_MLP 9        /* learned proposal: candidate sets, features, network; unit: scored pair */
+#define HGP_NKERNEL 10
+
+/*
+ * Network of the learned merge proposal (an extension outside the paper's
+ * method; HGP_LEARNED).  At each coarsening level the rating of Eq. 2 keeps,
+ * per node n, its k best valid candidates by (hist, id) (k <= 8).  The sets
+ * are made symmetric, C(n) = topk(n) u {m : n in topk(m)}, every unordered pair
+ * {a < b} in them is scored, and pair(n) = the m in C(n) maximising
+ * (score, id).  Symmetric sets and scores keep the pairing graph free of
+ * cycles longer than two, which the matching of Sec. III-A relies on.
+ *
+ * Input codes of {a < b} (exact integers f, code = min(255, 8 e + t) with
+ * e = floor(log2(f+1)) and t the three bits of f+1 below its leading one):
+ *   hist(a,b), c(a,b) = |in(a) n in(b)|, size(a), size(b), |in(a) u in(b)|,
+ *   |I(a)|, |I(b)|, level, Omega - size(a) - size(b), Delta - |in(a) u in(b)|,
+ *   then six zero inputs.
+ * Network, integers throughout (rshift rounds half to even):
+ *   a1[j] = clamp(rshift(b1[j] + sum_f x[f] w1[f][j], r1), 0, 255)   j < 64
+ *   a2[j] = clamp(rshift(b2[j] + sum_i a1[i] w2[i][j], r2), 0, 255)
+ *   score = b3 + sum_j a2[j] w3[j]
+ * with |w| <= 255, |b| <= 2^22, 0 <= r <= 30.  Every partial sum stays below
+ * 2^24, so the library's BF16 MFMA evaluation with FP32 accumulation is exact.
+ * Fallback: the plain pairs (each node's first candidate) are matched too;
+ * a level whose learned matching merges fewer than half as many pairs uses
+ * the plain matching (counted in hgp_result.n_fallback).
+ */
+#define HGP_MLP_F 16
+#define HGP_MLP_H 64
+typedef struct {
+  int32_t k;  /* candidates per node, 1..8 */
+  int32_t r1, r2;
+  int32_t b3;
+  int32_t w1[HGP_MLP_F * HGP_MLP_H]; /* [f][j] */
+  int32_t b1[HGP_MLP_H];
+  int32_t w2[HGP_MLP_H * HGP_MLP_H]; /* [i][j] */
+  int32_t b2[HGP_MLP_H];
+  int32_t w3[HGP_MLP_H];
+} hgp_mlp;
 
 typedef struct {
   int32_t k;                 /* 0: coarsen to ceil(sum w / Omega) clusters (Sec. II-B); k > 0: to k */
   int32_t max_refine_rounds; /* refinement rounds per level (default 8); a level stops early
                                 once a round applies no move */
   uint64_t seed;             /* not used by the plain method (its result is seed-independent) */
-  int32_t proposal;          /* HGP_PLAIN */
+  int32_t proposal;          /* HGP_PLAIN or HGP_LEARNED */
   int32_t flags;             /* HGP_FLAG_* bits, 0 by default */
+  const hgp_mlp *mlp;        /* host memory; required with HGP_LEARNED, read during the call */
 } hgp_options;
 
 typedef struct {
@@ -96,7 +136,7 @@ typedef struct {
   int32_t n_parts;      /* parts are numbered 0 .. n_parts-1 */
   int32_t n_levels;     /* hypergraph levels built (1 + contractions) */
   int32_t n_rounds;     /* refinement rounds run, all levels */
-  int32_t pad;
+  int32_t n_fallback;   /* HGP_LEARNED: levels that used the plain matching */
   double ms_coarsen;    /* host wall-clock of the coarsening phase */
   double ms_refine;     /* host wall-clock of the refinement phase */
   /* with HGP_FLAG_TIME_KERNELS: summed kernel time, launches and algorithmic
@@ -217,6 +257,144 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
 int hgp_level_refine_round(hgp_ctx *ctx, const hgp_level *lv, const int32_t *rho, int32_t n_parts, int32_t omega,
                            int32_t delta, void *stream, int32_t *pdest, int64_t *pgain, int32_t *seq, int64_t *gsum,
                            int32_t *viol, int32_t *rho_out, int64_t *info);
+
+/*
+ * Learned proposal, one level (see hgp_mlp): the candidate sets, their input
+ * codes and scores, and the learned and plain pairs of level `level` (the
+ * level index enters the features).  mlp is host memory.  Device outputs,
+ * capacities as given (cap >= 16 * n_nodes always suffices):
+ *   coff [n+1]          offsets of each node's entries (ascending neighbour ids)
+ *   cand [cap]          neighbour id of each entry
+ *   xq   [cap * 16]     input codes of each entry (may be NULL)
+ *   cscore [cap]        network score of each entry (int64)
+ *   pair [n], score [n] learned pair (-1: none) and its score (0 if none)
+ *   ppair [n]           plain pair: the first candidate by (hist, id)
+ * *count (host) receives the number of entries; HGP_EINVAL if it exceeds cap.
+ */
+int hgp_level_learned(hgp_ctx *ctx, const hgp_level *lv, int32_t level, int32_t omega, int32_t delta,
+                      const hgp_mlp *mlp, void *stream, int64_t cap, int64_t *coff, int32_t *cand, int32_t *xq,
+                      int64_t *cscore, int32_t *pair, int64_t *score, int32_t *ppair, int64_t *count);
+
+/*
+ * The network of hgp_mlp on n rows of 16 input codes (device xq[n*16], each
+ * code 0..255; not checked), scores to device score[n].  Stream-ordered.
+ */
+int hgp_mlp_score_device(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score,
+                         void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent hypergraphs
+ * ------------------------------------------------------------------------- */
+
+#define HGP_ORDER_LPT 1        /* largest pin count first */
+#define HGP_ORDER_INPUT 2      /* the caller's order */
+#define HGP_LATE_INCREMENTAL 1 /* incremental late-level rating and proposal carry */
+#define HGP_LATE_FULL 2        /* every level and round from scratch */
+
+/* Schedule of a batch; every knob leaves each graph's result unchanged.
+ * Zero fields take the context's tuned value (hgp_batch_tune), else the
+ * default (4 workers, LPT, 512, incremental). */
+typedef struct {
+  int32_t workers;     /* concurrent streams, each with its own workspace: 1..16 */
+  int32_t order;       /* HGP_ORDER_* */
+  int32_t rate_tile;   /* workgroup size of the rating kernel: 256 or 512 */
+  int32_t late_levels; /* HGP_LATE_* */
+} hgp_batch_sched;
+
+/*
+ * Partitions n_graphs independent hypergraphs held in device memory
+ * (graphs[i] as for hgp_partition_device, with its own omega[i], delta[i]).
+ * part_out[i] (device, [graphs[i].n_nodes]) receives graph i's part ids,
+ * identical to a single hgp_partition_device call on it.  res (host,
+ * [n_graphs]) and t_start_ms / t_end_ms (host, [n_graphs]: wall-clock ms from
+ * the batch start to graph i's start and completion) may be NULL.  `stream`
+ * is synchronised before the batch starts; the call returns when every graph
+ * is done.  The first failing graph's error is returned.
+ */
+int hgp_partition_batch_device(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs, const int32_t *omega,
+                               const int32_t *delta, const hgp_options *opt, const hgp_batch_sched *sched,
+                               void *stream, int32_t *const *part_out, hgp_result *res, double *t_start_ms,
+                               double *t_end_ms);
+
+/*
+ * Autotuner: runs the batch under candidate schedules (coordinate search over
+ * workers 1/2/4/8, then order, rating tile and late-level schedule), keeps the
+ * fastest in the context for later batches and returns it in *best (and its
+ * wall time in *best_ms); both may be NULL.  part_out receives valid results.
+ */
+int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs, const int32_t *omega,
+                   const int32_t *delta, const hgp_options *opt, void *stream, int32_t *const *part_out,
+                   hgp_batch_sched *best, double *best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Training the learned proposal's network (hand-written GPU kernels)
+ * ------------------------------------------------------------------------- */
+
+/* Float model with the shape of hgp_mlp: inputs x[f] = code[f] / 8,
+ * h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), z = h2 . w3 + b3. */
+typedef struct {
+  float w1[HGP_MLP_F * HGP_MLP_H]; /* [f][j] */
+  float b1[HGP_MLP_H];
+  float w2[HGP_MLP_H * HGP_MLP_H]; /* [i][j] */
+  float b2[HGP_MLP_H];
+  float w3[HGP_MLP_H];
+  float b3;
+} hgp_mlp_f32;
+
+typedef struct {
+  int32_t epochs;  /* passes over the rows */
+  int32_t batch;   /* rows per Adam step */
+  float lr, beta1, beta2, eps;
+  uint64_t seed;   /* shuffle order */
+} hgp_train_opts;
+
+/* Seeded initial weights (uniform, scaled by fan-in; unused inputs 10..15 zero). */
+void hgp_mlp_init(hgp_mlp_f32 *w, uint64_t seed);
+
+/*
+ * Mean binary cross-entropy on logits, (1/n) sum softplus(z) - y z, and its
+ * gradient over n device rows: xq [n*16] codes, y [n] labels in {0, 1}.
+ * w, grad and loss are host memory.  Synchronous.
+ */
+int hgp_mlp_grad(hgp_ctx *ctx, const hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n,
+                 hgp_mlp_f32 *grad, double *loss, void *stream);
+
+/*
+ * Adam on minibatches of the rows in a seeded shuffled order; w (host) holds
+ * the initial weights and receives the trained ones; loss_epochs (host,
+ * [opt->epochs], may be NULL) the mean loss of each epoch.  Deterministic for
+ * a given seed.  Synchronous.
+ */
+int hgp_mlp_train(hgp_ctx *ctx, hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n,
+                  const hgp_train_opts *opt, float *loss_epochs, void *stream);
+
+/*
+ * Integer network from float weights: power-of-two scales per layer chosen
+ * from the largest weight and from the largest activations on n host
+ * calibration rows xq [n*16].  score ~ z * 2^score_shift.  k: candidates per
+ * node (1..8).
+ */
+int hgp_mlp_quantize(const hgp_mlp_f32 *w, const int32_t *xq, int64_t n, int32_t k, hgp_mlp *out,
+                     int32_t *score_shift);
+
+/*
+ * Merge traces of the plain method.  hgp_partition_traced runs the plain
+ * partitioner (host arrays, like hgp_partition) and records, at every
+ * coarsening level, each unordered candidate pair {n < m} of the symmetric
+ * 8-best candidate sets (see hgp_mlp) with its 16 input codes; after the run
+ * each pair is labelled 1 if the smallest level-0 members of n and of m end
+ * in the same part, else 0.  The partition is the plain method's.
+ */
+typedef struct hgp_trace hgp_trace;
+int hgp_trace_create(hgp_trace **t);
+void hgp_trace_destroy(hgp_trace *t);
+int hgp_partition_traced(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta,
+                         const hgp_options *opt, hgp_trace *t, int32_t *part_out, hgp_result *res);
+/* Rows recorded (-1 if t is NULL). */
+int64_t hgp_trace_rows(const hgp_trace *t);
+/* Copies the rows out (host arrays; any may be NULL): xq [rows*16], label
+ * [rows], level [rows], node [rows] and cand [rows] (n < m). */
+int hgp_trace_read(const hgp_trace *t, int32_t *xq, float *label, int32_t *level, int32_t *node, int32_t *cand);
 
 #ifdef __cplusplus
 }

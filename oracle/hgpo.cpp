@@ -385,6 +385,29 @@ void symmetric_candidates(const std::vector<std::vector<Cand>> &top, std::vector
   }
 }
 
+/* Plain runs with a tracer also record the symmetric 8-best candidate sets
+ * and their input codes (the rows a learned network is trained on). */
+void record_candidates(const Level &L, int32_t level, const std::vector<int32_t> &w, int64_t omega, int64_t delta,
+                       hgpo_trace *trace) {
+  std::vector<std::vector<Cand>> top, cand;
+  rate_topk(L, w, omega, delta, 8, top);
+  symmetric_candidates(top, cand);
+  std::vector<int64_t> coff((size_t)L.n + 1, 0);
+  std::vector<int32_t> cid, feat;
+  int32_t x[HGPO_MLP_F];
+  for (int32_t n = 0; n < L.n; ++n) {
+    for (const Cand &cd : cand[n]) {
+      cid.push_back(cd.m);
+      pair_codes(L, level, omega, delta, n, cd, x);
+      feat.insert(feat.end(), x, x + HGPO_MLP_F);
+    }
+    coff[(size_t)n + 1] = (int64_t)cid.size();
+  }
+  trace->put64(HGPO_LV_COFF, level, coff);
+  trace->put32(HGPO_LV_CAND, level, cid);
+  trace->put32(HGPO_LV_FEAT, level, feat);
+}
+
 /* One coarsening level with the learned proposal: top-K rating, symmetric
  * candidate sets, network scores, pair(n) = argmax (score, id) over C(n),
  * the matching of Sec. III-A on those pairs, and the plain fallback. */
@@ -868,6 +891,7 @@ static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta
       if (!mlp) {
         rate_select(L, w, omega, delta, pair, score);
         match_pairs(pair, score, match);
+        if (trace) record_candidates(L, l, w, omega, delta, trace);
       } else {
         learned_level(L, l, w, omega, delta, *mlp, pair, score, match, n_fallback, trace);
       }

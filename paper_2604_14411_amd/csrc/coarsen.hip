@@ -82,14 +82,22 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
 // (node, hedge|dst) pairs in hedge order, then a stable radix sort by node:
 // every I(n) comes out ascending by hedge id, with no contended atomics.
 __global__ void k_expand(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
-                         uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+                         uint32_t *__restrict__ key, uint32_t *__restrict__ pos, uint32_t *__restrict__ he) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= E) return;
   for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
     const uint32_t x = hpin[j];
     key[j] = x & kIdMask;
-    val[j] = (uint32_t)wid | (x & kDst);
+    pos[j] = (uint32_t)j;
+    he[j] = (uint32_t)wid | (x & kDst);
   }
+}
+
+// inc[k] = (hedge | dst) of the pin at position perm[k]
+__global__ void k_gather_inc(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ he, int64_t P,
+                             uint32_t *__restrict__ inc) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < P) inc[k] = he[perm[k]];
 }
 
 // ioff[v] = first position of node v in the sorted keys (P if none after).
@@ -406,13 +414,15 @@ static int bits_of(int64_t x) {
 }
 
 void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
-                     int32_t *ioff, uint32_t *inc, int32_t *indeg, int32_t *total, uint32_t *tkey,
-                     uint32_t *tkey2, uint32_t *tval2, DevBuf &sort_tmp, hipStream_t s) {
+                     int32_t *ioff, uint32_t *inc, uint32_t *perm, int32_t *indeg, int32_t *total, uint32_t *tkey,
+                     uint32_t *tkey2, uint32_t *tval2, uint32_t *he, DevBuf &sort_tmp, hipStream_t s) {
   KScope ks(5, s);
   if (E > 0 && P > 0) {
-    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, inc);
+    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, perm, he);
     HGP_LAUNCH_CHECK();
-    radix_sort_u32(tkey, tkey2, inc, tval2, P, bits_of(N > 0 ? N - 1 : 0), sort_tmp, s);
+    radix_sort_u32(tkey, tkey2, perm, tval2, P, bits_of(N > 0 ? N - 1 : 0), sort_tmp, s);
+    k_gather_inc<<<div_up(P, 256), 256, 0, s>>>(perm, he, P, inc);
+    HGP_LAUNCH_CHECK();
   }
   k_offsets_from_sorted<<<div_up(P + 1, 256), 256, 0, s>>>(tkey, P, N, ioff);
   HGP_LAUNCH_CHECK();
@@ -432,24 +442,33 @@ void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32
 constexpr int RATE_NT = 512;
 constexpr int RATE_LDS_BYTES = 128 * 1024;
 
+template <int NT>
+static void launch_rate_nt(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
+                           int64_t *score, int words, hipStream_t s) {
+  // thread-safe one-time opt-in to the large dynamic LDS size
+  static const bool attr_set = [] {
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                RATE_LDS_BYTES));
+    return true;
+  }();
+  (void)attr_set;
+  k_rate<NT><<<L.n, NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
+                                                omega, delta, words, pair, score, units_ptr(0));
+  HGP_LAUNCH_CHECK();
+}
+
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
-                 int64_t *score, hipStream_t s) {
+                 int64_t *score, hipStream_t s, int tile) {
   if (L.n <= 0) return;
   // dense window: whole id range if it fits, else RATE_LDS_BYTES of counters
   const int max_words = RATE_LDS_BYTES / 4;
   int words = L.n <= max_words / 2 ? 2 * L.n : max_words;
   words = (words + 1) & ~1;
-  const size_t bytes = (size_t)words * 4;
-  static bool attr_set = false;
-  if (!attr_set) {
-    HGP_HIP(hipFuncSetAttribute((const void *)k_rate<RATE_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                RATE_LDS_BYTES));
-    attr_set = true;
-  }
   KScope ks(0, s);
-  k_rate<RATE_NT><<<L.n, RATE_NT, bytes, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
-                                              omega, delta, words, pair, score, units_ptr(0));
-  HGP_LAUNCH_CHECK();
+  if (tile == 256)
+    launch_rate_nt<256>(L, total, omega, delta, pair, score, words, s);
+  else
+    launch_rate_nt<RATE_NT>(L, total, omega, delta, pair, score, words, s);
 }
 
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,

@@ -29,7 +29,8 @@ struct LevelView {
   const int32_t *hoff = nullptr;   // [E+1]
   const uint32_t *hpin = nullptr;  // [P] id | dst << 31, ascending ids per hedge
   const int32_t *ioff = nullptr;   // [n+1]
-  const uint32_t *inc = nullptr;   // [P] hedge | dst << 31 (any order within a node)
+  const uint32_t *inc = nullptr;   // [P] hedge | dst << 31, ascending hedge ids within a node
+  const uint32_t *perm = nullptr;  // [P] pin position of incidence k
   const int32_t *size = nullptr;   // [n]
   const int32_t *indeg = nullptr;  // [n]
   const int32_t *hw = nullptr;     // [E]
@@ -42,15 +43,16 @@ void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32
                           unsigned long long *sums, hipStream_t s);
 void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
                   uint32_t *hpin, hipStream_t s);
-// Incidence I(n) (ascending hedge ids, destination flag in bit 31), |in(n)|
-// and total(n) of a level; tkey/tkey2/tval2 are P-element scratch.
+// Incidence I(n) (ascending hedge ids, destination flag in bit 31), the pin
+// position perm[k] of every incidence k, |in(n)| and total(n) of a level;
+// tkey/tkey2/tval2/he are P-element scratch.
 void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
-                     int32_t *ioff, uint32_t *inc, int32_t *indeg, int32_t *total, uint32_t *tkey,
-                     uint32_t *tkey2, uint32_t *tval2, DevBuf &sort_tmp, hipStream_t s);
+                     int32_t *ioff, uint32_t *inc, uint32_t *perm, int32_t *indeg, int32_t *total, uint32_t *tkey,
+                     uint32_t *tkey2, uint32_t *tval2, uint32_t *he, DevBuf &sort_tmp, hipStream_t s);
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
                      int32_t *err, hipStream_t s);
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
-                 int64_t *score, hipStream_t s);
+                 int64_t *score, hipStream_t s, int tile = 512);
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,
                   int32_t *match, int32_t *gamma, int32_t *rep, int32_t *n_next_dev, int32_t *err,
                   DevBuf &scan_tmp, hipStream_t s);
@@ -71,6 +73,26 @@ void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, in
                         hipStream_t s);
 
 
+// device scalars of a refinement round (RoundBufs::scal)
+enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4, SC_HEAVY = 5 };
+
+// (pins, pins_in) of part p in the sorted part table pt[b .. b+len) of a hedge.
+__device__ __forceinline__ int2 pt_lookup(const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, int b,
+                                          int len, int p) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pt[b + mid].x < p) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < len && pt[b + lo].x == p) return make_int2(pt[b + lo].y, ptin[b + lo]);
+  return make_int2(0, 0);
+}
+
+int bits_for(int64_t x);  // smallest b with 2^b > x
+// ascending sort of n 64-bit keys over their low `bits` bits
+void sort_keys(uint64_t *keys, uint64_t *alt, int64_t n, int bits, DevBuf &sort_tmp, hipStream_t s);
+
 // --- refine.hip ---
 struct RoundBufs {
   // part table (oversized: one slot per pin, at the hedge's pin offset)
@@ -88,11 +110,14 @@ struct RoundBufs {
   uint64_t *keys2 = nullptr;   // [cap_events]
   int32_t *gp = nullptr;       // [n+1] in-sequence gain per position
   int32_t *vdelta = nullptr;   // [n+1] violation deltas per position
-  int32_t *pcnt = nullptr;     // [n_parts+1] events per part -> offsets
   int64_t *G = nullptr;        // [n+1]
   int32_t *viol = nullptr;     // [n+1]
   int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, init_invalid, heavy count
-  int32_t *heavy = nullptr;    // [E] hedges queued for the large-LDS event kernel
+  int32_t *heavy = nullptr;    // [E] hedges queued for the workgroup event kernel
+  int2 *contrib = nullptr;     // [P] per moving pin: in-sequence gain terms (source, destination role)
+  int64_t *esum = nullptr;     // [cap_events + 1] prefix sums of size deltas over sorted events
+  int32_t *isum = nullptr;     // [cap_events + 1] prefix sums of inbound deltas over sorted events
+  int64_t *poff = nullptr;     // [n_parts + 1] first sorted event of every part
   int64_t cap_events = 0;
 };
 

@@ -262,7 +262,7 @@ __host__ __device__ inline int next_pow2(int x) {
 // ---------------------------------------------------------------------------
 // Optional per-kernel-class timing with HIP events (enabled per call).
 // ---------------------------------------------------------------------------
-constexpr int kNKClass = 9;
+constexpr int kNKClass = 10;
 struct KTimer {
   bool on = false;
   std::vector<hipEvent_t> pool;

@@ -3,10 +3,16 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <atomic>
 #include <memory>
+#include <mutex>
+#include <numeric>
+#include <thread>
 
 #include "../../include/hgp.h"
 #include "coarsen.hpp"
+#include "learned.hpp"
 #include "tail.hpp"
 
 namespace hgp {
@@ -25,10 +31,11 @@ static bool log_on() {
 struct Workspace {
   DevBuf err, sums, scal2;
   DevBuf hpin0, hoffA, hoffB, hpinA, hpinB, hoffR, hpinR, tmp_pins, cnt;
-  DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2;
+  DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2, perm, pin_he;
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
-  DevBuf heavy, pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, pcnt, G, viol, scal;
+  DevBuf heavy, pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
+  DevBuf contrib, esum, isum, poff;
   DevBuf scan_tmp, sort_tmp;
   DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
   DevBuf ones_e, ones_n;
@@ -39,6 +46,12 @@ struct Workspace {
   // incremental late levels
   DevBuf tkA_key, tkA_cnt, tkA_kap, tkB_key, tkB_cnt, tkB_kap, rows, newc, row_slot, nflag, rerate, dev_cnt;
   DevBuf split, cdest, cgain, maxbits, biglist;
+  // learned proposal
+  hgp_trace *trace = nullptr;  // set for the duration of a traced run
+  int rate_tile = 512;         // rating workgroup size (schedule knob; same result)
+  DevBuf tr_xq, tr_prm, tr_mom, tr_part, tr_perm, tr_loss, tr_grad;
+  DevBuf mlp, ck, cc, ccnt, coff32, ctot, ckey, ckey2, cval, cval2, cflag, cnm, csrc, cs, ccoff, ppair, pscore,
+      pmatch, pgam;
   std::vector<DevBuf> lv_match;
 
   void clear_levels() {
@@ -55,15 +68,15 @@ struct Workspace {
 
   void release_all() {
     DevBuf *all[] = {&err,  &sums,  &scal2,  &hpin0,  &hoffA,    &hoffB,  &hpinA,  &hpinB,   &hoffR,   &hpinR,
-                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2,   &pair,    &score,   &best,
+                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2, &perm, &pin_he,   &pair,    &score,   &best,
                      &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptin,    &lam, &heavy,
                      &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
-                     &vdelta, &pcnt, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
+                     &vdelta, &contrib, &esum, &isum, &poff, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     clear_levels();
@@ -72,10 +85,25 @@ struct Workspace {
 
 }  // namespace hgp
 
+// Merge trace of one plain run (see hgp_partition_traced).
+struct hgp_trace {
+  std::vector<int32_t> xq, level, node, cand;
+  std::vector<float> label;
+  std::vector<std::vector<int32_t>> gammas;  // per level, filled during the run
+};
+
 struct hgp_ctx {
   int device = 0;
   hgp::Workspace ws;
-  ~hgp_ctx() { ws.release_all(); }
+  // batch workers: one workspace and one stream each
+  std::vector<std::unique_ptr<hgp::Workspace>> pool;
+  std::vector<hipStream_t> pool_streams;
+  hgp_batch_sched tuned{};  // zero until hgp_batch_tune ran
+  ~hgp_ctx() {
+    ws.release_all();
+    for (auto &w : pool) w->release_all();
+    for (hipStream_t st : pool_streams) (void)hipStreamDestroy(st);
+  }
 };
 
 namespace hgp {
@@ -211,7 +239,9 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   uint32_t *tkey = need<uint32_t>(W.tkey, P);
   uint32_t *tkey2 = need<uint32_t>(W.tkey2, P);
   uint32_t *tval2 = need<uint32_t>(W.tval2, P);
-  build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, indeg, total, tkey, tkey2, tval2, W.sort_tmp, s);
+  uint32_t *perm = need<uint32_t>(W.perm, P);
+  uint32_t *he = need<uint32_t>(W.pin_he, P);
+  build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, perm, indeg, total, tkey, tkey2, tval2, he, W.sort_tmp, s);
   add_units(HGP_K_INCIDENCE, P);
   LevelView L;
   L.n = n;
@@ -220,6 +250,7 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   L.hpin = hpin;
   L.ioff = ioff;
   L.inc = inc;
+  L.perm = perm;
   L.size = size;
   L.indeg = indeg;
   L.hw = hw;
@@ -244,7 +275,10 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.keys2 = need<uint64_t>(W.keys2, B.cap_events);
   B.gp = need<int32_t>(W.gp, (int64_t)n + 1);
   B.vdelta = need<int32_t>(W.vdelta, (int64_t)n + 1);
-  B.pcnt = need<int32_t>(W.pcnt, (int64_t)n_parts + 1);
+  B.contrib = need<int2>(W.contrib, P);
+  B.esum = need<int64_t>(W.esum, B.cap_events + 1);
+  B.isum = need<int32_t>(W.isum, B.cap_events + 1);
+  B.poff = need<int64_t>(W.poff, (int64_t)n_parts + 1);
   B.G = need<int64_t>(W.G, (int64_t)n + 1);
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);
   B.scal = need<int64_t>(W.scal, 8);
@@ -305,7 +339,7 @@ static int topk_words_per_id(Workspace &W, const LevelView &L, hipStream_t s) {
 
 struct RunStats {
   int64_t conn = 0;
-  int32_t n_parts = 0, n_levels = 0, n_rounds = 0;
+  int32_t n_parts = 0, n_levels = 0, n_rounds = 0, n_fallback = 0;
   double ms_coarsen = 0, ms_refine = 0;
   double ms_kernel[HGP_NKERNEL] = {};
   int64_t n_kernel[HGP_NKERNEL] = {};
@@ -341,6 +375,81 @@ struct TimerGuard {
   }
 };
 
+// Learned-level buffers for n nodes; pair/score are the caller's arrays.
+static CandBufs cand_bufs(Workspace &W, int32_t n, int32_t *pair, int64_t *score) {
+  CandBufs B;
+  const int64_t nk = (int64_t)n * kCandK, m = 2 * nk;
+  B.ck = need<uint64_t>(W.ck, nk);
+  B.cc = need<int32_t>(W.cc, nk);
+  B.ccnt = need<int32_t>(W.ccnt, n);
+  B.coff32 = need<int32_t>(W.coff32, n);
+  B.tot32 = need<int32_t>(W.ctot, 4);
+  B.key = need<uint64_t>(W.ckey, m);
+  B.key2 = need<uint64_t>(W.ckey2, m);
+  B.val = need<uint32_t>(W.cval, m);
+  B.val2 = need<uint32_t>(W.cval2, m);
+  B.flag = need<int32_t>(W.cflag, m);
+  B.cnm = need<uint64_t>(W.cnm, m);
+  B.csrc = need<uint32_t>(W.csrc, m);
+  B.cs = need<int32_t>(W.cs, m);
+  B.coff = need<int64_t>(W.ccoff, (int64_t)n + 1);
+  B.pair = pair;
+  B.score = score;
+  B.ppair = need<int32_t>(W.ppair, n);
+  B.pscore = need<int64_t>(W.pscore, n);
+  return B;
+}
+
+// Records the unordered candidate pairs {n < m} of level `lvl` and their codes.
+static void trace_level(Workspace &W, const LevelView &L, int lvl, int32_t omega, int32_t delta, int32_t *pair,
+                        int64_t *score, hipStream_t s) {
+  const int32_t n = L.n;
+  if (n <= 0) return;
+  CandBufs CB = cand_bufs(W, n, pair, score);
+  const int64_t C = build_candidates(L, W.total.as<int32_t>(), omega, delta, kCandK, CB, W.scan_tmp, W.sort_tmp, s);
+  if (C <= 0) return;
+  int32_t *xq = need<int32_t>(W.tr_xq, C * kMlpF);
+  launch_cand_codes(L, omega, delta, lvl, CB, C, xq, s);
+  std::vector<uint64_t> nm((size_t)C);
+  std::vector<int32_t> codes((size_t)C * kMlpF);
+  HGP_HIP(hipMemcpyAsync(nm.data(), CB.cnm, sizeof(uint64_t) * (size_t)C, hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(codes.data(), xq, sizeof(int32_t) * (size_t)C * kMlpF, hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  const int idbits = std::max(1, bits_for(n - 1));
+  const uint64_t mask = (1ull << idbits) - 1ull;
+  hgp_trace &T = *W.trace;
+  for (int64_t i = 0; i < C; ++i) {
+    const int32_t a = (int32_t)(nm[(size_t)i] >> idbits), b = (int32_t)(nm[(size_t)i] & mask);
+    if (a >= b) continue;
+    T.node.push_back(a);
+    T.cand.push_back(b);
+    T.level.push_back(lvl);
+    T.xq.insert(T.xq.end(), codes.begin() + i * kMlpF, codes.begin() + (i + 1) * kMlpF);
+  }
+}
+
+// Labels of the recorded pairs from the cluster maps and the final parts.
+static void trace_label(hgp_trace &T, int32_t N, const int32_t *part) {
+  std::vector<std::vector<int32_t>> rep(1);
+  rep[0].resize((size_t)N);
+  for (int32_t v = 0; v < N; ++v) rep[0][(size_t)v] = v;
+  int maxl = 0;
+  for (int32_t l : T.level) maxl = std::max(maxl, l);
+  for (int l = 0; l < maxl; ++l) {
+    const std::vector<int32_t> &g = T.gammas.at((size_t)l);
+    int32_t nn = 0;
+    for (int32_t c : g) nn = std::max(nn, c + 1);
+    std::vector<int32_t> r((size_t)nn, INT32_MAX);
+    for (size_t v = 0; v < g.size(); ++v) r[(size_t)g[v]] = std::min(r[(size_t)g[v]], rep[(size_t)l][v]);
+    rep.push_back(std::move(r));
+  }
+  T.label.resize(T.node.size());
+  for (size_t i = 0; i < T.node.size(); ++i) {
+    const std::vector<int32_t> &r = rep[(size_t)T.level[i]];
+    T.label[i] = part[r[(size_t)T.node[i]]] == part[r[(size_t)T.cand[i]]] ? 1.0f : 0.0f;
+  }
+}
+
 static double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -356,6 +465,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
                               const hgp_options &opt, hipStream_t s, int32_t *part_out) {
   RunStats st;
   if (opt.k < 0 || opt.max_refine_rounds < 0) throw Error(HGP_EINVAL, "k < 0 or max_refine_rounds < 0");
+  if (opt.proposal != HGP_PLAIN && opt.proposal != HGP_LEARNED) throw Error(HGP_EINVAL, "unknown proposal");
+  const bool learned = opt.proposal == HGP_LEARNED;
+  if (learned) check_mlp(opt.mlp);
   const double t0 = now_ms();
   Ingest I = ingest(W, g, omega, delta, s);
   const int32_t N = g->n_nodes, E = g->n_hedges;
@@ -363,6 +475,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const int32_t *hoff0 = g->hedge_off;
   const uint32_t *hpin0 = I.hpin0;
   const int32_t *hw = I.hw;
+  const int32_t *mlp_params = learned ? upload_mlp(W.mlp, opt.mlp, s) : nullptr;
   W.clear_levels();
   W.lv_size.emplace_back();
   W.lv_n.push_back(N);
@@ -401,7 +514,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   // Late levels that merge few pairs are rated incrementally (tail.hip):
   // lists of the exact top candidates per node are carried between levels,
   // new clusters are rated in full and offered to their neighbours.
-  const bool incremental = (opt.flags & HGP_FLAG_NO_INCREMENTAL) == 0;
+  const bool incremental = (opt.flags & HGP_FLAG_NO_INCREMENTAL) == 0 && !learned;
   int32_t n_parts = 0;
   int lvl = 0;
   const int32_t *cur_hoff = hoff0;
@@ -429,24 +542,53 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     if (!have_pairs) {
       path = "plain";
       const int wpi = (incremental && tail) ? topk_words_per_id(W, L, s) : 0;
-      if (wpi > 0) {
+      if (learned) {
+        path = "learned";
+        CandBufs CB = cand_bufs(W, n, pair, score);
+        learned_candidates(L, W.total.as<int32_t>(), omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
+                           W.sort_tmp, s);
+        lists_ok = false;
+      } else if (wpi > 0) {
         path = "topk";
         launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, nullptr, nullptr, pair, score,
                          tk_cur, wpi, W.err.as<int32_t>(), s);
         lists_ok = true;
       } else {
-        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s);
+        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s, W.rate_tile);
         lists_ok = false;
       }
     }
     have_pairs = false;
+    if (W.trace) trace_level(W, L, lvl, omega, delta, pair, score, s);
     W.lv_gamma.emplace_back();
     W.lv_match.emplace_back();
     int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
     int32_t *lmatch = need<int32_t>(W.lv_match[lvl], n);
     launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
-    const int32_t n_next = read_i32(nnext_dev, s);
+    int32_t n_next = read_i32(nnext_dev, s);
     check_err(W, s);
+    if (learned) {
+      // fallback: the plain pairs' matching, used if it merges over twice as many pairs
+      int32_t *pm = need<int32_t>(W.pmatch, n);
+      int32_t *pg = need<int32_t>(W.pgam, n);
+      launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
+                   W.err.as<int32_t>(), W.scan_tmp, s);
+      const int32_t n_next_p = read_i32(nnext_dev + 1, s);
+      check_err(W, s);
+      if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
+        HGP_HIP(hipMemcpyAsync(lmatch, pm, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        HGP_HIP(hipMemcpyAsync(gam, pg, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        n_next = n_next_p;
+        ++st.n_fallback;
+        path = "learned, plain fallback";
+      }
+    }
+    if (W.trace) {
+      W.trace->gammas.emplace_back((size_t)n);
+      HGP_HIP(hipMemcpyAsync(W.trace->gammas.back().data(), gam, sizeof(int32_t) * (size_t)n,
+                             hipMemcpyDeviceToHost, s));
+      HGP_HIP(hipStreamSynchronize(s));
+    }
     if (log_on())
       fprintf(stderr, "[hgp] level %d n=%d pins=%lld merged=%d rating=%s\n", lvl, n, (long long)cur_P, n - n_next,
               path);
@@ -657,6 +799,7 @@ static void fill_result(hgp_result *res, const RunStats &st) {
   res->n_parts = st.n_parts;
   res->n_levels = st.n_levels;
   res->n_rounds = st.n_rounds;
+  res->n_fallback = st.n_fallback;
   res->ms_coarsen = st.ms_coarsen;
   res->ms_refine = st.ms_refine;
   for (int c = 0; c < HGP_NKERNEL; ++c) {
@@ -761,8 +904,8 @@ int hgp_partition_device(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, i
   });
 }
 
-int hgp_partition(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta, const hgp_options *opt,
-                  int32_t *part_out, hgp_result *res) {
+static int partition_host_impl(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta,
+                               const hgp_options *opt, int32_t *part_out, hgp_result *res, hgp_trace *trace) {
   if (!ctx) {
     g_last_error = "ctx is NULL";
     return HGP_EINVAL;
@@ -805,14 +948,111 @@ int hgp_partition(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t 
     }
     int32_t *po = need<int32_t>(W.in_part, N);
     const hgp_options o = opts_or_default(opt);
+    if (trace && o.proposal != HGP_PLAIN) throw Error(HGP_EINVAL, "traces record the plain method");
     TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+    struct TraceGuard {
+      Workspace &W;
+      ~TraceGuard() { W.trace = nullptr; }
+    } trg{W};
+    if (trace) *trace = hgp_trace();
+    W.trace = trace;
     RunStats st = run_partition(W, &d, omega, delta, o, s, po);
+    W.trace = nullptr;
     tg.collect(st, s);
     if (N > 0) HGP_HIP(hipMemcpyAsync(part_out, po, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToHost, s));
     HGP_HIP(hipStreamSynchronize(s));
+    if (trace) trace_label(*trace, N, part_out);
     fill_result(res, st);
   });
 }
+
+int hgp_partition(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta, const hgp_options *opt,
+                  int32_t *part_out, hgp_result *res) {
+  return partition_host_impl(ctx, g, omega, delta, opt, part_out, res, nullptr);
+}
+
+int hgp_partition_traced(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta,
+                         const hgp_options *opt, hgp_trace *t, int32_t *part_out, hgp_result *res) {
+  if (!t) {
+    g_last_error = "trace is NULL";
+    return HGP_EINVAL;
+  }
+  return partition_host_impl(ctx, g, omega, delta, opt, part_out, res, t);
+}
+
+int hgp_trace_create(hgp_trace **t) {
+  if (!t) {
+    g_last_error = "t is NULL";
+    return HGP_EINVAL;
+  }
+  *t = new (std::nothrow) hgp_trace();
+  return *t ? HGP_OK : HGP_ENOMEM;
+}
+
+void hgp_trace_destroy(hgp_trace *t) { delete t; }
+
+int64_t hgp_trace_rows(const hgp_trace *t) { return t ? (int64_t)t->node.size() : -1; }
+
+int hgp_trace_read(const hgp_trace *t, int32_t *xq, float *label, int32_t *level, int32_t *node, int32_t *cand) {
+  if (!t) {
+    g_last_error = "t is NULL";
+    return HGP_EINVAL;
+  }
+  const size_t r = t->node.size();
+  if (xq && r) std::memcpy(xq, t->xq.data(), sizeof(int32_t) * r * kMlpF);
+  if (label && r) std::memcpy(label, t->label.data(), sizeof(float) * r);
+  if (level && r) std::memcpy(level, t->level.data(), sizeof(int32_t) * r);
+  if (node && r) std::memcpy(node, t->node.data(), sizeof(int32_t) * r);
+  if (cand && r) std::memcpy(cand, t->cand.data(), sizeof(int32_t) * r);
+  return HGP_OK;
+}
+
+void hgp_mlp_init(hgp_mlp_f32 *w, uint64_t seed) {
+  if (w) mlp_init(w, seed);
+}
+
+int hgp_mlp_grad(hgp_ctx *ctx, const hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n,
+                 hgp_mlp_f32 *grad, double *loss, void *stream) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    if (!w || !grad || !loss || n < 1 || !xq || !y) throw Error(HGP_EINVAL, "bad arguments");
+    Workspace &W = ctx->ws;
+    mlp_grad(w, xq, y, n, W.tr_prm, W.tr_part, W.tr_grad, W.tr_loss, grad, loss, static_cast<hipStream_t>(stream));
+  });
+}
+
+int hgp_mlp_train(hgp_ctx *ctx, hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n,
+                  const hgp_train_opts *opt, float *loss_epochs, void *stream) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    if (!w || !opt || n < 1 || !xq || !y) throw Error(HGP_EINVAL, "bad arguments");
+    if (opt->epochs < 0 || opt->batch < 1 || !(opt->lr > 0) || !(opt->eps > 0)) throw Error(HGP_EINVAL, "bad options");
+    Workspace &W = ctx->ws;
+    mlp_train(w, xq, y, n, *opt, W.tr_prm, W.tr_mom, W.tr_part, W.tr_perm, W.tr_loss, loss_epochs,
+              static_cast<hipStream_t>(stream));
+  });
+}
+
+int hgp_mlp_quantize(const hgp_mlp_f32 *w, const int32_t *xq, int64_t n, int32_t k, hgp_mlp *out,
+                     int32_t *score_shift) {
+  return guarded([&] {
+    if (!w || !out || n < 0 || (n > 0 && !xq)) throw Error(HGP_EINVAL, "bad arguments");
+    if (k < 1 || k > kCandK) throw Error(HGP_EINVAL, "k outside 1..8");
+    for (int64_t i = 0; i < n * kMlpF; ++i)
+      if (xq[i] < 0 || xq[i] > 255) throw Error(HGP_EINVAL, "code outside 0..255");
+    mlp_quantize(w, xq, n, k, out, score_shift);
+    check_mlp(out);
+  });
+}
+
 
 int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, void *stream,
                             int64_t *out) {
@@ -990,6 +1230,261 @@ int hgp_level_refine_round(hgp_ctx *ctx, const hgp_level *lv, const int32_t *rho
     info[1] = R.istar;
     info[2] = R.gstar;
     info[3] = R.applied ? 1 : 0;
+  });
+}
+
+int hgp_level_learned(hgp_ctx *ctx, const hgp_level *lv, int32_t level, int32_t omega, int32_t delta,
+                      const hgp_mlp *mlp, void *stream, int64_t cap, int64_t *coff, int32_t *cand, int32_t *xq,
+                      int64_t *cscore, int32_t *pair, int64_t *score, int32_t *ppair, int64_t *count) {
+  if (!ctx || !count) {
+    g_last_error = "ctx or count is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (omega < 1 || delta < 0 || level < 0 || cap < 0) throw Error(HGP_EINVAL, "bad scalar");
+    check_mlp(mlp);
+    if (lv && lv->n_nodes > 0 && (!coff || !cscore || !pair || !score || !ppair || (cap > 0 && !cand)))
+      throw Error(HGP_EINVAL, "NULL array");
+    Workspace &W = ctx->ws;
+    int64_t P = 0;
+    LevelView L = level_view_from(W, lv, s, &P);
+    const int32_t n = L.n;
+    *count = 0;
+    if (n == 0) {
+      if (coff) fill_i64(coff, 1, 0, s);
+      HGP_HIP(hipStreamSynchronize(s));
+      return;
+    }
+    const int32_t *params = upload_mlp(W.mlp, mlp, s);
+    int32_t *lp = need<int32_t>(W.pair, n);
+    int64_t *ls = need<int64_t>(W.score, n);
+    CandBufs B = cand_bufs(W, n, lp, ls);
+    const int64_t C = learned_candidates(L, W.total.as<int32_t>(), omega, delta, level, mlp->k, params, B,
+                                         W.scan_tmp, W.sort_tmp, s);
+    if (C > cap) throw Error(HGP_EINVAL, "candidate capacity too small");
+    HGP_HIP(hipMemcpyAsync(coff, B.coff, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+    launch_cand_ids(B, C, n, cand, s);
+    if (xq) launch_cand_codes(L, omega, delta, level, B, C, xq, s);
+    launch_widen_scores(B.cs, C, cscore, s);
+    HGP_HIP(hipMemcpyAsync(pair, lp, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    launch_unkey(lp, ls, n, score, s);
+    HGP_HIP(hipMemcpyAsync(ppair, B.ppair, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    HGP_HIP(hipStreamSynchronize(s));
+    *count = C;
+  });
+}
+
+int hgp_mlp_score_device(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score,
+                         void *stream) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n < 0 || (n > 0 && (!xq || !score))) throw Error(HGP_EINVAL, "bad arguments");
+    check_mlp(mlp);
+    if (n == 0) return;
+    Workspace &W = ctx->ws;
+    const int32_t *params = upload_mlp(W.mlp, mlp, s);
+    int32_t *tmp = need<int32_t>(W.cs, n);
+    launch_mlp_score_codes(xq, n, params, tmp, s);
+    launch_widen_scores(tmp, n, score, s);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent hypergraphs
+// ---------------------------------------------------------------------------
+static hgp_batch_sched sched_resolve(const hgp_ctx *ctx, const hgp_batch_sched *sc) {
+  hgp_batch_sched r{};
+  if (sc) r = *sc;
+  const hgp_batch_sched &t = ctx->tuned;
+  if (r.workers == 0) r.workers = t.workers ? t.workers : 4;
+  if (r.order == 0) r.order = t.order ? t.order : HGP_ORDER_LPT;
+  if (r.rate_tile == 0) r.rate_tile = t.rate_tile ? t.rate_tile : 512;
+  if (r.late_levels == 0) r.late_levels = t.late_levels ? t.late_levels : HGP_LATE_INCREMENTAL;
+  if (r.workers < 1 || r.workers > 16) throw Error(HGP_EINVAL, "workers outside 1..16");
+  if (r.order != HGP_ORDER_LPT && r.order != HGP_ORDER_INPUT) throw Error(HGP_EINVAL, "unknown order");
+  if (r.rate_tile != 256 && r.rate_tile != 512) throw Error(HGP_EINVAL, "rate_tile must be 256 or 512");
+  if (r.late_levels != HGP_LATE_INCREMENTAL && r.late_levels != HGP_LATE_FULL)
+    throw Error(HGP_EINVAL, "unknown late-level schedule");
+  return r;
+}
+
+static int64_t pins_of(const hgp_hypergraph &g, hipStream_t s) {
+  if (g.n_hedges <= 0) return 0;
+  return read_i32(g.hedge_off + g.n_hedges, s);
+}
+
+// Runs every graph once on `sc.workers` concurrent streams (one workspace
+// each), taking graphs in the schedule's order.  Times are host wall clock
+// in ms from the batch start.
+static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, const int32_t *omega,
+                      const int32_t *delta, const hgp_options &opt, const hgp_batch_sched &sc, hipStream_t caller,
+                      int32_t *const *part_out, hgp_result *res, double *t_start, double *t_end) {
+  while ((int)ctx->pool.size() < sc.workers) {
+    ctx->pool.emplace_back(new Workspace());
+    hipStream_t st = nullptr;
+    HGP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    ctx->pool_streams.push_back(st);
+  }
+  HGP_HIP(hipStreamSynchronize(caller));
+  std::vector<int64_t> pins((size_t)n);
+  for (int32_t i = 0; i < n; ++i) pins[(size_t)i] = pins_of(graphs[i], caller);
+  std::vector<int32_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  if (sc.order == HGP_ORDER_LPT)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return pins[(size_t)a] > pins[(size_t)b]; });
+  hgp_options o = opt;
+  if (sc.late_levels == HGP_LATE_FULL) o.flags |= HGP_FLAG_NO_INCREMENTAL;
+  std::atomic<int32_t> next{0};
+  std::atomic<bool> failed{false};
+  std::mutex mu;
+  int err_code = HGP_OK;
+  std::string err_msg;
+  const double t0 = now_ms();
+  auto work = [&](int w) {
+    try {
+      HGP_HIP(hipSetDevice(ctx->device));
+      Workspace &W = *ctx->pool[(size_t)w];
+      W.rate_tile = sc.rate_tile;
+      hipStream_t s = ctx->pool_streams[(size_t)w];
+      while (!failed.load()) {
+        const int32_t i = next.fetch_add(1);
+        if (i >= n) break;
+        const int32_t g = order[(size_t)i];
+        const double a = now_ms() - t0;
+        TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+        RunStats st = run_partition(W, &graphs[g], omega[g], delta[g], o, s, part_out[g]);
+        tg.collect(st, s);
+        HGP_HIP(hipStreamSynchronize(s));
+        const double b = now_ms() - t0;
+        if (t_start) t_start[g] = a;
+        if (t_end) t_end[g] = b;
+        if (res) fill_result(&res[g], st);
+      }
+    } catch (const Error &e) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!failed.exchange(true)) {
+        err_code = e.code;
+        err_msg = e.what();
+      }
+    } catch (const std::exception &e) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!failed.exchange(true)) {
+        err_code = HGP_EINTERNAL;
+        err_msg = e.what();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < sc.workers; ++w) th.emplace_back(work, w);
+  for (auto &t : th) t.join();
+  if (failed.load()) throw Error(err_code, err_msg);
+}
+
+static void check_batch_args(int32_t n, const hgp_hypergraph *graphs, const int32_t *omega, const int32_t *delta,
+                             int32_t *const *part_out) {
+  if (n < 0) throw Error(HGP_EINVAL, "n_graphs < 0");
+  if (n > 0 && (!graphs || !omega || !delta || !part_out)) throw Error(HGP_EINVAL, "NULL array");
+  for (int32_t i = 0; i < n; ++i) {
+    check_scalars(&graphs[i], omega[i], delta[i]);
+    if (graphs[i].n_nodes > 0 && !part_out[i]) throw Error(HGP_EINVAL, "part_out[i] is NULL");
+  }
+}
+
+int hgp_partition_batch_device(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs, const int32_t *omega,
+                               const int32_t *delta, const hgp_options *opt, const hgp_batch_sched *sched,
+                               void *stream, int32_t *const *part_out, hgp_result *res, double *t_start_ms,
+                               double *t_end_ms) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    check_batch_args(n_graphs, graphs, omega, delta, part_out);
+    const hgp_batch_sched sc = sched_resolve(ctx, sched);
+    run_batch(ctx, n_graphs, graphs, omega, delta, opts_or_default(opt), sc, static_cast<hipStream_t>(stream),
+              part_out, res, t_start_ms, t_end_ms);
+  });
+}
+
+int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs, const int32_t *omega,
+                   const int32_t *delta, const hgp_options *opt, void *stream, int32_t *const *part_out,
+                   hgp_batch_sched *best, double *best_ms) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    check_batch_args(n_graphs, graphs, omega, delta, part_out);
+    const hgp_options o = opts_or_default(opt);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // coordinate search: workers first (the dominant knob), then each other
+    // knob in turn with the best setting so far; every candidate runs the
+    // whole batch once after one warm-up of the largest worker count
+    hgp_batch_sched cur{};
+    cur.workers = 4;
+    cur.order = HGP_ORDER_LPT;
+    cur.rate_tile = 512;
+    cur.late_levels = HGP_LATE_INCREMENTAL;
+    auto time_of = [&](const hgp_batch_sched &c) {
+      const double a = now_ms();
+      run_batch(ctx, n_graphs, graphs, omega, delta, o, c, s, part_out, nullptr, nullptr, nullptr);
+      return now_ms() - a;
+    };
+    {
+      hgp_batch_sched warm = cur;
+      warm.workers = 8;
+      (void)time_of(warm);
+    }
+    double best_t = 1e300;
+    for (int w : {1, 2, 4, 8}) {
+      hgp_batch_sched c = cur;
+      c.workers = w;
+      const double t = time_of(c);
+      if (t < best_t) {
+        best_t = t;
+        cur = c;
+      }
+    }
+    {
+      hgp_batch_sched c = cur;
+      c.order = HGP_ORDER_INPUT;
+      const double t = time_of(c);
+      if (t < best_t) {
+        best_t = t;
+        cur = c;
+      }
+    }
+    {
+      hgp_batch_sched c = cur;
+      c.rate_tile = 256;
+      const double t = time_of(c);
+      if (t < best_t) {
+        best_t = t;
+        cur = c;
+      }
+    }
+    {
+      hgp_batch_sched c = cur;
+      c.late_levels = HGP_LATE_FULL;
+      const double t = time_of(c);
+      if (t < best_t) {
+        best_t = t;
+        cur = c;
+      }
+    }
+    ctx->tuned = cur;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = best_t;
   });
 }
 

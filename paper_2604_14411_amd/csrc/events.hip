@@ -1,0 +1,540 @@
+// In-sequence gains and sequence validity (Sec. IV-B), without contended
+// atomics.
+//
+// Gains.  For the moving pins of hedge e, every move i of node v (p_s -> p_d)
+// gives a source event on (p_s, i) and a destination event on (p_d, i).
+// Sorted by (part, position), a prefix within each part gives
+// pins_{i-1}(p, e) = pins_0(p, e) + earlier arrivals - earlier departures,
+// and the exact change of Eq. 1 caused by move i on hedge e is
+//   +w(e) if pins_{i-1}(p_s, e) = 1   (p_s leaves the hedge)
+//   -w(e) if pins_{i-1}(p_d, e) = 0   (p_d joins the hedge).
+// The two terms are stored per pin (contrib[j] = (source term, destination
+// term)); g'(i) is then the sum over the incidences of v, read through the
+// incidence -> pin permutation of the transpose.
+//
+// Validity.  Destination pins do the same on pins_in(p, e) and emit an
+// inbound-count event (p, i, -1) on a 1 -> 0 transition of p_s and (p, i, +1)
+// on a 0 -> 1 transition of p_d.  With the size events (p_s, i) and (p_d, i)
+// of every move, all events are sorted by (part, position); prefix sums give
+// each part's size and inbound count after every position, and a change of
+// validity between consecutive positions of a part adds +-1 to viol there.
+#include "coarsen.hpp"
+
+namespace hgp {
+
+constexpr int kClsEvents = 3;        // timing class of these kernels (sequence evaluation)
+constexpr int EVW_NT = 128;          // two waves per workgroup
+constexpr int EVW_MAX_MOVING = 512;  // moving pins of a hedge handled by one wave
+constexpr int EVB_NT = 256;          // workgroup kernel for the remaining hedges
+constexpr int EVB_GRID = 512;
+static_assert(kSegCap <= 4096, "slot field of the workgroup event keys is 12 bits");
+
+// Sorts a wave's nev (<= 64 * KPL) event keys held in LDS, in registers, and
+// writes them back with the exclusive prefix of their count deltas: pins in
+// the low 16 bits, pins_in in the high 16 bits (both signed).
+template <int KPL>
+__device__ __forceinline__ void ev_wave_sort_scan(int nev, uint64_t *evk, int32_t *pre) {
+  const int l = lane_id();
+  uint64_t k[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    k[j] = i < nev ? evk[i] : ~0ull;
+  }
+  wave_bitonic_sort<KPL>(k);
+  int32_t d[KPL];
+  int32_t run = 0;
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    int32_t x = 0;
+    if (i < nev) {
+      const int sgn = (k[j] & 2ull) ? 1 : -1;
+      x = sgn + ((k[j] & 1ull) ? sgn * 65536 : 0);
+    }
+    d[j] = run;
+    run += x;
+  }
+  const int32_t base = wave_exclusive_scan(run);
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    if (i < nev) {
+      evk[i] = k[j];
+      pre[i] = base + d[j];
+    }
+  }
+}
+
+// Splits a prefix difference of packed deltas into (pins, pins_in).
+__device__ __forceinline__ int2 unpack_delta(int32_t pd) {
+  const int32_t p = (int32_t)(int16_t)(pd & 0xffff);
+  return make_int2(p, (pd - p) >> 16);
+}
+
+// One wave per hedge with at most EVW_MAX_MOVING moving pins; other hedges
+// with moving pins are queued in heavy[] for k_ev_block.
+// Key of a pin event: part << (qbits + 11) | position << 11 | slot << 2 |
+// role << 1 | dst, slot = index of the moving pin (< 512), role 1 = destination.
+__global__ __launch_bounds__(EVW_NT) void k_ev_wave(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
+    int2 *__restrict__ contrib, uint64_t *__restrict__ ev, int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
+  __shared__ uint64_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
+  __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
+  __shared__ int16_t li_s[EVW_NT / 64][EVW_MAX_MOVING];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int e = (int)(blockIdx.x * (EVW_NT / 64) + w);
+  if (e >= E) return;
+  const int b = hoff[e], len = hoff[e + 1] - b;
+  int m = 0;
+  for (int c = 0; c < len; c += 64) {
+    const int i = c + l;
+    m += __popcll(__ballot(i < len && pos[hpin[b + i] & kIdMask] > 0));
+  }
+  if (m == 0) return;
+  if (m > EVW_MAX_MOVING) {
+    if (l == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
+    return;
+  }
+  const int pshift = qbits + 11;
+  const uint64_t qmask = (1ull << qbits) - 1ull;
+  uint64_t *evk = evk_s[w];
+  int32_t *pre = pre_s[w];
+  int16_t *li = li_s[w];
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  int slot0 = 0;
+  for (int c = 0; c < len; c += 64) {
+    const int i = c + l;
+    uint32_t x = 0;
+    int q = 0;
+    if (i < len) {
+      x = hpin[b + i];
+      q = pos[x & kIdMask];
+    }
+    const uint64_t mask = __ballot(q > 0);
+    if (q > 0) {
+      const int slot = slot0 + __popcll(mask & lt);
+      const int v = (int)(x & kIdMask);
+      const uint64_t tail = ((uint64_t)q << 11) | ((uint64_t)slot << 2) | (uint64_t)(x >> 31);
+      li[slot] = (int16_t)i;
+      evk[2 * slot] = ((uint64_t)(uint32_t)rho[v] << pshift) | tail;
+      evk[2 * slot + 1] = ((uint64_t)(uint32_t)dest[v] << pshift) | tail | 2ull;
+    }
+    slot0 += __popcll(mask);
+  }
+  wave_lds_sync();
+  const int nev = 2 * m;
+  if (nev <= 64) ev_wave_sort_scan<1>(nev, evk, pre);
+  else if (nev <= 128) ev_wave_sort_scan<2>(nev, evk, pre);
+  else if (nev <= 256) ev_wave_sort_scan<4>(nev, evk, pre);
+  else if (nev <= 512) ev_wave_sort_scan<8>(nev, evk, pre);
+  else ev_wave_sort_scan<16>(nev, evk, pre);
+  wave_lds_sync();
+  const int32_t we = hw[e];
+  const int plen = lam[e];
+  uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
+  int nout = 0;
+  for (int t = 0; t * 64 < nev; ++t) {
+    const int i = l + 64 * t;
+    if (i >= nev) continue;
+    const uint64_t k = evk[i];
+    const uint64_t part = k >> pshift;
+    int lo = 0, hi = i;  // first event of this part
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((evk[mid] >> pshift) < part) lo = mid + 1;
+      else hi = mid;
+    }
+    const int2 before = unpack_delta(pre[i] - pre[lo]);
+    const int2 c0 = pt_lookup(pt, ptin, b, plen, (int)part);
+    const bool dst_role = (k & 2ull) != 0;
+    int2 *cp = &contrib[b + li[(int)((k >> 2) & 511ull)]];
+    if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
+    else cp->x = (c0.x + before.x == 1) ? we : 0;
+    if (k & 1ull) {
+      const int bin = c0.y + before.y;
+      if ((!dst_role && bin == 1) || (dst_role && bin == 0)) {
+        evbits |= 1u << t;
+        ++nout;
+      }
+    }
+  }
+  const int off = wave_exclusive_scan(nout);
+  const int tot = __shfl(off + nout, 63, 64);
+  if (tot == 0) return;
+  unsigned long long base = 0;
+  if (l == 0) base = atomicAdd((unsigned long long *)&scal[SC_EVENTS], (unsigned long long)tot);
+  base = __shfl(base, 0, 64);
+  const int vshift = qbits + 2;
+  int64_t o = (int64_t)base + off;
+  for (int t = 0; evbits; ++t, evbits >>= 1) {
+    if (!(evbits & 1u)) continue;
+    const uint64_t k = evk[l + 64 * t];
+    const uint64_t q = (k >> 11) & qmask;
+    ev[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+  }
+}
+
+// Part table of a hedge staged in LDS (parts ascending; counts packed as
+// pins | pins_in << 16, both <= kSegCap).
+__device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t *sc, int len, int p) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sp[mid] < p) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < len && sp[lo] == p) return make_int2((int)(sc[lo] & 0xffffu), (int)(sc[lo] >> 16));
+  return make_int2(0, 0);
+}
+
+// One workgroup per queued hedge (more than EVW_MAX_MOVING moving pins; at
+// most kSegCap pins).  Same events as k_ev_wave with a 12-bit slot field:
+// part << (qbits + 14) | position << 14 | slot << 2 | role << 1 | dst.
+__global__ __launch_bounds__(EVB_NT) void k_ev_block(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
+    int2 *__restrict__ contrib, uint64_t *__restrict__ ev, int64_t *__restrict__ scal,
+    const int32_t *__restrict__ heavy) {
+  __shared__ uint64_t key[2 * kSegCap];
+  __shared__ int32_t dl[2 * kSegCap];
+  __shared__ int32_t sp[kSegCap];
+  __shared__ uint32_t sc[kSegCap];
+  __shared__ int16_t li[kSegCap];
+  __shared__ int32_t tmp[EVB_NT / 64 + 1];
+  __shared__ int32_t s_cnt;
+  const int tid = threadIdx.x, l = lane_id();
+  const int hshift = qbits + 14;
+  const uint64_t qmask = (1ull << qbits) - 1ull;
+  const int vshift = qbits + 2;
+  const int64_t nh = scal[SC_HEAVY];
+  for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const int e = heavy[h];
+    const int b = hoff[e], len = hoff[e + 1] - b;
+    if (tid == 0) s_cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < len; i += EVB_NT) {
+      const uint32_t x = hpin[b + i];
+      const int v = (int)(x & kIdMask);
+      const int q = pos[v];
+      if (q > 0) {
+        const int slot = atomicAdd(&s_cnt, 1);
+        li[slot] = (int16_t)i;
+        const uint64_t tail = ((uint64_t)q << 14) | ((uint64_t)slot << 2) | (uint64_t)(x >> 31);
+        key[2 * slot] = ((uint64_t)(uint32_t)rho[v] << hshift) | tail;
+        key[2 * slot + 1] = ((uint64_t)(uint32_t)dest[v] << hshift) | tail | 2ull;
+      }
+    }
+    __syncthreads();
+    const int nev = 2 * s_cnt;
+    const int np = next_pow2(nev);
+    for (int i = nev + tid; i < np; i += EVB_NT) key[i] = ~0ull;
+    __syncthreads();
+    block_bitonic_sort<uint64_t, EVB_NT>(key, np);
+    for (int i = tid; i < nev; i += EVB_NT) {
+      const uint64_t k = key[i];
+      const int sgn = (k & 2ull) ? 1 : -1;
+      dl[i] = sgn + ((k & 1ull) ? sgn * 65536 : 0);
+    }
+    __syncthreads();
+    block_exclusive_scan<int32_t, EVB_NT>(dl, nev, tmp);
+    const int32_t we = hw[e];
+    const int plen = lam[e];
+    for (int i = tid; i < plen; i += EVB_NT) {
+      const int2 x = pt[b + i];
+      sp[i] = x.x;
+      sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
+    }
+    __syncthreads();
+    uint32_t evbits = 0;  // bit t: event tid + EVB_NT t changes an inbound count (nev <= 32 EVB_NT)
+    int nout = 0;
+    for (int t = 0, i = tid; i < nev; ++t, i += EVB_NT) {
+      const uint64_t k = key[i];
+      const uint64_t part = k >> hshift;
+      int lo = 0, hi = i;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((key[mid] >> hshift) < part) lo = mid + 1;
+        else hi = mid;
+      }
+      const int2 before = unpack_delta(dl[i] - dl[lo]);
+      const int2 c0 = pt_lookup_lds(sp, sc, plen, (int)part);
+      const bool dst_role = (k & 2ull) != 0;
+      int2 *cp = &contrib[b + li[(int)((k >> 2) & 4095ull)]];
+      if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
+      else cp->x = (c0.x + before.x == 1) ? we : 0;
+      if (k & 1ull) {
+        const int bin = c0.y + before.y;
+        if ((!dst_role && bin == 1) || (dst_role && bin == 0)) {
+          evbits |= 1u << t;
+          ++nout;
+        }
+      }
+    }
+    const int off = wave_exclusive_scan(nout);
+    const int tot = __shfl(off + nout, 63, 64);
+    unsigned long long base = 0;
+    if (l == 0 && tot) base = atomicAdd((unsigned long long *)&scal[SC_EVENTS], (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    int64_t o = (int64_t)base + off;
+    for (int t = 0; evbits; ++t, evbits >>= 1) {
+      if (!(evbits & 1u)) continue;
+      const uint64_t k = key[tid + EVB_NT * t];
+      const uint64_t q = (k >> 14) & qmask;
+      ev[o++] = ((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+    }
+    __syncthreads();
+  }
+}
+
+// g'(i) for move i = 1..S: the sum, over the incidences k of the moving node,
+// of both terms stored at its pin perm[k].  One wave per move.
+__global__ __launch_bounds__(256) void k_move_gain(const int32_t *__restrict__ seq, int64_t S,
+                                                   const int32_t *__restrict__ ioff, const uint32_t *__restrict__ perm,
+                                                   const int2 *__restrict__ contrib, int32_t *__restrict__ gp) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (i >= S) return;
+  const int v = seq[i];
+  const int a = ioff[v], z = ioff[v + 1];
+  int32_t g = 0;
+  for (int k = a + lane_id(); k < z; k += 64) {
+    const int2 c = contrib[perm[k]];
+    g += c.x + c.y;
+  }
+  g = wave_sum(g);
+  if (lane_id() == 0) gp[i + 1] = g;
+}
+
+// size events (p_s, i, size) and (p_d, i, size) of every move i
+__global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const int32_t *__restrict__ rho,
+                              const int32_t *__restrict__ dest, int vshift, uint64_t *__restrict__ ev, int64_t base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S) return;
+  const int v = seq[i];
+  const uint64_t tail = ((uint64_t)(i + 1) << 2) | 2ull;
+  ev[base + 2 * i] = ((uint64_t)(uint32_t)rho[v] << vshift) | tail;
+  ev[base + 2 * i + 1] = ((uint64_t)(uint32_t)dest[v] << vshift) | tail;
+}
+
+// poff[p] = first sorted event of part p (p = 0 .. P; poff[P] = nev).
+__global__ void k_part_offsets(const uint64_t *__restrict__ ev, int64_t nev, int vshift, int32_t P,
+                               int64_t *__restrict__ poff) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > P) return;
+  int64_t lo = 0, hi = nev;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)(ev[mid] >> vshift) < p) lo = mid + 1;
+    else hi = mid;
+  }
+  poff[p] = lo;
+}
+
+// Per sorted event: size delta (+-size(v) for the part left / joined) and
+// inbound-count delta (-1 / +1).
+__global__ void k_ev_vals(const uint64_t *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
+                          const int32_t *__restrict__ seq, const int32_t *__restrict__ rho,
+                          const int32_t *__restrict__ size, int64_t *__restrict__ esum, int32_t *__restrict__ isum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nev) return;
+  const uint64_t k = ev[i];
+  const int type = (int)(k & 3ull);
+  int64_t ds = 0;
+  int32_t di = 0;
+  if (type == 2) {
+    const int v = seq[((k >> 2) & qmask) - 1];
+    ds = (uint64_t)(uint32_t)rho[v] == (k >> vshift) ? -(int64_t)size[v] : (int64_t)size[v];
+  } else {
+    di = type == 1 ? 1 : -1;
+  }
+  esum[i] = ds;
+  isum[i] = di;
+}
+
+// At the last event of every (part, position) group: validity of the part
+// before the group (its previous position) and after it; a change adds +1
+// (valid -> invalid) or -1 to the violation delta at that position.
+__global__ void k_ev_transitions(const uint64_t *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
+                                 const int64_t *__restrict__ poff, const int32_t *__restrict__ psize,
+                                 const int32_t *__restrict__ pinb, const int64_t *__restrict__ esum,
+                                 const int32_t *__restrict__ isum, int32_t omega, int32_t delta,
+                                 int32_t *__restrict__ vdelta) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nev) return;
+  const uint64_t g = ev[i] >> 2;
+  if (i + 1 < nev && (ev[i + 1] >> 2) == g) return;
+  const int p = (int)(ev[i] >> vshift);
+  const int64_t b = poff[p];
+  int64_t lo = b, hi = i;  // first event of the group
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((ev[mid] >> 2) < g) lo = mid + 1;
+    else hi = mid;
+  }
+  const int64_t s0 = psize[p] - esum[b], i0 = (int64_t)pinb[p] - isum[b];
+  const bool valid_before = s0 + esum[lo] <= omega && i0 + isum[lo] <= delta;
+  const bool valid_after = s0 + esum[i + 1] <= omega && i0 + isum[i + 1] <= delta;
+  if (valid_before != valid_after) atomicAdd(&vdelta[g & qmask], valid_after ? -1 : 1);
+}
+
+__global__ void k_init_invalid(const int32_t *__restrict__ psize, const int32_t *__restrict__ pinb, int32_t P,
+                               int32_t omega, int32_t delta, int64_t *__restrict__ scal) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int bad = (p < P && (psize[p] > omega || pinb[p] > delta)) ? 1 : 0;
+  bad = wave_sum(bad);
+  if (lane_id() == 0 && bad) atomicAdd((unsigned long long *)&scal[SC_INVALID0], (unsigned long long)bad);
+}
+
+// Single workgroup: G(i) = prefix of g', viol(i) = viol(0) + prefix of the
+// violation deltas, and i* = argmax over viol(i) = 0 of (G(i), i).
+constexpr int FIN_NT = 1024;
+__global__ __launch_bounds__(FIN_NT) void k_finish(const int32_t *__restrict__ gp, const int32_t *__restrict__ vdelta,
+                                                   int64_t S, int64_t *__restrict__ G, int32_t *__restrict__ viol,
+                                                   int64_t *__restrict__ scal) {
+  __shared__ int64_t wsum[FIN_NT / 64];
+  __shared__ int32_t wvs[FIN_NT / 64];
+  __shared__ int64_t s_carry_g;
+  __shared__ int32_t s_carry_v;
+  __shared__ int64_t bestg[FIN_NT / 64];
+  __shared__ int64_t besti[FIN_NT / 64];
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  if (tid == 0) {
+    s_carry_g = 0;
+    s_carry_v = (int32_t)scal[SC_INVALID0];
+  }
+  __syncthreads();
+  int64_t my_g = 0, my_i = -1;
+  for (int64_t c = 0; c <= S; c += FIN_NT) {
+    const int64_t i = c + tid;
+    const bool act = i <= S;
+    const int64_t x = (act && i > 0) ? (int64_t)gp[i] : 0;
+    const int32_t y = (act && i > 0) ? vdelta[i] : 0;
+    const int64_t ix = wave_inclusive_scan(x);
+    const int32_t iy = wave_inclusive_scan(y);
+    if (l == 63) {
+      wsum[w] = ix;
+      wvs[w] = iy;
+    }
+    __syncthreads();
+    int64_t og = s_carry_g;
+    int32_t ov = s_carry_v;
+    for (int q = 0; q < w; ++q) {
+      og += wsum[q];
+      ov += wvs[q];
+    }
+    const int64_t g = og + ix;
+    const int32_t v = ov + iy;
+    if (act) {
+      G[i] = g;
+      viol[i] = v;
+      if (v == 0 && (my_i < 0 || g >= my_g)) {
+        my_g = g;
+        my_i = i;
+      }
+    }
+    __syncthreads();
+    if (tid == FIN_NT - 1) {
+      int64_t tg = 0;
+      int32_t tv = 0;
+      for (int q = 0; q < FIN_NT / 64; ++q) {
+        tg += wsum[q];
+        tv += wvs[q];
+      }
+      s_carry_g += tg;
+      s_carry_v += tv;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t og = __shfl_xor(my_g, o, 64);
+    const int64_t oi = __shfl_xor(my_i, o, 64);
+    if (oi >= 0 && (my_i < 0 || og > my_g || (og == my_g && oi > my_i))) {
+      my_g = og;
+      my_i = oi;
+    }
+  }
+  if (l == 0) {
+    bestg[w] = my_g;
+    besti[w] = my_i;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 1; q < FIN_NT / 64; ++q)
+      if (besti[q] >= 0 && (my_i < 0 || bestg[q] > my_g || (bestg[q] == my_g && besti[q] > my_i))) {
+        my_g = bestg[q];
+        my_i = besti[q];
+      }
+    scal[SC_ISTAR] = my_i;
+    scal[SC_GSTAR] = my_i >= 0 ? my_g : 0;
+  }
+}
+
+
+void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta,
+                       int64_t S, RoundBufs &B, int32_t *err, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s,
+                       int64_t *istar, int64_t *gstar) {
+  (void)err;
+  const int qbits = bits_for(S) > 0 ? bits_for(S) : 1;
+  const int pbits = bits_for(n_parts > 1 ? n_parts - 1 : 1);
+  const int vshift = qbits + 2;
+  if (pbits + qbits + 14 > 64) throw Error(-6, "sequence too long for the 64-bit event keys");
+  fill_i32(B.vdelta, S + 1, 0, s);
+  fill_i32(B.gp, 1, 0, s);
+  fill_i64(B.scal + SC_EVENTS, 1, 0, s);
+  fill_i64(B.scal + SC_INVALID0, 1, 0, s);
+  fill_i64(B.scal + SC_HEAVY, 1, 0, s);
+  if (S > 0) {
+    KScope ks(kClsEvents, s);
+    if (L.E > 0) {
+      k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
+                                                            B.ptin, B.lam, qbits, B.contrib, B.keys, B.scal, B.heavy);
+      HGP_LAUNCH_CHECK();
+      k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam, qbits,
+                                             B.contrib, B.keys, B.scal, B.heavy);
+      HGP_LAUNCH_CHECK();
+    }
+    k_move_gain<<<div_up(S, 4), 256, 0, s>>>(B.seq, S, L.ioff, L.perm, B.contrib, B.gp);
+    HGP_LAUNCH_CHECK();
+  }
+  int64_t nin = 0;
+  HGP_HIP(hipMemcpyAsync(&nin, B.scal + SC_EVENTS, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  const int64_t nev = nin + 2 * S;
+  if (nev > B.cap_events) throw Error(-7, "event buffer overflow");
+  if (S > 0) {
+    k_size_events<<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, vshift, B.keys, nin);
+    HGP_LAUNCH_CHECK();
+  }
+  k_init_invalid<<<div_up(n_parts > 0 ? n_parts : 1, 256), 256, 0, s>>>(B.psize, B.pinb, n_parts, omega, delta,
+                                                                         B.scal);
+  HGP_LAUNCH_CHECK();
+  sort_keys(B.keys, B.keys2, nev, vshift + pbits, sort_tmp, s);
+  {
+    KScope ks(kClsEvents, s);
+    const uint64_t qmask = (1ull << qbits) - 1ull;
+    if (nev > 0) {
+      k_part_offsets<<<div_up((int64_t)n_parts + 1, 256), 256, 0, s>>>(B.keys, nev, vshift, n_parts, B.poff);
+      HGP_LAUNCH_CHECK();
+      k_ev_vals<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, vshift, qmask, B.seq, rho, L.size, B.esum, B.isum);
+      HGP_LAUNCH_CHECK();
+      scan_i64(B.esum, B.esum, nev, B.esum + nev, scan_tmp, s);
+      scan_i32(B.isum, B.isum, nev, B.isum + nev, scan_tmp, s);
+      k_ev_transitions<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, vshift, qmask, B.poff, B.psize, B.pinb, B.esum,
+                                                        B.isum, omega, delta, B.vdelta);
+      HGP_LAUNCH_CHECK();
+    }
+    k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);
+    HGP_LAUNCH_CHECK();
+  }
+  int64_t res[2];
+  HGP_HIP(hipMemcpyAsync(res, B.scal + SC_ISTAR, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  *istar = res[0];
+  *gstar = res[1];
+}
+
+}  // namespace hgp

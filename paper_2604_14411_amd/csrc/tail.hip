@@ -243,12 +243,12 @@ void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, i
   if (words > kTopKMaxWords) throw Error(-7, "top-K window exceeds LDS");
   KScope ks(8, s);
   const size_t bytes = (size_t)words * 4;
-  static bool attr_set = false;
-  if (!attr_set) {
-    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kTopKMaxWords * 4));
-    attr_set = true;
-  }
+  // thread-safe one-time opt-in to the large dynamic LDS size
+  static const bool attr_set = [] {
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize, kTopKMaxWords * 4));
+    return true;
+  }();
+  (void)attr_set;
   const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, bytes, s>>>(L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size,
                                                     L.indeg, total, omega, delta, row_slot, rows, pair, score, tk.key,

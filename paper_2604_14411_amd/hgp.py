@@ -15,11 +15,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
-PLAIN = 0
+PLAIN, LEARNED = 0, 1
+MLP_F, MLP_H = 16, 64
 FLAG_TIME_KERNELS = 1
 FLAG_NO_INCREMENTAL = 2
 KERNEL_CLASSES = ["rate", "propose", "part_table", "seq_events", "contract", "incidence", "sort", "match",
-                  "rate_tail"]
+                  "rate_tail", "mlp"]
+NK = len(KERNEL_CLASSES)
 
 
 class HgpError(RuntimeError):
@@ -34,16 +36,81 @@ class Hypergraph_t(ctypes.Structure):
                 ("node_w", ctypes.c_void_p)]
 
 
+class Mlp_t(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32), ("b3", ctypes.c_int32),
+                ("w1", ctypes.c_int32 * (MLP_F * MLP_H)), ("b1", ctypes.c_int32 * MLP_H),
+                ("w2", ctypes.c_int32 * (MLP_H * MLP_H)), ("b2", ctypes.c_int32 * MLP_H),
+                ("w3", ctypes.c_int32 * MLP_H)]
+
+
+def mlp_struct(q) -> Mlp_t:
+    """Packs an integer network given as a dict (k, r1, r2, b3, w1[16,64], b1, w2[64,64], b2, w3)."""
+    m = Mlp_t()
+    m.k, m.r1, m.r2, m.b3 = int(q["k"]), int(q["r1"]), int(q["r2"]), int(q["b3"])
+    for name, n in (("w1", MLP_F * MLP_H), ("b1", MLP_H), ("w2", MLP_H * MLP_H), ("b2", MLP_H), ("w3", MLP_H)):
+        a = np.ascontiguousarray(np.asarray(q[name]).reshape(-1), dtype=np.int32)
+        if a.size != n:
+            raise ValueError(f"network field {name} has {a.size} values, expected {n}")
+        ctypes.memmove(getattr(m, name), a.ctypes.data, 4 * n)
+    return m
+
+
+class MlpF32_t(ctypes.Structure):
+    _fields_ = [("w1", ctypes.c_float * (MLP_F * MLP_H)), ("b1", ctypes.c_float * MLP_H),
+                ("w2", ctypes.c_float * (MLP_H * MLP_H)), ("b2", ctypes.c_float * MLP_H),
+                ("w3", ctypes.c_float * MLP_H), ("b3", ctypes.c_float)]
+
+
+class TrainOpts_t(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
+def f32_to_dict(w: MlpF32_t) -> dict:
+    """Float weights as numpy arrays (w1[16,64], b1, w2[64,64], b2, w3, b3)."""
+    return dict(w1=np.ctypeslib.as_array(w.w1).reshape(MLP_F, MLP_H).copy(), b1=np.ctypeslib.as_array(w.b1).copy(),
+                w2=np.ctypeslib.as_array(w.w2).reshape(MLP_H, MLP_H).copy(), b2=np.ctypeslib.as_array(w.b2).copy(),
+                w3=np.ctypeslib.as_array(w.w3).copy(), b3=float(w.b3))
+
+
+def f32_from_dict(d) -> MlpF32_t:
+    w = MlpF32_t()
+    for name, n in (("w1", MLP_F * MLP_H), ("b1", MLP_H), ("w2", MLP_H * MLP_H), ("b2", MLP_H), ("w3", MLP_H)):
+        a = np.ascontiguousarray(np.asarray(d[name]).reshape(-1), dtype=np.float32)
+        if a.size != n:
+            raise ValueError(f"float network field {name} has {a.size} values, expected {n}")
+        ctypes.memmove(getattr(w, name), a.ctypes.data, 4 * n)
+    w.b3 = float(d["b3"])
+    return w
+
+
+def mlp_to_dict(m: Mlp_t) -> dict:
+    """Integer network as a dict of numpy arrays."""
+    return dict(k=m.k, r1=m.r1, r2=m.r2, b3=m.b3, w1=np.ctypeslib.as_array(m.w1).reshape(MLP_F, MLP_H).copy(),
+                b1=np.ctypeslib.as_array(m.b1).copy(), w2=np.ctypeslib.as_array(m.w2).reshape(MLP_H, MLP_H).copy(),
+                b2=np.ctypeslib.as_array(m.b2).copy(), w3=np.ctypeslib.as_array(m.w3).copy())
+
+
+ORDER_LPT, ORDER_INPUT = 1, 2
+LATE_INCREMENTAL, LATE_FULL = 1, 2
+
+
+class BatchSched_t(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("order", ctypes.c_int32), ("rate_tile", ctypes.c_int32),
+                ("late_levels", ctypes.c_int32)]
+
+
 class Options_t(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("max_refine_rounds", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32), ("mlp", ctypes.POINTER(Mlp_t))]
 
 
 class Result_t(ctypes.Structure):
     _fields_ = [("connectivity", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("n_rounds", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms_coarsen", ctypes.c_double),
-                ("ms_refine", ctypes.c_double), ("ms_kernel", ctypes.c_double * 9),
-                ("n_kernel", ctypes.c_int64 * 9), ("units_kernel", ctypes.c_int64 * 9)]
+                ("n_rounds", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("ms_coarsen", ctypes.c_double),
+                ("ms_refine", ctypes.c_double), ("ms_kernel", ctypes.c_double * NK),
+                ("n_kernel", ctypes.c_int64 * NK), ("units_kernel", ctypes.c_int64 * NK)]
 
 
 class Level_t(ctypes.Structure):
@@ -54,7 +121,10 @@ class Level_t(ctypes.Structure):
 EXPORTS = [
     "hgp_ctx_create", "hgp_ctx_destroy", "hgp_options_default", "hgp_partition", "hgp_partition_device",
     "hgp_connectivity_device", "hgp_strerror", "hgp_last_error", "hgp_level_canonical", "hgp_level_rate",
-    "hgp_level_match", "hgp_level_contract", "hgp_level_refine_round",
+    "hgp_level_match", "hgp_level_contract", "hgp_level_refine_round", "hgp_level_learned",
+    "hgp_mlp_score_device", "hgp_mlp_init", "hgp_mlp_grad", "hgp_mlp_train", "hgp_mlp_quantize",
+    "hgp_trace_create", "hgp_trace_destroy", "hgp_partition_traced", "hgp_trace_rows", "hgp_trace_read",
+    "hgp_partition_batch_device", "hgp_batch_tune",
 ]
 
 _lib = None
@@ -89,9 +159,33 @@ def load():
     lib.hgp_level_match.argtypes = [vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
     lib.hgp_level_contract.argtypes = [vp, LV, vp, i32, vp, vp, vp, vp]
     lib.hgp_level_refine_round.argtypes = [vp, LV, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64p]
+    MP = ctypes.POINTER(Mlp_t)
+    lib.hgp_level_learned.argtypes = [vp, LV, i32, i32, i32, MP, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp,
+                                      i64p]
+    lib.hgp_mlp_score_device.argtypes = [vp, MP, vp, ctypes.c_int64, vp, vp]
+    FP = ctypes.POINTER(MlpF32_t)
+    lib.hgp_mlp_init.argtypes = [FP, ctypes.c_uint64]
+    lib.hgp_mlp_grad.argtypes = [vp, FP, vp, vp, ctypes.c_int64, FP, ctypes.POINTER(ctypes.c_double), vp]
+    lib.hgp_mlp_train.argtypes = [vp, FP, vp, vp, ctypes.c_int64, ctypes.POINTER(TrainOpts_t), vp, vp]
+    lib.hgp_mlp_quantize.argtypes = [FP, vp, ctypes.c_int64, i32, MP, ctypes.POINTER(i32)]
+    lib.hgp_trace_create.argtypes = [ctypes.POINTER(vp)]
+    lib.hgp_trace_destroy.argtypes = [vp]
+    lib.hgp_partition_traced.argtypes = [vp, HG, i32, i32, ctypes.POINTER(Options_t), vp, vp,
+                                         ctypes.POINTER(Result_t)]
+    lib.hgp_trace_rows.argtypes = [vp]
+    lib.hgp_trace_read.argtypes = [vp, vp, vp, vp, vp, vp]
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.hgp_partition_batch_device.argtypes = [vp, i32, HG, vp, vp, ctypes.POINTER(Options_t),
+                                               ctypes.POINTER(BatchSched_t), vp, vp, ctypes.POINTER(Result_t), dp, dp]
+    lib.hgp_batch_tune.argtypes = [vp, i32, HG, vp, vp, ctypes.POINTER(Options_t), vp, vp,
+                                   ctypes.POINTER(BatchSched_t), dp]
     for name in EXPORTS:
-        if name not in ("hgp_ctx_destroy", "hgp_options_default", "hgp_strerror", "hgp_last_error"):
+        if name not in ("hgp_ctx_destroy", "hgp_options_default", "hgp_strerror", "hgp_last_error",
+                        "hgp_mlp_init", "hgp_trace_destroy", "hgp_trace_rows"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.hgp_mlp_init.restype = None
+    lib.hgp_trace_destroy.restype = None
+    lib.hgp_trace_rows.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -130,16 +224,23 @@ class Context:
         self.close()
 
 
-def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0) -> Options_t:
+def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0, mlp=None):
+    """hgp_options; with an integer network dict `mlp` the learned proposal is selected.
+    Returns (Options_t, keep-alive object)."""
     o = Options_t()
     load().hgp_options_default(ctypes.byref(o))
     o.k, o.max_refine_rounds, o.seed, o.flags = k, max_refine_rounds, seed, flags
-    return o
+    m = None
+    if mlp is not None:
+        m = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
+        o.proposal = LEARNED
+        o.mlp = ctypes.pointer(m)
+    return o, m
 
 
 def _result_dict(r: Result_t) -> dict:
     return dict(connectivity=r.connectivity, n_parts=r.n_parts, n_levels=r.n_levels, n_rounds=r.n_rounds,
-                ms_coarsen=r.ms_coarsen, ms_refine=r.ms_refine,
+                n_fallback=r.n_fallback, ms_coarsen=r.ms_coarsen, ms_refine=r.ms_refine,
                 kernels={name: dict(ms=r.ms_kernel[i], launches=r.n_kernel[i], units=r.units_kernel[i])
                          for i, name in enumerate(KERNEL_CLASSES)})
 
@@ -162,7 +263,7 @@ class DeviceHypergraph:
                             _ptr(self.n_src), _ptr(self.hedge_w), _ptr(self.node_w))
 
 
-def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refine_rounds: int = 8):
+def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refine_rounds: int = 8, mlp=None):
     """hgp_partition on numpy arrays; returns (parts ndarray, result dict)."""
     lib = load()
     arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (g.hedge_off, g.pins, g.n_src, g.hedge_w, g.node_w)]
@@ -170,14 +271,14 @@ def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refi
     hg = Hypergraph_t(g.n_nodes, g.n_hedges, arrs[0].ctypes.data, p[1], p[2], p[3], p[4])
     parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
     res = Result_t()
-    o = options(k, max_refine_rounds)
+    o, _keep = options(k, max_refine_rounds, mlp=mlp)
     _check(lib.hgp_partition(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), parts.ctypes.data,
                              ctypes.byref(res)))
     return parts[:g.n_nodes], _result_dict(res)
 
 
 def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int, k: int = 0,
-                     max_refine_rounds: int = 8, out=None, flags: int = 0):
+                     max_refine_rounds: int = 8, out=None, flags: int = 0, mlp=None):
     """hgp_partition_device; returns (parts tensor on device, result dict)."""
     import torch
 
@@ -186,7 +287,7 @@ def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int,
         out = torch.empty(max(dg.n_nodes, 1), dtype=torch.int32, device=dg.hedge_off.device)
     hg = dg.struct()
     res = Result_t()
-    o = options(k, max_refine_rounds, 0, flags)
+    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp)
     _check(lib.hgp_partition_device(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), _stream(),
                                     out.data_ptr(), ctypes.byref(res)))
     return out[:dg.n_nodes], _result_dict(res)
@@ -279,3 +380,164 @@ def level_refine_round(ctx: Context, n, hoff, hpin, size, hw, rho, n_parts: int,
     S = int(info[0])
     return dict(dest=pdest[:n], gain=pgain[:n], seq=seq[:S], G=gsum[:S + 1], viol=viol[:S + 1], rho=rho_out[:n],
                 S=S, istar=int(info[1]), gstar=int(info[2]), applied=bool(info[3]))
+
+
+def level_learned(ctx: Context, n, hoff, hpin, size, hw, level: int, omega: int, delta: int, mlp, codes=True):
+    """hgp_level_learned: candidate sets, codes, scores and pairs of one level."""
+    import torch
+
+    lib = load()
+    dev = hoff.device
+    m = max(n, 1)
+    cap = 16 * m
+    coff = torch.empty(m + 1, dtype=torch.int64, device=dev)
+    cand = torch.empty(cap, dtype=torch.int32, device=dev)
+    xq = torch.empty(cap * MLP_F, dtype=torch.int32, device=dev) if codes else None
+    cscore = torch.empty(cap, dtype=torch.int64, device=dev)
+    pair = torch.empty(m, dtype=torch.int32, device=dev)
+    score = torch.empty(m, dtype=torch.int64, device=dev)
+    ppair = torch.empty(m, dtype=torch.int32, device=dev)
+    cnt = ctypes.c_int64()
+    lv = _level(n, hoff, hpin, size, hw)
+    q = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
+    _check(lib.hgp_level_learned(ctx.handle, ctypes.byref(lv), level, omega, delta, ctypes.byref(q), _stream(), cap,
+                                 coff.data_ptr(), cand.data_ptr(), xq.data_ptr() if codes else None,
+                                 cscore.data_ptr(), pair.data_ptr(), score.data_ptr(), ppair.data_ptr(),
+                                 ctypes.byref(cnt)))
+    C = int(cnt.value)
+    return dict(coff=coff[:n + 1], cand=cand[:C], xq=xq[:C * MLP_F].view(C, MLP_F) if codes else None,
+                cscore=cscore[:C], pair=pair[:n], score=score[:n], ppair=ppair[:n])
+
+
+def mlp_score_device(ctx: Context, mlp, xq):
+    """hgp_mlp_score_device on a device int32 tensor of shape [n, 16]; returns int64 scores."""
+    import torch
+
+    lib = load()
+    n = xq.shape[0]
+    out = torch.empty(max(n, 1), dtype=torch.int64, device=xq.device)
+    q = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
+    _check(lib.hgp_mlp_score_device(ctx.handle, ctypes.byref(q), _ptr(xq.contiguous()), n, out.data_ptr(),
+                                    _stream()))
+    return out[:n]
+
+
+# ---------------------------------------------------------------- training
+def mlp_init(seed: int) -> dict:
+    """Seeded initial float weights (hgp_mlp_init)."""
+    w = MlpF32_t()
+    load().hgp_mlp_init(ctypes.byref(w), seed)
+    return f32_to_dict(w)
+
+
+def mlp_grad(ctx: Context, w: dict, xq, y):
+    """Mean loss and gradient on device rows (xq int32 [n,16], y float32 [n])."""
+    lib = load()
+    wf = f32_from_dict(w)
+    g = MlpF32_t()
+    loss = ctypes.c_double()
+    _check(lib.hgp_mlp_grad(ctx.handle, ctypes.byref(wf), _ptr(xq.contiguous()), _ptr(y.contiguous()), xq.shape[0],
+                            ctypes.byref(g), ctypes.byref(loss), _stream()))
+    return f32_to_dict(g), float(loss.value)
+
+
+def mlp_train(ctx: Context, w: dict, xq, y, epochs=4, batch=4096, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              seed=0):
+    """Adam training on device rows; returns (trained float weights, per-epoch mean loss)."""
+    lib = load()
+    wf = f32_from_dict(w)
+    o = TrainOpts_t(epochs, batch, lr, beta1, beta2, eps, seed)
+    losses = (ctypes.c_float * max(epochs, 1))()
+    _check(lib.hgp_mlp_train(ctx.handle, ctypes.byref(wf), _ptr(xq.contiguous()), _ptr(y.contiguous()),
+                             xq.shape[0], ctypes.byref(o), losses, _stream()))
+    return f32_to_dict(wf), [float(losses[i]) for i in range(epochs)]
+
+
+def mlp_quantize(w: dict, xq_calib, k: int = 8):
+    """Integer network from float weights and host calibration codes; returns (dict, score_shift)."""
+    lib = load()
+    wf = f32_from_dict(w)
+    x = np.ascontiguousarray(xq_calib, dtype=np.int32).reshape(-1, MLP_F)
+    q = Mlp_t()
+    sh = ctypes.c_int32()
+    _check(lib.hgp_mlp_quantize(ctypes.byref(wf), x.ctypes.data if x.size else None, len(x), k, ctypes.byref(q),
+                                ctypes.byref(sh)))
+    return mlp_to_dict(q), int(sh.value)
+
+
+def partition_traced(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refine_rounds: int = 8):
+    """Plain partition of a host hypergraph with merge traces.  Returns
+    (parts, result dict, trace dict with xq[rows,16], label, level, node, cand)."""
+    lib = load()
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (g.hedge_off, g.pins, g.n_src, g.hedge_w, g.node_w)]
+    p = [a.ctypes.data if a.size else None for a in arrs]
+    hg = Hypergraph_t(g.n_nodes, g.n_hedges, arrs[0].ctypes.data, p[1], p[2], p[3], p[4])
+    parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
+    res = Result_t()
+    o, _keep = options(k, max_refine_rounds)
+    t = ctypes.c_void_p()
+    _check(lib.hgp_trace_create(ctypes.byref(t)))
+    try:
+        _check(lib.hgp_partition_traced(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), t,
+                                        parts.ctypes.data, ctypes.byref(res)))
+        rows = int(lib.hgp_trace_rows(t))
+        xq = np.zeros((max(rows, 1), MLP_F), np.int32)
+        label = np.zeros(max(rows, 1), np.float32)
+        level = np.zeros(max(rows, 1), np.int32)
+        node = np.zeros(max(rows, 1), np.int32)
+        cand = np.zeros(max(rows, 1), np.int32)
+        _check(lib.hgp_trace_read(t, xq.ctypes.data, label.ctypes.data, level.ctypes.data, node.ctypes.data,
+                                  cand.ctypes.data))
+    finally:
+        lib.hgp_trace_destroy(t)
+    tr = dict(xq=xq[:rows], label=label[:rows], level=level[:rows], node=node[:rows], cand=cand[:rows])
+    return parts[:g.n_nodes], _result_dict(res), tr
+
+
+# ---------------------------------------------------------------- batches
+def _batch_args(dgs, omegas, deltas, outs):
+    import torch
+
+    n = len(dgs)
+    hg = (Hypergraph_t * max(n, 1))()
+    for i, d in enumerate(dgs):
+        hg[i] = d.struct()
+    om = np.ascontiguousarray(omegas, dtype=np.int32)
+    de = np.ascontiguousarray(deltas, dtype=np.int32)
+    if outs is None:
+        outs = [torch.empty(max(d.n_nodes, 1), dtype=torch.int32, device=d.hedge_off.device) for d in dgs]
+    po = (ctypes.c_void_p * max(n, 1))()
+    for i, o in enumerate(outs):
+        po[i] = o.data_ptr()
+    return n, hg, om, de, outs, po
+
+
+def partition_batch_device(ctx: Context, dgs, omegas, deltas, sched=None, outs=None, k: int = 0,
+                           max_refine_rounds: int = 8, flags: int = 0, mlp=None):
+    """hgp_partition_batch_device on a list of DeviceHypergraph.  sched: dict of
+    BatchSched_t fields (missing = tuned/default).  Returns (parts list,
+    result dicts, t_start_ms, t_end_ms)."""
+    lib = load()
+    n, hg, om, de, outs, po = _batch_args(dgs, omegas, deltas, outs)
+    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp)
+    sc = BatchSched_t(**(sched or {}))
+    res = (Result_t * max(n, 1))()
+    t0 = (ctypes.c_double * max(n, 1))()
+    t1 = (ctypes.c_double * max(n, 1))()
+    _check(lib.hgp_partition_batch_device(ctx.handle, n, hg, om.ctypes.data, de.ctypes.data, ctypes.byref(o),
+                                          ctypes.byref(sc), _stream(), po, res, t0, t1))
+    return ([outs[i][:dgs[i].n_nodes] for i in range(n)], [_result_dict(res[i]) for i in range(n)],
+            np.array(t0[:n]), np.array(t1[:n]))
+
+
+def batch_tune(ctx: Context, dgs, omegas, deltas, outs=None, flags: int = 0):
+    """hgp_batch_tune; returns (schedule dict, wall ms of the best schedule)."""
+    lib = load()
+    n, hg, om, de, outs, po = _batch_args(dgs, omegas, deltas, outs)
+    o, _keep = options(0, 8, 0, flags)
+    best = BatchSched_t()
+    ms = ctypes.c_double()
+    _check(lib.hgp_batch_tune(ctx.handle, n, hg, om.ctypes.data, de.ctypes.data, ctypes.byref(o), _stream(), po,
+                              ctypes.byref(best), ctypes.byref(ms)))
+    return dict(workers=best.workers, order=best.order, rate_tile=best.rate_tile,
+                late_levels=best.late_levels), float(ms.value)

@@ -36,7 +36,7 @@ def test_strerror_and_defaults_without_gpu():
     lib = hgp.load()
     assert lib.hgp_strerror(hgp.EBADCSR) == b"malformed CSR hypergraph"
     assert lib.hgp_strerror(12345) == b"unknown error"
-    o = hgp.options()
+    o, _ = hgp.options()
     assert o.k == 0 and o.max_refine_rounds == 8 and o.proposal == hgp.PLAIN
     assert lib.hgp_ctx_create(None, 0) == hgp.EINVAL
     assert lib.hgp_partition(None, None, 1, 1, None, None, None) == hgp.EINVAL

@@ -1,0 +1,220 @@
+"""Learned merge proposal on the GPU vs the CPU oracle (through the C-ABI).
+
+The network is a fixed-point integer network evaluated with BF16 MFMA and
+FP32 accumulation; all partial sums are exact, so every comparison is exact:
+scores, candidate sets, input codes, pairs, matchings and whole partitions.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2604_14411_amd import synth
+from paper_2604_14411_amd.synth import feature_codes, from_lists, random_int_mlp
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2604_14411_amd import hgp
+
+    assert torch.cuda.is_available()
+    c = hgp.Context(0)
+    yield c
+    c.close()
+
+
+def _t(a, dt=None):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a) if dt is None else np.ascontiguousarray(a, dtype=dt)).to("cuda:0")
+
+
+def _zero_mlp(k=8, b3=0):
+    return dict(k=k, r1=0, r2=0, b3=b3, w1=np.zeros((16, 64), np.int32), b1=np.zeros(64, np.int32),
+                w2=np.zeros((64, 64), np.int32), b2=np.zeros(64, np.int32), w3=np.zeros(64, np.int32))
+
+
+def _identity_on(feature, k=8):
+    q = _zero_mlp(k)
+    q["w1"][feature, 0] = 1
+    q["w2"][0, 0] = 1
+    q["w3"][0] = 1
+    return q
+
+
+# ------------------------------------------------------------------ network
+@pytest.mark.parametrize("seed,n", [(0, 1), (1, 31), (2, 32), (3, 33), (4, 1000), (5, 40961)])
+def test_network_scores_exact(ctx, seed, n):
+    from paper_2604_14411_amd import hgp
+
+    q = random_int_mlp(100 + seed)
+    x = feature_codes(200 + seed, n)
+    # full-range rows too: all 16 codes at the extremes
+    if n > 4:
+        x[0, :] = 255
+        x[1, :] = 0
+        x[2, :10] = 255
+    say(f"[mlp] seed={seed} rows={n}")
+    got = hgp.mlp_score_device(ctx, q, _t(x, np.int32)).cpu().numpy()
+    ref = oracle.mlp_score(q, x)
+    assert np.array_equal(got, ref)
+
+
+def test_network_special_cases_exact(ctx):
+    from paper_2604_14411_amd import hgp
+
+    x = np.zeros((70, 16), np.int32)
+    x[:, 0] = np.arange(70) * 3 % 256
+    x[:, 1] = np.arange(70)[::-1]
+    nets = [_zero_mlp(b3=-17), _identity_on(0), _identity_on(1)]
+    q = _identity_on(0)
+    q["r1"] = 1
+    nets.append(q)
+    q = random_int_mlp(7, r1=0, r2=0)
+    nets.append(q)  # saturating activations
+    q = random_int_mlp(8, r1=20, r2=20)
+    nets.append(q)  # vanishing activations
+    for i, q in enumerate(nets):
+        say(f"[mlp] special {i}")
+        got = hgp.mlp_score_device(ctx, q, _t(x, np.int32)).cpu().numpy()
+        assert np.array_equal(got, oracle.mlp_score(q, x)), i
+
+
+def test_network_rejects_bad_parameters(ctx):
+    from paper_2604_14411_amd import hgp
+
+    x = _t(np.zeros((4, 16), np.int32))
+    q = random_int_mlp(1)
+    q["w2"][0, 0] = 300
+    with pytest.raises(hgp.HgpError) as e:
+        hgp.mlp_score_device(ctx, q, x)
+    assert e.value.code == hgp.EINVAL
+    q = random_int_mlp(1, k=9)
+    g = synth.random_snn(50, 4.0, 1)
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    with pytest.raises(hgp.HgpError) as e:
+        hgp.partition_device(ctx, dg, 8, 40, mlp=q)
+    assert e.value.code == hgp.EUNSUPPORTED
+
+
+# ------------------------------------------------------------------ one level
+LEVEL_CASES = [
+    ("rand900", lambda: synth.random_snn(900, 14.0, 41), 40, 200, 8),
+    ("rand900_k3", lambda: synth.random_snn(900, 14.0, 42), 40, 200, 3),
+    ("conv", lambda: synth.layered_conv(4, 5, 7, 7, 3, 0.1, 43), 40, 900, 8),
+]
+
+
+@pytest.mark.parametrize("name,make,omega,delta,k", LEVEL_CASES, ids=[c[0] for c in LEVEL_CASES])
+def test_each_learned_level_matches_oracle_trace(ctx, name, make, omega, delta, k):
+    from paper_2604_14411_amd import hgp
+
+    g = make()
+    q = random_int_mlp(300, k=k)
+    rc, parts, res, tr = oracle.partition_learned(g, omega, delta, q, trace=True)
+    assert rc == 0
+    hw = _t(g.hedge_w, np.int32)
+    for l in range(tr.levels):
+        hoff = _t(tr.get(oracle.LV_HOFF, l), np.int32)
+        hpin = _t(tr.get(oracle.LV_HPIN, l), np.int32)
+        size = _t(tr.get(oracle.LV_SIZE, l), np.int32)
+        n = size.numel()
+        say(f"[learned-steps] {name} level {l} n={n}")
+        out = hgp.level_learned(ctx, n, hoff, hpin, size, hw, l, omega, delta, q)
+        assert np.array_equal(out["coff"].cpu().numpy(), tr.get(oracle.LV_COFF, l)), f"offsets level {l}"
+        assert np.array_equal(out["cand"].cpu().numpy(), tr.get(oracle.LV_CAND, l)), f"candidates level {l}"
+        assert np.array_equal(out["xq"].cpu().numpy().reshape(-1), tr.get(oracle.LV_FEAT, l)), f"codes level {l}"
+        assert np.array_equal(out["cscore"].cpu().numpy(), tr.get(oracle.LV_CSCORE, l)), f"scores level {l}"
+        assert np.array_equal(out["pair"].cpu().numpy(), tr.get(oracle.LV_PAIR, l)), f"pair level {l}"
+        assert np.array_equal(out["score"].cpu().numpy(), tr.get(oracle.LV_SCORE, l)), f"score level {l}"
+        assert np.array_equal(out["ppair"].cpu().numpy(), tr.get(oracle.LV_PPAIR, l)), f"plain pair level {l}"
+
+
+# ------------------------------------------------------------------ whole partitions
+def _gpu_learned(ctx, g, omega, delta, q, k=0, rounds=8):
+    from paper_2604_14411_amd import hgp
+
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    try:
+        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds, mlp=q)
+        return 0, parts.cpu().numpy(), res
+    except hgp.HgpError as e:
+        return e.code, None, None
+
+
+def _compare(ctx, g, omega, delta, q, k=0, rounds=8, label=""):
+    say(f"[learned] {label} n={g.n_nodes} E={g.n_hedges} P={g.n_pins} omega={omega} delta={delta} K={q['k']}")
+    rc, ref, rres, _ = oracle.partition_learned(g, omega, delta, q, k=k, max_rounds=rounds)
+    grc, got, gres = _gpu_learned(ctx, g, omega, delta, q, k, rounds)
+    assert grc == rc, (grc, rc)
+    if rc != 0:
+        return None
+    assert np.array_equal(got, ref), "part ids differ"
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds", "n_fallback"):
+        assert gres[key] == rres[key], (key, gres[key], rres[key])
+    return gres
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_tiny_learned_end_to_end(ctx, seed):
+    rng = random.Random(seed)
+    n = rng.randint(1, 14)
+    hedges, w, nw = brute.random_tiny(rng, n, rng.randint(0, 12), 6, wmax=6, node_wmax=rng.choice([1, 1, 3]))
+    g = from_lists(n, hedges, w, nw)
+    q = random_int_mlp(seed, k=rng.choice([1, 2, 5, 8])) if seed % 4 else _zero_mlp(k=8)
+    _compare(ctx, g, rng.randint(1, 9), rng.randint(0, 8), q, rng.choice([0, 0, 2]), rng.choice([1, 8]),
+             label=f"tiny seed={seed}")
+
+
+MEDIUM = [
+    ("rand1500", lambda: synth.random_snn(1500, 24.0, 51), 64, 200),
+    ("rand4000", lambda: synth.random_snn(4000, 40.0, 52), 128, 600),
+    ("conv_small", lambda: synth.layered_conv(4, 6, 8, 8, 3, 0.1, 53), 64, 2000),
+    ("conv_wide", lambda: synth.layered_conv(5, 4, 10, 9, 5, 0.2, 54), 96, 500),
+]
+
+
+@pytest.mark.parametrize("name,make,omega,delta", MEDIUM, ids=[m[0] for m in MEDIUM])
+def test_medium_learned_end_to_end(ctx, name, make, omega, delta):
+    _compare(ctx, make(), omega, delta, random_int_mlp(77), label=name)
+
+
+def test_constant_network_exercises_fallback(ctx):
+    total = 0
+    for i, (name, make, omega, delta) in enumerate(MEDIUM[:2]):
+        res = _compare(ctx, make(), omega, delta, _zero_mlp(k=8), label=f"{name} constant")
+        total += res["n_fallback"]
+    assert total > 0
+
+
+def test_identity_on_hist_reproduces_plain_gpu(ctx):
+    from paper_2604_14411_amd import hgp
+
+    for seed in range(20):
+        rng = random.Random(5000 + seed)
+        n = rng.randint(2, 12)
+        hedges, _, nw = brute.random_tiny(rng, n, rng.randint(1, 14), 5, wmax=1, node_wmax=rng.choice([1, 2]))
+        g = from_lists(n, hedges, None, nw)
+        omega, delta = rng.randint(2, 9), rng.randint(1, 7)
+        dg = hgp.DeviceHypergraph(g, "cuda:0")
+        say(f"[learned] identity-on-hist seed={seed}")
+        try:
+            p1, r1 = hgp.partition_device(ctx, dg, omega, delta)
+            p2, r2 = hgp.partition_device(ctx, dg, omega, delta, mlp=_identity_on(0))
+        except hgp.HgpError as e:
+            assert e.code == hgp.EINFEASIBLE
+            continue
+        assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy())
+        assert r1["connectivity"] == r2["connectivity"] and r2["n_fallback"] == 0

@@ -147,7 +147,7 @@ def test_seed_does_not_change_plain_result(ctx):
 
     outs = []
     for seed in (1, 987654321):
-        o = hgp.options(0, 8, seed)
+        o, _ = hgp.options(0, 8, seed)
         import torch
 
         out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
