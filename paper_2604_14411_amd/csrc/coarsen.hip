@@ -158,7 +158,9 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
   __shared__ int64_t red_h[NT / 64];
   __shared__ int32_t red_m[NT / 64];
   __shared__ int32_t tbl[NT / 64 * 192];
-  const int n = blockIdx.x;
+  __shared__ int2 rng_s[NT / 64];
+  const int n = xcd_node((int)blockIdx.x, N);
+  if (n < 0) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = lane_id();
   int best_m = -1;
@@ -175,8 +177,10 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
     const int R = packed ? words : (words >> 1);
     const int i0 = ioff[n], i1 = ioff[n + 1];
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
-    for (int lo = 0; lo < N; lo += R) {
-      const int span = min(R, N - lo);
+    // windows over the neighbours' id range only
+    const int2 rg = neighbour_range<NT>(i0, i1, inc, hoff, hpin, rng_s);
+    for (int lo = rg.x; lo <= rg.y; lo += R) {
+      const int span = min(R, rg.y + 1 - lo);
       const int zw = packed ? span : 2 * span;
       for (int i = tid; i < zw; i += NT) lds[i] = 0u;
       __syncthreads();
@@ -452,7 +456,7 @@ static void launch_rate_nt(const LevelView &L, const int32_t *total, int32_t ome
     return true;
   }();
   (void)attr_set;
-  k_rate<NT><<<L.n, NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
+  k_rate<NT><<<xcd_grid(L.n), NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
                                                 omega, delta, words, pair, score, units_ptr(0));
   HGP_LAUNCH_CHECK();
 }

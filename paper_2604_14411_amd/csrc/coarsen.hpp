@@ -64,8 +64,11 @@ void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const
 // --- seg.hip ---
 void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
                           int32_t *cnt, hipStream_t s);
+// Part tables of hedges with at most kWaveSegMax pins and inb(p) of their
+// entries: pinb[0 .. n_parts) is written (not accumulated).  partial: scratch.
 void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, int32_t *pinb, hipStream_t s);
+                            int32_t *ptin, int32_t *lam, int32_t *pinb, int32_t n_parts, DevBuf &partial,
+                            hipStream_t s);
 void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s);
 
 void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s);
@@ -118,6 +121,7 @@ struct RoundBufs {
   int64_t *esum = nullptr;     // [cap_events + 1] prefix sums of size deltas over sorted events
   int32_t *isum = nullptr;     // [cap_events + 1] prefix sums of inbound deltas over sorted events
   int64_t *poff = nullptr;     // [n_parts + 1] first sorted event of every part
+  DevBuf *partial = nullptr;   // per-workgroup inb(p) rows of the part-table kernel
   int64_t cap_events = 0;
 };
 

@@ -206,6 +206,51 @@ __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_
   return streamed;
 }
 
+// Workgroups are dealt to the device's 8 XCDs round-robin by workgroup index.
+// xcd_node maps workgroup b of a grid of xcd_grid(N) to a node so that XCD x
+// handles the contiguous ids [x*per, (x+1)*per): nodes with nearby ids share
+// hedges in layered networks, and their pin re-reads then hit the same L2.
+// Returns -1 for the padding workgroups.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_grid(int N) { return ((N + kXcds - 1) / kXcds) * kXcds; }
+__device__ __forceinline__ int xcd_node(int b, int N) {
+  const int per = (N + kXcds - 1) / kXcds;
+  const int n = (b % kXcds) * per + b / kXcds;
+  return n < N ? n : -1;
+}
+
+// Smallest and largest pin id over the hedges of incidences [i0, i1) (pins are
+// ascending per hedge: first and last pin).  Block-wide; red: NT/64 int2 of LDS.
+// Empty range: (INT_MAX, -1).
+template <int NT>
+__device__ int2 neighbour_range(int i0, int i1, const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
+                                const uint32_t *__restrict__ hpin, int2 *red) {
+  int lo = 0x7fffffff, hi = -1;
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += NT) {
+    const int e = (int)(inc[i] & kIdMask);
+    const int b = hoff[e], en = hoff[e + 1];
+    if (en > b) {
+      lo = min(lo, (int)(hpin[b] & kIdMask));
+      hi = max(hi, (int)(hpin[en - 1] & kIdMask));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o, 64));
+    hi = max(hi, __shfl_xor(hi, o, 64));
+  }
+  if (lane_id() == 0) red[threadIdx.x >> 6] = make_int2(lo, hi);
+  __syncthreads();
+  int2 r = red[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) {
+    r.x = min(r.x, red[q].x);
+    r.y = max(r.y, red[q].y);
+  }
+  __syncthreads();
+  return r;
+}
+
 // Adds a per-wave count to a device counter (one atomic per wave).
 __device__ __forceinline__ void add_wave_units(unsigned long long *units, int64_t v) {
   if (units && lane_id() == 0 && v) atomicAdd(units, (unsigned long long)v);

@@ -70,7 +70,9 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
   __shared__ uint64_t wk[CAND_NT / 64][kCandK];
   __shared__ int32_t wc[CAND_NT / 64][kCandK];
   __shared__ int32_t tbl[CAND_NT / 64 * 192];
-  const int n = blockIdx.x;
+  __shared__ int2 rng_s[CAND_NT / 64];
+  const int n = xcd_node((int)blockIdx.x, N);
+  if (n < 0) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = lane_id();
   uint64_t kk[kCandK];
@@ -92,8 +94,10 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     const int R = packed ? words : (words >> 1);
     const int i0 = ioff[n], i1 = ioff[n + 1];
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
-    for (int lo = 0; lo < N; lo += R) {
-      const int span = min(R, N - lo);
+    // windows over the neighbours' id range only
+    const int2 rg = neighbour_range<CAND_NT>(i0, i1, inc, hoff, hpin, rng_s);
+    for (int lo = rg.x; lo <= rg.y; lo += R) {
+      const int span = min(R, rg.y + 1 - lo);
       const int zw = packed ? span : 2 * span;
       for (int i = tid; i < zw; i += CAND_NT) lds[i] = 0u;
       __syncthreads();
@@ -535,7 +539,7 @@ int64_t build_candidates(const LevelView &L, const int32_t *total, int32_t omega
     int words = N <= max_words / 2 ? 2 * N : max_words;
     words = (words + 1) & ~1;
     KScope ks(HGP_K_RATE, s);
-    k_rate_cand<<<N, CAND_NT, (size_t)words * 4, s>>>(N, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
+    k_rate_cand<<<xcd_grid(N), CAND_NT, (size_t)words * 4, s>>>(N, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
                                                       omega, delta, words, keep, B.ck, B.cc, B.ccnt,
                                                       units_ptr(HGP_K_RATE));
     HGP_LAUNCH_CHECK();

@@ -78,12 +78,12 @@ __global__ void k_part_size(const int32_t *__restrict__ rho, const int32_t *__re
 
 void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, RoundBufs &B, int32_t *err,
                        hipStream_t s) {
-  fill_i32(B.pinb, n_parts, 0, s);
   fill_i32(B.psize, n_parts, 0, s);
   KScope ks(2, s);
   add_units(2, 0);
+  if (!B.partial) throw Error(-7, "part-table scratch missing");
+  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.pinb, n_parts, *B.partial, s);
   if (L.E > 0) {
-    launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.pinb, s);
     if (L.big.n > 0) {
       k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.pinb, err, L.big.list);
       HGP_LAUNCH_CHECK();

@@ -2,6 +2,8 @@
 // registers (wave_bitonic_sort) without workgroup barriers.  Hedges with more
 // than kWaveSegMax pins are left to the workgroup-per-hedge kernels, which run
 // over the list of such hedges.
+#include <algorithm>
+
 #include "coarsen.hpp"
 
 namespace hgp {
@@ -122,27 +124,57 @@ __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uin
   wave_lds_sync();
 }
 
+// Grid-stride over hedges, one wave each.  inb(p) counts go to `cnt`: the
+// workgroup's LDS histogram when it covers every part (flushed to row
+// blockIdx.x of `partial`, summed per part by k_pinb_reduce), else the global
+// pinb array.
+constexpr int PTW_GRID = 512;
+constexpr int PTW_LDS_PARTS = 8192;
+
 __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restrict__ hoff,
                                                          const uint32_t *__restrict__ hpin, int32_t E,
                                                          const int32_t *__restrict__ rho, int2 *__restrict__ pt,
                                                          int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
-                                                         int32_t *__restrict__ pinb) {
+                                                         int32_t *__restrict__ pinb, int32_t n_parts,
+                                                         int32_t *__restrict__ partial) {
   __shared__ uint32_t sbuf[4][kWaveSegMax];
-  const int w = threadIdx.x >> 6;
-  const int e = (int)(blockIdx.x * 4 + w);
-  if (e >= E) return;
-  const int b = hoff[e], len = hoff[e + 1] - b;
-  if (len > kWaveSegMax) return;
-  if (len == 0) {
-    if (lane_id() == 0) lam[e] = 0;
-    return;
+  __shared__ int32_t hist[PTW_LDS_PARTS];
+  const bool local = partial != nullptr;
+  if (local) {
+    for (int i = threadIdx.x; i < n_parts; i += 256) hist[i] = 0;
+    __syncthreads();
   }
+  int32_t *cnt = local ? hist : pinb;
+  const int w = threadIdx.x >> 6;
   uint32_t *s = sbuf[w];
-  if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
-  else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
-  else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
-  else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
-  else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, pinb, s);
+  for (int e = (int)(blockIdx.x * 4 + w); e < E; e += (int)(gridDim.x * 4)) {
+    const int b = hoff[e], len = hoff[e + 1] - b;
+    if (len > kWaveSegMax) continue;
+    if (len == 0) {
+      if (lane_id() == 0) lam[e] = 0;
+      continue;
+    }
+    if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+    else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+    else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+    else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+    else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+  }
+  if (local) {
+    __syncthreads();
+    int32_t *row = partial + (int64_t)blockIdx.x * n_parts;
+    for (int i = threadIdx.x; i < n_parts; i += 256) row[i] = hist[i];
+  }
+}
+
+// pinb[p] = sum over the rows of partial (fixed order).
+__global__ void k_pinb_reduce(const int32_t *__restrict__ partial, int rows, int32_t n_parts,
+                              int32_t *__restrict__ pinb) {
+  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (p >= n_parts) return;
+  int32_t t = 0;
+  for (int r = 0; r < rows; ++r) t += partial[(int64_t)r * n_parts + p];
+  pinb[p] = t;
 }
 
 void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
@@ -153,9 +185,26 @@ void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, 
 }
 
 void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, int32_t *pinb, hipStream_t s) {
+                            int32_t *ptin, int32_t *lam, int32_t *pinb, int32_t n_parts, DevBuf &partial,
+                            hipStream_t s) {
+  if (n_parts > 0 && n_parts <= PTW_LDS_PARTS) {
+    const int grid = E > 0 ? std::min(PTW_GRID, div_up(E, 4)) : 0;
+    if (grid > 0) {
+      partial.reserve((size_t)grid * n_parts * sizeof(int32_t));
+      k_part_table_wave<<<grid, 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb, n_parts,
+                                             partial.as<int32_t>());
+      HGP_LAUNCH_CHECK();
+      k_pinb_reduce<<<div_up(n_parts, 256), 256, 0, s>>>(partial.as<int32_t>(), grid, n_parts, pinb);
+      HGP_LAUNCH_CHECK();
+    } else {
+      fill_i32(pinb, n_parts, 0, s);
+    }
+    return;
+  }
+  fill_i32(pinb, n_parts, 0, s);
   if (E <= 0) return;
-  k_part_table_wave<<<div_up(E, 4), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb);
+  k_part_table_wave<<<std::min(PTW_GRID, div_up(E, 4)), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb,
+                                                                     n_parts, nullptr);
   HGP_LAUNCH_CHECK();
 }
 

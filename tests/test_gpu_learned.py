@@ -218,3 +218,40 @@ def test_identity_on_hist_reproduces_plain_gpu(ctx):
             continue
         assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy())
         assert r1["connectivity"] == r2["connectivity"] and r2["n_fallback"] == 0
+
+
+# ------------------------------------------------------------------ the trained network
+def _trained():
+    import os
+
+    from paper_2604_14411_amd.learn import load_checkpoint
+
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_14411_amd",
+                        "mlp_v1.json")
+    q, w, ck = load_checkpoint(path)
+    return q
+
+
+def test_trained_network_matches_oracle(ctx):
+    q = _trained()
+    _compare(ctx, synth.random_snn(3000, 30.0, 81), 128, 600, q, label="trained rand3000")
+    _compare(ctx, synth.layered_conv(4, 8, 9, 9, 3, 0.1, 82), 256, 4000, q, label="trained conv")
+
+
+def test_trained_network_gains_over_plain(ctx):
+    """On a held-out random SNN (not a training graph) the trained proposal
+    coarsens in under half the levels of the plain rating and keeps the
+    connectivity within 2% of the plain method's."""
+    from paper_2604_14411_amd import hgp
+
+    q = _trained()
+    g = synth.random_snn(16384, 127.0, 1)
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    say("[gain] plain")
+    _, rp = hgp.partition_device(ctx, dg, 1024, 4096)
+    say("[gain] learned")
+    _, rl = hgp.partition_device(ctx, dg, 1024, 4096, mlp=q)
+    say(f"[gain] levels plain {rp['n_levels']} learned {rl['n_levels']}; conn plain {rp['connectivity']} "
+        f"learned {rl['connectivity']}")
+    assert 2 * rl["n_levels"] < rp["n_levels"]
+    assert rl["connectivity"] <= 1.02 * rp["connectivity"]
