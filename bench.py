@@ -44,6 +44,33 @@ COST = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(cls: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+    size), or None when there is none or a source it was taken from changed."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get("classes", {}).get(cls)
+    if not e:
+        return None
+    for rel, digest in e.get("sources", {}).items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return e["bytes_per_launch"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -211,13 +238,16 @@ def main():
     units_per_launch = a["units"] / a["launches"]
     if bound == "hbm":
         achieved = per_unit * units_per_launch / avg_s / 1e9
+        tb = measured_traffic(dom)
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None)
+                    traffic=None if tb is None else tb / avg_s / 1e9)
     else:
         achieved = per_unit * units_per_launch / avg_s / 1e12
+        tb = measured_traffic(dom)
         roof = dict(bound="alu", achieved=achieved, peak=LDS_ATOMIC_PEAK_TOPS, unit="TOP/s",
-                    frac=achieved / LDS_ATOMIC_PEAK_TOPS, traffic=None)
-    roof.update(kernel=dom, avg_launch_us=avg_s * 1e6, launches_per_step=a["launches"] / args.steps,
+                    frac=achieved / LDS_ATOMIC_PEAK_TOPS, traffic=None if tb is None else tb / avg_s / 1e9)
+    roof.update(kernel=dom, traffic_unit="GB/s", avg_launch_us=avg_s * 1e6,
+                launches_per_step=a["launches"] / args.steps,
                 units_per_launch=units_per_launch, share_of_step=a["ms"] / args.steps / ms_step)
 
     line = dict(metric="pins/s (sum |e| per second), whole constrained multilevel partition",

@@ -33,6 +33,7 @@ struct LevelView {
   const uint32_t *perm = nullptr;  // [P] pin position of incidence k
   const int32_t *size = nullptr;   // [n]
   const int32_t *indeg = nullptr;  // [n]
+  const int32_t *total = nullptr;  // [n] sum of w(e) over I(n)
   const int32_t *hw = nullptr;     // [E]
   BigHedges big;                   // hedges longer than kWaveSegMax (a superset is fine)
 };

@@ -28,6 +28,30 @@ static bool log_on() {
   return on;
 }
 
+// Bytes of coarse levels a context keeps for refinement: HGP_LEVEL_CACHE_GB
+// (default 48; 0 disables).  Batch workers keep 2 GB each.
+static int64_t level_cache_default() {
+  static const int64_t v = [] {
+    const char *e = std::getenv("HGP_LEVEL_CACHE_GB");
+    const double gb = e && e[0] ? std::atof(e) : 48.0;
+    return (int64_t)(gb > 0 ? gb * (double)(int64_t(1) << 30) : 0.0);
+  }();
+  return v;
+}
+
+// A coarse level kept in HBM between coarsening and refinement (its hedge
+// CSR and incidence), so refinement need not rebuild it from level 0.
+struct CachedLevel {
+  int lvl = -1;
+  int32_t n = 0;
+  int64_t P = 0;
+  int64_t bytes = 0;
+  DevBuf hoff, hpin, ioff, inc, perm, indeg, total;
+  void release() {
+    for (DevBuf *b : {&hoff, &hpin, &ioff, &inc, &perm, &indeg, &total}) b->release();
+  }
+};
+
 struct Workspace {
   DevBuf err, sums, scal2;
   DevBuf hpin0, hoffA, hoffB, hpinA, hpinB, hoffR, hpinR, tmp_pins, cnt;
@@ -48,11 +72,21 @@ struct Workspace {
   DevBuf split, cdest, cgain, maxbits, biglist;
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
+  // coarse levels kept for refinement: most recent last, within the budget
+  std::vector<std::unique_ptr<CachedLevel>> lcache, lcache_free;
+  int64_t lcache_bytes = 0;
+  int64_t lcache_budget = level_cache_default();
   int rate_tile = 512;         // rating workgroup size (schedule knob; same result)
   DevBuf tr_xq, tr_prm, tr_mom, tr_part, tr_perm, tr_loss, tr_grad;
   DevBuf mlp, ck, cc, ccnt, coff32, ctot, ckey, ckey2, cval, cval2, cflag, cnm, csrc, cs, ccoff, ppair, pscore,
       pmatch, pgam;
   std::vector<DevBuf> lv_match;
+
+  void clear_level_cache() {
+    for (auto &c : lcache) lcache_free.push_back(std::move(c));
+    lcache.clear();
+    lcache_bytes = 0;
+  }
 
   void clear_levels() {
     for (auto &b : lv_size) b.release();
@@ -75,6 +109,9 @@ struct Workspace {
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
+    clear_level_cache();
+    for (auto &c : lcache_free) c->release();
+    lcache_free.clear();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
                           &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam};
     for (DevBuf *b : inc_bufs) b->release();
@@ -84,6 +121,7 @@ struct Workspace {
 };
 
 }  // namespace hgp
+
 
 // Merge trace of one plain run (see hgp_partition_traced).
 struct hgp_trace {
@@ -253,6 +291,7 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   L.perm = perm;
   L.size = size;
   L.indeg = indeg;
+  L.total = total;
   L.hw = hw;
   L.big = big;
   return L;
@@ -311,9 +350,9 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
     int64_t *cnt = need<int64_t>(W.dev_cnt, 4);
     launch_prop_gather(L.n, carry->match, carry->gamma, W.cdest.as<int32_t>(), W.cgain.as<int32_t>(), B, list, cnt,
                        s);
-    launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s, list, cnt);
+    launch_propose(L, L.total, rho, n_parts, omega, B, s, list, cnt);
   } else {
-    launch_propose(L, W.total.as<int32_t>(), rho, n_parts, omega, B, s);
+    launch_propose(L, L.total, rho, n_parts, omega, B, s);
   }
   RoundResult R;
   R.S = build_sequence(L, B, W.scan_tmp, W.sort_tmp, s);
@@ -451,6 +490,49 @@ static void trace_label(hgp_trace &T, int32_t N, const int32_t *part) {
   }
 }
 
+// Keeps level `lvl` (view L over hoff/hpin with P pins) for refinement,
+// evicting the oldest kept levels beyond the budget.
+static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, hipStream_t s) {
+  const int32_t n = L.n, E = L.E;
+  const int64_t bytes = 4 * ((int64_t)E + 1) + 12 * P + 4 * ((int64_t)n + 1) + 8 * (int64_t)n;
+  if (bytes > W.lcache_budget) return;
+  while (!W.lcache.empty() && W.lcache_bytes + bytes > W.lcache_budget) {
+    W.lcache_bytes -= W.lcache.front()->bytes;
+    W.lcache_free.push_back(std::move(W.lcache.front()));
+    W.lcache.erase(W.lcache.begin());
+  }
+  std::unique_ptr<CachedLevel> c;
+  if (!W.lcache_free.empty()) {
+    c = std::move(W.lcache_free.back());
+    W.lcache_free.pop_back();
+  } else {
+    c.reset(new CachedLevel());
+  }
+  c->lvl = lvl;
+  c->n = n;
+  c->P = P;
+  c->bytes = bytes;
+  auto cp = [&](DevBuf &dst, const void *src, size_t b) {
+    dst.reserve(b);
+    if (b) HGP_HIP(hipMemcpyAsync(dst.ptr, src, b, hipMemcpyDeviceToDevice, s));
+  };
+  cp(c->hoff, L.hoff, 4 * ((size_t)E + 1));
+  cp(c->hpin, L.hpin, 4 * (size_t)P);
+  cp(c->ioff, L.ioff, 4 * ((size_t)n + 1));
+  cp(c->inc, L.inc, 4 * (size_t)P);
+  cp(c->perm, L.perm, 4 * (size_t)P);
+  cp(c->indeg, L.indeg, 4 * (size_t)n);
+  cp(c->total, L.total, 4 * (size_t)n);
+  W.lcache_bytes += bytes;
+  W.lcache.push_back(std::move(c));
+}
+
+static const CachedLevel *cached_level(const Workspace &W, int lvl) {
+  for (const auto &c : W.lcache)
+    if (c->lvl == lvl) return c.get();
+  return nullptr;
+}
+
 static double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -478,6 +560,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const int32_t *hw = I.hw;
   const int32_t *mlp_params = learned ? upload_mlp(W.mlp, opt.mlp, s) : nullptr;
   W.clear_levels();
+  W.clear_level_cache();
   W.lv_size.emplace_back();
   W.lv_n.push_back(N);
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
@@ -625,6 +708,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     ping ^= 1;
     ++lvl;
     L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s);
+    cache_level(W, L, lvl, cur_P, s);
     tail = (int64_t)M * kTailRatio <= (int64_t)n;
     const int wpi = (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget)
                         ? topk_words_per_id(W, L, s)
@@ -678,9 +762,28 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       // rho_lv(v) = rho_{lv+1}(gamma_lv(v))
       launch_project(W.lv_gamma[lv].as<int32_t>(), rho, n, rho2, s);
       std::swap(rho, rho2);
-      const int32_t *h;
-      const uint32_t *p;
-      if (lv == 0) {
+      const int32_t *h = nullptr;
+      const uint32_t *p = nullptr;
+      const CachedLevel *c = lv > 0 ? cached_level(W, lv) : nullptr;
+      if (log_on())
+        fprintf(stderr, "[hgp] refine level %d view %s (%zu levels kept, %.2f GB)\n", lv, c ? "kept" : "rebuilt",
+                W.lcache.size(), W.lcache_bytes / 1e9);
+      if (c) {
+        V.n = n;
+        V.E = E;
+        V.hoff = c->hoff.as<int32_t>();
+        V.hpin = c->hpin.as<uint32_t>();
+        V.ioff = c->ioff.as<int32_t>();
+        V.inc = c->inc.as<uint32_t>();
+        V.perm = c->perm.as<uint32_t>();
+        V.indeg = c->indeg.as<int32_t>();
+        V.total = c->total.as<int32_t>();
+        V.size = W.lv_size[lv].as<int32_t>();
+        V.hw = hw;
+        V.big = big;
+        Pl = c->P;
+        if (c->n != n) throw Error(HGP_EINTERNAL, "cached level size");
+      } else if (lv == 0) {
         h = hoff0;
         p = hpin0;
         Pl = P;
@@ -694,7 +797,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         h = rh;
         p = rp;
       }
-      V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, big, s);
+      if (!c) V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, big, s);
     }
     bool last_applied = false;
     int ran = 0;
@@ -1329,6 +1432,7 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
                       int32_t *const *part_out, hgp_result *res, double *t_start, double *t_end) {
   while ((int)ctx->pool.size() < sc.workers) {
     ctx->pool.emplace_back(new Workspace());
+    ctx->pool.back()->lcache_budget = int64_t(2) << 30;
     hipStream_t st = nullptr;
     HGP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     ctx->pool_streams.push_back(st);

@@ -23,8 +23,10 @@
 namespace hgp {
 
 constexpr int kClsEvents = 3;        // timing class of these kernels (sequence evaluation)
+constexpr int kClsSort = 6;          // timing class of sorts
 constexpr int EVW_NT = 128;          // two waves per workgroup
-constexpr int EVW_MAX_MOVING = 512;  // moving pins of a hedge handled by one wave
+constexpr int EVW_MAX_MOVING = 256;  // moving pins of a hedge handled by one wave
+constexpr int EVW_PT_STAGE = 256;    // part-table entries staged in LDS per wave
 constexpr int EVB_NT = 256;          // workgroup kernel for the remaining hedges
 constexpr int EVB_GRID = 512;
 static_assert(kSegCap <= 4096, "slot field of the workgroup event keys is 12 bits");
@@ -72,6 +74,19 @@ __device__ __forceinline__ int2 unpack_delta(int32_t pd) {
   return make_int2(p, (pd - p) >> 16);
 }
 
+// Part table of a hedge staged in LDS (parts ascending; counts packed as
+// pins | pins_in << 16, both <= kSegCap).
+__device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t *sc, int len, int p) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sp[mid] < p) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < len && sp[lo] == p) return make_int2((int)(sc[lo] & 0xffffu), (int)(sc[lo] >> 16));
+  return make_int2(0, 0);
+}
+
 // One wave per hedge with at most EVW_MAX_MOVING moving pins; other hedges
 // with moving pins are queued in heavy[] for k_ev_block.
 // Key of a pin event: part << (qbits + 11) | position << 11 | slot << 2 |
@@ -84,6 +99,8 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
   __shared__ uint64_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int16_t li_s[EVW_NT / 64][EVW_MAX_MOVING];
+  __shared__ int32_t sp_s[EVW_NT / 64][EVW_PT_STAGE];
+  __shared__ uint32_t sc_s[EVW_NT / 64][EVW_PT_STAGE];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int e = (int)(blockIdx.x * (EVW_NT / 64) + w);
   if (e >= E) return;
@@ -126,14 +143,24 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
   }
   wave_lds_sync();
   const int nev = 2 * m;
+  const int32_t we = hw[e];
+  const int plen = lam[e];
+  // the hedge's part table in LDS (parts ascending; pins | pins_in << 16)
+  const bool staged = plen <= EVW_PT_STAGE;
+  int32_t *sp = sp_s[w];
+  uint32_t *sc = sc_s[w];
+  if (staged) {
+    for (int i = l; i < plen; i += 64) {
+      const int2 x = pt[b + i];
+      sp[i] = x.x;
+      sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
+    }
+  }
   if (nev <= 64) ev_wave_sort_scan<1>(nev, evk, pre);
   else if (nev <= 128) ev_wave_sort_scan<2>(nev, evk, pre);
   else if (nev <= 256) ev_wave_sort_scan<4>(nev, evk, pre);
-  else if (nev <= 512) ev_wave_sort_scan<8>(nev, evk, pre);
-  else ev_wave_sort_scan<16>(nev, evk, pre);
+  else ev_wave_sort_scan<8>(nev, evk, pre);
   wave_lds_sync();
-  const int32_t we = hw[e];
-  const int plen = lam[e];
   uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
   int nout = 0;
   for (int t = 0; t * 64 < nev; ++t) {
@@ -148,7 +175,7 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
       else hi = mid;
     }
     const int2 before = unpack_delta(pre[i] - pre[lo]);
-    const int2 c0 = pt_lookup(pt, ptin, b, plen, (int)part);
+    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, (int)part) : pt_lookup(pt, ptin, b, plen, (int)part);
     const bool dst_role = (k & 2ull) != 0;
     int2 *cp = &contrib[b + li[(int)((k >> 2) & 511ull)]];
     if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
@@ -175,19 +202,6 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const uint64_t q = (k >> 11) & qmask;
     ev[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
   }
-}
-
-// Part table of a hedge staged in LDS (parts ascending; counts packed as
-// pins | pins_in << 16, both <= kSegCap).
-__device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t *sc, int len, int p) {
-  int lo = 0, hi = len;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (sp[mid] < p) lo = mid + 1;
-    else hi = mid;
-  }
-  if (lo < len && sp[lo] == p) return make_int2((int)(sc[lo] & 0xffffu), (int)(sc[lo] >> 16));
-  return make_int2(0, 0);
 }
 
 // One workgroup per queued hedge (more than EVW_MAX_MOVING moving pins; at
@@ -320,14 +334,15 @@ __global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const 
 }
 
 // poff[p] = first sorted event of part p (p = 0 .. P; poff[P] = nev).
-__global__ void k_part_offsets(const uint64_t *__restrict__ ev, int64_t nev, int vshift, int32_t P,
+template <class K>
+__global__ void k_part_offsets(const K *__restrict__ ev, int64_t nev, int vshift, int32_t P,
                                int64_t *__restrict__ poff) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p > P) return;
   int64_t lo = 0, hi = nev;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)(ev[mid] >> vshift) < p) lo = mid + 1;
+    if ((int64_t)((uint64_t)ev[mid] >> vshift) < p) lo = mid + 1;
     else hi = mid;
   }
   poff[p] = lo;
@@ -335,12 +350,13 @@ __global__ void k_part_offsets(const uint64_t *__restrict__ ev, int64_t nev, int
 
 // Per sorted event: size delta (+-size(v) for the part left / joined) and
 // inbound-count delta (-1 / +1).
-__global__ void k_ev_vals(const uint64_t *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
+template <class K>
+__global__ void k_ev_vals(const K *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
                           const int32_t *__restrict__ seq, const int32_t *__restrict__ rho,
                           const int32_t *__restrict__ size, int64_t *__restrict__ esum, int32_t *__restrict__ isum) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nev) return;
-  const uint64_t k = ev[i];
+  const uint64_t k = (uint64_t)ev[i];
   const int type = (int)(k & 3ull);
   int64_t ds = 0;
   int32_t di = 0;
@@ -357,27 +373,48 @@ __global__ void k_ev_vals(const uint64_t *__restrict__ ev, int64_t nev, int vshi
 // At the last event of every (part, position) group: validity of the part
 // before the group (its previous position) and after it; a change adds +1
 // (valid -> invalid) or -1 to the violation delta at that position.
-__global__ void k_ev_transitions(const uint64_t *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
+template <class K>
+__global__ void k_ev_transitions(const K *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
                                  const int64_t *__restrict__ poff, const int32_t *__restrict__ psize,
                                  const int32_t *__restrict__ pinb, const int64_t *__restrict__ esum,
                                  const int32_t *__restrict__ isum, int32_t omega, int32_t delta,
                                  int32_t *__restrict__ vdelta) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nev) return;
-  const uint64_t g = ev[i] >> 2;
-  if (i + 1 < nev && (ev[i + 1] >> 2) == g) return;
-  const int p = (int)(ev[i] >> vshift);
+  const uint64_t g = (uint64_t)ev[i] >> 2;
+  if (i + 1 < nev && ((uint64_t)ev[i + 1] >> 2) == g) return;
+  const int p = (int)((uint64_t)ev[i] >> vshift);
   const int64_t b = poff[p];
   int64_t lo = b, hi = i;  // first event of the group
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((ev[mid] >> 2) < g) lo = mid + 1;
+    if (((uint64_t)ev[mid] >> 2) < g) lo = mid + 1;
     else hi = mid;
   }
   const int64_t s0 = psize[p] - esum[b], i0 = (int64_t)pinb[p] - isum[b];
   const bool valid_before = s0 + esum[lo] <= omega && i0 + isum[lo] <= delta;
   const bool valid_after = s0 + esum[i + 1] <= omega && i0 + isum[i + 1] <= delta;
   if (valid_before != valid_after) atomicAdd(&vdelta[g & qmask], valid_after ? -1 : 1);
+}
+
+__global__ void k_keys_to_u32(const uint64_t *__restrict__ in, int64_t n, uint32_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint32_t)in[i];
+}
+
+template <class K>
+static void events_after_sort(const LevelView &L, const K *keys, int64_t nev, int vshift, uint64_t qmask,
+                              const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta, RoundBufs &B,
+                              DevBuf &scan_tmp, hipStream_t s) {
+  k_part_offsets<K><<<div_up((int64_t)n_parts + 1, 256), 256, 0, s>>>(keys, nev, vshift, n_parts, B.poff);
+  HGP_LAUNCH_CHECK();
+  k_ev_vals<K><<<div_up(nev, 256), 256, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, B.esum, B.isum);
+  HGP_LAUNCH_CHECK();
+  scan_i64(B.esum, B.esum, nev, B.esum + nev, scan_tmp, s);
+  scan_i32(B.isum, B.isum, nev, B.isum + nev, scan_tmp, s);
+  k_ev_transitions<K><<<div_up(nev, 256), 256, 0, s>>>(keys, nev, vshift, qmask, B.poff, B.psize, B.pinb, B.esum,
+                                                       B.isum, omega, delta, B.vdelta);
+  HGP_LAUNCH_CHECK();
 }
 
 __global__ void k_init_invalid(const int32_t *__restrict__ psize, const int32_t *__restrict__ pinb, int32_t P,
@@ -512,20 +549,27 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   k_init_invalid<<<div_up(n_parts > 0 ? n_parts : 1, 256), 256, 0, s>>>(B.psize, B.pinb, n_parts, omega, delta,
                                                                          B.scal);
   HGP_LAUNCH_CHECK();
-  sort_keys(B.keys, B.keys2, nev, vshift + pbits, sort_tmp, s);
+  // keys of at most 32 bits are sorted as 32-bit words (half the traffic)
+  const int kbits = vshift + pbits;
+  const bool narrow = kbits <= 32 && nev > 8192;
+  uint32_t *k32 = reinterpret_cast<uint32_t *>(B.keys2);
+  if (narrow) {
+    KScope ks(kClsSort, s);
+    add_units(kClsSort, nev);
+    k_keys_to_u32<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, k32);
+    HGP_LAUNCH_CHECK();
+    radix_sort_u32(k32, reinterpret_cast<uint32_t *>(B.keys), nullptr, nullptr, nev, kbits, sort_tmp, s);
+  } else {
+    sort_keys(B.keys, B.keys2, nev, kbits, sort_tmp, s);
+  }
   {
     KScope ks(kClsEvents, s);
     const uint64_t qmask = (1ull << qbits) - 1ull;
     if (nev > 0) {
-      k_part_offsets<<<div_up((int64_t)n_parts + 1, 256), 256, 0, s>>>(B.keys, nev, vshift, n_parts, B.poff);
-      HGP_LAUNCH_CHECK();
-      k_ev_vals<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, vshift, qmask, B.seq, rho, L.size, B.esum, B.isum);
-      HGP_LAUNCH_CHECK();
-      scan_i64(B.esum, B.esum, nev, B.esum + nev, scan_tmp, s);
-      scan_i32(B.isum, B.isum, nev, B.isum + nev, scan_tmp, s);
-      k_ev_transitions<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, vshift, qmask, B.poff, B.psize, B.pinb, B.esum,
-                                                        B.isum, omega, delta, B.vdelta);
-      HGP_LAUNCH_CHECK();
+      if (narrow)
+        events_after_sort<uint32_t>(L, k32, nev, vshift, qmask, rho, n_parts, omega, delta, B, scan_tmp, s);
+      else
+        events_after_sort<uint64_t>(L, B.keys, nev, vshift, qmask, rho, n_parts, omega, delta, B, scan_tmp, s);
     }
     k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);
     HGP_LAUNCH_CHECK();

@@ -188,7 +188,8 @@ constexpr int RS_TILE = RS_NT * RS_ROUNDS;
 
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                   int32_t *__restrict__ hist, int ntiles) {
+                                                   int32_t *__restrict__ hist, int32_t *__restrict__ tcnt,
+                                                   int ntiles) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
@@ -198,15 +199,90 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
     if (j < n) atomicAdd(&cnt[(uint32_t)(keys[j] >> shift) & 255u], 1);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+  const int64_t o = (int64_t)threadIdx.x * ntiles + blockIdx.x;
+  hist[o] = cnt[threadIdx.x];
+  tcnt[o] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one 4096-key tile: keys are ranked in tile order within
-// their digit using wave match masks (8 ballots) and per-wave digit counts.
+// Stable scatter of one 4096-key tile.  Keys are ranked in tile order within
+// their digit (wave match masks from 8 ballots, per-wave digit counts) and
+// placed in LDS at their position in the tile's digit-sorted order; the tile
+// is then written out in that order, so each digit's run goes to consecutive
+// addresses.  offs: global start of (digit, tile); tcnt: (digit, tile) counts.
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
-                                                      int ntiles, K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
+                                                      const int32_t *__restrict__ tcnt, int ntiles,
+                                                      K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
+  __shared__ int32_t gbase[256];
+  __shared__ int32_t lstart[256];
+  __shared__ int32_t lnext[256];
+  __shared__ int32_t wcnt[RS_NT / 64][256];
+  __shared__ int32_t stmp[RS_NT / 64 + 1];
+  __shared__ K lkeys[RS_TILE];
+  __shared__ uint32_t lvals[RS_TILE];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int l = lane_id();
+  const int64_t o = (int64_t)tid * ntiles + blockIdx.x;
+  gbase[tid] = offs[o];
+  lstart[tid] = tcnt[o];
+  __syncthreads();
+  block_exclusive_scan<int32_t, RS_NT>(lstart, 256, stmp);
+  lnext[tid] = lstart[tid];
+  __syncthreads();
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+  const int tn = (int)min((int64_t)RS_TILE, n - tbase);
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
+    __syncthreads();
+    const int j = r * RS_NT + tid;
+    const bool valid = j < tn;
+    const K key = valid ? keys[tbase + j] : K(0);
+    const uint32_t val = (valid && vals) ? vals[tbase + j] : 0u;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(valid && bit);
+      match &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(match & lt);
+    const int cnt = __popcll(match);
+    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;  // last lane of the group publishes
+    __syncthreads();
+    if (valid) {
+      int pre = 0;
+      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
+      const int lp = lnext[d] + pre + rank;
+      lkeys[lp] = key;
+      if (vals) lvals[lp] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
+    lnext[tid] += add;
+    __syncthreads();
+  }
+  for (int i = tid; i < tn; i += RS_NT) {
+    const K key = lkeys[i];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
+    okeys[pos] = key;
+    if (vals) ovals[pos] = lvals[i];
+  }
+}
+
+// Direct variant for 64-bit keys: each ranked key goes straight to its
+// global slot (the LDS staging of 64-bit tiles costs more occupancy than the
+// coalescing gains).
+template <class K>
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict__ keys,
+                                                             const uint32_t *__restrict__ vals, int64_t n, int shift,
+                                                             const int32_t *__restrict__ offs, int ntiles,
+                                                             K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
   __shared__ int32_t base[256];
   __shared__ int32_t wcnt[RS_NT / 64][256];
   const int tid = threadIdx.x;
@@ -232,7 +308,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
     }
     const int rank = __popcll(match & lt);
     const int cnt = __popcll(match);
-    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;  // last lane of the group publishes
+    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
       int pre = 0;
@@ -256,18 +332,22 @@ static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int
   const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
   const int64_t hn = 256LL * ntiles;
   const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
-  const size_t need = hist_bytes + scan_tmp_elems(hn) * sizeof(int32_t);
+  const size_t need = 2 * hist_bytes + scan_tmp_elems(hn) * sizeof(int32_t);
   tmp.reserve(need);
   int32_t *hist = tmp.as<int32_t>();
-  int32_t *stmp = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
+  int32_t *tcnt = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
+  int32_t *stmp = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + 2 * hist_bytes);
   K *src = keys, *dst = alt;
   uint32_t *vs = vals, *vd = valt;
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
+    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, tcnt, ntiles);
     HGP_LAUNCH_CHECK();
     scan_impl<int32_t>(hist, hist, hn, nullptr, stmp, s);
-    k_rs_scatter<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+    if (sizeof(K) == 4)
+      k_rs_scatter<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
+    else
+      k_rs_scatter_direct<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
     HGP_LAUNCH_CHECK();
     std::swap(src, dst);
     std::swap(vs, vd);

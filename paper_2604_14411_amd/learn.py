@@ -42,6 +42,15 @@ TRAIN_SET = [
 ]
 
 
+# v2 adds layered networks with the evaluation instances' channel widths
+# (96 and 42 channels) on other spatial shapes and seeds.
+TRAIN_SET_V2 = TRAIN_SET + [
+    ("conv 8x(96x10x10) 3x3", lambda: synth.layered_conv(8, 96, 10, 10, 3, 0.1, 1201), 4096, 65536),
+    ("conv 8x(42x18x18) 5x5", lambda: synth.layered_conv(8, 42, 18, 18, 5, 0.1, 1202), 4096, 65536),
+]
+TRAIN_SETS = {"v1": TRAIN_SET, "v2": TRAIN_SET_V2}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -85,8 +94,8 @@ def train(out: str, epochs: int = 6, batch: int = 2048, lr: float = 2e-3, seed: 
     ck = dict(format="hgp-mlp-1", k=k, score_shift=shift,
               float={kk: (np.asarray(v).tolist() if not np.isscalar(v) else float(v)) for kk, v in w.items()},
               int={kk: (np.asarray(v).tolist() if not np.isscalar(v) else int(v)) for kk, v in q.items()},
-              train=dict(graphs=info, rows=int(len(y)), positive=float(y.mean()), epochs=epochs, batch=batch, lr=lr,
-                         seed=seed, loss=losses))
+              train=dict(set=[name for name, *_ in (train_set or TRAIN_SET)], graphs=info, rows=int(len(y)),
+                         positive=float(y.mean()), epochs=epochs, batch=batch, lr=lr, seed=seed, loss=losses))
     with open(out, "w") as f:
         json.dump(ck, f)
     log(f"[learn] wrote {out}")
@@ -115,8 +124,9 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=7)
     ap.add_argument("--max-rows", type=int, default=400_000)
+    ap.add_argument("--set", default="v1", choices=sorted(TRAIN_SETS))
     a = ap.parse_args()
-    train(a.out, a.epochs, a.batch, a.lr, a.seed, a.max_rows)
+    train(a.out, a.epochs, a.batch, a.lr, a.seed, a.max_rows, train_set=TRAIN_SETS[a.set])
 
 
 if __name__ == "__main__":
