@@ -95,15 +95,21 @@ def cpu_baseline(sample_n: int, mu: float, omega: int, delta: int):
 def bench_batch(args):
     """256 random SNNs (node counts log-uniform in [2048, 32768], |T_v| ~
     Poisson(mu)+1 with mu uniform in [32, 256], w in [1,16], seeds 4000+g),
-    partitioned as one batch; the schedule is tuned once, on a 32-graph
+    partitioned as one batch; the schedule is tuned once, on a 16-graph
     sample, before timing."""
     import numpy as np
     import torch
 
+    # one line per finished graph and per tuned schedule (the batch calls are long)
+    os.environ.setdefault("HGP_LOG_BATCH", "1")
     from paper_2604_14411_amd import hgp, synth
 
     t = time.perf_counter()
-    gs = [synth.random_snn_family(4000 + i)[0] for i in range(256)]
+    gs = []
+    for i in range(256):
+        gs.append(synth.random_snn_family(4000 + i)[0])
+        if i % 32 == 31:
+            log(f"[bench] generated {i + 1} graphs")
     pins = sum(g.n_pins for g in gs)
     log(f"[bench] batch of {len(gs)} graphs, {pins} pins, generated in {time.perf_counter() - t:.1f} s")
     ctx = hgp.Context(0)
@@ -112,11 +118,11 @@ def bench_batch(args):
     om, de = [1024] * len(gs), [4096] * len(gs)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    # tune on every 8th graph (32 graphs spanning the size range)
-    sample = list(range(0, len(gs), 8))
+    # tune on every 16th graph (16 graphs spanning the size range)
+    sample = list(range(0, len(gs), 16))
     sched, tune_ms = hgp.batch_tune(ctx, [dgs[i] for i in sample], [om[i] for i in sample], [de[i] for i in sample],
                                     outs=[outs[i] for i in sample])
-    log(f"[bench] tuned schedule {sched} ({tune_ms:.0f} ms for the 32-graph sample) in "
+    log(f"[bench] tuned schedule {sched} ({tune_ms:.0f} ms for the 16-graph sample) in "
         f"{time.perf_counter() - t:.1f} s")
     lat, done = [], []
     torch.cuda.synchronize()

@@ -20,6 +20,16 @@ namespace hgp {
 static thread_local std::string g_last_error;
 
 // HGP_LOG=1 prints one line per level and per refinement round to stderr.
+// HGP_LOG_BATCH=1 prints one line per finished graph of a batch and per
+// schedule the tuner times.
+static bool log_batch_on() {
+  static const bool on = [] {
+    const char *v = std::getenv("HGP_LOG_BATCH");
+    return v && v[0] && v[0] != '0';
+  }();
+  return on;
+}
+
 static bool log_on() {
   static const bool on = [] {
     const char *v = std::getenv("HGP_LOG");
@@ -29,7 +39,7 @@ static bool log_on() {
 }
 
 // Bytes of coarse levels a context keeps for refinement: HGP_LEVEL_CACHE_GB
-// (default 48; 0 disables).  Batch workers keep 2 GB each.
+// (default 48; 0 disables).  Batch workers keep none.
 static int64_t level_cache_default() {
   static const int64_t v = [] {
     const char *e = std::getenv("HGP_LEVEL_CACHE_GB");
@@ -82,6 +92,9 @@ struct Workspace {
       pmatch, pgam;
   std::vector<DevBuf> lv_match;
 
+  // Entries go back in level order and are taken from the front, so a
+  // repeated run on the same hypergraph gets each level's own buffers back
+  // (no reallocation, hence no device-wide synchronisation in hipFree).
   void clear_level_cache() {
     for (auto &c : lcache) lcache_free.push_back(std::move(c));
     lcache.clear();
@@ -503,8 +516,8 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, hi
   }
   std::unique_ptr<CachedLevel> c;
   if (!W.lcache_free.empty()) {
-    c = std::move(W.lcache_free.back());
-    W.lcache_free.pop_back();
+    c = std::move(W.lcache_free.front());
+    W.lcache_free.erase(W.lcache_free.begin());
   } else {
     c.reset(new CachedLevel());
   }
@@ -1432,7 +1445,10 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
                       int32_t *const *part_out, hgp_result *res, double *t_start, double *t_end) {
   while ((int)ctx->pool.size() < sc.workers) {
     ctx->pool.emplace_back(new Workspace());
-    ctx->pool.back()->lcache_budget = int64_t(2) << 30;
+    // no level cache in batch workers: graphs of different sizes would
+    // reallocate its buffers, and every hipFree synchronises the device
+    // across all workers
+    ctx->pool.back()->lcache_budget = 0;
     hipStream_t st = nullptr;
     HGP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     ctx->pool_streams.push_back(st);
@@ -1471,6 +1487,8 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
         const double b = now_ms() - t0;
         if (t_start) t_start[g] = a;
         if (t_end) t_end[g] = b;
+        if (log_batch_on())
+          fprintf(stderr, "[hgp] batch graph %d (n=%d) done at %.0f ms by worker %d\n", g, graphs[g].n_nodes, b, w);
         if (res) fill_result(&res[g], st);
       }
     } catch (const Error &e) {
@@ -1543,7 +1561,11 @@ int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs,
     auto time_of = [&](const hgp_batch_sched &c) {
       const double a = now_ms();
       run_batch(ctx, n_graphs, graphs, omega, delta, o, c, s, part_out, nullptr, nullptr, nullptr);
-      return now_ms() - a;
+      const double t = now_ms() - a;
+      if (log_batch_on())
+        fprintf(stderr, "[hgp] tune workers=%d order=%d tile=%d late=%d: %.0f ms\n", c.workers, c.order,
+                c.rate_tile, c.late_levels, t);
+      return t;
     };
     {
       hgp_batch_sched warm = cur;

@@ -59,8 +59,12 @@ void KTimer::destroy() {
 
 void DevBuf::reserve(size_t need) {
   if (need <= bytes) return;
+  const size_t old = bytes;
   release();
+  // grow by at least a quarter: fewer reallocations (each hipFree
+  // synchronises the device)
   size_t b = need < 256 ? 256 : need;
+  if (old && b < old + old / 4) b = old + old / 4;
   b = (b + 255) & ~size_t(255);
   hipError_t e = hipMalloc(&ptr, b);
   if (e != hipSuccess) {

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def test_checkpoint_is_a_valid_integer_network():
-    q, w, ck = load_checkpoint(os.path.join(HERE, "..", "paper_2604_14411_amd", "mlp_v1.json"))
+    q, w, ck = load_checkpoint(os.path.join(HERE, "..", "paper_2604_14411_amd", "mlp_v2.json"))
     assert ck["format"] == "hgp-mlp-1" and 1 <= q["k"] <= 8
     for key in ("w1", "w2", "w3"):
         assert np.abs(q[key]).max() <= 255

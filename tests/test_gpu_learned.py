@@ -227,7 +227,7 @@ def _trained():
     from paper_2604_14411_amd.learn import load_checkpoint
 
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2604_14411_amd",
-                        "mlp_v1.json")
+                        "mlp_v2.json")
     q, w, ck = load_checkpoint(path)
     return q
 
