@@ -67,6 +67,14 @@ typedef struct {
 #define HGP_PLAIN 0
 #define HGP_LEARNED 1 /* learned merge proposal (hgp_options.mlp) */
 
+/* hgp_options.constraint: which distinct hedges a part's Delta bound counts.
+ * The paper's constraint (Sec. II-A) counts inbound hedges (a destination pin
+ * in the part); the variants count hedges with a source pin in the part, or
+ * with any pin in it.  Every step runs unchanged on the selected pin role. */
+#define HGP_INBOUND 0
+#define HGP_OUTBOUND 1
+#define HGP_INCIDENT 2
+
 /* hgp_options.flags */
 #define HGP_FLAG_TIME_KERNELS 1   /* time kernel classes with HIP events on the call's stream */
 #define HGP_FLAG_NO_INCREMENTAL 2 /* rate every level and propose every round from scratch (same result) */
@@ -129,6 +137,8 @@ typedef struct {
   int32_t proposal;          /* HGP_PLAIN or HGP_LEARNED */
   int32_t flags;             /* HGP_FLAG_* bits, 0 by default */
   const hgp_mlp *mlp;        /* host memory; required with HGP_LEARNED, read during the call */
+  int32_t constraint;        /* HGP_INBOUND (default), HGP_OUTBOUND or HGP_INCIDENT */
+  int32_t reserved;          /* 0 */
 } hgp_options;
 
 typedef struct {

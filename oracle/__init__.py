@@ -76,6 +76,10 @@ def _load():
         lib.hgpo_partition.restype = ctypes.c_int
         lib.hgpo_partition.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_Res), ctypes.c_void_p]
+        lib.hgpo_partition_role.restype = ctypes.c_int
+        lib.hgpo_partition_role.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_Res),
+                                            ctypes.c_void_p]
         lib.hgpo_partition_learned.restype = ctypes.c_int
         lib.hgpo_partition_learned.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.POINTER(_MLP), ctypes.c_void_p,
@@ -148,16 +152,20 @@ class Trace:
         return np.frombuffer(buf, dtype=dt).copy()
 
 
-def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace: bool = False):
-    """Run the oracle.  Returns (rc, parts, result dict, Trace or None)."""
+INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
+
+
+def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace: bool = False, role: int = INBOUND):
+    """Run the oracle (role: which pins' hedges count toward Delta).
+    Returns (rc, parts, result dict, Trace or None)."""
     lib = _load()
     keep = []
     hg = _hg(g, keep)
     parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
     res = _Res()
     tr = Trace() if trace else None
-    rc = lib.hgpo_partition(ctypes.byref(hg), omega, delta, k, max_rounds, parts.ctypes.data, ctypes.byref(res),
-                            tr.ptr if tr else None)
+    rc = lib.hgpo_partition_role(ctypes.byref(hg), omega, delta, k, max_rounds, role, parts.ctypes.data,
+                                 ctypes.byref(res), tr.ptr if tr else None)
     out = dict(connectivity=res.connectivity, n_parts=res.n_parts, n_levels=res.n_levels, n_rounds=res.n_rounds)
     return rc, parts[:g.n_nodes], out, tr
 

@@ -841,7 +841,7 @@ int hgpo_connectivity(const hgpo_hypergraph *g, const int32_t *part, int64_t *ou
  * initial-part id, skipping emptied parts.
  */
 static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
-                          const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+                          const hgpo_mlp *mlp, int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
   int rc = validate(g, omega, delta, k, max_rounds);
   if (rc != HGPO_OK) return rc;
   if (!part_out && g->n_nodes > 0) return HGPO_EINVAL;
@@ -865,7 +865,13 @@ static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta
       const int32_t b = g->hedge_off[e], en = g->hedge_off[e + 1];
       const int32_t ns = g->n_src ? g->n_src[e] : 1;
       buf.clear();
-      for (int32_t j = b; j < en; ++j) buf.push_back({g->pins[j], (uint8_t)((j - b) >= ns ? 1 : 0)});
+      /* the pins whose hedges count toward Delta: destinations (inbound,
+       * Sec. II-A), sources (outbound) or all pins (incident) */
+      for (int32_t j = b; j < en; ++j) {
+        const bool dst = (j - b) >= ns;
+        const bool counted = role == HGPO_INBOUND ? dst : (role == HGPO_OUTBOUND ? !dst : true);
+        buf.push_back({g->pins[j], (uint8_t)(counted ? 1 : 0)});
+      }
       std::sort(buf.begin(), buf.end());
       for (auto &x : buf) {
         L0.hpin.push_back(x.first);
@@ -977,13 +983,19 @@ static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta
 
 int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                    int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
-  return partition_impl(g, omega, delta, k, max_rounds, nullptr, part_out, res, trace);
+  return partition_impl(g, omega, delta, k, max_rounds, nullptr, HGPO_INBOUND, part_out, res, trace);
+}
+
+int hgpo_partition_role(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                        int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+  if (role != HGPO_INBOUND && role != HGPO_OUTBOUND && role != HGPO_INCIDENT) return HGPO_EINVAL;
+  return partition_impl(g, omega, delta, k, max_rounds, nullptr, role, part_out, res, trace);
 }
 
 int hgpo_partition_learned(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                            const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
   if (!mlp_ok(mlp)) return HGPO_EINVAL;
-  return partition_impl(g, omega, delta, k, max_rounds, mlp, part_out, res, trace);
+  return partition_impl(g, omega, delta, k, max_rounds, mlp, HGPO_INBOUND, part_out, res, trace);
 }
 
 int hgpo_mlp_score(const hgpo_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score) {

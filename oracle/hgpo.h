@@ -124,6 +124,14 @@ enum {
 int hgpo_partition(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                    int32_t *part_out, hgpo_result *res, hgpo_trace *trace);
 
+/* Roles of the pins whose hedges count toward Delta: inbound (destination
+ * pins, the paper's constraint), outbound (source pins), incident (all). */
+enum { HGPO_INBOUND = 0, HGPO_OUTBOUND = 1, HGPO_INCIDENT = 2 };
+
+/* As hgpo_partition with the Delta bound counting the hedges of `role`. */
+int hgpo_partition_role(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                        int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace);
+
 /* As hgpo_partition with the learned merge proposal (mlp non-NULL). */
 int hgpo_partition_learned(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                            const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace);

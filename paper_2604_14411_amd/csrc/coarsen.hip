@@ -43,9 +43,12 @@ __global__ void k_check_weights(const int32_t *__restrict__ hw, int32_t E, const
 
 // One workgroup per hedge: tag destinations, sort pins by id, reject
 // out-of-range pins, duplicates and bad source counts.
+// Bit 31 of a canonical pin marks the pins whose hedges count toward Delta
+// for their part: destinations (inbound, Sec. II-A), sources (outbound) or
+// every pin (incident); `role` is HGP_INBOUND / HGP_OUTBOUND / HGP_INCIDENT.
 __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                  const int32_t *__restrict__ nsrc, int32_t N, int32_t *err,
-                                                  uint32_t *__restrict__ hpin) {
+                                                  const int32_t *__restrict__ nsrc, int32_t N, int32_t role,
+                                                  int32_t *err, uint32_t *__restrict__ hpin) {
   __shared__ uint32_t key[kSegCap];
   const int e = blockIdx.x;
   const int b = off[e];
@@ -62,7 +65,9 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
         atomicOr(err, kErrPin);
         k = 0xfffffffeu;
       } else {
-        k = ((uint32_t)v << 1) | (i >= ns ? 1u : 0u);
+        const bool dst = i >= ns;
+        const uint32_t f = role == 0 ? (dst ? 1u : 0u) : role == 1 ? (dst ? 0u : 1u) : 1u;
+        k = ((uint32_t)v << 1) | f;
       }
     }
     key[i] = k;
@@ -404,10 +409,10 @@ void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32
   HGP_LAUNCH_CHECK();
 }
 
-void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
+void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t role, int32_t *err,
                   uint32_t *hpin, hipStream_t s) {
   if (E <= 0) return;
-  k_canon<<<E, SEG_NT, 0, s>>>(off, pins, nsrc, N, err, hpin);
+  k_canon<<<E, SEG_NT, 0, s>>>(off, pins, nsrc, N, role, err, hpin);
   HGP_LAUNCH_CHECK();
 }
 

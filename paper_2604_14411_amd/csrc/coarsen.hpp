@@ -42,7 +42,7 @@ struct LevelView {
 void launch_check_offsets(const int32_t *off, int32_t E, int32_t *err, hipStream_t s);
 void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32_t N, int32_t *err,
                           unsigned long long *sums, hipStream_t s);
-void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t *err,
+void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t role, int32_t *err,
                   uint32_t *hpin, hipStream_t s);
 // Incidence I(n) (ascending hedge ids, destination flag in bit 31), the pin
 // position perm[k] of every incidence k, |in(n)| and total(n) of a level;

@@ -79,7 +79,7 @@ struct Workspace {
   DevBuf units_dev;
   // incremental late levels
   DevBuf tkA_key, tkA_cnt, tkA_kap, tkB_key, tkB_cnt, tkB_kap, rows, newc, row_slot, nflag, rerate, dev_cnt;
-  DevBuf split, cdest, cgain, maxbits, biglist;
+  DevBuf split, cdest, cgain, maxbits, biglist, tail_acc;
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
   // coarse levels kept for refinement: most recent last, within the budget
@@ -126,7 +126,7 @@ struct Workspace {
     for (auto &c : lcache_free) c->release();
     lcache_free.clear();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     clear_levels();
@@ -227,7 +227,8 @@ struct Ingest {
 
 // Validate a device hypergraph (Sec. II-C layout) and build its canonical
 // level-0 pins: per hedge, ids ascending with the destination flag in bit 31.
-static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32_t delta, hipStream_t s) {
+static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32_t delta, hipStream_t s,
+                     int32_t role = HGP_INBOUND) {
   check_scalars(g, omega, delta);
   Ingest I;
   const int32_t N = g->n_nodes, E = g->n_hedges;
@@ -242,7 +243,7 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
   unsigned long long *sums = need<unsigned long long>(W.sums, 2);
   fill_i64(reinterpret_cast<int64_t *>(sums), 2, 0, s);
   launch_check_weights(g->hedge_w, E, g->node_w, N, err, sums, s);
-  launch_canon(g->hedge_off, g->pins, g->n_src, E, N, err, I.hpin0, s);
+  launch_canon(g->hedge_off, g->pins, g->n_src, E, N, role, err, I.hpin0, s);
   unsigned long long hs[2] = {0, 0};
   HGP_HIP(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, s));
   check_err(W, s, kErrCsr | kErrPin | kErrNsrc | kErrWeight);
@@ -565,7 +566,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const bool learned = opt.proposal == HGP_LEARNED;
   if (learned) check_mlp(opt.mlp);
   const double t0 = now_ms();
-  Ingest I = ingest(W, g, omega, delta, s);
+  if (opt.constraint != HGP_INBOUND && opt.constraint != HGP_OUTBOUND && opt.constraint != HGP_INCIDENT)
+    throw Error(HGP_EINVAL, "unknown constraint");
+  Ingest I = ingest(W, g, omega, delta, s, opt.constraint);
   const int32_t N = g->n_nodes, E = g->n_hedges;
   const int64_t P = I.P;
   const int32_t *hoff0 = g->hedge_off;
@@ -731,8 +734,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       int32_t *rows = need<int32_t>(W.rows, (int64_t)M * n_next);
       launch_new_clusters(lmatch, gam, n, n_next, nflag, newc, row_slot, W.scan_tmp, s);
       fill_i64(dcnt, 1, M, s);
-      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot, rows, pair, score, tk_nxt,
-                       wpi, W.err.as<int32_t>(), s);
+      launch_rate_topk_rows(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot, rows, pair, score,
+                            tk_nxt, wpi, W.tail_acc, W.err.as<int32_t>(), s);
       fill_i64(dcnt + 1, 1, 0, s);
       launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, tk_nxt, pair, score, rerate, dcnt + 1, s);
       launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, nullptr, nullptr, pair,

@@ -121,17 +121,9 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
   __shared__ int64_t red[NT / 64];
   __shared__ int32_t redp[NT / 64];
   __shared__ int64_t s_saving;
-  __shared__ int32_t s_ntouch;
   __shared__ int32_t tbl[NT / 64 * 192];
   const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
   const int64_t cnt_nodes = list ? *count : (int64_t)N;
-  // sparse mode: the dynamic LDS holds conn[n_parts] then touched[n_parts]
-  const bool sparse = 2 * n_parts <= words;
-  int32_t *touched = reinterpret_cast<int32_t *>(conn + n_parts);
-  if (sparse) {
-    for (int i = tid; i < n_parts; i += NT) conn[i] = 0u;
-    __syncthreads();
-  }
   int64_t streamed = 0;
   for (int64_t t = blockIdx.x; t < cnt_nodes; t += gridDim.x) {
     const int n = list ? list[t] : (int)t;
@@ -156,33 +148,7 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
     const int64_t saving = s_saving;
     int bp = -1;
     int64_t bg = 0;
-    if (saving > 0 && sparse) {
-      // conn[] is all zero between nodes; parts touched first are listed in
-      // touched[] and only they are examined and cleared
-      const int64_t tot = total[n];
-      const int64_t sn = size[n];
-      if (tid == 0) s_ntouch = 0;
-      __syncthreads();
-      streamed += stream_segments<NT / 64, 4, false, int32_t>(
-          i0, i1, inc, hoff, lam, hw, tbl, [&](int j) { return pt[j].x; },
-          [&](int32_t p, uint32_t info) {
-            if (atomicAdd(&conn[p], info & kIdMask) == 0u) touched[atomicAdd(&s_ntouch, 1)] = p;
-          });
-      __syncthreads();
-      const int nt = s_ntouch;
-      for (int i = tid; i < nt; i += NT) {
-        const int p = touched[i];
-        const uint32_t c = conn[p];
-        conn[p] = 0u;
-        if (p == ps) continue;
-        const int64_t g = saving - tot + (int64_t)c;
-        if (g > 0 && (g > bg || (g == bg && p > bp)) && (int64_t)psize[p] + sn <= omega) {
-          bg = g;
-          bp = p;
-        }
-      }
-      __syncthreads();
-    } else if (saving > 0) {
+    if (saving > 0) {
       const int64_t tot = total[n];
       const int64_t sn = size[n];
       for (int lo = 0; lo < n_parts; lo += words) {
@@ -247,9 +213,7 @@ void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho
                     RoundBufs &B, hipStream_t s, const int32_t *list, const int64_t *count) {
   if (L.n <= 0) return;
   const int max_words = PROP_LDS_BYTES / 4;
-  // two words per part (counters + touched list) when they fit, else a dense window
-  const int words = 2 * (int64_t)n_parts <= max_words ? (n_parts > 0 ? 2 * n_parts : 1)
-                                                       : (n_parts < max_words ? n_parts : max_words);
+  const int words = n_parts < max_words ? (n_parts > 0 ? n_parts : 1) : max_words;
   KScope ks(1, s);
   const int grid = list ? (L.n < PROP_GRID ? L.n : PROP_GRID) : L.n;
   k_propose<PROP_NT><<<grid, PROP_NT, (size_t)words * 4, s>>>(list, count, L.n, L.ioff, L.inc, L.hoff, B.pt, B.ptin,

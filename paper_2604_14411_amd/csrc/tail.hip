@@ -20,6 +20,8 @@
 //  - the head is the best valid candidate when its hist exceeds kappa;
 //    otherwise (empty list with kappa > 0, or a tie with hidden candidates)
 //    the node gets a full rating again.
+#include <algorithm>
+
 #include "coarsen.hpp"
 #include "tail.hpp"
 
@@ -42,7 +44,8 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
                                                   int32_t *__restrict__ pair, int64_t *__restrict__ score,
                                                   uint64_t *__restrict__ tk_key, int32_t *__restrict__ tk_cnt,
                                                   uint64_t *__restrict__ tk_kappa, int32_t words,
-                                                  int32_t *err, unsigned long long *__restrict__ units) {
+                                                  const uint32_t *__restrict__ pre, int32_t *err,
+                                                  unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t lds[];
   __shared__ int32_t tbl[NT / 64 * 192];
   __shared__ uint64_t red[NT / 64];
@@ -65,9 +68,15 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
       if (tid == 0) atomicOr(err, kErrInternal);
       continue;
     }
-    for (int i = tid; i < zw; i += NT) lds[i] = 0u;
-    __syncthreads();
-    if (sn < omega) {
+    if (pre) {
+      // histogram row summed by k_tail_hist
+      for (int i = tid; i < zw; i += NT) lds[i] = pre[t * (int64_t)words + i];
+      __syncthreads();
+    } else {
+      for (int i = tid; i < zw; i += NT) lds[i] = 0u;
+      __syncthreads();
+    }
+    if (!pre && sn < omega) {
       streamed += stream_segments<NT / 64, 4, true, uint32_t>(
           ioff[n], ioff[n + 1], inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
           [&](uint32_t y, uint32_t info) {
@@ -232,6 +241,74 @@ __global__ void k_new_list(const int32_t *__restrict__ match, const int32_t *__r
   }
 }
 
+// Histogram rows of the listed nodes, each node's incidences split into
+// `slices` parts streamed by different workgroups (a late level rates only a
+// few large clusters: one workgroup per row would leave the device idle).
+// Workgroup b handles slice b % slices of row b / slices and adds its LDS
+// counters to acc[row * words ..] (same packing as k_rate_topk).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__restrict__ list, int32_t rows_n,
+                                                  int32_t slices, const int32_t *__restrict__ ioff,
+                                                  const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
+                                                  const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+                                                  const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
+                                                  const int32_t *__restrict__ total, int32_t omega, int32_t words,
+                                                  uint32_t *__restrict__ acc, int32_t *err,
+                                                  unsigned long long *__restrict__ units) {
+  extern __shared__ uint32_t lds[];
+  __shared__ int32_t tbl[NT / 64 * 192];
+  const int tid = threadIdx.x;
+  const int r = (int)(blockIdx.x / slices), sl = (int)(blockIdx.x % slices);
+  if (r >= rows_n) return;
+  const int n = list[r];
+  if (size[n] >= omega) return;
+  const uint32_t tot = (uint32_t)total[n];
+  const uint32_t din = (uint32_t)indeg[n];
+  const int hb = tot ? 32 - __clz(tot) : 0;
+  const int cb = din ? 32 - __clz(din) : 0;
+  const bool packed = hb + cb <= 32;
+  const int zw = packed ? N : 2 * N;
+  if (zw > words) {
+    if (tid == 0) atomicOr(err, kErrInternal);
+    return;
+  }
+  const int i0 = ioff[n], i1 = ioff[n + 1];
+  const int chunk = (i1 - i0 + slices - 1) / slices;
+  const int a = i0 + sl * chunk, z = min(i1, a + chunk);
+  if (a >= z) return;
+  uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
+  for (int i = tid; i < zw; i += NT) lds[i] = 0u;
+  __syncthreads();
+  const int64_t streamed = stream_segments<NT / 64, 4, true, uint32_t>(
+      a, z, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+      [&](uint32_t y, uint32_t info) {
+        const int m = (int)(y & kIdMask);
+        if (m != n) {
+          const uint32_t we = info & kIdMask;
+          const uint32_t both = (info >> 31) & (y >> 31);
+          if (packed)
+            atomicAdd(&lds[m], we + (both << hb));
+          else
+            atomicAdd((unsigned long long *)&lds64[m], (unsigned long long)we | ((unsigned long long)both << 32));
+        }
+      });
+  __syncthreads();
+  uint32_t *row = acc + (int64_t)r * words;
+  if (packed) {
+    for (int i = tid; i < N; i += NT) {
+      const uint32_t v = lds[i];
+      if (v) atomicAdd(&row[i], v);
+    }
+  } else {
+    unsigned long long *row64 = reinterpret_cast<unsigned long long *>(row);
+    for (int i = tid; i < N; i += NT) {
+      const unsigned long long v = lds64[i];
+      if (v) atomicAdd(&row64[i], v);
+    }
+  }
+  add_wave_units(units, streamed);
+}
+
 constexpr int TOPK_NT = 256;
 constexpr int TOPK_GRID = 2048;
 
@@ -252,7 +329,40 @@ void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, i
   const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, bytes, s>>>(L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size,
                                                     L.indeg, total, omega, delta, row_slot, rows, pair, score, tk.key,
-                                                    tk.cnt, tk.kappa, (int32_t)words, err, units_ptr(8));
+                                                    tk.cnt, tk.kappa, (int32_t)words, nullptr, err, units_ptr(8));
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta,
+                           const int32_t *list, const int64_t *count, int32_t n_rows, const int32_t *row_slot,
+                           int32_t *rows, int32_t *pair, int64_t *score, TopK &tk, int words_per_id, DevBuf &acc,
+                           int32_t *err, hipStream_t s) {
+  if (L.n <= 0 || n_rows <= 0) return;
+  const int64_t words = (int64_t)words_per_id * L.n;
+  if (words > kTopKMaxWords) throw Error(-7, "top-K window exceeds LDS");
+  KScope ks(8, s);
+  const size_t bytes = (size_t)words * 4;
+  static const bool attr_set = [] {
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kTopKMaxWords * 4));
+    HGP_HIP(hipFuncSetAttribute((const void *)k_tail_hist<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kTopKMaxWords * 4));
+    return true;
+  }();
+  (void)attr_set;
+  // about 2048 workgroups over the rows, at most 256 slices per row
+  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(256, (2048 + n_rows - 1) / n_rows));
+  acc.reserve((size_t)n_rows * words * 4);
+  uint32_t *a = acc.as<uint32_t>();
+  fill_i32(reinterpret_cast<int32_t *>(a), (int64_t)n_rows * words, 0, s);
+  k_tail_hist<TOPK_NT><<<n_rows * slices, TOPK_NT, bytes, s>>>(L.n, list, n_rows, slices, L.ioff, L.inc, L.hoff,
+                                                               L.hpin, L.hw, L.size, L.indeg, total, omega,
+                                                               (int32_t)words, a, err, units_ptr(8));
+  HGP_LAUNCH_CHECK();
+  const int grid = n_rows < TOPK_GRID ? n_rows : TOPK_GRID;
+  k_rate_topk<TOPK_NT><<<grid, TOPK_NT, bytes, s>>>(L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size,
+                                                    L.indeg, total, omega, delta, row_slot, rows, pair, score, tk.key,
+                                                    tk.cnt, tk.kappa, (int32_t)words, a, err, units_ptr(8));
   HGP_LAUNCH_CHECK();
 }
 

@@ -21,6 +21,13 @@ struct TopK {
 void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, const int32_t *list,
                       const int64_t *count, int64_t grid_nodes, const int32_t *row_slot, int32_t *rows, int32_t *pair,
                       int64_t *score, TopK &tk, int words_per_id, int32_t *err, hipStream_t s);
+// As launch_rate_topk for the n_rows (host) nodes of list, with each row's
+// pin stream split over many workgroups (acc: scratch of n_rows windows).
+// *count must equal n_rows.
+void launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta,
+                           const int32_t *list, const int64_t *count, int32_t n_rows, const int32_t *row_slot,
+                           int32_t *rows, int32_t *pair, int64_t *score, TopK &tk, int words_per_id, DevBuf &acc,
+                           int32_t *err, hipStream_t s);
 // Largest bits(total(n)) + bits(|in(n)|) over the level (device int32, reset inside).
 void launch_max_counter_bits(const int32_t *total, const int32_t *indeg, int32_t n, int32_t *out, hipStream_t s);
 void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gamma, const TopK &old_tk,

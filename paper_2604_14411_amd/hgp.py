@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PLAIN, LEARNED = 0, 1
+INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
 MLP_F, MLP_H = 16, 64
 FLAG_TIME_KERNELS = 1
 FLAG_NO_INCREMENTAL = 2
@@ -103,7 +104,8 @@ class BatchSched_t(ctypes.Structure):
 
 class Options_t(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("max_refine_rounds", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32), ("mlp", ctypes.POINTER(Mlp_t))]
+                ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32), ("mlp", ctypes.POINTER(Mlp_t)),
+                ("constraint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result_t(ctypes.Structure):
@@ -224,12 +226,13 @@ class Context:
         self.close()
 
 
-def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0, mlp=None):
+def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0, mlp=None, constraint: int = 0):
     """hgp_options; with an integer network dict `mlp` the learned proposal is selected.
     Returns (Options_t, keep-alive object)."""
     o = Options_t()
     load().hgp_options_default(ctypes.byref(o))
     o.k, o.max_refine_rounds, o.seed, o.flags = k, max_refine_rounds, seed, flags
+    o.constraint = constraint
     m = None
     if mlp is not None:
         m = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
@@ -263,7 +266,8 @@ class DeviceHypergraph:
                             _ptr(self.n_src), _ptr(self.hedge_w), _ptr(self.node_w))
 
 
-def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refine_rounds: int = 8, mlp=None):
+def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refine_rounds: int = 8, mlp=None,
+                   constraint: int = 0):
     """hgp_partition on numpy arrays; returns (parts ndarray, result dict)."""
     lib = load()
     arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (g.hedge_off, g.pins, g.n_src, g.hedge_w, g.node_w)]
@@ -271,14 +275,14 @@ def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refi
     hg = Hypergraph_t(g.n_nodes, g.n_hedges, arrs[0].ctypes.data, p[1], p[2], p[3], p[4])
     parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
     res = Result_t()
-    o, _keep = options(k, max_refine_rounds, mlp=mlp)
+    o, _keep = options(k, max_refine_rounds, mlp=mlp, constraint=constraint)
     _check(lib.hgp_partition(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), parts.ctypes.data,
                              ctypes.byref(res)))
     return parts[:g.n_nodes], _result_dict(res)
 
 
 def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int, k: int = 0,
-                     max_refine_rounds: int = 8, out=None, flags: int = 0, mlp=None):
+                     max_refine_rounds: int = 8, out=None, flags: int = 0, mlp=None, constraint: int = 0):
     """hgp_partition_device; returns (parts tensor on device, result dict)."""
     import torch
 
@@ -287,7 +291,7 @@ def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int,
         out = torch.empty(max(dg.n_nodes, 1), dtype=torch.int32, device=dg.hedge_off.device)
     hg = dg.struct()
     res = Result_t()
-    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp)
+    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp, constraint=constraint)
     _check(lib.hgp_partition_device(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), _stream(),
                                     out.data_ptr(), ctypes.byref(res)))
     return out[:dg.n_nodes], _result_dict(res)

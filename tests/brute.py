@@ -27,14 +27,17 @@ class Lvl:
         return {e for e, h in enumerate(self.hedges) if h.get(v, False)}
 
 
-def level_from_input(g):
+def level_from_input(g, role=0):
+    """role: the pins whose hedges count toward Delta — 0 destinations
+    (inbound), 1 sources (outbound), 2 every pin (incident)."""
     hedges = []
     for e in range(g.n_hedges):
         b, en = int(g.hedge_off[e]), int(g.hedge_off[e + 1])
         ns = int(g.n_src[e])
         h = {}
         for j in range(b, en):
-            h[int(g.pins[j])] = (j - b) >= ns
+            dst = (j - b) >= ns
+            h[int(g.pins[j])] = dst if role == 0 else (not dst if role == 1 else True)
         hedges.append(h)
     return Lvl(g.n_nodes, hedges, [int(x) for x in g.hedge_w], [int(x) for x in g.node_w])
 

@@ -38,21 +38,23 @@ def ctx():
     c.close()
 
 
-def _gpu_partition(ctx, g, omega, delta, k=0, rounds=8, flags=0):
+def _gpu_partition(ctx, g, omega, delta, k=0, rounds=8, flags=0, role=0):
     from paper_2604_14411_amd import hgp
 
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     try:
-        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds, flags=flags)
+        parts, res = hgp.partition_device(ctx, dg, omega, delta, k=k, max_refine_rounds=rounds, flags=flags,
+                                          constraint=role)
         return 0, parts.cpu().numpy(), res
     except hgp.HgpError as e:
         return e.code, None, None
 
 
-def _compare(ctx, g, omega, delta, k=0, rounds=8, label=""):
-    say(f"[parity] {label} n={g.n_nodes} E={g.n_hedges} P={g.n_pins} omega={omega} delta={delta} k={k} R={rounds}")
-    rc, ref, rres, _ = oracle.partition(g, omega, delta, k=k, max_rounds=rounds)
-    grc, got, gres = _gpu_partition(ctx, g, omega, delta, k, rounds)
+def _compare(ctx, g, omega, delta, k=0, rounds=8, label="", role=0):
+    say(f"[parity] {label} n={g.n_nodes} E={g.n_hedges} P={g.n_pins} omega={omega} delta={delta} k={k} R={rounds} "
+        f"role={role}")
+    rc, ref, rres, _ = oracle.partition(g, omega, delta, k=k, max_rounds=rounds, role=role)
+    grc, got, gres = _gpu_partition(ctx, g, omega, delta, k, rounds, role=role)
     assert grc == rc, (grc, rc)
     if rc != 0:
         return
@@ -73,6 +75,19 @@ def _tiny(seed):
 def test_tiny_random_end_to_end(ctx, seed):
     g, omega, delta, k, rounds = _tiny(seed)
     _compare(ctx, g, omega, delta, k, rounds, label=f"tiny seed={seed}")
+
+
+@pytest.mark.parametrize("role", [1, 2])
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_constraint_variants_end_to_end(ctx, seed, role):
+    g, omega, delta, k, rounds = _tiny(300 + seed)
+    _compare(ctx, g, omega, delta, k, rounds, label=f"tiny seed={300 + seed}", role=role)
+
+
+@pytest.mark.parametrize("role", [1, 2])
+def test_medium_constraint_variants_end_to_end(ctx, role):
+    _compare(ctx, synth.random_snn(2000, 24.0, 111), 64, 40 if role == 1 else 400, label="rand2000", role=role)
+    _compare(ctx, synth.layered_conv(4, 6, 8, 8, 3, 0.1, 112), 64, 300, label="conv", role=role)
 
 
 MEDIUM = [

@@ -33,9 +33,9 @@ def _case(seed):
     return g, omega, delta, k, rounds
 
 
-def _check_case(g, omega, delta, k, rounds):
-    L0 = brute.level_from_input(g)
-    rc, parts, res, tr = oracle.partition(g, omega, delta, k=k, max_rounds=rounds, trace=True)
+def _check_case(g, omega, delta, k, rounds, role=0):
+    L0 = brute.level_from_input(g, role)
+    rc, parts, res, tr = oracle.partition(g, omega, delta, k=k, max_rounds=rounds, trace=True, role=role)
     if not _feasible(L0, omega, delta):
         assert rc == oracle.EINFEASIBLE
         return
@@ -86,6 +86,13 @@ def _check_case(g, omega, delta, k, rounds):
 @pytest.mark.parametrize("seed", range(400))
 def test_oracle_steps_match_brute_force(seed):
     _check_case(*_case(seed))
+
+
+@pytest.mark.parametrize("role", [1, 2])
+@pytest.mark.parametrize("seed", range(150))
+def test_oracle_constraint_variants_match_brute_force(seed, role):
+    # outbound (source pins) and incident (all pins) variants of the Delta bound
+    _check_case(*_case(20_000 + seed), role=role)
 
 
 @pytest.mark.parametrize("seed", range(40))
