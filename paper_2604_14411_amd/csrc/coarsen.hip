@@ -151,14 +151,18 @@ __global__ void k_feasible(const int32_t *__restrict__ size, const int32_t *__re
 // (high bits) in 32 bits when they fit, else a 64-bit (c << 32 | hist) pair.
 // A candidate is checked against Omega and Delta only when it would improve
 // the thread's running best, with |in(n) u in(m)| = |in(n)|+|in(m)|-c.
+// When |in(n)| + max_m |in(m)| <= Delta every candidate passes the Delta test
+// whatever c is; then only hist is counted, in 16-bit halves of the LDS words
+// when hist < 2^16 (hist(n,m) <= total(n)), so a window covers twice the ids.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restrict__ ioff,
                                              const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
                                              const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
                                              const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
-                                             const int32_t *__restrict__ total, int32_t omega, int32_t delta,
-                                             int32_t words, int32_t *__restrict__ pair,
-                                             int64_t *__restrict__ score, unsigned long long *__restrict__ units) {
+                                             const int32_t *__restrict__ total, const int32_t *__restrict__ maxin,
+                                             int32_t omega, int32_t delta, int32_t words,
+                                             int32_t *__restrict__ pair, int64_t *__restrict__ score,
+                                             unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t lds[];
   __shared__ int64_t red_h[NT / 64];
   __shared__ int32_t red_m[NT / 64];
@@ -178,15 +182,16 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
     const int hb = tot ? 32 - __clz(tot) : 0;
     const int cb = din ? 32 - __clz(din) : 0;
     const bool packed = hb + cb <= 32;
+    const bool half = hb <= 16 && (int64_t)din + (int64_t)(*maxin) <= (int64_t)delta;
     const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
-    const int R = packed ? words : (words >> 1);
+    const int R = half ? 2 * words : (packed ? words : (words >> 1));
     const int i0 = ioff[n], i1 = ioff[n + 1];
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
     // windows over the neighbours' id range only
     const int2 rg = neighbour_range<NT>(i0, i1, inc, hoff, hpin, rng_s);
     for (int lo = rg.x; lo <= rg.y; lo += R) {
       const int span = min(R, rg.y + 1 - lo);
-      const int zw = packed ? span : 2 * span;
+      const int zw = half ? (span + 1) >> 1 : (packed ? span : 2 * span);
       for (int i = tid; i < zw; i += NT) lds[i] = 0u;
       __syncthreads();
       streamed += stream_segments<NT / 64, 4, true, uint32_t>(
@@ -197,7 +202,9 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
             if (m != n && rel < (uint32_t)span) {
               const uint32_t we = info & kIdMask;
               const uint32_t both = (info >> 31) & (y >> 31);
-              if (packed)
+              if (half)
+                atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
+              else if (packed)
                 atomicAdd(&lds[rel], we + (both << hb));
               else
                 atomicAdd((unsigned long long *)&lds64[rel],
@@ -205,6 +212,23 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
             }
           });
       __syncthreads();
+      if (half) {
+        for (int i = tid; i < zw; i += NT) {
+          const uint32_t v = lds[i];
+          if (!v) continue;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const int64_t h = hh ? (int64_t)(v >> 16) : (int64_t)(v & 0xffffu);
+            const int m = lo + 2 * i + hh;
+            if (h && (h > best_h || (h == best_h && m > best_m)) && sn + size[m] <= omega) {
+              best_h = h;
+              best_m = m;
+            }
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       for (int i = tid; i < span; i += NT) {
         uint64_t h, c;
         if (packed) {
@@ -451,9 +475,21 @@ void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32
 constexpr int RATE_NT = 512;
 constexpr int RATE_LDS_BYTES = 128 * 1024;
 
+// max over the nodes of |in(n)| into *out (zeroed by the caller)
+__global__ __launch_bounds__(256) void k_max_i32(const int32_t *__restrict__ a, int32_t n, int32_t *__restrict__ out) {
+  __shared__ int32_t red[4];
+  int32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) m = max(m, a[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if (lane_id() == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(out, max(max(red[0], red[1]), max(red[2], red[3])));
+}
+
 template <int NT>
-static void launch_rate_nt(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
-                           int64_t *score, int words, hipStream_t s) {
+static void launch_rate_nt(const LevelView &L, const int32_t *total, const int32_t *maxin, int32_t omega,
+                           int32_t delta, int32_t *pair, int64_t *score, int words, hipStream_t s) {
   // thread-safe one-time opt-in to the large dynamic LDS size
   static const bool attr_set = [] {
     HGP_HIP(hipFuncSetAttribute((const void *)k_rate<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -462,22 +498,25 @@ static void launch_rate_nt(const LevelView &L, const int32_t *total, int32_t ome
   }();
   (void)attr_set;
   k_rate<NT><<<xcd_grid(L.n), NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
-                                                omega, delta, words, pair, score, units_ptr(0));
+                                                maxin, omega, delta, words, pair, score, units_ptr(0));
   HGP_LAUNCH_CHECK();
 }
 
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
-                 int64_t *score, hipStream_t s, int tile) {
+                 int64_t *score, int32_t *maxin, hipStream_t s, int tile) {
   if (L.n <= 0) return;
   // dense window: whole id range if it fits, else RATE_LDS_BYTES of counters
   const int max_words = RATE_LDS_BYTES / 4;
   int words = L.n <= max_words / 2 ? 2 * L.n : max_words;
   words = (words + 1) & ~1;
   KScope ks(0, s);
+  fill_i32(maxin, 1, 0, s);
+  k_max_i32<<<std::min(div_up(L.n, 2048), 256), 256, 0, s>>>(L.indeg, L.n, maxin);
+  HGP_LAUNCH_CHECK();
   if (tile == 256)
-    launch_rate_nt<256>(L, total, omega, delta, pair, score, words, s);
+    launch_rate_nt<256>(L, total, maxin, omega, delta, pair, score, words, s);
   else
-    launch_rate_nt<RATE_NT>(L, total, omega, delta, pair, score, words, s);
+    launch_rate_nt<RATE_NT>(L, total, maxin, omega, delta, pair, score, words, s);
 }
 
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,

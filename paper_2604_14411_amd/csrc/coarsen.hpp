@@ -52,8 +52,9 @@ void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32
                      uint32_t *tkey2, uint32_t *tval2, uint32_t *he, DevBuf &sort_tmp, hipStream_t s);
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
                      int32_t *err, hipStream_t s);
+// maxin: one device int32 of scratch (max |in(n)| of the level)
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
-                 int64_t *score, hipStream_t s, int tile = 512);
+                 int64_t *score, int32_t *maxin, hipStream_t s, int tile = 512);
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,
                   int32_t *match, int32_t *gamma, int32_t *rep, int32_t *n_next_dev, int32_t *err,
                   DevBuf &scan_tmp, hipStream_t s);
@@ -68,8 +69,8 @@ void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, 
 // Part tables of hedges with at most kWaveSegMax pins and inb(p) of their
 // entries: pinb[0 .. n_parts) is written (not accumulated).  partial: scratch.
 void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, int32_t *pinb, int32_t n_parts, DevBuf &partial,
-                            hipStream_t s);
+                            int32_t *ptin, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
+                            DevBuf &partial, hipStream_t s);
 void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s);
 
 void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s);
@@ -103,6 +104,7 @@ struct RoundBufs {
   int2 *pt = nullptr;          // [P] (part, pins(p,e))
   int32_t *ptin = nullptr;     // [P] pins_in(p,e)
   int32_t *lam = nullptr;      // [E] entries per hedge
+  uint8_t *solo = nullptr;     // [P] 1 if the pin is the only pin of its part in its hedge
   int32_t *psize = nullptr;    // [n_parts]
   int32_t *pinb = nullptr;     // [n_parts]
   int32_t *dest = nullptr;     // [n]
@@ -118,6 +120,7 @@ struct RoundBufs {
   int32_t *viol = nullptr;     // [n+1]
   int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, init_invalid, heavy count
   int32_t *heavy = nullptr;    // [E] hedges queued for the workgroup event kernel
+  int64_t *evoff = nullptr;    // [E + 1] inbound-count events per hedge, then their offsets
   int2 *contrib = nullptr;     // [P] per moving pin: in-sequence gain terms (source, destination role)
   int64_t *esum = nullptr;     // [cap_events + 1] prefix sums of size deltas over sorted events
   int32_t *isum = nullptr;     // [cap_events + 1] prefix sums of inbound deltas over sorted events

@@ -68,7 +68,7 @@ struct Workspace {
   DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2, perm, pin_he;
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
-  DevBuf heavy, pt, ptin, lam, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
+  DevBuf heavy, evoff, maxin, pt, ptin, lam, solo, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
   DevBuf contrib, esum, isum, poff, pt_partial;
   DevBuf scan_tmp, sort_tmp;
   DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
@@ -316,6 +316,7 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.pt = need<int2>(W.pt, P);
   B.ptin = need<int32_t>(W.ptin, P);
   B.lam = need<int32_t>(W.lam, E);
+  B.solo = need<uint8_t>(W.solo, P);
   B.psize = need<int32_t>(W.psize, n_parts);
   B.pinb = need<int32_t>(W.pinb, n_parts);
   B.dest = need<int32_t>(W.dest, n);
@@ -337,6 +338,7 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);
   B.scal = need<int64_t>(W.scal, 8);
   B.heavy = need<int32_t>(W.heavy, E);
+  B.evoff = need<int64_t>(W.evoff, (int64_t)E + 1);
   return B;
 }
 
@@ -654,7 +656,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
                          tk_cur, wpi, W.err.as<int32_t>(), s);
         lists_ok = true;
       } else {
-        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, s, W.rate_tile);
+        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, need<int32_t>(W.maxin, 1), s,
+                    W.rate_tile);
         lists_ok = false;
       }
     }
@@ -1247,7 +1250,8 @@ int hgp_level_rate(hgp_ctx *ctx, const hgp_level *lv, int32_t omega, int32_t del
     if (lv && lv->n_nodes > 0 && (!pair_out || !score_out)) throw Error(HGP_EINVAL, "output is NULL");
     int64_t P = 0;
     LevelView L = level_view_from(ctx->ws, lv, s, &P);
-    launch_rate(L, ctx->ws.total.as<int32_t>(), omega, delta, pair_out, score_out, s);
+    launch_rate(L, ctx->ws.total.as<int32_t>(), omega, delta, pair_out, score_out, need<int32_t>(ctx->ws.maxin, 1),
+                s);
     HGP_HIP(hipStreamSynchronize(s));
   });
 }

@@ -27,15 +27,18 @@ constexpr int kClsSort = 6;          // timing class of sorts
 constexpr int EVW_NT = 128;          // two waves per workgroup
 constexpr int EVW_MAX_MOVING = 256;  // moving pins of a hedge handled by one wave
 constexpr int EVW_PT_STAGE = 256;    // part-table entries staged in LDS per wave
+constexpr int EVW_U = 4;             // 64-pin chunks loaded together
 constexpr int EVB_NT = 256;          // workgroup kernel for the remaining hedges
 constexpr int EVB_GRID = 512;
 static_assert(kSegCap <= 4096, "slot field of the workgroup event keys is 12 bits");
 
 // Sorts a wave's nev (<= 64 * KPL) event keys held in LDS, in registers, and
-// writes them back with the exclusive prefix of their count deltas: pins in
-// the low 16 bits, pins_in in the high 16 bits (both signed).
+// writes them back with the exclusive prefix of their count deltas within
+// their part (key >> pshift): pins in the low 16 bits, pins_in in the high 16
+// bits (both signed).  The first event of every part is found by a max-scan
+// of part-start indices, so no event searches for it.
 template <int KPL>
-__device__ __forceinline__ void ev_wave_sort_scan(int nev, uint64_t *evk, int32_t *pre) {
+__device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, uint64_t *evk, int32_t *pre) {
   const int l = lane_id();
   uint64_t k[KPL];
 #pragma unroll
@@ -44,8 +47,11 @@ __device__ __forceinline__ void ev_wave_sort_scan(int nev, uint64_t *evk, int32_
     k[j] = i < nev ? evk[i] : ~0ull;
   }
   wave_bitonic_sort<KPL>(k);
+  const uint64_t prev_last = __shfl_up(k[KPL - 1], 1, 64);
   int32_t d[KPL];
+  int st[KPL];
   int32_t run = 0;
+  int cur = -1;  // latest part start seen in this lane
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int i = l * KPL + j;
@@ -56,15 +62,37 @@ __device__ __forceinline__ void ev_wave_sort_scan(int nev, uint64_t *evk, int32_
     }
     d[j] = run;
     run += x;
+    const uint64_t pk = j == 0 ? prev_last : k[j - 1];
+    if (i == 0 || (k[j] >> pshift) != (pk >> pshift)) cur = i;
+    st[j] = cur;
   }
   const int32_t base = wave_exclusive_scan(run);
+  int carry = cur;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(carry, o, 64);
+    if (l >= o) carry = max(carry, t);
+  }
+  int cin = __shfl_up(carry, 1, 64);
+  if (l == 0) cin = 0;
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int i = l * KPL + j;
+    if (st[j] < 0) st[j] = cin;
     if (i < nev) {
       evk[i] = k[j];
       pre[i] = base + d[j];
     }
+  }
+  wave_lds_sync();
+  int32_t at_start[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) at_start[j] = (l * KPL + j < nev) ? pre[st[j]] : 0;
+  wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    if (i < nev) pre[i] = base + d[j] - at_start[j];
   }
 }
 
@@ -91,11 +119,15 @@ __device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t 
 // with moving pins are queued in heavy[] for k_ev_block.
 // Key of a pin event: part << (qbits + 11) | position << 11 | slot << 2 |
 // role << 1 | dst, slot = index of the moving pin (< 512), role 1 = destination.
+// The inbound-count events of hedge e go to its own region evpad[2 hoff[e] ..)
+// (at most one per pin event, i.e. 2 |e|) and their number to evcnt[e]; a
+// scan of evcnt then packs them (k_ev_compact), so no counter is shared.
 __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
     const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
-    int2 *__restrict__ contrib, uint64_t *__restrict__ ev, int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
+    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
   __shared__ uint64_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int16_t li_s[EVW_NT / 64][EVW_MAX_MOVING];
@@ -105,46 +137,64 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
   const int e = (int)(blockIdx.x * (EVW_NT / 64) + w);
   if (e >= E) return;
   const int b = hoff[e], len = hoff[e + 1] - b;
-  int m = 0;
-  for (int c = 0; c < len; c += 64) {
-    const int i = c + l;
-    m += __popcll(__ballot(i < len && pos[hpin[b + i] & kIdMask] > 0));
-  }
-  if (m == 0) return;
-  if (m > EVW_MAX_MOVING) {
-    if (l == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
-    return;
-  }
+  const int32_t we = hw[e];
+  const int plen = lam[e];
   const int pshift = qbits + 11;
   const uint64_t qmask = (1ull << qbits) - 1ull;
   uint64_t *evk = evk_s[w];
   int32_t *pre = pre_s[w];
   int16_t *li = li_s[w];
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
-  int slot0 = 0;
-  for (int c = 0; c < len; c += 64) {
-    const int i = c + l;
-    uint32_t x = 0;
-    int q = 0;
-    if (i < len) {
-      x = hpin[b + i];
-      q = pos[x & kIdMask];
+  // one pass over the pins, EVW_U chunks of 64 at a time: all pin loads of a
+  // batch are issued before the position gathers, and those before the part
+  // gathers of the moving pins
+  int m = 0;
+  for (int c = 0; c < len && m <= EVW_MAX_MOVING; c += 64 * EVW_U) {
+    uint32_t x[EVW_U];
+    int q[EVW_U];
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const int i = c + 64 * u + l;
+      x[u] = i < len ? hpin[b + i] : 0u;
     }
-    const uint64_t mask = __ballot(q > 0);
-    if (q > 0) {
-      const int slot = slot0 + __popcll(mask & lt);
-      const int v = (int)(x & kIdMask);
-      const uint64_t tail = ((uint64_t)q << 11) | ((uint64_t)slot << 2) | (uint64_t)(x >> 31);
-      li[slot] = (int16_t)i;
-      evk[2 * slot] = ((uint64_t)(uint32_t)rho[v] << pshift) | tail;
-      evk[2 * slot + 1] = ((uint64_t)(uint32_t)dest[v] << pshift) | tail | 2ull;
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const int i = c + 64 * u + l;
+      q[u] = i < len ? pos[x[u] & kIdMask] : 0;
     }
-    slot0 += __popcll(mask);
+    int32_t ps[EVW_U], pd[EVW_U];
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      ps[u] = 0;
+      pd[u] = 0;
+      if (q[u] > 0) {
+        ps[u] = rho[x[u] & kIdMask];
+        pd[u] = dest[x[u] & kIdMask];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const uint64_t mask = __ballot(q[u] > 0);
+      const int slot = m + __popcll(mask & lt);
+      if (q[u] > 0 && slot < EVW_MAX_MOVING) {
+        const uint64_t tail = ((uint64_t)q[u] << 11) | ((uint64_t)slot << 2) | (uint64_t)(x[u] >> 31);
+        li[slot] = (int16_t)(c + 64 * u + l);
+        evk[2 * slot] = ((uint64_t)(uint32_t)ps[u] << pshift) | tail;
+        evk[2 * slot + 1] = ((uint64_t)(uint32_t)pd[u] << pshift) | tail | 2ull;
+      }
+      m += __popcll(mask);
+    }
+  }
+  if (m == 0) {
+    if (l == 0) evcnt[e] = 0;
+    return;
+  }
+  if (m > EVW_MAX_MOVING) {
+    if (l == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
+    return;
   }
   wave_lds_sync();
   const int nev = 2 * m;
-  const int32_t we = hw[e];
-  const int plen = lam[e];
   // the hedge's part table in LDS (parts ascending; pins | pins_in << 16)
   const bool staged = plen <= EVW_PT_STAGE;
   int32_t *sp = sp_s[w];
@@ -156,10 +206,10 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
       sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
     }
   }
-  if (nev <= 64) ev_wave_sort_scan<1>(nev, evk, pre);
-  else if (nev <= 128) ev_wave_sort_scan<2>(nev, evk, pre);
-  else if (nev <= 256) ev_wave_sort_scan<4>(nev, evk, pre);
-  else ev_wave_sort_scan<8>(nev, evk, pre);
+  if (nev <= 64) ev_wave_sort_scan<1>(nev, pshift, evk, pre);
+  else if (nev <= 128) ev_wave_sort_scan<2>(nev, pshift, evk, pre);
+  else if (nev <= 256) ev_wave_sort_scan<4>(nev, pshift, evk, pre);
+  else ev_wave_sort_scan<8>(nev, pshift, evk, pre);
   wave_lds_sync();
   uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
   int nout = 0;
@@ -167,15 +217,9 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const int i = l + 64 * t;
     if (i >= nev) continue;
     const uint64_t k = evk[i];
-    const uint64_t part = k >> pshift;
-    int lo = 0, hi = i;  // first event of this part
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((evk[mid] >> pshift) < part) lo = mid + 1;
-      else hi = mid;
-    }
-    const int2 before = unpack_delta(pre[i] - pre[lo]);
-    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, (int)part) : pt_lookup(pt, ptin, b, plen, (int)part);
+    const int part = (int)(k >> pshift);
+    const int2 before = unpack_delta(pre[i]);
+    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, part) : pt_lookup(pt, ptin, b, plen, part);
     const bool dst_role = (k & 2ull) != 0;
     int2 *cp = &contrib[b + li[(int)((k >> 2) & 511ull)]];
     if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
@@ -189,18 +233,14 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     }
   }
   const int off = wave_exclusive_scan(nout);
-  const int tot = __shfl(off + nout, 63, 64);
-  if (tot == 0) return;
-  unsigned long long base = 0;
-  if (l == 0) base = atomicAdd((unsigned long long *)&scal[SC_EVENTS], (unsigned long long)tot);
-  base = __shfl(base, 0, 64);
+  if (l == 63) evcnt[e] = off + nout;
   const int vshift = qbits + 2;
-  int64_t o = (int64_t)base + off;
+  int64_t o = 2 * (int64_t)b + off;
   for (int t = 0; evbits; ++t, evbits >>= 1) {
     if (!(evbits & 1u)) continue;
     const uint64_t k = evk[l + 64 * t];
     const uint64_t q = (k >> 11) & qmask;
-    ev[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+    evpad[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
   }
 }
 
@@ -211,14 +251,15 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
     const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
-    int2 *__restrict__ contrib, uint64_t *__restrict__ ev, int64_t *__restrict__ scal,
-    const int32_t *__restrict__ heavy) {
+    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    const int64_t *__restrict__ scal, const int32_t *__restrict__ heavy) {
   __shared__ uint64_t key[2 * kSegCap];
   __shared__ int32_t dl[2 * kSegCap];
   __shared__ int32_t sp[kSegCap];
   __shared__ uint32_t sc[kSegCap];
   __shared__ int16_t li[kSegCap];
   __shared__ int32_t tmp[EVB_NT / 64 + 1];
+  __shared__ int32_t s_wtot[EVB_NT / 64];
   __shared__ int32_t s_cnt;
   const int tid = threadIdx.x, l = lane_id();
   const int hshift = qbits + 14;
@@ -288,20 +329,39 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
         }
       }
     }
+    // this hedge's events go to evpad[2b ..), wave by wave
     const int off = wave_exclusive_scan(nout);
-    const int tot = __shfl(off + nout, 63, 64);
-    unsigned long long base = 0;
-    if (l == 0 && tot) base = atomicAdd((unsigned long long *)&scal[SC_EVENTS], (unsigned long long)tot);
-    base = __shfl(base, 0, 64);
-    int64_t o = (int64_t)base + off;
+    if (l == 63) s_wtot[tid >> 6] = off + nout;
+    __syncthreads();
+    int wbase = 0, btot = 0;
+    for (int q = 0; q < EVB_NT / 64; ++q) {
+      if (q < (tid >> 6)) wbase += s_wtot[q];
+      btot += s_wtot[q];
+    }
+    if (tid == 0) evcnt[e] = btot;
+    int64_t o = 2 * (int64_t)b + wbase + off;
     for (int t = 0; evbits; ++t, evbits >>= 1) {
       if (!(evbits & 1u)) continue;
       const uint64_t k = key[tid + EVB_NT * t];
       const uint64_t q = (k >> 14) & qmask;
-      ev[o++] = ((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+      evpad[o++] = ((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
     }
     __syncthreads();
   }
+}
+
+// Packs the inbound-count events of every hedge (evpad[2 hoff[e] ..), evcnt
+// already scanned into offsets evoff) into ev[0 .. evoff[E]).  One wave per
+// hedge.
+__global__ __launch_bounds__(256) void k_ev_compact(const int32_t *__restrict__ hoff, int32_t E,
+                                                    const int64_t *__restrict__ evoff,
+                                                    const uint64_t *__restrict__ evpad, uint64_t *__restrict__ ev) {
+  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (e >= E) return;
+  const int64_t o = evoff[e], c = evoff[e + 1] - o;
+  if (c == 0) return;
+  const int64_t src = 2 * (int64_t)hoff[e];
+  for (int64_t i = lane_id(); i < c; i += 64) ev[o + i] = evpad[src + i];
 }
 
 // g'(i) for move i = 1..S: the sum, over the incidences k of the moving node,
@@ -521,24 +581,30 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   if (pbits + qbits + 14 > 64) throw Error(-6, "sequence too long for the 64-bit event keys");
   fill_i32(B.vdelta, S + 1, 0, s);
   fill_i32(B.gp, 1, 0, s);
-  fill_i64(B.scal + SC_EVENTS, 1, 0, s);
   fill_i64(B.scal + SC_INVALID0, 1, 0, s);
   fill_i64(B.scal + SC_HEAVY, 1, 0, s);
+  fill_i64(B.evoff + L.E, 1, 0, s);
   if (S > 0) {
     KScope ks(kClsEvents, s);
     if (L.E > 0) {
+      // inbound-count events per hedge into keys2 (one region of 2|e| per
+      // hedge), then packed into keys[0 .. nin)
       k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
-                                                            B.ptin, B.lam, qbits, B.contrib, B.keys, B.scal, B.heavy);
+                                                            B.ptin, B.lam, qbits, B.contrib, B.keys2, B.evoff,
+                                                            B.scal, B.heavy);
       HGP_LAUNCH_CHECK();
       k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam, qbits,
-                                             B.contrib, B.keys, B.scal, B.heavy);
+                                             B.contrib, B.keys2, B.evoff, B.scal, B.heavy);
+      HGP_LAUNCH_CHECK();
+      scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);
+      k_ev_compact<<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, B.keys);
       HGP_LAUNCH_CHECK();
     }
     k_move_gain<<<div_up(S, 4), 256, 0, s>>>(B.seq, S, L.ioff, L.perm, B.contrib, B.gp);
     HGP_LAUNCH_CHECK();
   }
   int64_t nin = 0;
-  HGP_HIP(hipMemcpyAsync(&nin, B.scal + SC_EVENTS, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&nin, B.evoff + L.E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
   const int64_t nev = nin + 2 * S;
   if (nev > B.cap_events) throw Error(-7, "event buffer overflow");

@@ -190,17 +190,26 @@ constexpr int RS_NT = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_NT * RS_ROUNDS;
 
+// Digit counts of one 4096-key tile.  All of the tile's loads are issued
+// before the first count.
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                    int32_t *__restrict__ hist, int32_t *__restrict__ tcnt,
                                                    int ntiles) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  K kr[RS_ROUNDS];
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t j = base + r * RS_NT + threadIdx.x;
-    if (j < n) atomicAdd(&cnt[(uint32_t)(keys[j] >> shift) & 255u], 1);
+    kr[r] = j < n ? keys[j] : K(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t j = base + r * RS_NT + threadIdx.x;
+    if (j < n) atomicAdd(&cnt[(uint32_t)(kr[r] >> shift) & 255u], 1);
   }
   __syncthreads();
   const int64_t o = (int64_t)threadIdx.x * ntiles + blockIdx.x;
@@ -208,12 +217,27 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
   tcnt[o] = cnt[threadIdx.x];
 }
 
-// Stable scatter of one 4096-key tile.  Keys are ranked in tile order within
-// their digit (wave match masks from 8 ballots, per-wave digit counts) and
+// Rank of a key within its digit among the valid lanes of the wave (match
+// mask from 8 ballots); returns the rank, *cnt = size of the digit group.
+__device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt, int *cnt) {
+  uint64_t match = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
+    match &= bit ? bb : ~bb;
+  }
+  *cnt = __popcll(match);
+  return __popcll(match & lt);
+}
+
+// Stable scatter of one 4096-key tile.  The tile's keys (and values) are
+// loaded into registers first; then, 256 at a time, keys are ranked in tile
+// order within their digit (wave match masks, per-wave digit counts) and
 // placed in LDS at their position in the tile's digit-sorted order; the tile
 // is then written out in that order, so each digit's run goes to consecutive
 // addresses.  offs: global start of (digit, tile); tcnt: (digit, tile) counts.
-template <class K>
+template <class K, bool V>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
                                                       const int32_t *__restrict__ tcnt, int ntiles,
@@ -224,10 +248,20 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
   __shared__ int32_t wcnt[RS_NT / 64][256];
   __shared__ int32_t stmp[RS_NT / 64 + 1];
   __shared__ K lkeys[RS_TILE];
-  __shared__ uint32_t lvals[RS_TILE];
+  __shared__ uint32_t lvals[V ? RS_TILE : 1];
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
+  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+  const int tn = (int)min((int64_t)RS_TILE, n - tbase);
+  K kr[RS_ROUNDS];
+  uint32_t vr[V ? RS_ROUNDS : 1];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int j = r * RS_NT + tid;
+    kr[r] = j < tn ? keys[tbase + j] : K(0);
+    if (V) vr[r] = j < tn ? vals[tbase + j] : 0u;
+  }
   const int64_t o = (int64_t)tid * ntiles + blockIdx.x;
   gbase[tid] = offs[o];
   lstart[tid] = tcnt[o];
@@ -236,53 +270,43 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
   lnext[tid] = lstart[tid];
   __syncthreads();
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
-  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
-  const int tn = (int)min((int64_t)RS_TILE, n - tbase);
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
     __syncthreads();
     const int j = r * RS_NT + tid;
     const bool valid = j < tn;
-    const K key = valid ? keys[tbase + j] : K(0);
-    const uint32_t val = (valid && vals) ? vals[tbase + j] : 0u;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    uint64_t match = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(valid && bit);
-      match &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(match & lt);
-    const int cnt = __popcll(match);
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    int cnt;
+    const int rank = rs_wave_rank(valid, d, lt, &cnt);
     if (valid && rank == cnt - 1) wcnt[w][d] = cnt;  // last lane of the group publishes
     __syncthreads();
     if (valid) {
       int pre = 0;
       for (int q = 0; q < w; ++q) pre += wcnt[q][d];
       const int lp = lnext[d] + pre + rank;
-      lkeys[lp] = key;
-      if (vals) lvals[lp] = val;
+      lkeys[lp] = kr[r];
+      if (V) lvals[lp] = vr[r];
     }
     __syncthreads();
     int add = 0;
     for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
     lnext[tid] += add;
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = tid; i < tn; i += RS_NT) {
     const K key = lkeys[i];
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
     const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
     okeys[pos] = key;
-    if (vals) ovals[pos] = lvals[i];
+    if (V) ovals[pos] = lvals[i];
   }
 }
 
 // Direct variant for 64-bit keys: each ranked key goes straight to its
 // global slot (the LDS staging of 64-bit tiles costs more occupancy than the
-// coalescing gains).
-template <class K>
+// coalescing gains).  The tile is loaded into registers first.
+template <class K, bool V>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict__ keys,
                                                              const uint32_t *__restrict__ vals, int64_t n, int shift,
                                                              const int32_t *__restrict__ offs, int ntiles,
@@ -292,40 +316,39 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
+  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+  K kr[RS_ROUNDS];
+  uint32_t vr[V ? RS_ROUNDS : 1];
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    const int64_t j = tbase + r * RS_NT + tid;
+    kr[r] = j < n ? keys[j] : K(0);
+    if (V) vr[r] = j < n ? vals[j] : 0u;
+  }
   base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
-  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
     __syncthreads();
     const int64_t j = tbase + r * RS_NT + tid;
     const bool valid = j < n;
-    const K key = valid ? keys[j] : K(0);
-    const uint32_t val = (valid && vals) ? vals[j] : 0u;
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    uint64_t match = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(valid && bit);
-      match &= bit ? bb : ~bb;
-    }
-    const int rank = __popcll(match & lt);
-    const int cnt = __popcll(match);
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    int cnt;
+    const int rank = rs_wave_rank(valid, d, lt, &cnt);
     if (valid && rank == cnt - 1) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
       int pre = 0;
       for (int q = 0; q < w; ++q) pre += wcnt[q][d];
       const int64_t pos = (int64_t)base[d] + pre + rank;
-      okeys[pos] = key;
-      if (vals) ovals[pos] = val;
+      okeys[pos] = kr[r];
+      if (V) ovals[pos] = vr[r];
     }
     __syncthreads();
     int add = 0;
     for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
     base[tid] += add;
-    __syncthreads();
   }
 }
 
@@ -348,10 +371,17 @@ static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int
     k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, tcnt, ntiles);
     HGP_LAUNCH_CHECK();
     scan_impl<int32_t>(hist, hist, hn, nullptr, stmp, s);
-    if (sizeof(K) == 4)
-      k_rs_scatter<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
-    else
-      k_rs_scatter_direct<K><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+    if constexpr (sizeof(K) == 4) {
+      if (vs)
+        k_rs_scatter<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
+      else
+        k_rs_scatter<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
+    } else {
+      if (vs)
+        k_rs_scatter_direct<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+      else
+        k_rs_scatter_direct<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+    }
     HGP_LAUNCH_CHECK();
     std::swap(src, dst);
     std::swap(vs, vd);

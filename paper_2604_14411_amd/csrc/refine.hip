@@ -27,8 +27,8 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
                                                       const uint32_t *__restrict__ hpin,
                                                       const int32_t *__restrict__ rho, int2 *__restrict__ pt,
                                                       int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
-                                                      int32_t *__restrict__ pinb, int32_t *err,
-                                                      const int32_t *__restrict__ list) {
+                                                      uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
+                                                      int32_t *err, const int32_t *__restrict__ list) {
   __shared__ uint32_t key[kSegCap];
   __shared__ int32_t first[kSegCap];
   __shared__ int32_t tmp[PT_NT / 64 + 1];
@@ -68,6 +68,11 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
     }
   }
   if (threadIdx.x == 0) lam[e] = runs;
+  // solo flags in pin order (the only pin of its part in the hedge)
+  for (int i = threadIdx.x; i < len; i += PT_NT) {
+    const uint32_t part = (uint32_t)rho[hpin[b + i] & kIdMask];
+    solo[b + i] = (lower_bound_u32(key, len, (part + 1) << 1) - lower_bound_u32(key, len, part << 1)) == 1 ? 1 : 0;
+  }
 }
 
 __global__ void k_part_size(const int32_t *__restrict__ rho, const int32_t *__restrict__ size, int32_t N,
@@ -82,10 +87,11 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   KScope ks(2, s);
   add_units(2, 0);
   if (!B.partial) throw Error(-7, "part-table scratch missing");
-  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.pinb, n_parts, *B.partial, s);
+  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.solo, B.pinb, n_parts, *B.partial, s);
   if (L.E > 0) {
     if (L.big.n > 0) {
-      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.pinb, err, L.big.list);
+      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.solo, B.pinb, err,
+                                             L.big.list);
       HGP_LAUNCH_CHECK();
     }
   }
@@ -99,8 +105,8 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // proposals (Eq. 3)
 // ---------------------------------------------------------------------------
 // One workgroup per node n in part p_s (node list[t], or t when list is
-// null; grid-stride over *count nodes).  saving(n) is summed first by one
-// lookup of p_s per hedge; if it is zero no move can have positive gain
+// null; grid-stride over *count nodes).  saving(n) is summed first from the
+// solo flags of n's pins (pins(p_s, e) = 1); if it is zero no move can have positive gain
 // (loss >= 0) and the node is done.  Otherwise every part table entry of
 // every hedge of I(n) adds w(e) to conn[p] in LDS; then
 //   gain(n,p) = saving - loss(n,p) = saving - total(n) + conn[p]
@@ -109,8 +115,9 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list, const int64_t *__restrict__ count,
                                                 int32_t N, const int32_t *__restrict__ ioff,
-                                                const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
-                                                const int2 *__restrict__ pt, const int32_t *__restrict__ ptin,
+                                                const uint32_t *__restrict__ inc, const uint32_t *__restrict__ perm,
+                                                const int32_t *__restrict__ hoff, const int2 *__restrict__ pt,
+                                                const uint8_t *__restrict__ solo,
                                                 const int32_t *__restrict__ lam, const int32_t *__restrict__ hw,
                                                 const int32_t *__restrict__ rho, const int32_t *__restrict__ size,
                                                 const int32_t *__restrict__ psize, const int32_t *__restrict__ total,
@@ -129,13 +136,10 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
     const int n = list ? list[t] : (int)t;
     const int ps = rho[n];
     const int i0 = ioff[n], i1 = ioff[n + 1];
-    // saving(n)
+    // saving(n): hedges where n is the only pin of p_s
     int64_t sav = 0;
-    for (int i = i0 + tid; i < i1; i += NT) {
-      const int e = (int)(inc[i] & kIdMask);
-      const int2 c = pt_lookup(pt, ptin, hoff[e], lam[e], ps);
-      if (c.x == 1) sav += hw[e];
-    }
+    for (int i = i0 + tid; i < i1; i += NT)
+      if (solo[perm[i]]) sav += hw[inc[i] & kIdMask];
     sav = wave_sum(sav);
     if (l == 0) red[w] = sav;
     __syncthreads();
@@ -216,9 +220,9 @@ void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho
   const int words = n_parts < max_words ? (n_parts > 0 ? n_parts : 1) : max_words;
   KScope ks(1, s);
   const int grid = list ? (L.n < PROP_GRID ? L.n : PROP_GRID) : L.n;
-  k_propose<PROP_NT><<<grid, PROP_NT, (size_t)words * 4, s>>>(list, count, L.n, L.ioff, L.inc, L.hoff, B.pt, B.ptin,
-                                                             B.lam, L.hw, rho, L.size, B.psize, total, n_parts, omega,
-                                                             words, B.dest, B.gain, units_ptr(1));
+  k_propose<PROP_NT><<<grid, PROP_NT, (size_t)words * 4, s>>>(list, count, L.n, L.ioff, L.inc, L.perm, L.hoff, B.pt,
+                                                             B.solo, B.lam, L.hw, rho, L.size, B.psize, total, n_parts,
+                                                             omega, words, B.dest, B.gain, units_ptr(1));
   HGP_LAUNCH_CHECK();
 }
 

@@ -73,12 +73,15 @@ __global__ __launch_bounds__(256) void k_contract_wave(const int32_t *__restrict
 
 // Part table of one hedge (Sec. IV-B): keys (rho(v) << 1 | dst) sorted; each
 // run of one part gives (part, pins(p,e)) and pins_in(p,e), written at the
-// hedge's pin offset; lam[e] = number of runs.  s: 64*KPL words of LDS.
+// hedge's pin offset; lam[e] = number of runs.  solo[b + i] = 1 when pin i is
+// the only pin of its part in the hedge (pins(rho(v), e) = 1: the hedge is
+// in saving(v) of Eq. 3).  s: 64*KPL words of LDS.
 template <int KPL>
 __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uint32_t *__restrict__ hpin,
                                                 const int32_t *__restrict__ rho, int2 *__restrict__ pt,
                                                 int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
-                                                int32_t *__restrict__ pinb, uint32_t *s) {
+                                                uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
+                                                uint32_t *s) {
   const int l = lane_id();
   uint32_t k[KPL];
 #pragma unroll
@@ -91,10 +94,21 @@ __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uin
     }
     k[j] = key;
   }
+  uint32_t ku[KPL];  // keys in pin order
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) ku[j] = k[j];
   wave_bitonic_sort<KPL>(k);
 #pragma unroll
   for (int j = 0; j < KPL; ++j) s[l * KPL + j] = k[j];
   wave_lds_sync();
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int i = l * KPL + j;
+    if (i < len) {
+      const uint32_t part = ku[j] >> 1;
+      solo[b + i] = (lb_u32(s, len, (part + 1) << 1) - lb_u32(s, len, part << 1)) == 1 ? 1 : 0;
+    }
+  }
   const uint32_t prev_lane_last = __shfl_up(k[KPL - 1], 1, 64);
   bool first[KPL];
   int c = 0;
@@ -135,7 +149,8 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
                                                          const uint32_t *__restrict__ hpin, int32_t E,
                                                          const int32_t *__restrict__ rho, int2 *__restrict__ pt,
                                                          int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
-                                                         int32_t *__restrict__ pinb, int32_t n_parts,
+                                                         uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
+                                                         int32_t n_parts,
                                                          int32_t *__restrict__ partial) {
   __shared__ uint32_t sbuf[4][kWaveSegMax];
   __shared__ int32_t hist[PTW_LDS_PARTS];
@@ -154,11 +169,11 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
       if (lane_id() == 0) lam[e] = 0;
       continue;
     }
-    if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
-    else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
-    else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
-    else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
-    else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, cnt, s);
+    if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
+    else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
+    else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
+    else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
+    else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
   }
   if (local) {
     __syncthreads();
@@ -167,14 +182,34 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
   }
 }
 
-// pinb[p] = sum over the rows of partial (fixed order).
-__global__ void k_pinb_reduce(const int32_t *__restrict__ partial, int rows, int32_t n_parts,
-                              int32_t *__restrict__ pinb) {
-  const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (p >= n_parts) return;
+// pinb[p] = sum over the rows of partial.  A workgroup covers 64 parts (one
+// per lane); its PR_W waves sum interleaved rows, 8 loads in flight each.
+constexpr int PR_W = 16;
+
+__global__ __launch_bounds__(64 * PR_W) void k_pinb_reduce(const int32_t *__restrict__ partial, int rows,
+                                                           int32_t n_parts, int32_t *__restrict__ pinb) {
+  __shared__ int32_t red[PR_W][64];
+  const int l = lane_id(), w = (int)(threadIdx.x >> 6);
+  const int p = (int)(blockIdx.x * 64) + l;
   int32_t t = 0;
-  for (int r = 0; r < rows; ++r) t += partial[(int64_t)r * n_parts + p];
-  pinb[p] = t;
+  if (p < n_parts) {
+    int r = w;
+    for (; r + 7 * PR_W < rows; r += 8 * PR_W) {
+      int32_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(r + u * PR_W) * n_parts + p];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t += v[u];
+    }
+    for (; r < rows; r += PR_W) t += partial[(int64_t)r * n_parts + p];
+  }
+  red[w][l] = t;
+  __syncthreads();
+  if (w == 0 && p < n_parts) {
+    int32_t sum = 0;
+    for (int q = 0; q < PR_W; ++q) sum += red[q][l];
+    pinb[p] = sum;
+  }
 }
 
 void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
@@ -185,16 +220,16 @@ void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, 
 }
 
 void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, int32_t *pinb, int32_t n_parts, DevBuf &partial,
-                            hipStream_t s) {
+                            int32_t *ptin, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
+                            DevBuf &partial, hipStream_t s) {
   if (n_parts > 0 && n_parts <= PTW_LDS_PARTS) {
     const int grid = E > 0 ? std::min(PTW_GRID, div_up(E, 4)) : 0;
     if (grid > 0) {
       partial.reserve((size_t)grid * n_parts * sizeof(int32_t));
-      k_part_table_wave<<<grid, 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb, n_parts,
+      k_part_table_wave<<<grid, 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, solo, pinb, n_parts,
                                              partial.as<int32_t>());
       HGP_LAUNCH_CHECK();
-      k_pinb_reduce<<<div_up(n_parts, 256), 256, 0, s>>>(partial.as<int32_t>(), grid, n_parts, pinb);
+      k_pinb_reduce<<<div_up(n_parts, 64), 64 * PR_W, 0, s>>>(partial.as<int32_t>(), grid, n_parts, pinb);
       HGP_LAUNCH_CHECK();
     } else {
       fill_i32(pinb, n_parts, 0, s);
@@ -203,8 +238,8 @@ void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E
   }
   fill_i32(pinb, n_parts, 0, s);
   if (E <= 0) return;
-  k_part_table_wave<<<std::min(PTW_GRID, div_up(E, 4)), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, pinb,
-                                                                     n_parts, nullptr);
+  k_part_table_wave<<<std::min(PTW_GRID, div_up(E, 4)), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, solo,
+                                                                     pinb, n_parts, nullptr);
   HGP_LAUNCH_CHECK();
 }
 

@@ -92,9 +92,13 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
           });
     }
     __syncthreads();
-    // validity pass, in place: each counter becomes the hist of a valid
-    // candidate or 0 (a thread touches only its own counters)
+    // validity pass fused with the top-(TK+1) selection by key (hist, id):
+    // each thread keeps the largest TK+1 keys of its own counters, in
+    // registers, descending
     const int slot = row_slot ? row_slot[n] : -1;
+    uint64_t top[kTopK + 1];
+#pragma unroll
+    for (int z = 0; z <= kTopK; ++z) top[z] = 0ull;
     for (int i = tid; i < N; i += NT) {
       uint64_t h = 0, c = 0;
       if (packed) {
@@ -112,24 +116,26 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
         ok = sn + size[i] <= omega && un <= delta;
       }
       if (slot >= 0) rows[(int64_t)slot * N + i] = ok ? (int32_t)h : 0;
-      if (packed)
-        lds[i] = ok ? (uint32_t)h : 0u;
-      else
-        lds64[i] = ok ? h : 0ull;
-    }
-    __syncthreads();
-    // top-(TK+1) by key (hist, id), larger first
-    uint64_t prev = ~0ull;
-    int nf = 0;
-    for (int r = 0; r <= kTopK; ++r) {
-      uint64_t best = 0;
-      for (int i = tid; i < N; i += NT) {
-        const uint32_t h = packed ? lds[i] : (uint32_t)lds64[i];
-        if (h) {
-          const uint64_t k = cand_key(h, (uint32_t)i);
-          if (k < prev && k > best) best = k;
+      if (ok) {
+        uint64_t x = cand_key(h, (uint32_t)i);
+        if (x > top[kTopK]) {
+#pragma unroll
+          for (int z = 0; z <= kTopK; ++z) {
+            if (x > top[z]) {
+              const uint64_t t = top[z];
+              top[z] = x;
+              x = t;
+            }
+          }
         }
       }
+    }
+    // merge of the per-thread lists: TK+1 rounds of a block max over the
+    // heads; keys are distinct (the id is in the low bits), so exactly one
+    // thread owns each winner and drops it from its list
+    int nf = 0;
+    for (int r = 0; r <= kTopK; ++r) {
+      uint64_t best = top[0];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const uint64_t x = __shfl_xor(best, o, 64);
@@ -143,10 +149,14 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
         found[r] = b;
       }
       __syncthreads();
-      prev = found[r];
-      if (prev == 0) break;
+      const uint64_t win = found[r];
+      if (win == 0) break;
       nf = r + 1;
-      __syncthreads();
+      if (top[0] == win) {
+#pragma unroll
+        for (int z = 0; z < kTopK; ++z) top[z] = top[z + 1];
+        top[kTopK] = 0ull;
+      }
     }
     if (tid == 0) {
       const int keep = nf < kTopK ? nf : kTopK;

@@ -56,9 +56,12 @@ def _run(conv208k, mlp):
     ctx = hgp.Context(0)
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     say(f"[fullsize] partition conv208k {'learned' if mlp else 'plain'}")
-    parts, res = hgp.partition_device(ctx, dg, w.omega, w.delta, mlp=mlp)
+    parts, res = hgp.partition_device(ctx, dg, w.omega, w.delta, mlp=mlp, flags=hgp.FLAG_TIME_KERNELS)
     parts = parts.cpu().numpy()
     say(f"[fullsize] levels={res['n_levels']} parts={res['n_parts']} conn={res['connectivity']}; checking")
+    for name, k in sorted(res["kernels"].items(), key=lambda kv: -kv[1]["ms"]):
+        if k["launches"]:
+            say(f"[fullsize]   {name:11s} {k['ms']:9.1f} ms  launches {k['launches']}")
     _check_partition(g, parts, w.omega, w.delta, res)
     ctx.close()
     return res
