@@ -20,6 +20,7 @@ constexpr int kWaveSegMax = 1024;
 struct BigHedges {
   const int32_t *list = nullptr;
   int32_t n = 0;
+  int32_t max_len = 0x7fffffff;  // bound of the hedge lengths (coarse hedges only shrink)
 };
 
 // One hierarchy level resident on the device.
@@ -68,9 +69,12 @@ void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, 
                           int32_t *cnt, hipStream_t s);
 // Part tables of hedges with at most kWaveSegMax pins and inb(p) of their
 // entries: pinb[0 .. n_parts) is written (not accumulated).  partial: scratch.
-void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
-                            DevBuf &partial, hipStream_t s);
+// max_len: an upper bound of the hedge lengths (selects the kernel variant).
+void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int32_t *pt,
+                            uint32_t *ptc, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
+                            int32_t max_len, DevBuf &partial, hipStream_t s);
+// list[0 .. count[0]) = hedges longer than kWaveSegMax; count[1] = the
+// longest hedge's length.
 void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s);
 
 void launch_check_range(const int32_t *a, int64_t n, int32_t lo, int32_t hi, int32_t *err, hipStream_t s);
@@ -81,16 +85,17 @@ void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, in
 // device scalars of a refinement round (RoundBufs::scal)
 enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4, SC_HEAVY = 5 };
 
-// (pins, pins_in) of part p in the sorted part table pt[b .. b+len) of a hedge.
-__device__ __forceinline__ int2 pt_lookup(const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, int b,
+// (pins, pins_in) of part p in the sorted part table of a hedge: part ids
+// pt[b .. b+len), counts ptc (pins | pins_in << 16).
+__device__ __forceinline__ int2 pt_lookup(const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, int b,
                                           int len, int p) {
   int lo = 0, hi = len;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
-    if (pt[b + mid].x < p) lo = mid + 1;
+    if (pt[b + mid] < p) lo = mid + 1;
     else hi = mid;
   }
-  if (lo < len && pt[b + lo].x == p) return make_int2(pt[b + lo].y, ptin[b + lo]);
+  if (lo < len && pt[b + lo] == p) return make_int2((int)(ptc[b + lo] & 0xffffu), (int)(ptc[b + lo] >> 16));
   return make_int2(0, 0);
 }
 
@@ -101,8 +106,8 @@ void sort_keys(uint64_t *keys, uint64_t *alt, int64_t n, int bits, DevBuf &sort_
 // --- refine.hip ---
 struct RoundBufs {
   // part table (oversized: one slot per pin, at the hedge's pin offset)
-  int2 *pt = nullptr;          // [P] (part, pins(p,e))
-  int32_t *ptin = nullptr;     // [P] pins_in(p,e)
+  int32_t *pt = nullptr;       // [P] part ids, ascending per hedge
+  uint32_t *ptc = nullptr;     // [P] pins(p,e) | pins_in(p,e) << 16 (both <= kSegCap)
   int32_t *lam = nullptr;      // [E] entries per hedge
   uint8_t *solo = nullptr;     // [P] 1 if the pin is the only pin of its part in its hedge
   int32_t *psize = nullptr;    // [n_parts]

@@ -68,7 +68,7 @@ struct Workspace {
   DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2, perm, pin_he;
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
-  DevBuf heavy, evoff, maxin, pt, ptin, lam, solo, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
+  DevBuf heavy, evoff, maxin, pt, ptc, lam, solo, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
   DevBuf contrib, esum, isum, poff, pt_partial;
   DevBuf scan_tmp, sort_tmp;
   DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
@@ -116,7 +116,7 @@ struct Workspace {
   void release_all() {
     DevBuf *all[] = {&err,  &sums,  &scal2,  &hpin0,  &hoffA,    &hoffB,  &hpinA,  &hpinB,   &hoffR,   &hpinR,
                      &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2, &perm, &pin_he,   &pair,    &score,   &best,
-                     &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptin,    &lam, &heavy,
+                     &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptc,     &lam, &heavy, &evoff, &maxin, &solo,
                      &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
                      &vdelta, &contrib, &esum, &isum, &poff, &pt_partial, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
@@ -272,10 +272,14 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
 // Hedges of `hoff` longer than kWaveSegMax pins (list kept in W.biglist).
 static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStream_t s) {
   BigHedges b;
-  int32_t *list = need<int32_t>(W.biglist, (int64_t)E + 1);
-  launch_big_hedges(hoff, E, list + 1, list, s);
-  b.n = read_i32(list, s);
-  b.list = list + 1;
+  int32_t *list = need<int32_t>(W.biglist, (int64_t)E + 2);
+  launch_big_hedges(hoff, E, list + 2, list, s);
+  int32_t hdr[2];
+  HGP_HIP(hipMemcpyAsync(hdr, list, sizeof hdr, hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  b.n = hdr[0];
+  b.max_len = hdr[1];
+  b.list = list + 2;
   return b;
 }
 
@@ -313,8 +317,8 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
 
 static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32_t n_parts) {
   RoundBufs B;
-  B.pt = need<int2>(W.pt, P);
-  B.ptin = need<int32_t>(W.ptin, P);
+  B.pt = need<int32_t>(W.pt, P);
+  B.ptc = need<uint32_t>(W.ptc, P);
   B.lam = need<int32_t>(W.lam, E);
   B.solo = need<uint8_t>(W.solo, P);
   B.psize = need<int32_t>(W.psize, n_parts);

@@ -125,7 +125,7 @@ __device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t 
 __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
-    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
+    const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
     int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
     int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
   __shared__ uint64_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
@@ -201,9 +201,8 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
   uint32_t *sc = sc_s[w];
   if (staged) {
     for (int i = l; i < plen; i += 64) {
-      const int2 x = pt[b + i];
-      sp[i] = x.x;
-      sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
+      sp[i] = pt[b + i];
+      sc[i] = ptc[b + i];
     }
   }
   if (nev <= 64) ev_wave_sort_scan<1>(nev, pshift, evk, pre);
@@ -219,7 +218,7 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const uint64_t k = evk[i];
     const int part = (int)(k >> pshift);
     const int2 before = unpack_delta(pre[i]);
-    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, part) : pt_lookup(pt, ptin, b, plen, part);
+    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, part) : pt_lookup(pt, ptc, b, plen, part);
     const bool dst_role = (k & 2ull) != 0;
     int2 *cp = &contrib[b + li[(int)((k >> 2) & 511ull)]];
     if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
@@ -250,7 +249,7 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
 __global__ __launch_bounds__(EVB_NT) void k_ev_block(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
-    const int2 *__restrict__ pt, const int32_t *__restrict__ ptin, const int32_t *__restrict__ lam, int qbits,
+    const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
     int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
     const int64_t *__restrict__ scal, const int32_t *__restrict__ heavy) {
   __shared__ uint64_t key[2 * kSegCap];
@@ -299,9 +298,8 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
     const int32_t we = hw[e];
     const int plen = lam[e];
     for (int i = tid; i < plen; i += EVB_NT) {
-      const int2 x = pt[b + i];
-      sp[i] = x.x;
-      sc[i] = (uint32_t)x.y | ((uint32_t)ptin[b + i] << 16);
+      sp[i] = pt[b + i];
+      sc[i] = ptc[b + i];
     }
     __syncthreads();
     uint32_t evbits = 0;  // bit t: event tid + EVB_NT t changes an inbound count (nev <= 32 EVB_NT)
@@ -590,10 +588,10 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
       // inbound-count events per hedge into keys2 (one region of 2|e| per
       // hedge), then packed into keys[0 .. nin)
       k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
-                                                            B.ptin, B.lam, qbits, B.contrib, B.keys2, B.evoff,
+                                                            B.ptc, B.lam, qbits, B.contrib, B.keys2, B.evoff,
                                                             B.scal, B.heavy);
       HGP_LAUNCH_CHECK();
-      k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptin, B.lam, qbits,
+      k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam, qbits,
                                              B.contrib, B.keys2, B.evoff, B.scal, B.heavy);
       HGP_LAUNCH_CHECK();
       scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);

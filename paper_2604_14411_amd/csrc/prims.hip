@@ -217,6 +217,27 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
   tcnt[o] = cnt[threadIdx.x];
 }
 
+// Per digit d (one workgroup each): exclusive scan over the tiles of
+// hist[d * ntiles ..], in place, and the digit's total in dtot[d].
+__global__ __launch_bounds__(RS_NT) void k_rs_dscan(int32_t *__restrict__ hist, int ntiles,
+                                                    int32_t *__restrict__ dtot) {
+  __shared__ int32_t stmp[RS_NT / 64 + 1];
+  const int32_t t = block_exclusive_scan<int32_t, RS_NT>(hist + (int64_t)blockIdx.x * ntiles, ntiles, stmp);
+  if (threadIdx.x == 0) dtot[blockIdx.x] = t;
+}
+
+// gbase[d] = start of digit d in the output (exclusive scan of dtot, in LDS)
+// + start of this tile within digit d.  One thread per digit.
+__device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, const int32_t *__restrict__ dtot,
+                                              int ntiles, int32_t *gbase, int32_t *stmp) {
+  const int tid = threadIdx.x;
+  gbase[tid] = dtot[tid];
+  __syncthreads();
+  block_exclusive_scan<int32_t, RS_NT>(gbase, 256, stmp);
+  gbase[tid] += offs[(int64_t)tid * ntiles + blockIdx.x];
+  __syncthreads();
+}
+
 // Rank of a key within its digit among the valid lanes of the wave (match
 // mask from 8 ballots); returns the rank, *cnt = size of the digit group.
 __device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt, int *cnt) {
@@ -240,6 +261,7 @@ __device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt,
 template <class K, bool V>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
+                                                      const int32_t *__restrict__ dtot,
                                                       const int32_t *__restrict__ tcnt, int ntiles,
                                                       K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
   __shared__ int32_t gbase[256];
@@ -263,7 +285,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
     if (V) vr[r] = j < tn ? vals[tbase + j] : 0u;
   }
   const int64_t o = (int64_t)tid * ntiles + blockIdx.x;
-  gbase[tid] = offs[o];
+  rs_tile_bases(offs, dtot, ntiles, gbase, stmp);
   lstart[tid] = tcnt[o];
   __syncthreads();
   block_exclusive_scan<int32_t, RS_NT>(lstart, 256, stmp);
@@ -309,10 +331,12 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
 template <class K, bool V>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict__ keys,
                                                              const uint32_t *__restrict__ vals, int64_t n, int shift,
-                                                             const int32_t *__restrict__ offs, int ntiles,
+                                                             const int32_t *__restrict__ offs,
+                                                             const int32_t *__restrict__ dtot, int ntiles,
                                                              K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
   __shared__ int32_t base[256];
   __shared__ int32_t wcnt[RS_NT / 64][256];
+  __shared__ int32_t stmp[RS_NT / 64 + 1];
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int l = lane_id();
@@ -325,7 +349,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict
     kr[r] = j < n ? keys[j] : K(0);
     if (V) vr[r] = j < n ? vals[j] : 0u;
   }
-  base[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+  rs_tile_bases(offs, dtot, ntiles, base, stmp);
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
@@ -359,28 +383,29 @@ static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int
   const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
   const int64_t hn = 256LL * ntiles;
   const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
-  const size_t need = 2 * hist_bytes + scan_tmp_elems(hn) * sizeof(int32_t);
+  const size_t need = 2 * hist_bytes + 256 * sizeof(int32_t);
   tmp.reserve(need);
   int32_t *hist = tmp.as<int32_t>();
   int32_t *tcnt = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
-  int32_t *stmp = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + 2 * hist_bytes);
+  int32_t *dtot = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + 2 * hist_bytes);
   K *src = keys, *dst = alt;
   uint32_t *vs = vals, *vd = valt;
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
     k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, tcnt, ntiles);
     HGP_LAUNCH_CHECK();
-    scan_impl<int32_t>(hist, hist, hn, nullptr, stmp, s);
+    k_rs_dscan<<<256, RS_NT, 0, s>>>(hist, ntiles, dtot);
+    HGP_LAUNCH_CHECK();
     if constexpr (sizeof(K) == 4) {
       if (vs)
-        k_rs_scatter<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
+        k_rs_scatter<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, tcnt, ntiles, dst, vd);
       else
-        k_rs_scatter<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, tcnt, ntiles, dst, vd);
+        k_rs_scatter<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, tcnt, ntiles, dst, vd);
     } else {
       if (vs)
-        k_rs_scatter_direct<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+        k_rs_scatter_direct<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
       else
-        k_rs_scatter_direct<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, ntiles, dst, vd);
+        k_rs_scatter_direct<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
     }
     HGP_LAUNCH_CHECK();
     std::swap(src, dst);

@@ -25,8 +25,8 @@ __device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int n, uint32_
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict__ hoff,
                                                       const uint32_t *__restrict__ hpin,
-                                                      const int32_t *__restrict__ rho, int2 *__restrict__ pt,
-                                                      int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
+                                                      const int32_t *__restrict__ rho, int32_t *__restrict__ pt,
+                                                      uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
                                                       uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
                                                       int32_t *err, const int32_t *__restrict__ list) {
   __shared__ uint32_t key[kSegCap];
@@ -62,8 +62,8 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
       const int end = lower_bound_u32(key, len, (part + 1) << 1);
       const int dst0 = lower_bound_u32(key, len, (part << 1) | 1u);
       const int r = first[i];
-      pt[b + r] = make_int2((int)part, end - i);
-      ptin[b + r] = end - dst0;
+      pt[b + r] = (int)part;
+      ptc[b + r] = (uint32_t)(end - i) | ((uint32_t)(end - dst0) << 16);
       if (end > dst0) atomicAdd(&pinb[part], 1);
     }
   }
@@ -87,10 +87,11 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   KScope ks(2, s);
   add_units(2, 0);
   if (!B.partial) throw Error(-7, "part-table scratch missing");
-  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptin, B.lam, B.solo, B.pinb, n_parts, *B.partial, s);
+  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, n_parts, L.big.max_len,
+                         *B.partial, s);
   if (L.E > 0) {
     if (L.big.n > 0) {
-      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptin, B.lam, B.solo, B.pinb, err,
+      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
                                              L.big.list);
       HGP_LAUNCH_CHECK();
     }
@@ -116,7 +117,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list, const int64_t *__restrict__ count,
                                                 int32_t N, const int32_t *__restrict__ ioff,
                                                 const uint32_t *__restrict__ inc, const uint32_t *__restrict__ perm,
-                                                const int32_t *__restrict__ hoff, const int2 *__restrict__ pt,
+                                                const int32_t *__restrict__ hoff, const int32_t *__restrict__ pt,
                                                 const uint8_t *__restrict__ solo,
                                                 const int32_t *__restrict__ lam, const int32_t *__restrict__ hw,
                                                 const int32_t *__restrict__ rho, const int32_t *__restrict__ size,
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
         for (int i = tid; i < span; i += NT) conn[i] = 0u;
         __syncthreads();
         streamed += stream_segments<NT / 64, 4, false, int32_t>(
-            i0, i1, inc, hoff, lam, hw, tbl, [&](int j) { return pt[j].x; },
+            i0, i1, inc, hoff, lam, hw, tbl, [&](int j) { return pt[j]; },
             [&](int32_t p, uint32_t info) {
               const uint32_t rel = (uint32_t)(p - lo);
               if (rel < (uint32_t)span) atomicAdd(&conn[rel], info & kIdMask);

@@ -78,8 +78,8 @@ __global__ __launch_bounds__(256) void k_contract_wave(const int32_t *__restrict
 // in saving(v) of Eq. 3).  s: 64*KPL words of LDS.
 template <int KPL>
 __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uint32_t *__restrict__ hpin,
-                                                const int32_t *__restrict__ rho, int2 *__restrict__ pt,
-                                                int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
+                                                const int32_t *__restrict__ rho, int32_t *__restrict__ pt,
+                                                uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
                                                 uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
                                                 uint32_t *s) {
   const int l = lane_id();
@@ -128,8 +128,8 @@ __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uin
       const uint32_t part = k[j] >> 1;
       const int end = lb_u32(s, len, (part + 1) << 1);
       const int dst0 = lb_u32(s, len, (part << 1) | 1u);
-      pt[b + r] = make_int2((int)part, end - i);
-      ptin[b + r] = end - dst0;
+      pt[b + r] = (int)part;
+      ptc[b + r] = (uint32_t)(end - i) | ((uint32_t)(end - dst0) << 16);
       if (end > dst0) atomicAdd(&pinb[part], 1);
       ++r;
     }
@@ -139,21 +139,23 @@ __device__ __forceinline__ void part_table_wave(int e, int b, int len, const uin
 }
 
 // Grid-stride over hedges, one wave each.  inb(p) counts go to `cnt`: the
-// workgroup's LDS histogram when it covers every part (flushed to row
-// blockIdx.x of `partial`, summed per part by k_pinb_reduce), else the global
-// pinb array.
-constexpr int PTW_GRID = 512;
+// workgroup's LDS histogram (dynamic LDS, n_parts words) when it covers every
+// part (flushed to row blockIdx.x of `partial`, summed per part by
+// k_pinb_reduce), else the global pinb array.  MAXKPL bounds the hedge length
+// handled here (64 * MAXKPL); a variant with MAXKPL = 8 is used when no hedge
+// is longer than 512 pins, for its lower register and LDS use.
 constexpr int PTW_LDS_PARTS = 8192;
 
+template <int MAXKPL>
 __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restrict__ hoff,
                                                          const uint32_t *__restrict__ hpin, int32_t E,
-                                                         const int32_t *__restrict__ rho, int2 *__restrict__ pt,
-                                                         int32_t *__restrict__ ptin, int32_t *__restrict__ lam,
+                                                         const int32_t *__restrict__ rho, int32_t *__restrict__ pt,
+                                                         uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
                                                          uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
                                                          int32_t n_parts,
                                                          int32_t *__restrict__ partial) {
-  __shared__ uint32_t sbuf[4][kWaveSegMax];
-  __shared__ int32_t hist[PTW_LDS_PARTS];
+  __shared__ uint32_t sbuf[4][64 * MAXKPL];
+  extern __shared__ int32_t hist[];
   const bool local = partial != nullptr;
   if (local) {
     for (int i = threadIdx.x; i < n_parts; i += 256) hist[i] = 0;
@@ -164,16 +166,16 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
   uint32_t *s = sbuf[w];
   for (int e = (int)(blockIdx.x * 4 + w); e < E; e += (int)(gridDim.x * 4)) {
     const int b = hoff[e], len = hoff[e + 1] - b;
-    if (len > kWaveSegMax) continue;
+    if (len > 64 * MAXKPL) continue;
     if (len == 0) {
       if (lane_id() == 0) lam[e] = 0;
       continue;
     }
-    if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
-    else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
-    else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
-    else if (len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
-    else part_table_wave<16>(e, b, len, hpin, rho, pt, ptin, lam, solo, cnt, s);
+    if (len <= 64) part_table_wave<1>(e, b, len, hpin, rho, pt, ptc, lam, solo, cnt, s);
+    else if (len <= 128) part_table_wave<2>(e, b, len, hpin, rho, pt, ptc, lam, solo, cnt, s);
+    else if (len <= 256) part_table_wave<4>(e, b, len, hpin, rho, pt, ptc, lam, solo, cnt, s);
+    else if (MAXKPL == 8 || len <= 512) part_table_wave<8>(e, b, len, hpin, rho, pt, ptc, lam, solo, cnt, s);
+    else part_table_wave<MAXKPL>(e, b, len, hpin, rho, pt, ptc, lam, solo, cnt, s);
   }
   if (local) {
     __syncthreads();
@@ -181,6 +183,7 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
     for (int i = threadIdx.x; i < n_parts; i += 256) row[i] = hist[i];
   }
 }
+static_assert(kWaveSegMax == 1024, "k_part_table_wave<16> covers the wave-path hedge lengths");
 
 // pinb[p] = sum over the rows of partial.  A workgroup covers 64 parts (one
 // per lane); its PR_W waves sum interleaved rows, 8 loads in flight each.
@@ -219,39 +222,60 @@ void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, 
   HGP_LAUNCH_CHECK();
 }
 
-void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int2 *pt,
-                            int32_t *ptin, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
-                            DevBuf &partial, hipStream_t s) {
-  if (n_parts > 0 && n_parts <= PTW_LDS_PARTS) {
-    const int grid = E > 0 ? std::min(PTW_GRID, div_up(E, 4)) : 0;
-    if (grid > 0) {
-      partial.reserve((size_t)grid * n_parts * sizeof(int32_t));
-      k_part_table_wave<<<grid, 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, solo, pinb, n_parts,
-                                             partial.as<int32_t>());
-      HGP_LAUNCH_CHECK();
-      k_pinb_reduce<<<div_up(n_parts, 64), 64 * PR_W, 0, s>>>(partial.as<int32_t>(), grid, n_parts, pinb);
-      HGP_LAUNCH_CHECK();
-    } else {
-      fill_i32(pinb, n_parts, 0, s);
-    }
-    return;
-  }
-  fill_i32(pinb, n_parts, 0, s);
-  if (E <= 0) return;
-  k_part_table_wave<<<std::min(PTW_GRID, div_up(E, 4)), 256, 0, s>>>(hoff, hpin, E, rho, pt, ptin, lam, solo,
-                                                                     pinb, n_parts, nullptr);
+template <int MAXKPL>
+static void launch_ptw(int grid, size_t lds, const int32_t *hoff, const uint32_t *hpin, int32_t E,
+                       const int32_t *rho, int32_t *pt, uint32_t *ptc, int32_t *lam, uint8_t *solo, int32_t *pinb,
+                       int32_t n_parts, int32_t *partial, hipStream_t s) {
+  k_part_table_wave<MAXKPL><<<grid, 256, lds, s>>>(hoff, hpin, E, rho, pt, ptc, lam, solo, pinb, n_parts, partial);
   HGP_LAUNCH_CHECK();
 }
 
+void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int32_t *pt,
+                            uint32_t *ptc, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
+                            int32_t max_len, DevBuf &partial, hipStream_t s) {
+  const bool small = max_len <= 512;
+  const bool local = n_parts > 0 && n_parts <= PTW_LDS_PARTS;
+  const size_t lds = local ? (size_t)n_parts * sizeof(int32_t) : 0;
+  // resident workgroups per CU (registers: 5 or 3; LDS: 160 KB), 256 CUs
+  const size_t lds_wg = lds + (small ? 8u : 16u) * 1024u;
+  const int per_cu = std::max(1, std::min(small ? 5 : 3, (int)((160u * 1024u) / lds_wg)));
+  const int grid = E > 0 ? std::min(256 * per_cu, div_up(E, 4)) : 0;
+  if (!local) fill_i32(pinb, n_parts, 0, s);
+  if (grid <= 0) {
+    if (local) fill_i32(pinb, n_parts, 0, s);
+    return;
+  }
+  int32_t *rows = nullptr;
+  if (local) {
+    partial.reserve((size_t)grid * n_parts * sizeof(int32_t));
+    rows = partial.as<int32_t>();
+  }
+  if (small)
+    launch_ptw<8>(grid, lds, hoff, hpin, E, rho, pt, ptc, lam, solo, pinb, n_parts, rows, s);
+  else
+    launch_ptw<16>(grid, lds, hoff, hpin, E, rho, pt, ptc, lam, solo, pinb, n_parts, rows, s);
+  if (local) {
+    k_pinb_reduce<<<div_up(n_parts, 64), 64 * PR_W, 0, s>>>(rows, grid, n_parts, pinb);
+    HGP_LAUNCH_CHECK();
+  }
+}
+
 // Hedges longer than kWaveSegMax pins (fixed by level 0: coarse hedges only shrink).
-__global__ void k_big_hedges(const int32_t *__restrict__ hoff, int32_t E, int32_t *__restrict__ list,
-                             int32_t *__restrict__ count) {
+__global__ __launch_bounds__(256) void k_big_hedges(const int32_t *__restrict__ hoff, int32_t E,
+                                                    int32_t *__restrict__ list, int32_t *__restrict__ count) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < E && hoff[e + 1] - hoff[e] > kWaveSegMax) list[atomicAdd(count, 1)] = (int32_t)e;
+  int len = 0;
+  if (e < E) {
+    len = hoff[e + 1] - hoff[e];
+    if (len > kWaveSegMax) list[atomicAdd(count, 1)] = (int32_t)e;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+  if (lane_id() == 0 && len > 0) atomicMax(count + 1, len);
 }
 
 void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s) {
-  fill_i32(count, 1, 0, s);
+  fill_i32(count, 2, 0, s);
   if (E <= 0) return;
   k_big_hedges<<<div_up(E, 256), 256, 0, s>>>(hoff, E, list, count);
   HGP_LAUNCH_CHECK();

@@ -41,7 +41,18 @@ def _check_partition(g, parts, omega, delta, res):
 
 
 @pytest.fixture(scope="module")
-def conv208k():
+def gpu():
+    """The device is initialised before the large host arrays are made."""
+    import torch
+
+    assert torch.cuda.is_available()
+    torch.zeros(1, device="cuda:0")
+    torch.cuda.synchronize()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def conv208k(gpu):
     from paper_2604_14411_amd.synth.configs import WORKLOADS
 
     w = WORKLOADS["conv208k"]
