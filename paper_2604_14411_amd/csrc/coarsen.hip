@@ -189,28 +189,34 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
     // windows over the neighbours' id range only
     const int2 rg = neighbour_range<NT>(i0, i1, inc, hoff, hpin, rng_s);
+    const uint32_t *clip = ((int64_t)rg.y - rg.x >= R) ? hpin : nullptr;  // several windows
     for (int lo = rg.x; lo <= rg.y; lo += R) {
       const int span = min(R, rg.y + 1 - lo);
       const int zw = half ? (span + 1) >> 1 : (packed ? span : 2 * span);
       for (int i = tid; i < zw; i += NT) lds[i] = 0u;
       __syncthreads();
-      streamed += stream_segments<NT / 64, 4, true, uint32_t>(
-          i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-          [&](uint32_t y, uint32_t info) {
-            const int m = (int)(y & kIdMask);
-            const uint32_t rel = (uint32_t)(m - lo);
-            if (m != n && rel < (uint32_t)span) {
-              const uint32_t we = info & kIdMask;
-              const uint32_t both = (info >> 31) & (y >> 31);
-              if (half)
-                atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
-              else if (packed)
-                atomicAdd(&lds[rel], we + (both << hb));
-              else
-                atomicAdd((unsigned long long *)&lds64[rel],
-                          (unsigned long long)we | ((unsigned long long)both << 32));
-            }
-          });
+      // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
+      streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        return stream_segments<NT / 64, 4, true, uint32_t>(
+            i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+            [&](uint32_t y, uint32_t info) {
+              const int m = (int)(y & kIdMask);
+              const uint32_t rel = (uint32_t)(m - lo);
+              if ((m != n) & (rel < (uint32_t)span)) {
+                const uint32_t we = info & kIdMask;
+                const uint32_t both = (info & y) >> 31;
+                if constexpr (MODE == 0)
+                  atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
+                else if constexpr (MODE == 1)
+                  atomicAdd(&lds[rel], we + (both << hb));
+                else
+                  atomicAdd((unsigned long long *)&lds64[rel],
+                            (unsigned long long)we | ((unsigned long long)both << 32));
+              }
+            },
+            clip, lo, lo + span);
+      });
       __syncthreads();
       if (half) {
         for (int i = tid; i < zw; i += NT) {

@@ -1,5 +1,6 @@
 // Internal declarations shared by the libhgp translation units (gfx950, wave64).
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
@@ -141,11 +142,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // busy and U loads in flight per lane: load(j) fetches entry j, apply(v, info)
 // consumes it with info = w(e) | (dst << 31).  tbl: 192 ints of LDS per wave.
 // Returns the number of entries this wave streamed (uniform across the wave).
+// With clip non-null (the segments' ascending pin ids, bit 31 masked off),
+// each segment is first narrowed by binary search to the entries whose id
+// lies in [clip_lo, clip_hi): a rating over several LDS windows then streams
+// each pin once instead of once per window.
 template <int NW, int U, bool LEN_FROM_END, class V, class Load, class Apply>
 __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_t *__restrict__ inc,
                                                    const int32_t *__restrict__ soff, const int32_t *__restrict__ slen,
                                                    const int32_t *__restrict__ hw, int32_t *tbl, Load load,
-                                                   Apply apply) {
+                                                   Apply apply, const uint32_t *__restrict__ clip = nullptr,
+                                                   int clip_lo = 0, int clip_hi = 0) {
   const int w = threadIdx.x >> 6, l = lane_id();
   int64_t streamed = 0;
   int32_t *t_end = tbl + w * 192;
@@ -161,6 +167,23 @@ __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_
       b = soff[e];
       len = LEN_FROM_END ? soff[e + 1] - b : slen[e];
       info = (uint32_t)hw[e] | (x & kDst);
+      if (clip) {
+        int a = b, z = b + len;
+        while (a < z) {
+          const int mid = (a + z) >> 1;
+          if ((int)(clip[mid] & kIdMask) < clip_lo) a = mid + 1;
+          else z = mid;
+        }
+        int c = a;
+        z = b + len;
+        while (c < z) {
+          const int mid = (c + z) >> 1;
+          if ((int)(clip[mid] & kIdMask) < clip_hi) c = mid + 1;
+          else z = mid;
+        }
+        b = a;
+        len = c - a;
+      }
     }
     const int incl = wave_inclusive_scan(len);
     const int total = __shfl(incl, 63, 64);
@@ -174,36 +197,46 @@ __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_
     int k_shift = t_shift[0];
     uint32_t k_info = t_info[0];
     streamed += total;
+    // lanes past the end re-read the last entry (always in bounds), so the
+    // loads need no branch; only apply is masked
     for (int v0 = 0; v0 < total; v0 += 64 * U) {
       int jj[U];
       uint32_t ii[U];
+      bool ok[U];
       V vv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int v = v0 + u * 64 + l;
-        jj[u] = -1;
-        ii[u] = 0;
-        if (v < total) {
-          while (k_end <= v) {
-            ++k;
-            k_end = t_end[k];
-            k_shift = t_shift[k];
-            k_info = t_info[k];
-          }
-          jj[u] = v + k_shift;
-          ii[u] = k_info;
+        ok[u] = v < total;
+        const int vc = ok[u] ? v : total - 1;
+        while (k_end <= vc) {
+          ++k;
+          k_end = t_end[k];
+          k_shift = t_shift[k];
+          k_info = t_info[k];
         }
+        jj[u] = vc + k_shift;
+        ii[u] = k_info;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (jj[u] >= 0) vv[u] = load(jj[u]);
+      for (int u = 0; u < U; ++u) vv[u] = load(jj[u]);
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (jj[u] >= 0) apply(vv[u], ii[u]);
+        if (ok[u]) apply(vv[u], ii[u]);
     }
     wave_lds_sync();
   }
   return streamed;
+}
+
+// Calls f(std::integral_constant<int, mode>) for mode 0, 1 or 2, so that a
+// streaming loop is compiled once per counter layout instead of branching on
+// it for every entry.
+template <class F>
+__device__ __forceinline__ int64_t with_mode(int mode, F f) {
+  if (mode == 0) return f(std::integral_constant<int, 0>{});
+  if (mode == 1) return f(std::integral_constant<int, 1>{});
+  return f(std::integral_constant<int, 2>{});
 }
 
 // Workgroups are dealt to the device's 8 XCDs round-robin by workgroup index.

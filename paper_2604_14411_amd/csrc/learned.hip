@@ -96,26 +96,31 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
     // windows over the neighbours' id range only
     const int2 rg = neighbour_range<CAND_NT>(i0, i1, inc, hoff, hpin, rng_s);
+    const uint32_t *clip = ((int64_t)rg.y - rg.x >= R) ? hpin : nullptr;  // several windows
     for (int lo = rg.x; lo <= rg.y; lo += R) {
       const int span = min(R, rg.y + 1 - lo);
       const int zw = packed ? span : 2 * span;
       for (int i = tid; i < zw; i += CAND_NT) lds[i] = 0u;
       __syncthreads();
-      streamed += stream_segments<CAND_NT / 64, 4, true, uint32_t>(
-          i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-          [&](uint32_t y, uint32_t info) {
-            const int m = (int)(y & kIdMask);
-            const uint32_t rel = (uint32_t)(m - lo);
-            if (m != n && rel < (uint32_t)span) {
-              const uint32_t we = info & kIdMask;
-              const uint32_t both = (info >> 31) & (y >> 31);
-              if (packed)
-                atomicAdd(&lds[rel], we + (both << hb));
-              else
-                atomicAdd((unsigned long long *)&lds64[rel],
-                          (unsigned long long)we | ((unsigned long long)both << 32));
-            }
-          });
+      streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        return stream_segments<CAND_NT / 64, 4, true, uint32_t>(
+            i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+            [&](uint32_t y, uint32_t info) {
+              const int m = (int)(y & kIdMask);
+              const uint32_t rel = (uint32_t)(m - lo);
+              if ((m != n) & (rel < (uint32_t)span)) {
+                const uint32_t we = info & kIdMask;
+                const uint32_t both = (info & y) >> 31;
+                if constexpr (MODE == 1)
+                  atomicAdd(&lds[rel], we + (both << hb));
+                else
+                  atomicAdd((unsigned long long *)&lds64[rel],
+                            (unsigned long long)we | ((unsigned long long)both << 32));
+              }
+            },
+            clip, lo, lo + span);
+      });
       __syncthreads();
       for (int i = tid; i < span; i += CAND_NT) {
         uint64_t h, c;

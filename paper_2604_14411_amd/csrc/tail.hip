@@ -77,19 +77,23 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
       __syncthreads();
     }
     if (!pre && sn < omega) {
-      streamed += stream_segments<NT / 64, 4, true, uint32_t>(
-          ioff[n], ioff[n + 1], inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-          [&](uint32_t y, uint32_t info) {
-            const int m = (int)(y & kIdMask);
-            if (m != n) {
-              const uint32_t we = info & kIdMask;
-              const uint32_t both = (info >> 31) & (y >> 31);
-              if (packed)
-                atomicAdd(&lds[m], we + (both << hb));
-              else
-                atomicAdd((unsigned long long *)&lds64[m], (unsigned long long)we | ((unsigned long long)both << 32));
-            }
-          });
+      streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        return stream_segments<NT / 64, 4, true, uint32_t>(
+            ioff[n], ioff[n + 1], inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+            [&](uint32_t y, uint32_t info) {
+              const int m = (int)(y & kIdMask);
+              if (m != n) {
+                const uint32_t we = info & kIdMask;
+                const uint32_t both = (info & y) >> 31;
+                if constexpr (MODE == 1)
+                  atomicAdd(&lds[m], we + (both << hb));
+                else
+                  atomicAdd((unsigned long long *)&lds64[m],
+                            (unsigned long long)we | ((unsigned long long)both << 32));
+              }
+            });
+      });
     }
     __syncthreads();
     // validity pass fused with the top-(TK+1) selection by key (hist, id):
@@ -289,19 +293,22 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
   uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
   for (int i = tid; i < zw; i += NT) lds[i] = 0u;
   __syncthreads();
-  const int64_t streamed = stream_segments<NT / 64, 4, true, uint32_t>(
-      a, z, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-      [&](uint32_t y, uint32_t info) {
-        const int m = (int)(y & kIdMask);
-        if (m != n) {
-          const uint32_t we = info & kIdMask;
-          const uint32_t both = (info >> 31) & (y >> 31);
-          if (packed)
-            atomicAdd(&lds[m], we + (both << hb));
-          else
-            atomicAdd((unsigned long long *)&lds64[m], (unsigned long long)we | ((unsigned long long)both << 32));
-        }
-      });
+  const int64_t streamed = with_mode(packed ? 1 : 2, [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+    return stream_segments<NT / 64, 4, true, uint32_t>(
+        a, z, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
+        [&](uint32_t y, uint32_t info) {
+          const int m = (int)(y & kIdMask);
+          if (m != n) {
+            const uint32_t we = info & kIdMask;
+            const uint32_t both = (info & y) >> 31;
+            if constexpr (MODE == 1)
+              atomicAdd(&lds[m], we + (both << hb));
+            else
+              atomicAdd((unsigned long long *)&lds64[m], (unsigned long long)we | ((unsigned long long)both << 32));
+          }
+        });
+  });
   __syncthreads();
   uint32_t *row = acc + (int64_t)r * words;
   if (packed) {

@@ -6,6 +6,7 @@ reported connectivity equal to Eq. 1 recomputed by the oracle's routine.
 full-size case compared id by id, tests/golden/rand64k.json.)"""
 import os
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -67,9 +68,11 @@ def _run(conv208k, mlp):
     ctx = hgp.Context(0)
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     say(f"[fullsize] partition conv208k {'learned' if mlp else 'plain'}")
+    t = time.perf_counter()
     parts, res = hgp.partition_device(ctx, dg, w.omega, w.delta, mlp=mlp, flags=hgp.FLAG_TIME_KERNELS)
     parts = parts.cpu().numpy()
-    say(f"[fullsize] levels={res['n_levels']} parts={res['n_parts']} conn={res['connectivity']}; checking")
+    say(f"[fullsize] {time.perf_counter() - t:.2f} s levels={res['n_levels']} parts={res['n_parts']} "
+        f"conn={res['connectivity']}; checking")
     for name, k in sorted(res["kernels"].items(), key=lambda kv: -kv[1]["ms"]):
         if k["launches"]:
             say(f"[fullsize]   {name:11s} {k['ms']:9.1f} ms  launches {k['launches']}")
