@@ -78,7 +78,7 @@ struct Workspace {
   KTimer timer;
   DevBuf units_dev;
   // incremental late levels
-  DevBuf tkA_key, tkA_cnt, tkA_kap, tkB_key, tkB_cnt, tkB_kap, rows, newc, row_slot, nflag, rerate, dev_cnt;
+  DevBuf tkA_key, tkA_c, tkA_cnt, tkA_kap, tkB_key, tkB_c, tkB_cnt, tkB_kap, newc, row_slot, nflag, rerate, dev_cnt;
   DevBuf split, cdest, cgain, maxbits, biglist, tail_acc;
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
@@ -125,7 +125,7 @@ struct Workspace {
     clear_level_cache();
     for (auto &c : lcache_free) c->release();
     lcache_free.clear();
-    DevBuf *inc_bufs[] = {&tkA_key, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_cnt, &tkB_kap, &rows, &newc, &row_slot,
+    DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
                           &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
@@ -389,13 +389,6 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
 
 // LDS words per id for the top-K rating of level L: 2 if the wide window fits,
 // 1 if every node's counters pack in 32 bits and the narrow window fits, else 0.
-static int topk_words_per_id(Workspace &W, const LevelView &L, hipStream_t s) {
-  if (2 * (int64_t)L.n <= kTopKMaxWords) return 2;
-  if ((int64_t)L.n > kTopKMaxWords) return 0;
-  int32_t *d = need<int32_t>(W.maxbits, 4);
-  launch_max_counter_bits(W.total.as<int32_t>(), L.indeg, L.n, d, s);
-  return read_i32(d, s) <= 32 ? 1 : 0;
-}
 
 struct RunStats {
   int64_t conn = 0;
@@ -620,7 +613,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   // Late levels that merge few pairs are rated incrementally (tail.hip):
   // lists of the exact top candidates per node are carried between levels,
   // new clusters are rated in full and offered to their neighbours.
-  const bool incremental = (opt.flags & HGP_FLAG_NO_INCREMENTAL) == 0 && !learned;
+  const bool incremental = (opt.flags & HGP_FLAG_NO_INCREMENTAL) == 0;
   int32_t n_parts = 0;
   int lvl = 0;
   const int32_t *cur_hoff = hoff0;
@@ -629,9 +622,11 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int ping = 0;
   TopK tk_cur, tk_nxt;
   tk_cur.key = need<uint64_t>(W.tkA_key, (int64_t)N * kTopK);
+  tk_cur.c = need<int32_t>(W.tkA_c, (int64_t)N * kTopK);
   tk_cur.cnt = need<int32_t>(W.tkA_cnt, N);
   tk_cur.kappa = need<uint64_t>(W.tkA_kap, N);
   tk_nxt.key = need<uint64_t>(W.tkB_key, (int64_t)N * kTopK);
+  tk_nxt.c = need<int32_t>(W.tkB_c, (int64_t)N * kTopK);
   tk_nxt.cnt = need<int32_t>(W.tkB_cnt, N);
   tk_nxt.kappa = need<uint64_t>(W.tkB_kap, N);
   int32_t *newc = need<int32_t>(W.newc, N);
@@ -641,23 +636,41 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int64_t *dcnt = need<int64_t>(W.dev_cnt, 4);
   bool have_pairs = false;  // pair/score of the current level already computed
   bool lists_ok = false;    // tk_cur holds exact lists for the current level
+  bool lists_fresh = false; // ... carried to it incrementally (learned: first k entries certain)
   bool tail = false;        // the previous matching merged few pairs
   const char *path = "plain";
   while (true) {
     const int32_t n = L.n;
     if (!have_pairs) {
       path = "plain";
-      const int wpi = (incremental && tail) ? topk_words_per_id(W, L, s) : 0;
       if (learned) {
         path = "learned";
         CandBufs CB = cand_bufs(W, n, pair, score);
-        learned_candidates(L, W.total.as<int32_t>(), omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
-                           W.sort_tmp, s);
-        lists_ok = false;
-      } else if (wpi > 0) {
+        if (lists_fresh || (incremental && tail)) {
+          // candidate lists from the top-K lists (rated in full here unless
+          // carried from the previous level)
+          if (!lists_fresh) {
+            path = "learned, topk";
+            launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
+            lists_ok = true;
+          } else {
+            path = "learned, incremental";
+          }
+          {
+            KScope ks(HGP_K_RATE, s);
+            launch_cand_from_lists(n, opt.mlp->k, tk_cur, CB.ck, CB.cc, CB.ccnt, s);
+          }
+          const int64_t C = candidate_sets(L, CB, W.scan_tmp, W.sort_tmp, s);
+          score_and_select(L, omega, delta, lvl, mlp_params, CB, C, s);
+        } else {
+          learned_candidates(L, W.total.as<int32_t>(), omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
+                             W.sort_tmp, s);
+          lists_ok = false;
+        }
+        lists_fresh = false;
+      } else if (incremental && tail) {
         path = "topk";
-        launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, nullptr, nullptr, pair, score,
-                         tk_cur, wpi, W.err.as<int32_t>(), s);
+        launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
         lists_ok = true;
       } else {
         launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, need<int32_t>(W.maxin, 1), s,
@@ -697,8 +710,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       HGP_HIP(hipStreamSynchronize(s));
     }
     if (log_on())
-      fprintf(stderr, "[hgp] level %d n=%d pins=%lld merged=%d rating=%s\n", lvl, n, (long long)cur_P, n - n_next,
-              path);
+      fprintf(stderr, "[hgp] level %d n=%d pins=%lld merged=%d rating=%s at %.1f ms\n", lvl, n, (long long)cur_P,
+              n - n_next, path, now_ms());
     if (n_next == n) {
       iota_i32(rho, n, s);
       n_parts = n;
@@ -733,21 +746,18 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s);
     cache_level(W, L, lvl, cur_P, s);
     tail = (int64_t)M * kTailRatio <= (int64_t)n;
-    const int wpi = (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget)
-                        ? topk_words_per_id(W, L, s)
-                        : 0;
-    if (wpi > 0) {
+    if (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget) {
       // rate level lvl incrementally from the lists of level lvl-1
-      int32_t *rows = need<int32_t>(W.rows, (int64_t)M * n_next);
       launch_new_clusters(lmatch, gam, n, n_next, nflag, newc, row_slot, W.scan_tmp, s);
       fill_i64(dcnt, 1, M, s);
-      launch_rate_topk_rows(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot, rows, pair, score,
-                            tk_nxt, wpi, W.tail_acc, W.err.as<int32_t>(), s);
+      const uint64_t *rows = launch_rate_topk_rows(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot,
+                                                   pair, score, tk_nxt, W.tail_acc, s);
       fill_i64(dcnt + 1, 1, 0, s);
-      launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, tk_nxt, pair, score, rerate, dcnt + 1, s);
-      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, nullptr, nullptr, pair,
-                       score, tk_nxt, wpi, W.err.as<int32_t>(), s);
-      have_pairs = true;
+      launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, learned ? opt.mlp->k : 1, tk_nxt, pair,
+                         score, rerate, dcnt + 1, s);
+      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
+      have_pairs = !learned;
+      lists_fresh = learned;
       lists_ok = true;
       path = "incremental";
       if (log_on()) {

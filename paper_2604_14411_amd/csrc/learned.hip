@@ -549,6 +549,12 @@ int64_t build_candidates(const LevelView &L, const int32_t *total, int32_t omega
                                                       units_ptr(HGP_K_RATE));
     HGP_LAUNCH_CHECK();
   }
+  return candidate_sets(L, B, scan_tmp, sort_tmp, s);
+}
+
+int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s) {
+  const int32_t N = L.n;
+  if (N <= 0) return 0;
   const int idbits = std::max(1, bits_for(N - 1));
   int64_t C = 0, M = 0;
   {

@@ -51,6 +51,9 @@ int64_t learned_candidates(const LevelView &L, const int32_t *total, int32_t ome
 // keep: candidates per node (1..8).
 int64_t build_candidates(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int keep,
                          CandBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
+// Symmetric candidate sets, deduplicated pairs and offsets from ck / cc / ccnt
+// (the second half of build_candidates); returns the number of pairs.
+int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
 // Steps 3-4 on C entries built by build_candidates.
 void score_and_select(const LevelView &L, int32_t omega, int32_t delta, int level, const int32_t *params,
                       CandBufs &B, int64_t C, hipStream_t s);
