@@ -158,6 +158,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, help="only copy this many bytes on the device (profiling)")
     ap.add_argument("--mlp", default=None, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
     args = ap.parse_args()
+    if args.workload == "batch256":
+        # one hardware queue per batch worker stream (HIP's default is 4);
+        # set before the first HIP call of the process
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     if args.copy_probe:
         # a plain device-to-device copy of known size: reference for the HBM
         # byte counters (FETCH_SIZE / WRITE_SIZE) of a profiled kernel

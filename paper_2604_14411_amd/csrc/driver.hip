@@ -1590,11 +1590,11 @@ int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs,
     };
     {
       hgp_batch_sched warm = cur;
-      warm.workers = 8;
+      warm.workers = 16;
       (void)time_of(warm);
     }
     double best_t = 1e300;
-    for (int w : {1, 2, 4, 8}) {
+    for (int w : {1, 2, 4, 8, 16}) {
       hgp_batch_sched c = cur;
       c.workers = w;
       const double t = time_of(c);
