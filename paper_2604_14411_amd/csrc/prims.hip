@@ -190,31 +190,59 @@ constexpr int RS_NT = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_NT * RS_ROUNDS;
 
-// Digit counts of one 4096-key tile.  All of the tile's loads are issued
-// before the first count.
+// Rank of a key within its digit among the valid lanes of the wave (match
+// mask from 8 ballots); returns the rank, *cnt = size of the digit group.
+__device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt, int *cnt) {
+  uint64_t match = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(valid && bit);
+    match &= bit ? bb : ~bb;
+  }
+  *cnt = __popcll(match);
+  return __popcll(match & lt);
+}
+
+// Wave w of a tile owns its keys w * RS_WKEYS + r * 64 + lane (r < RS_ROUNDS):
+// the waves' key ranges are contiguous and in tile order, so a wave ranks
+// its keys alone (tile order within the wave: round, then lane) and the
+// waves' digit counts are combined once.
+constexpr int RS_WKEYS = RS_ROUNDS * 64;
+
+// Digit counts of one 4096-key tile, without atomics: per wave and round,
+// the last lane of each digit group (ballot match masks) adds the group's
+// size to the wave's counter.  All of the tile's loads are issued first.
 template <class K>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                   int32_t *__restrict__ hist, int32_t *__restrict__ tcnt,
-                                                   int ntiles) {
-  __shared__ int32_t cnt[256];
-  cnt[threadIdx.x] = 0;
-  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+                                                   int32_t *__restrict__ hist, int ntiles) {
+  __shared__ int32_t cw[RS_NT / 64][256];
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+#pragma unroll
+  for (int q = 0; q < RS_NT / 64; ++q) cw[q][tid] = 0;
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE + w * RS_WKEYS + l;
   K kr[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t j = base + r * RS_NT + threadIdx.x;
+    const int64_t j = base + r * 64;
     kr[r] = j < n ? keys[j] : K(0);
   }
   __syncthreads();
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t j = base + r * RS_NT + threadIdx.x;
-    if (j < n) atomicAdd(&cnt[(uint32_t)(kr[r] >> shift) & 255u], 1);
+    const bool valid = base + r * 64 < n;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    int cnt;
+    const int rank = rs_wave_rank(valid, d, lt, &cnt);
+    if (valid && rank == cnt - 1) cw[w][d] += cnt;
+    wave_lds_sync();
   }
   __syncthreads();
-  const int64_t o = (int64_t)threadIdx.x * ntiles + blockIdx.x;
-  hist[o] = cnt[threadIdx.x];
-  tcnt[o] = cnt[threadIdx.x];
+  int32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < RS_NT / 64; ++q) c += cw[q][tid];
+  hist[(int64_t)tid * ntiles + blockIdx.x] = c;
 }
 
 // Per digit d (one workgroup each): exclusive scan over the tiles of
@@ -238,141 +266,92 @@ __device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, 
   __syncthreads();
 }
 
-// Rank of a key within its digit among the valid lanes of the wave (match
-// mask from 8 ballots); returns the rank, *cnt = size of the digit group.
-__device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt, int *cnt) {
-  uint64_t match = __ballot(valid);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(valid && bit);
-    match &= bit ? bb : ~bb;
-  }
-  *cnt = __popcll(match);
-  return __popcll(match & lt);
-}
-
-// Stable scatter of one 4096-key tile.  The tile's keys (and values) are
-// loaded into registers first; then, 256 at a time, keys are ranked in tile
-// order within their digit (wave match masks, per-wave digit counts) and
-// placed in LDS at their position in the tile's digit-sorted order; the tile
-// is then written out in that order, so each digit's run goes to consecutive
-// addresses.  offs: global start of (digit, tile); tcnt: (digit, tile) counts.
-template <class K, bool V>
+// Stable scatter of one 4096-key tile.  Each wave loads its contiguous key
+// range into registers and ranks every key within its digit among the
+// wave's earlier keys (ballot match masks and a running per-wave count in
+// LDS, no workgroup barrier); one barrier later the waves' counts give each
+// digit's offset per wave.  With LDS staging (32-bit keys) the tile is placed
+// in LDS in digit order and written out so that each digit's run goes to
+// consecutive addresses; 64-bit keys go straight to their slots.
+// offs: scanned (digit, tile) offsets within each digit; dtot: digit totals.
+template <class K, bool V, bool STAGE>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
-                                                      const int32_t *__restrict__ dtot,
-                                                      const int32_t *__restrict__ tcnt, int ntiles,
+                                                      const int32_t *__restrict__ dtot, int ntiles,
                                                       K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
   __shared__ int32_t gbase[256];
   __shared__ int32_t lstart[256];
-  __shared__ int32_t lnext[256];
-  __shared__ int32_t wcnt[RS_NT / 64][256];
+  __shared__ int32_t cw[RS_NT / 64][256];
   __shared__ int32_t stmp[RS_NT / 64 + 1];
-  __shared__ K lkeys[RS_TILE];
-  __shared__ uint32_t lvals[V ? RS_TILE : 1];
-  const int tid = threadIdx.x;
-  const int w = tid >> 6;
-  const int l = lane_id();
+  __shared__ K lkeys[STAGE ? RS_TILE : 1];
+  __shared__ uint32_t lvals[(STAGE && V) ? RS_TILE : 1];
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
   const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
-  const int tn = (int)min((int64_t)RS_TILE, n - tbase);
+  const int64_t base = tbase + w * RS_WKEYS + l;
   K kr[RS_ROUNDS];
   uint32_t vr[V ? RS_ROUNDS : 1];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int j = r * RS_NT + tid;
-    kr[r] = j < tn ? keys[tbase + j] : K(0);
-    if (V) vr[r] = j < tn ? vals[tbase + j] : 0u;
-  }
-  const int64_t o = (int64_t)tid * ntiles + blockIdx.x;
-  rs_tile_bases(offs, dtot, ntiles, gbase, stmp);
-  lstart[tid] = tcnt[o];
-  __syncthreads();
-  block_exclusive_scan<int32_t, RS_NT>(lstart, 256, stmp);
-  lnext[tid] = lstart[tid];
-  __syncthreads();
-  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
-#pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
-    __syncthreads();
-    const int j = r * RS_NT + tid;
-    const bool valid = j < tn;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
-    int cnt;
-    const int rank = rs_wave_rank(valid, d, lt, &cnt);
-    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;  // last lane of the group publishes
-    __syncthreads();
-    if (valid) {
-      int pre = 0;
-      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-      const int lp = lnext[d] + pre + rank;
-      lkeys[lp] = kr[r];
-      if (V) lvals[lp] = vr[r];
-    }
-    __syncthreads();
-    int add = 0;
-    for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
-    lnext[tid] += add;
-  }
-  __syncthreads();
-  for (int i = tid; i < tn; i += RS_NT) {
-    const K key = lkeys[i];
-    const uint32_t d = (uint32_t)(key >> shift) & 255u;
-    const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
-    okeys[pos] = key;
-    if (V) ovals[pos] = lvals[i];
-  }
-}
-
-// Direct variant for 64-bit keys: each ranked key goes straight to its
-// global slot (the LDS staging of 64-bit tiles costs more occupancy than the
-// coalescing gains).  The tile is loaded into registers first.
-template <class K, bool V>
-__global__ __launch_bounds__(RS_NT) void k_rs_scatter_direct(const K *__restrict__ keys,
-                                                             const uint32_t *__restrict__ vals, int64_t n, int shift,
-                                                             const int32_t *__restrict__ offs,
-                                                             const int32_t *__restrict__ dtot, int ntiles,
-                                                             K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
-  __shared__ int32_t base[256];
-  __shared__ int32_t wcnt[RS_NT / 64][256];
-  __shared__ int32_t stmp[RS_NT / 64 + 1];
-  const int tid = threadIdx.x;
-  const int w = tid >> 6;
-  const int l = lane_id();
-  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
-  K kr[RS_ROUNDS];
-  uint32_t vr[V ? RS_ROUNDS : 1];
-#pragma unroll
-  for (int r = 0; r < RS_ROUNDS; ++r) {
-    const int64_t j = tbase + r * RS_NT + tid;
+    const int64_t j = base + r * 64;
     kr[r] = j < n ? keys[j] : K(0);
     if (V) vr[r] = j < n ? vals[j] : 0u;
   }
-  rs_tile_bases(offs, dtot, ntiles, base, stmp);
+#pragma unroll
+  for (int q = 0; q < RS_NT / 64; ++q) cw[q][tid] = 0;
+  rs_tile_bases(offs, dtot, ntiles, gbase, stmp);  // also orders the zeroing above
+  // ranks within the wave (running per-wave digit counts)
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  int16_t rk[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
-    for (int q = 0; q < RS_NT / 64; ++q) wcnt[q][tid] = 0;
-    __syncthreads();
-    const int64_t j = tbase + r * RS_NT + tid;
-    const bool valid = j < n;
+    const bool valid = base + r * 64 < n;
     const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
     int cnt;
     const int rank = rs_wave_rank(valid, d, lt, &cnt);
-    if (valid && rank == cnt - 1) wcnt[w][d] = cnt;
-    __syncthreads();
-    if (valid) {
-      int pre = 0;
-      for (int q = 0; q < w; ++q) pre += wcnt[q][d];
-      const int64_t pos = (int64_t)base[d] + pre + rank;
+    rk[r] = (int16_t)(cw[w][d] + rank);
+    wave_lds_sync();
+    if (valid && rank == cnt - 1) cw[w][d] += cnt;
+    wave_lds_sync();
+  }
+  __syncthreads();
+  // per digit: counts of the earlier waves, and the digit's start in the tile
+  {
+    int32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < RS_NT / 64; ++q) {
+      const int32_t c = cw[q][tid];
+      cw[q][tid] = run;
+      run += c;
+    }
+    lstart[tid] = run;
+  }
+  __syncthreads();
+  block_exclusive_scan<int32_t, RS_NT>(lstart, 256, stmp);
+#pragma unroll
+  for (int r = 0; r < RS_ROUNDS; ++r) {
+    if (base + r * 64 >= n) continue;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    const int within = cw[w][d] + rk[r];  // position among the tile's keys of digit d
+    if (STAGE) {
+      const int lp = lstart[d] + within;
+      lkeys[lp] = kr[r];
+      if (V) lvals[lp] = vr[r];
+    } else {
+      const int64_t pos = (int64_t)gbase[d] + within;
       okeys[pos] = kr[r];
       if (V) ovals[pos] = vr[r];
     }
+  }
+  if (STAGE) {
     __syncthreads();
-    int add = 0;
-    for (int q = 0; q < RS_NT / 64; ++q) add += wcnt[q][tid];
-    base[tid] += add;
+    const int tn = (int)min((int64_t)RS_TILE, n - tbase);
+    for (int i = tid; i < tn; i += RS_NT) {
+      const K key = lkeys[i];
+      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
+      okeys[pos] = key;
+      if (V) ovals[pos] = lvals[i];
+    }
   }
 }
 
@@ -383,30 +362,23 @@ static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int
   const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
   const int64_t hn = 256LL * ntiles;
   const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
-  const size_t need = 2 * hist_bytes + 256 * sizeof(int32_t);
-  tmp.reserve(need);
+  tmp.reserve(hist_bytes + 256 * sizeof(int32_t));
   int32_t *hist = tmp.as<int32_t>();
-  int32_t *tcnt = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
-  int32_t *dtot = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + 2 * hist_bytes);
+  int32_t *dtot = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
   K *src = keys, *dst = alt;
   uint32_t *vs = vals, *vd = valt;
   int passes = 0;
   for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, tcnt, ntiles);
+    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
     HGP_LAUNCH_CHECK();
     k_rs_dscan<<<256, RS_NT, 0, s>>>(hist, ntiles, dtot);
     HGP_LAUNCH_CHECK();
-    if constexpr (sizeof(K) == 4) {
-      if (vs)
-        k_rs_scatter<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, tcnt, ntiles, dst, vd);
-      else
-        k_rs_scatter<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, tcnt, ntiles, dst, vd);
-    } else {
-      if (vs)
-        k_rs_scatter_direct<K, true><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
-      else
-        k_rs_scatter_direct<K, false><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
-    }
+    // 32-bit keys are staged in LDS for coalesced runs; 64-bit keys go direct
+    constexpr bool kStage = sizeof(K) == 4;
+    if (vs)
+      k_rs_scatter<K, true, kStage><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
+    else
+      k_rs_scatter<K, false, kStage><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
     HGP_LAUNCH_CHECK();
     std::swap(src, dst);
     std::swap(vs, vd);
