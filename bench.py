@@ -35,7 +35,7 @@ COST = {
     "rate_tail": ("alu", 1.0),
     "propose": ("alu", 1.0),
     "part_table": ("hbm", 16.0),
-    "seq_events": ("hbm", 4.0),
+    "seq_events": ("hbm", 1.0),  # units are algorithmic bytes: 4 per pin, 16 per event
     "contract": ("hbm", 16.0),
     "incidence": ("hbm", 8.0),
     "sort": ("hbm", 32.0),

@@ -83,7 +83,7 @@ typedef struct {
 #define HGP_K_RATE 0       /* candidate rating + selection; unit: pin-pair visit (sum |e|^2 per level) */
 #define HGP_K_PROPOSE 1    /* move proposal; unit: part-table entry visit (sum over e of |e| * lambda(e)) */
 #define HGP_K_PARTTABLE 2  /* per-hedge part tables; unit: pin */
-#define HGP_K_SEQEVENTS 3  /* in-sequence gains and inbound transitions; unit: pin */
+#define HGP_K_SEQEVENTS 3  /* in-sequence gains and inbound transitions; unit: algorithmic byte (4 per pin, 16 per event) */
 #define HGP_K_CONTRACT 4   /* coarse hedge construction; unit: pin */
 #define HGP_K_INCIDENCE 5  /* incidence transpose; unit: pin */
 #define HGP_K_SORT 6       /* move / event sorts; unit: key */

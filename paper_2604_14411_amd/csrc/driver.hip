@@ -376,7 +376,7 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
   }
   RoundResult R;
   R.S = build_sequence(L, B, W.scan_tmp, W.sort_tmp, s);
-  if (R.S > 0) add_units(HGP_K_SEQEVENTS, P);
+  if (R.S > 0) add_units(HGP_K_SEQEVENTS, 4 * P);  // 4 B per pin scanned (+16 B per event, counted with the events)
   evaluate_sequence(L, rho, n_parts, omega, delta, R.S, B, err, W.scan_tmp, W.sort_tmp, s, &R.istar, &R.gstar);
   check_err(W, s);
   if (R.istar >= 0 && R.gstar > 0) {

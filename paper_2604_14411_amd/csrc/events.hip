@@ -606,6 +606,7 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   HGP_HIP(hipStreamSynchronize(s));
   const int64_t nev = nin + 2 * S;
   if (nev > B.cap_events) throw Error(-7, "event buffer overflow");
+  add_units(kClsEvents, 16 * nev);  // algorithmic bytes: an 8-byte event key written and read once
   if (S > 0) {
     k_size_events<<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, vshift, B.keys, nin);
     HGP_LAUNCH_CHECK();
