@@ -102,6 +102,9 @@ __device__ __forceinline__ int2 pt_lookup(const int32_t *__restrict__ pt, const 
 int bits_for(int64_t x);  // smallest b with 2^b > x
 // ascending sort of n 64-bit keys over their low `bits` bits
 void sort_keys(uint64_t *keys, uint64_t *alt, int64_t n, int bits, DevBuf &sort_tmp, hipStream_t s);
+// 32-bit keys by bits [lo, bits) (the small-input path sorts by all bits);
+// keys equal on those bits end in any order.
+void sort_keys32(uint32_t *keys, uint32_t *alt, int64_t n, int bits, DevBuf &sort_tmp, hipStream_t s, int lo = 0);
 
 // --- refine.hip ---
 struct RoundBufs {

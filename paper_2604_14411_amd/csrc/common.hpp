@@ -396,8 +396,9 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, DevBuf
 void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
                     DevBuf &tmp, hipStream_t s);
 
+// (32-bit keys: bits [lo, bits) only; keys equal on them keep their order.)
 void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
-                    DevBuf &tmp, hipStream_t s);
+                    DevBuf &tmp, hipStream_t s, int lo = 0);
 
 // Fill / iota helpers.
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

@@ -351,15 +351,16 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
 // Packs the inbound-count events of every hedge (evpad[2 hoff[e] ..), evcnt
 // already scanned into offsets evoff) into ev[0 .. evoff[E]).  One wave per
 // hedge.
+template <class K>
 __global__ __launch_bounds__(256) void k_ev_compact(const int32_t *__restrict__ hoff, int32_t E,
                                                     const int64_t *__restrict__ evoff,
-                                                    const uint64_t *__restrict__ evpad, uint64_t *__restrict__ ev) {
+                                                    const uint64_t *__restrict__ evpad, K *__restrict__ ev) {
   const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (e >= E) return;
   const int64_t o = evoff[e], c = evoff[e + 1] - o;
   if (c == 0) return;
   const int64_t src = 2 * (int64_t)hoff[e];
-  for (int64_t i = lane_id(); i < c; i += 64) ev[o + i] = evpad[src + i];
+  for (int64_t i = lane_id(); i < c; i += 64) ev[o + i] = (K)evpad[src + i];
 }
 
 // g'(i) for move i = 1..S: the sum, over the incidences k of the moving node,
@@ -381,14 +382,15 @@ __global__ __launch_bounds__(256) void k_move_gain(const int32_t *__restrict__ s
 }
 
 // size events (p_s, i, size) and (p_d, i, size) of every move i
+template <class K>
 __global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const int32_t *__restrict__ rho,
-                              const int32_t *__restrict__ dest, int vshift, uint64_t *__restrict__ ev, int64_t base) {
+                              const int32_t *__restrict__ dest, int vshift, K *__restrict__ ev, int64_t base) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S) return;
   const int v = seq[i];
   const uint64_t tail = ((uint64_t)(i + 1) << 2) | 2ull;
-  ev[base + 2 * i] = ((uint64_t)(uint32_t)rho[v] << vshift) | tail;
-  ev[base + 2 * i + 1] = ((uint64_t)(uint32_t)dest[v] << vshift) | tail;
+  ev[base + 2 * i] = (K)(((uint64_t)(uint32_t)rho[v] << vshift) | tail);
+  ev[base + 2 * i + 1] = (K)(((uint64_t)(uint32_t)dest[v] << vshift) | tail);
 }
 
 // poff[p] = first sorted event of part p (p = 0 .. P; poff[P] = nev).
@@ -453,11 +455,6 @@ __global__ void k_ev_transitions(const K *__restrict__ ev, int64_t nev, int vshi
   const bool valid_before = s0 + esum[lo] <= omega && i0 + isum[lo] <= delta;
   const bool valid_after = s0 + esum[i + 1] <= omega && i0 + isum[i + 1] <= delta;
   if (valid_before != valid_after) atomicAdd(&vdelta[g & qmask], valid_after ? -1 : 1);
-}
-
-__global__ void k_keys_to_u32(const uint64_t *__restrict__ in, int64_t n, uint32_t *__restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (uint32_t)in[i];
 }
 
 template <class K>
@@ -577,6 +574,11 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   const int pbits = bits_for(n_parts > 1 ? n_parts - 1 : 1);
   const int vshift = qbits + 2;
   if (pbits + qbits + 14 > 64) throw Error(-6, "sequence too long for the 64-bit event keys");
+  // keys of at most 32 bits are packed and sorted as 32-bit words (half the
+  // traffic): keys (as uint32) then holds them, keys2 is the sort's other half
+  const int kbits = vshift + pbits;
+  const bool narrow = kbits <= 32;
+  uint32_t *k32 = reinterpret_cast<uint32_t *>(B.keys);
   fill_i32(B.vdelta, S + 1, 0, s);
   fill_i32(B.gp, 1, 0, s);
   fill_i64(B.scal + SC_INVALID0, 1, 0, s);
@@ -595,7 +597,10 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
                                              B.contrib, B.keys2, B.evoff, B.scal, B.heavy);
       HGP_LAUNCH_CHECK();
       scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);
-      k_ev_compact<<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, B.keys);
+      if (narrow)
+        k_ev_compact<uint32_t><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, k32);
+      else
+        k_ev_compact<uint64_t><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, B.keys);
       HGP_LAUNCH_CHECK();
     }
     k_move_gain<<<div_up(S, 4), 256, 0, s>>>(B.seq, S, L.ioff, L.perm, B.contrib, B.gp);
@@ -608,22 +613,19 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   if (nev > B.cap_events) throw Error(-7, "event buffer overflow");
   add_units(kClsEvents, 16 * nev);  // algorithmic bytes: an 8-byte event key written and read once
   if (S > 0) {
-    k_size_events<<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, vshift, B.keys, nin);
+    if (narrow)
+      k_size_events<uint32_t><<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, vshift, k32, nin);
+    else
+      k_size_events<uint64_t><<<div_up(S, 256), 256, 0, s>>>(B.seq, S, rho, B.dest, vshift, B.keys, nin);
     HGP_LAUNCH_CHECK();
   }
   k_init_invalid<<<div_up(n_parts > 0 ? n_parts : 1, 256), 256, 0, s>>>(B.psize, B.pinb, n_parts, omega, delta,
                                                                          B.scal);
   HGP_LAUNCH_CHECK();
-  // keys of at most 32 bits are sorted as 32-bit words (half the traffic)
-  const int kbits = vshift + pbits;
-  const bool narrow = kbits <= 32 && nev > 8192;
-  uint32_t *k32 = reinterpret_cast<uint32_t *>(B.keys2);
   if (narrow) {
-    KScope ks(kClsSort, s);
-    add_units(kClsSort, nev);
-    k_keys_to_u32<<<div_up(nev, 256), 256, 0, s>>>(B.keys, nev, k32);
-    HGP_LAUNCH_CHECK();
-    radix_sort_u32(k32, reinterpret_cast<uint32_t *>(B.keys), nullptr, nullptr, nev, kbits, sort_tmp, s);
+    // the two type bits need no order: only whole (part, position) groups
+    // are read after the sort
+    sort_keys32(k32, reinterpret_cast<uint32_t *>(B.keys2), nev, kbits, sort_tmp, s, 2);
   } else {
     sort_keys(B.keys, B.keys2, nev, kbits, sort_tmp, s);
   }

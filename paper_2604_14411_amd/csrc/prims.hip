@@ -184,18 +184,19 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, DevBuf
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort, 8-bit digits, 4096-key tiles
+// stable LSD radix sort, DB-bit digits (8 in use), 4096-key tiles
 // ---------------------------------------------------------------------------
 constexpr int RS_NT = 256;
 constexpr int RS_ROUNDS = 16;
 constexpr int RS_TILE = RS_NT * RS_ROUNDS;
 
 // Rank of a key within its digit among the valid lanes of the wave (match
-// mask from 8 ballots); returns the rank, *cnt = size of the digit group.
+// mask from DB ballots); returns the rank, *cnt = size of the digit group.
+template <int DB>
 __device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt, int *cnt) {
   uint64_t match = __ballot(valid);
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < DB; ++b) {
     const bool bit = (d >> b) & 1u;
     const uint64_t bb = __ballot(valid && bit);
     match &= bit ? bb : ~bb;
@@ -213,13 +214,14 @@ constexpr int RS_WKEYS = RS_ROUNDS * 64;
 // Digit counts of one 4096-key tile, without atomics: per wave and round,
 // the last lane of each digit group (ballot match masks) adds the group's
 // size to the wave's counter.  All of the tile's loads are issued first.
-template <class K>
+// hist is digit-major: hist[d * ntiles + tile].
+template <class K, int DB>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                    int32_t *__restrict__ hist, int ntiles) {
-  __shared__ int32_t cw[RS_NT / 64][256];
+  constexpr int RADIX = 1 << DB;
+  __shared__ int32_t cw[RS_NT / 64][RADIX];
   const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
-#pragma unroll
-  for (int q = 0; q < RS_NT / 64; ++q) cw[q][tid] = 0;
+  for (int i = tid; i < RS_NT / 64 * RADIX; i += RS_NT) (&cw[0][0])[i] = 0;
   const int64_t base = (int64_t)blockIdx.x * RS_TILE + w * RS_WKEYS + l;
   K kr[RS_ROUNDS];
 #pragma unroll
@@ -232,17 +234,19 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const bool valid = base + r * 64 < n;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & (uint32_t)(RADIX - 1);
     int cnt;
-    const int rank = rs_wave_rank(valid, d, lt, &cnt);
+    const int rank = rs_wave_rank<DB>(valid, d, lt, &cnt);
     if (valid && rank == cnt - 1) cw[w][d] += cnt;
     wave_lds_sync();
   }
   __syncthreads();
-  int32_t c = 0;
+  for (int d = tid; d < RADIX; d += RS_NT) {
+    int32_t c = 0;
 #pragma unroll
-  for (int q = 0; q < RS_NT / 64; ++q) c += cw[q][tid];
-  hist[(int64_t)tid * ntiles + blockIdx.x] = c;
+    for (int q = 0; q < RS_NT / 64; ++q) c += cw[q][d];
+    hist[(int64_t)d * ntiles + blockIdx.x] = c;
+  }
 }
 
 // Per digit d (one workgroup each): exclusive scan over the tiles of
@@ -255,14 +259,14 @@ __global__ __launch_bounds__(RS_NT) void k_rs_dscan(int32_t *__restrict__ hist, 
 }
 
 // gbase[d] = start of digit d in the output (exclusive scan of dtot, in LDS)
-// + start of this tile within digit d.  One thread per digit.
+// + start of this tile within digit d.
+template <int RADIX>
 __device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, const int32_t *__restrict__ dtot,
                                               int ntiles, int32_t *gbase, int32_t *stmp) {
-  const int tid = threadIdx.x;
-  gbase[tid] = dtot[tid];
+  for (int d = threadIdx.x; d < RADIX; d += RS_NT) gbase[d] = dtot[d];
   __syncthreads();
-  block_exclusive_scan<int32_t, RS_NT>(gbase, 256, stmp);
-  gbase[tid] += offs[(int64_t)tid * ntiles + blockIdx.x];
+  block_exclusive_scan<int32_t, RS_NT>(gbase, RADIX, stmp);
+  for (int d = threadIdx.x; d < RADIX; d += RS_NT) gbase[d] += offs[(int64_t)d * ntiles + blockIdx.x];
   __syncthreads();
 }
 
@@ -274,14 +278,15 @@ __device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, 
 // in LDS in digit order and written out so that each digit's run goes to
 // consecutive addresses; 64-bit keys go straight to their slots.
 // offs: scanned (digit, tile) offsets within each digit; dtot: digit totals.
-template <class K, bool V, bool STAGE>
+template <class K, bool V, bool STAGE, int DB>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
                                                       const int32_t *__restrict__ dtot, int ntiles,
                                                       K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
-  __shared__ int32_t gbase[256];
-  __shared__ int32_t lstart[256];
-  __shared__ int32_t cw[RS_NT / 64][256];
+  constexpr int RADIX = 1 << DB;
+  __shared__ int32_t gbase[RADIX];
+  __shared__ int32_t lstart[RADIX];
+  __shared__ int32_t cw[RS_NT / 64][RADIX];
   __shared__ int32_t stmp[RS_NT / 64 + 1];
   __shared__ K lkeys[STAGE ? RS_TILE : 1];
   __shared__ uint32_t lvals[(STAGE && V) ? RS_TILE : 1];
@@ -296,18 +301,17 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
     kr[r] = j < n ? keys[j] : K(0);
     if (V) vr[r] = j < n ? vals[j] : 0u;
   }
-#pragma unroll
-  for (int q = 0; q < RS_NT / 64; ++q) cw[q][tid] = 0;
-  rs_tile_bases(offs, dtot, ntiles, gbase, stmp);  // also orders the zeroing above
+  for (int i = tid; i < RS_NT / 64 * RADIX; i += RS_NT) (&cw[0][0])[i] = 0;
+  rs_tile_bases<RADIX>(offs, dtot, ntiles, gbase, stmp);  // its barriers also order the zeroing above
   // ranks within the wave (running per-wave digit counts)
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
   int16_t rk[RS_ROUNDS];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const bool valid = base + r * 64 < n;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & (uint32_t)(RADIX - 1);
     int cnt;
-    const int rank = rs_wave_rank(valid, d, lt, &cnt);
+    const int rank = rs_wave_rank<DB>(valid, d, lt, &cnt);
     rk[r] = (int16_t)(cw[w][d] + rank);
     wave_lds_sync();
     if (valid && rank == cnt - 1) cw[w][d] += cnt;
@@ -315,22 +319,22 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
   }
   __syncthreads();
   // per digit: counts of the earlier waves, and the digit's start in the tile
-  {
+  for (int d = tid; d < RADIX; d += RS_NT) {
     int32_t run = 0;
 #pragma unroll
     for (int q = 0; q < RS_NT / 64; ++q) {
-      const int32_t c = cw[q][tid];
-      cw[q][tid] = run;
+      const int32_t c = cw[q][d];
+      cw[q][d] = run;
       run += c;
     }
-    lstart[tid] = run;
+    lstart[d] = run;
   }
   __syncthreads();
-  block_exclusive_scan<int32_t, RS_NT>(lstart, 256, stmp);
+  block_exclusive_scan<int32_t, RS_NT>(lstart, RADIX, stmp);
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     if (base + r * 64 >= n) continue;
-    const uint32_t d = (uint32_t)(kr[r] >> shift) & 255u;
+    const uint32_t d = (uint32_t)(kr[r] >> shift) & (uint32_t)(RADIX - 1);
     const int within = cw[w][d] + rk[r];  // position among the tile's keys of digit d
     if (STAGE) {
       const int lp = lstart[d] + within;
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
     const int tn = (int)min((int64_t)RS_TILE, n - tbase);
     for (int i = tid; i < tn; i += RS_NT) {
       const K key = lkeys[i];
-      const uint32_t d = (uint32_t)(key >> shift) & 255u;
+      const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RADIX - 1);
       const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
       okeys[pos] = key;
       if (V) ovals[pos] = lvals[i];
@@ -355,31 +359,41 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
   }
 }
 
+template <class K, int DB>
+static void radix_pass(const K *src, const uint32_t *vs, int64_t n, int shift, int ntiles, int32_t *hist,
+                       int32_t *dtot, K *dst, uint32_t *vd, hipStream_t s) {
+  k_rs_hist<K, DB><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
+  HGP_LAUNCH_CHECK();
+  k_rs_dscan<<<1 << DB, RS_NT, 0, s>>>(hist, ntiles, dtot);
+  HGP_LAUNCH_CHECK();
+  // 32-bit keys are staged in LDS for coalesced runs; 64-bit keys go direct
+  constexpr bool kStage = sizeof(K) == 4;
+  if (vs)
+    k_rs_scatter<K, true, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
+  else
+    k_rs_scatter<K, false, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
+  HGP_LAUNCH_CHECK();
+}
+
+// Sorts by bits [lo, bits) with 8-bit digits.  (10-bit digits, 3 passes
+// instead of 4 for 25-30 bits, measured slower on rand64k: 1,024 digit runs
+// per 4,096-key tile leave the scatter's writes poorly coalesced.)
 template <class K>
-static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits, DevBuf &tmp,
-                            hipStream_t s) {
-  if (n <= 1 || bits <= 0) return;
+static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int64_t n, int lo, int bits,
+                            DevBuf &tmp, hipStream_t s) {
+  if (n <= 1 || bits <= lo) return;
+  constexpr int db = 8;
   const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
-  const int64_t hn = 256LL * ntiles;
+  const int64_t hn = (int64_t)(1 << db) * ntiles;
   const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
-  tmp.reserve(hist_bytes + 256 * sizeof(int32_t));
+  tmp.reserve(hist_bytes + 1024 * sizeof(int32_t));
   int32_t *hist = tmp.as<int32_t>();
   int32_t *dtot = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
   K *src = keys, *dst = alt;
   uint32_t *vs = vals, *vd = valt;
   int passes = 0;
-  for (int shift = 0; shift < bits; shift += 8, ++passes) {
-    k_rs_hist<K><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
-    HGP_LAUNCH_CHECK();
-    k_rs_dscan<<<256, RS_NT, 0, s>>>(hist, ntiles, dtot);
-    HGP_LAUNCH_CHECK();
-    // 32-bit keys are staged in LDS for coalesced runs; 64-bit keys go direct
-    constexpr bool kStage = sizeof(K) == 4;
-    if (vs)
-      k_rs_scatter<K, true, kStage><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
-    else
-      k_rs_scatter<K, false, kStage><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
-    HGP_LAUNCH_CHECK();
+  for (int shift = lo; shift < bits; shift += db, ++passes) {
+    radix_pass<K, db>(src, vs, n, shift, ntiles, hist, dtot, dst, vd, s);
     std::swap(src, dst);
     std::swap(vs, vd);
   }
@@ -391,12 +405,12 @@ static void radix_sort_impl(K *keys, K *alt, uint32_t *vals, uint32_t *valt, int
 
 void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
                     DevBuf &tmp, hipStream_t s) {
-  radix_sort_impl<uint64_t>(keys, alt, vals, valt, n, bits, tmp, s);
+  radix_sort_impl<uint64_t>(keys, alt, vals, valt, n, 0, bits, tmp, s);
 }
 
 void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
-                    DevBuf &tmp, hipStream_t s) {
-  radix_sort_impl<uint32_t>(keys, alt, vals, valt, n, bits > 32 ? 32 : bits, tmp, s);
+                    DevBuf &tmp, hipStream_t s, int lo) {
+  radix_sort_impl<uint32_t>(keys, alt, vals, valt, n, lo, bits > 32 ? 32 : bits, tmp, s);
 }
 
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {

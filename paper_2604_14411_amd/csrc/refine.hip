@@ -285,12 +285,13 @@ __global__ void k_seq_from_keys(const uint64_t *__restrict__ keys, int64_t S, in
 constexpr int SMALL_SORT_NT = 1024;
 constexpr int SMALL_SORT_CAP = 8192;
 
-__global__ __launch_bounds__(SMALL_SORT_NT) void k_small_sort(uint64_t *keys, int n) {
-  __shared__ uint64_t s[SMALL_SORT_CAP];
+template <class K>
+__global__ __launch_bounds__(SMALL_SORT_NT) void k_small_sort(K *keys, int n) {
+  __shared__ K s[SMALL_SORT_CAP];
   const int np = next_pow2(n);
-  for (int i = threadIdx.x; i < np; i += SMALL_SORT_NT) s[i] = i < n ? keys[i] : ~0ull;
+  for (int i = threadIdx.x; i < np; i += SMALL_SORT_NT) s[i] = i < n ? keys[i] : ~K(0);
   __syncthreads();
-  block_bitonic_sort<uint64_t, SMALL_SORT_NT>(s, np);
+  block_bitonic_sort<K, SMALL_SORT_NT>(s, np);
   for (int i = threadIdx.x; i < n; i += SMALL_SORT_NT) keys[i] = s[i];
 }
 
@@ -299,10 +300,22 @@ void sort_keys(uint64_t *keys, uint64_t *alt, int64_t n, int bits, DevBuf &sort_
   KScope ks(6, s);
   add_units(6, n);
   if (n <= SMALL_SORT_CAP) {
-    k_small_sort<<<1, SMALL_SORT_NT, 0, s>>>(keys, (int)n);
+    k_small_sort<uint64_t><<<1, SMALL_SORT_NT, 0, s>>>(keys, (int)n);
     HGP_LAUNCH_CHECK();
   } else {
     radix_sort_u64(keys, alt, nullptr, nullptr, n, bits, sort_tmp, s);
+  }
+}
+
+void sort_keys32(uint32_t *keys, uint32_t *alt, int64_t n, int bits, DevBuf &sort_tmp, hipStream_t s, int lo) {
+  if (n <= 1) return;
+  KScope ks(6, s);
+  add_units(6, n);
+  if (n <= SMALL_SORT_CAP) {
+    k_small_sort<uint32_t><<<1, SMALL_SORT_NT, 0, s>>>(keys, (int)n);
+    HGP_LAUNCH_CHECK();
+  } else {
+    radix_sort_u32(keys, alt, nullptr, nullptr, n, bits, sort_tmp, s, lo);
   }
 }
 
