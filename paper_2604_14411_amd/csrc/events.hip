@@ -37,17 +37,17 @@ static_assert(kSegCap <= 4096, "slot field of the workgroup event keys is 12 bit
 // their part (key >> pshift): pins in the low 16 bits, pins_in in the high 16
 // bits (both signed).  The first event of every part is found by a max-scan
 // of part-start indices, so no event searches for it.
-template <int KPL>
-__device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, uint64_t *evk, int32_t *pre) {
+template <int KPL, class K>
+__device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, K *evk, int32_t *pre) {
   const int l = lane_id();
-  uint64_t k[KPL];
+  K k[KPL];
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int i = l * KPL + j;
-    k[j] = i < nev ? evk[i] : ~0ull;
+    k[j] = i < nev ? evk[i] : ~K(0);
   }
   wave_bitonic_sort<KPL>(k);
-  const uint64_t prev_last = __shfl_up(k[KPL - 1], 1, 64);
+  const K prev_last = __shfl_up(k[KPL - 1], 1, 64);
   int32_t d[KPL];
   int st[KPL];
   int32_t run = 0;
@@ -57,12 +57,12 @@ __device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, uint64_t 
     const int i = l * KPL + j;
     int32_t x = 0;
     if (i < nev) {
-      const int sgn = (k[j] & 2ull) ? 1 : -1;
-      x = sgn + ((k[j] & 1ull) ? sgn * 65536 : 0);
+      const int sgn = (k[j] & K(2)) ? 1 : -1;
+      x = sgn + ((k[j] & K(1)) ? sgn * 65536 : 0);
     }
     d[j] = run;
     run += x;
-    const uint64_t pk = j == 0 ? prev_last : k[j - 1];
+    const K pk = j == 0 ? prev_last : k[j - 1];
     if (i == 0 || (k[j] >> pshift) != (pk >> pshift)) cur = i;
     st[j] = cur;
   }
@@ -240,6 +240,169 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const uint64_t k = evk[l + 64 * t];
     const uint64_t q = (k >> 11) & qmask;
     evpad[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+  }
+}
+
+// 32-bit variant of k_ev_wave, for part ids below 2^22 and positions below
+// 2^24 (the register sort dominates the kernel, and 32-bit keys halve its
+// work).  The hedge's moving pins are first sorted by position (key
+// position << 8 | slot); a pin's rank r in that order replaces its position
+// in the event keys: part << 10 | r << 2 | role << 1 | dst.
+constexpr int EVN_PBITS = 22;
+constexpr int EVN_QBITS = 24;
+
+__global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
+    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
+  __shared__ uint32_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
+  __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
+  __shared__ uint32_t qs_s[EVW_NT / 64][EVW_MAX_MOVING];   // position << 8 | slot, then in rank order
+  __shared__ int32_t ps_s[EVW_NT / 64][EVW_MAX_MOVING];    // source part per slot
+  __shared__ uint32_t pd_s[EVW_NT / 64][EVW_MAX_MOVING];   // destination part | dst << 31 per slot
+  __shared__ int16_t li_s[EVW_NT / 64][EVW_MAX_MOVING];
+  __shared__ int32_t sp_s[EVW_NT / 64][EVW_PT_STAGE];
+  __shared__ uint32_t sc_s[EVW_NT / 64][EVW_PT_STAGE];
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const int e = (int)(blockIdx.x * (EVW_NT / 64) + w);
+  if (e >= E) return;
+  const int b = hoff[e], len = hoff[e + 1] - b;
+  const int32_t we = hw[e];
+  const int plen = lam[e];
+  uint32_t *evk = evk_s[w];
+  int32_t *pre = pre_s[w];
+  uint32_t *qs = qs_s[w];
+  int32_t *psl = ps_s[w];
+  uint32_t *pdl = pd_s[w];
+  int16_t *li = li_s[w];
+  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  // one pass over the pins, as in k_ev_wave
+  int m = 0;
+  for (int c = 0; c < len && m <= EVW_MAX_MOVING; c += 64 * EVW_U) {
+    uint32_t x[EVW_U];
+    int q[EVW_U];
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const int i = c + 64 * u + l;
+      x[u] = i < len ? hpin[b + i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const int i = c + 64 * u + l;
+      q[u] = i < len ? pos[x[u] & kIdMask] : 0;
+    }
+    int32_t ps[EVW_U], pd[EVW_U];
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      ps[u] = 0;
+      pd[u] = 0;
+      if (q[u] > 0) {
+        ps[u] = rho[x[u] & kIdMask];
+        pd[u] = dest[x[u] & kIdMask];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < EVW_U; ++u) {
+      const uint64_t mask = __ballot(q[u] > 0);
+      const int slot = m + __popcll(mask & lt);
+      if (q[u] > 0 && slot < EVW_MAX_MOVING) {
+        li[slot] = (int16_t)(c + 64 * u + l);
+        qs[slot] = ((uint32_t)q[u] << 8) | (uint32_t)slot;
+        psl[slot] = ps[u];
+        pdl[slot] = (uint32_t)pd[u] | (x[u] & kDst);
+      }
+      m += __popcll(mask);
+    }
+  }
+  if (m == 0) {
+    if (l == 0) evcnt[e] = 0;
+    return;
+  }
+  if (m > EVW_MAX_MOVING) {
+    if (l == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
+    return;
+  }
+  wave_lds_sync();
+  // the hedge's part table in LDS (parts ascending; pins | pins_in << 16)
+  const bool staged = plen <= EVW_PT_STAGE;
+  int32_t *sp = sp_s[w];
+  uint32_t *sc = sc_s[w];
+  if (staged) {
+    for (int i = l; i < plen; i += 64) {
+      sp[i] = pt[b + i];
+      sc[i] = ptc[b + i];
+    }
+  }
+  // moving pins in position order (positions are distinct)
+  {
+    auto sort_q = [&](auto kpl) {
+      constexpr int KPL = decltype(kpl)::value;
+      uint32_t k[KPL];
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        const int i = l * KPL + j;
+        k[j] = i < m ? qs[i] : ~0u;
+      }
+      wave_bitonic_sort<KPL>(k);
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        const int i = l * KPL + j;
+        if (i < m) qs[i] = k[j];
+      }
+    };
+    if (m <= 64) sort_q(std::integral_constant<int, 1>{});
+    else if (m <= 128) sort_q(std::integral_constant<int, 2>{});
+    else sort_q(std::integral_constant<int, 4>{});
+  }
+  wave_lds_sync();
+  for (int r = l; r < m; r += 64) {
+    const int slot = (int)(qs[r] & 255u);
+    const uint32_t pdd = pdl[slot];
+    const uint32_t tail = ((uint32_t)r << 2) | (pdd >> 31);
+    evk[2 * r] = ((uint32_t)psl[slot] << 10) | tail;
+    evk[2 * r + 1] = ((pdd & kIdMask) << 10) | tail | 2u;
+  }
+  wave_lds_sync();
+  const int nev = 2 * m;
+  if (nev <= 64) ev_wave_sort_scan<1>(nev, 10, evk, pre);
+  else if (nev <= 128) ev_wave_sort_scan<2>(nev, 10, evk, pre);
+  else if (nev <= 256) ev_wave_sort_scan<4>(nev, 10, evk, pre);
+  else ev_wave_sort_scan<8>(nev, 10, evk, pre);
+  wave_lds_sync();
+  uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
+  int nout = 0;
+  for (int t = 0; t * 64 < nev; ++t) {
+    const int i = l + 64 * t;
+    if (i >= nev) continue;
+    const uint32_t k = evk[i];
+    const int part = (int)(k >> 10);
+    const int2 before = unpack_delta(pre[i]);
+    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, part) : pt_lookup(pt, ptc, b, plen, part);
+    const bool dst_role = (k & 2u) != 0;
+    const int slot = (int)(qs[(k >> 2) & 255u] & 255u);
+    int2 *cp = &contrib[b + li[slot]];
+    if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
+    else cp->x = (c0.x + before.x == 1) ? we : 0;
+    if (k & 1u) {
+      const int bin = c0.y + before.y;
+      if ((!dst_role && bin == 1) || (dst_role && bin == 0)) {
+        evbits |= 1u << t;
+        ++nout;
+      }
+    }
+  }
+  const int off = wave_exclusive_scan(nout);
+  if (l == 63) evcnt[e] = off + nout;
+  const int vshift = qbits + 2;
+  int64_t o = 2 * (int64_t)b + off;
+  for (int t = 0; evbits; ++t, evbits >>= 1) {
+    if (!(evbits & 1u)) continue;
+    const uint32_t k = evk[l + 64 * t];
+    const uint64_t q = qs[(k >> 2) & 255u] >> 8;
+    evpad[o++] = ((uint64_t)(k >> 10) << vshift) | (q << 2) | ((k >> 1) & 1u);
   }
 }
 
@@ -589,9 +752,14 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     if (L.E > 0) {
       // inbound-count events per hedge into keys2 (one region of 2|e| per
       // hedge), then packed into keys[0 .. nin)
-      k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
-                                                            B.ptc, B.lam, qbits, B.contrib, B.keys2, B.evoff,
-                                                            B.scal, B.heavy);
+      if (pbits <= EVN_PBITS && qbits <= EVN_QBITS)
+        k_ev_wave32<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos,
+                                                                B.pt, B.ptc, B.lam, qbits, B.contrib, B.keys2,
+                                                                B.evoff, B.scal, B.heavy);
+      else
+        k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
+                                                              B.ptc, B.lam, qbits, B.contrib, B.keys2, B.evoff,
+                                                              B.scal, B.heavy);
       HGP_LAUNCH_CHECK();
       k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam, qbits,
                                              B.contrib, B.keys2, B.evoff, B.scal, B.heavy);
