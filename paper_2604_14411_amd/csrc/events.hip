@@ -36,9 +36,12 @@ static_assert(kSegCap <= 4096, "slot field of the workgroup event keys is 12 bit
 // writes them back with the exclusive prefix of their count deltas within
 // their part (key >> pshift): pins in the low 16 bits, pins_in in the high 16
 // bits (both signed).  The first event of every part is found by a max-scan
-// of part-start indices, so no event searches for it.
-template <int KPL, class K>
-__device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, K *evk, int32_t *pre) {
+// of part-start indices, so no event searches for it.  `at_starts` runs
+// between the two phases, when evk is sorted and pre holds the raw prefix:
+// whatever it subtracts from pre at a part's first event is added to every
+// event of that part.
+template <int KPL, class K, class AtStarts>
+__device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, K *evk, int32_t *pre, AtStarts at_starts) {
   const int l = lane_id();
   K k[KPL];
 #pragma unroll
@@ -85,6 +88,8 @@ __device__ __forceinline__ void ev_wave_sort_scan(int nev, int pshift, K *evk, i
     }
   }
   wave_lds_sync();
+  at_starts();
+  wave_lds_sync();
   int32_t at_start[KPL];
 #pragma unroll
   for (int j = 0; j < KPL; ++j) at_start[j] = (l * KPL + j < nev) ? pre[st[j]] : 0;
@@ -122,11 +127,12 @@ __device__ __forceinline__ int2 pt_lookup_lds(const int32_t *sp, const uint32_t 
 // The inbound-count events of hedge e go to its own region evpad[2 hoff[e] ..)
 // (at most one per pin event, i.e. 2 |e|) and their number to evcnt[e]; a
 // scan of evcnt then packs them (k_ev_compact), so no counter is shared.
+template <class KP>
 __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
     const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
-    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    int2 *__restrict__ contrib, KP *__restrict__ evpad, int64_t *__restrict__ evcnt,
     int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
   __shared__ uint64_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
@@ -205,10 +211,10 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
       sc[i] = ptc[b + i];
     }
   }
-  if (nev <= 64) ev_wave_sort_scan<1>(nev, pshift, evk, pre);
-  else if (nev <= 128) ev_wave_sort_scan<2>(nev, pshift, evk, pre);
-  else if (nev <= 256) ev_wave_sort_scan<4>(nev, pshift, evk, pre);
-  else ev_wave_sort_scan<8>(nev, pshift, evk, pre);
+  if (nev <= 64) ev_wave_sort_scan<1>(nev, pshift, evk, pre, [] {});
+  else if (nev <= 128) ev_wave_sort_scan<2>(nev, pshift, evk, pre, [] {});
+  else if (nev <= 256) ev_wave_sort_scan<4>(nev, pshift, evk, pre, [] {});
+  else ev_wave_sort_scan<8>(nev, pshift, evk, pre, [] {});
   wave_lds_sync();
   uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
   int nout = 0;
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
     if (!(evbits & 1u)) continue;
     const uint64_t k = evk[l + 64 * t];
     const uint64_t q = (k >> 11) & qmask;
-    evpad[o++] = ((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+    evpad[o++] = (KP)(((k >> pshift) << vshift) | (q << 2) | ((k >> 1) & 1ull));
   }
 }
 
@@ -247,24 +253,26 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave(
 // 2^24 (the register sort dominates the kernel, and 32-bit keys halve its
 // work).  The hedge's moving pins are first sorted by position (key
 // position << 8 | slot); a pin's rank r in that order replaces its position
-// in the event keys: part << 10 | r << 2 | role << 1 | dst.
+// in the event keys: part << 10 | r << 2 | role << 1 | dst.  The counts
+// pins_0 / pins_in_0 of the hedge's part table enter the prefixes at the
+// first event of each part (a search of the sorted events per table entry),
+// so neither the table nor per-event lookups take LDS.  KP: the word of the
+// padded event regions (32-bit when the packed keys fit).
 constexpr int EVN_PBITS = 22;
 constexpr int EVN_QBITS = 24;
+constexpr int EVN_PT_REG = 4;  // 64-entry chunks of the part table prefetched into registers
 
+template <class KP>
 __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
     const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
-    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    int2 *__restrict__ contrib, KP *__restrict__ evpad, int64_t *__restrict__ evcnt,
     int64_t *__restrict__ scal, int32_t *__restrict__ heavy) {
   __shared__ uint32_t evk_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ int32_t pre_s[EVW_NT / 64][2 * EVW_MAX_MOVING];
   __shared__ uint32_t qs_s[EVW_NT / 64][EVW_MAX_MOVING];   // position << 8 | slot, then in rank order
-  __shared__ int32_t ps_s[EVW_NT / 64][EVW_MAX_MOVING];    // source part per slot
-  __shared__ uint32_t pd_s[EVW_NT / 64][EVW_MAX_MOVING];   // destination part | dst << 31 per slot
   __shared__ int16_t li_s[EVW_NT / 64][EVW_MAX_MOVING];
-  __shared__ int32_t sp_s[EVW_NT / 64][EVW_PT_STAGE];
-  __shared__ uint32_t sc_s[EVW_NT / 64][EVW_PT_STAGE];
   const int w = threadIdx.x >> 6, l = lane_id();
   const int e = (int)(blockIdx.x * (EVW_NT / 64) + w);
   if (e >= E) return;
@@ -274,11 +282,10 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
   uint32_t *evk = evk_s[w];
   int32_t *pre = pre_s[w];
   uint32_t *qs = qs_s[w];
-  int32_t *psl = ps_s[w];
-  uint32_t *pdl = pd_s[w];
   int16_t *li = li_s[w];
   const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
-  // one pass over the pins, as in k_ev_wave
+  // one pass over the pins, as in k_ev_wave; the events carry the slot's
+  // rank once the positions are sorted
   int m = 0;
   for (int c = 0; c < len && m <= EVW_MAX_MOVING; c += 64 * EVW_U) {
     uint32_t x[EVW_U];
@@ -308,10 +315,11 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
       const uint64_t mask = __ballot(q[u] > 0);
       const int slot = m + __popcll(mask & lt);
       if (q[u] > 0 && slot < EVW_MAX_MOVING) {
+        const uint32_t dbit = x[u] >> 31;
         li[slot] = (int16_t)(c + 64 * u + l);
         qs[slot] = ((uint32_t)q[u] << 8) | (uint32_t)slot;
-        psl[slot] = ps[u];
-        pdl[slot] = (uint32_t)pd[u] | (x[u] & kDst);
+        evk[2 * slot] = ((uint32_t)ps[u] << 10) | dbit;
+        evk[2 * slot + 1] = ((uint32_t)pd[u] << 10) | dbit | 2u;
       }
       m += __popcll(mask);
     }
@@ -324,17 +332,17 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
     if (l == 0) heavy[atomicAdd((unsigned long long *)&scal[SC_HEAVY], 1ull)] = e;
     return;
   }
-  wave_lds_sync();
-  // the hedge's part table in LDS (parts ascending; pins | pins_in << 16)
-  const bool staged = plen <= EVW_PT_STAGE;
-  int32_t *sp = sp_s[w];
-  uint32_t *sc = sc_s[w];
-  if (staged) {
-    for (int i = l; i < plen; i += 64) {
-      sp[i] = pt[b + i];
-      sc[i] = ptc[b + i];
-    }
+  // the first chunks of the part table (parts ascending; pins | pins_in << 16),
+  // loaded while the positions sort
+  int32_t tp[EVN_PT_REG];
+  uint32_t tc[EVN_PT_REG];
+#pragma unroll
+  for (int u = 0; u < EVN_PT_REG; ++u) {
+    const int j = 64 * u + l;
+    tp[u] = j < plen ? pt[b + j] : -1;
+    tc[u] = j < plen ? ptc[b + j] : 0u;
   }
+  wave_lds_sync();
   // moving pins in position order (positions are distinct)
   {
     auto sort_q = [&](auto kpl) {
@@ -360,17 +368,32 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
   wave_lds_sync();
   for (int r = l; r < m; r += 64) {
     const int slot = (int)(qs[r] & 255u);
-    const uint32_t pdd = pdl[slot];
-    const uint32_t tail = ((uint32_t)r << 2) | (pdd >> 31);
-    evk[2 * r] = ((uint32_t)psl[slot] << 10) | tail;
-    evk[2 * r + 1] = ((pdd & kIdMask) << 10) | tail | 2u;
+    evk[2 * slot] |= (uint32_t)r << 2;
+    evk[2 * slot + 1] |= (uint32_t)r << 2;
   }
   wave_lds_sync();
   const int nev = 2 * m;
-  if (nev <= 64) ev_wave_sort_scan<1>(nev, 10, evk, pre);
-  else if (nev <= 128) ev_wave_sort_scan<2>(nev, 10, evk, pre);
-  else if (nev <= 256) ev_wave_sort_scan<4>(nev, 10, evk, pre);
-  else ev_wave_sort_scan<8>(nev, 10, evk, pre);
+  // table entry (p, c): the first sorted event of part p, if any, starts
+  // from c instead of 0
+  auto add_table = [&]() {
+    auto one = [&](int32_t p, uint32_t cnt) {
+      int lo = 0, hi = nev;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)(evk[mid] >> 10) < p) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < nev && (int32_t)(evk[lo] >> 10) == p) pre[lo] -= (int32_t)cnt;
+    };
+#pragma unroll
+    for (int u = 0; u < EVN_PT_REG; ++u)
+      if (tp[u] >= 0) one(tp[u], tc[u]);
+    for (int j = 64 * EVN_PT_REG + l; j < plen; j += 64) one(pt[b + j], ptc[b + j]);
+  };
+  if (nev <= 64) ev_wave_sort_scan<1>(nev, 10, evk, pre, add_table);
+  else if (nev <= 128) ev_wave_sort_scan<2>(nev, 10, evk, pre, add_table);
+  else if (nev <= 256) ev_wave_sort_scan<4>(nev, 10, evk, pre, add_table);
+  else ev_wave_sort_scan<8>(nev, 10, evk, pre, add_table);
   wave_lds_sync();
   uint32_t evbits = 0;  // bit t: event l + 64 t changes an inbound count
   int nout = 0;
@@ -378,16 +401,14 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
     const int i = l + 64 * t;
     if (i >= nev) continue;
     const uint32_t k = evk[i];
-    const int part = (int)(k >> 10);
-    const int2 before = unpack_delta(pre[i]);
-    const int2 c0 = staged ? pt_lookup_lds(sp, sc, plen, part) : pt_lookup(pt, ptc, b, plen, part);
+    const int2 before = unpack_delta(pre[i]);  // pins / pins_in of the part before this move
     const bool dst_role = (k & 2u) != 0;
     const int slot = (int)(qs[(k >> 2) & 255u] & 255u);
     int2 *cp = &contrib[b + li[slot]];
-    if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
-    else cp->x = (c0.x + before.x == 1) ? we : 0;
+    if (dst_role) cp->y = (before.x == 0) ? -we : 0;
+    else cp->x = (before.x == 1) ? we : 0;
     if (k & 1u) {
-      const int bin = c0.y + before.y;
+      const int bin = before.y;
       if ((!dst_role && bin == 1) || (dst_role && bin == 0)) {
         evbits |= 1u << t;
         ++nout;
@@ -402,18 +423,19 @@ __global__ __launch_bounds__(EVW_NT) void k_ev_wave32(
     if (!(evbits & 1u)) continue;
     const uint32_t k = evk[l + 64 * t];
     const uint64_t q = qs[(k >> 2) & 255u] >> 8;
-    evpad[o++] = ((uint64_t)(k >> 10) << vshift) | (q << 2) | ((k >> 1) & 1u);
+    evpad[o++] = (KP)(((uint64_t)(k >> 10) << vshift) | (q << 2) | ((k >> 1) & 1u));
   }
 }
 
 // One workgroup per queued hedge (more than EVW_MAX_MOVING moving pins; at
 // most kSegCap pins).  Same events as k_ev_wave with a 12-bit slot field:
 // part << (qbits + 14) | position << 14 | slot << 2 | role << 1 | dst.
+template <class KP>
 __global__ __launch_bounds__(EVB_NT) void k_ev_block(
     const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
     const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
     const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
-    int2 *__restrict__ contrib, uint64_t *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    int2 *__restrict__ contrib, KP *__restrict__ evpad, int64_t *__restrict__ evcnt,
     const int64_t *__restrict__ scal, const int32_t *__restrict__ heavy) {
   __shared__ uint64_t key[2 * kSegCap];
   __shared__ int32_t dl[2 * kSegCap];
@@ -505,7 +527,7 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
       if (!(evbits & 1u)) continue;
       const uint64_t k = key[tid + EVB_NT * t];
       const uint64_t q = (k >> 14) & qmask;
-      evpad[o++] = ((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull);
+      evpad[o++] = (KP)(((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull));
     }
     __syncthreads();
   }
@@ -517,13 +539,13 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
 template <class K>
 __global__ __launch_bounds__(256) void k_ev_compact(const int32_t *__restrict__ hoff, int32_t E,
                                                     const int64_t *__restrict__ evoff,
-                                                    const uint64_t *__restrict__ evpad, K *__restrict__ ev) {
+                                                    const K *__restrict__ evpad, K *__restrict__ ev) {
   const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (e >= E) return;
   const int64_t o = evoff[e], c = evoff[e + 1] - o;
   if (c == 0) return;
   const int64_t src = 2 * (int64_t)hoff[e];
-  for (int64_t i = lane_id(); i < c; i += 64) ev[o + i] = (K)evpad[src + i];
+  for (int64_t i = lane_id(); i < c; i += 64) ev[o + i] = evpad[src + i];
 }
 
 // g'(i) for move i = 1..S: the sum, over the incidences k of the moving node,
@@ -751,25 +773,28 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     KScope ks(kClsEvents, s);
     if (L.E > 0) {
       // inbound-count events per hedge into keys2 (one region of 2|e| per
-      // hedge), then packed into keys[0 .. nin)
-      if (pbits <= EVN_PBITS && qbits <= EVN_QBITS)
-        k_ev_wave32<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos,
-                                                                B.pt, B.ptc, B.lam, qbits, B.contrib, B.keys2,
-                                                                B.evoff, B.scal, B.heavy);
-      else
-        k_ev_wave<<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos, B.pt,
-                                                              B.ptc, B.lam, qbits, B.contrib, B.keys2, B.evoff,
-                                                              B.scal, B.heavy);
-      HGP_LAUNCH_CHECK();
-      k_ev_block<<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam, qbits,
-                                             B.contrib, B.keys2, B.evoff, B.scal, B.heavy);
-      HGP_LAUNCH_CHECK();
-      scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);
-      if (narrow)
-        k_ev_compact<uint32_t><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, k32);
-      else
-        k_ev_compact<uint64_t><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, B.keys2, B.keys);
-      HGP_LAUNCH_CHECK();
+      // hedge, 32-bit words when the packed keys fit), then packed into
+      // keys[0 .. nin)
+      auto emit = [&](auto *evpad, auto *ev) {
+        using KP = std::remove_pointer_t<decltype(evpad)>;
+        if (pbits <= EVN_PBITS && qbits <= EVN_QBITS)
+          k_ev_wave32<KP><<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest,
+                                                                      B.pos, B.pt, B.ptc, B.lam, qbits, B.contrib,
+                                                                      evpad, B.evoff, B.scal, B.heavy);
+        else
+          k_ev_wave<KP><<<div_up(L.E, EVW_NT / 64), EVW_NT, 0, s>>>(L.hoff, L.hpin, L.E, L.hw, rho, B.dest, B.pos,
+                                                                    B.pt, B.ptc, B.lam, qbits, B.contrib, evpad,
+                                                                    B.evoff, B.scal, B.heavy);
+        HGP_LAUNCH_CHECK();
+        k_ev_block<KP><<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam,
+                                                   qbits, B.contrib, evpad, B.evoff, B.scal, B.heavy);
+        HGP_LAUNCH_CHECK();
+        scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);
+        k_ev_compact<KP><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, evpad, ev);
+        HGP_LAUNCH_CHECK();
+      };
+      if (narrow) emit(reinterpret_cast<uint32_t *>(B.keys2), k32);
+      else emit(B.keys2, B.keys);
     }
     k_move_gain<<<div_up(S, 4), 256, 0, s>>>(B.seq, S, L.ioff, L.perm, B.contrib, B.gp);
     HGP_LAUNCH_CHECK();
