@@ -112,8 +112,12 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // every hedge of I(n) adds w(e) to conn[p] in LDS; then
 //   gain(n,p) = saving - loss(n,p) = saving - total(n) + conn[p]
 // and the best part by (gain, id) among those with size(p)+size(n) <= Omega
-// is kept if gain > 0.
-template <int NT>
+// is kept if gain > 0.  With DEFER, nodes of more than kPropHeavyDeg
+// incidences are only queued (hlist, *hcnt): the second launch gives each of
+// them a workgroup of many more waves, since a few such nodes (large clusters
+// at coarse levels) would otherwise decide the whole launch's duration.
+constexpr int kPropHeavyDeg = 2 * PROP_NT;
+template <int NT, int U, bool DEFER>
 __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list, const int64_t *__restrict__ count,
                                                 int32_t N, const int32_t *__restrict__ ioff,
                                                 const uint32_t *__restrict__ inc, const uint32_t *__restrict__ perm,
@@ -124,6 +128,7 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
                                                 const int32_t *__restrict__ psize, const int32_t *__restrict__ total,
                                                 int32_t n_parts, int32_t omega, int32_t words,
                                                 int32_t *__restrict__ dest, int32_t *__restrict__ gain,
+                                                int32_t *__restrict__ hlist, unsigned long long *__restrict__ hcnt,
                                                 unsigned long long *__restrict__ units) {
   extern __shared__ uint32_t conn[];
   __shared__ int64_t red[NT / 64];
@@ -137,6 +142,10 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
     const int n = list ? list[t] : (int)t;
     const int ps = rho[n];
     const int i0 = ioff[n], i1 = ioff[n + 1];
+    if (DEFER && i1 - i0 > kPropHeavyDeg) {
+      if (tid == 0) hlist[atomicAdd(hcnt, 1ull)] = n;
+      continue;
+    }
     // saving(n): hedges where n is the only pin of p_s
     int64_t sav = 0;
     for (int i = i0 + tid; i < i1; i += NT)
@@ -160,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
         const int span = min(words, n_parts - lo);
         for (int i = tid; i < span; i += NT) conn[i] = 0u;
         __syncthreads();
-        streamed += stream_segments<NT / 64, 4, false, int32_t>(
+        streamed += stream_segments<NT / 64, U, false, int32_t>(
             i0, i1, inc, hoff, lam, hw, tbl, [&](int j) { return pt[j]; },
             [&](int32_t p, uint32_t info) {
               const uint32_t rel = (uint32_t)(p - lo);
@@ -213,6 +222,8 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
 }
 
 constexpr int PROP_GRID = 8192;
+constexpr int PROP_HEAVY_NT = 1024;
+constexpr int PROP_HEAVY_GRID = 512;  // two 1024-thread workgroups per CU
 
 void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho, int32_t n_parts, int32_t omega,
                     RoundBufs &B, hipStream_t s, const int32_t *list, const int64_t *count) {
@@ -221,9 +232,17 @@ void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho
   const int words = n_parts < max_words ? (n_parts > 0 ? n_parts : 1) : max_words;
   KScope ks(1, s);
   const int grid = list ? (L.n < PROP_GRID ? L.n : PROP_GRID) : L.n;
-  k_propose<PROP_NT><<<grid, PROP_NT, (size_t)words * 4, s>>>(list, count, L.n, L.ioff, L.inc, L.perm, L.hoff, B.pt,
-                                                             B.solo, B.lam, L.hw, rho, L.size, B.psize, total, n_parts,
-                                                             omega, words, B.dest, B.gain, units_ptr(1));
+  // heavy nodes queue into flag (free until the sequence is built)
+  int64_t *hcnt = B.scal + SC_PHEAVY;
+  fill_i64(hcnt, 1, 0, s);
+  k_propose<PROP_NT, 4, true><<<grid, PROP_NT, (size_t)words * 4, s>>>(
+      list, count, L.n, L.ioff, L.inc, L.perm, L.hoff, B.pt, B.solo, B.lam, L.hw, rho, L.size, B.psize, total, n_parts,
+      omega, words, B.dest, B.gain, B.flag, reinterpret_cast<unsigned long long *>(hcnt), units_ptr(1));
+  HGP_LAUNCH_CHECK();
+  const int hgrid = L.n < PROP_HEAVY_GRID ? L.n : PROP_HEAVY_GRID;
+  k_propose<PROP_HEAVY_NT, 8, false><<<hgrid, PROP_HEAVY_NT, (size_t)words * 4, s>>>(
+      B.flag, hcnt, L.n, L.ioff, L.inc, L.perm, L.hoff, B.pt, B.solo, B.lam, L.hw, rho, L.size, B.psize, total,
+      n_parts, omega, words, B.dest, B.gain, nullptr, nullptr, units_ptr(1));
   HGP_LAUNCH_CHECK();
 }
 
