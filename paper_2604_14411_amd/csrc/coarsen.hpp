@@ -146,10 +146,11 @@ void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, c
                         const int32_t *cgain, RoundBufs &B, int32_t *list, int64_t *cnt, hipStream_t s);
 // Builds the sequence; returns |S| (host sync).
 int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
-// In-sequence gains, validity, best prefix; returns (istar, Gstar) via host sync.
+// In-sequence gains, validity, best prefix; returns (istar, Gstar) and the
+// device error bits *err (into *err_bits) in one host sync.
 void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta,
                        int64_t S, RoundBufs &B, int32_t *err, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s,
-                       int64_t *istar, int64_t *gstar);
+                       int64_t *istar, int64_t *gstar, int32_t *err_bits);
 void launch_apply(int32_t *rho, RoundBufs &B, int64_t istar, hipStream_t s);
 void launch_project(const int32_t *gamma, const int32_t *rho_coarse, int32_t n, int32_t *rho_fine, hipStream_t s);
 // Eq. 1 from a part table; result in *conn_dev (device int64).

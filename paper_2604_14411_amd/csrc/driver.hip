@@ -202,11 +202,24 @@ static int32_t read_i32(const int32_t *dptr, hipStream_t s) {
   return v;
 }
 
-static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
-  const int32_t bits = read_i32(W.err.as<int32_t>(), s) & mask;
+static void raise_err(int32_t bits) {
   const char *msg = "";
   const int rc = map_err(bits, &msg);
   if (rc != HGP_OK) throw Error(rc, msg);
+}
+
+static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
+  raise_err(read_i32(W.err.as<int32_t>(), s) & mask);
+}
+
+// *dptr and the error bits in one round trip; throws on an error
+static int32_t read_i32_checked(Workspace &W, const int32_t *dptr, hipStream_t s) {
+  int32_t v[2] = {0, 0};
+  HGP_HIP(hipMemcpyAsync(&v[0], dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&v[1], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  raise_err(v[1]);
+  return v[0];
 }
 
 static void check_scalars(const hgp_hypergraph *g, int32_t omega, int32_t delta) {
@@ -377,8 +390,10 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
   RoundResult R;
   R.S = build_sequence(L, B, W.scan_tmp, W.sort_tmp, s);
   if (R.S > 0) add_units(HGP_K_SEQEVENTS, 4 * P);  // 4 B per pin scanned (+16 B per event, counted with the events)
-  evaluate_sequence(L, rho, n_parts, omega, delta, R.S, B, err, W.scan_tmp, W.sort_tmp, s, &R.istar, &R.gstar);
-  check_err(W, s);
+  int32_t err_bits = 0;
+  evaluate_sequence(L, rho, n_parts, omega, delta, R.S, B, err, W.scan_tmp, W.sort_tmp, s, &R.istar, &R.gstar,
+                    &err_bits);
+  raise_err(err_bits);
   if (R.istar >= 0 && R.gstar > 0) {
     launch_apply(rho, B, R.istar, s);
     R.applied = true;
@@ -685,16 +700,14 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
     int32_t *lmatch = need<int32_t>(W.lv_match[lvl], n);
     launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
-    int32_t n_next = read_i32(nnext_dev, s);
-    check_err(W, s);
+    int32_t n_next = read_i32_checked(W, nnext_dev, s);
     if (learned) {
       // fallback: the plain pairs' matching, used if it merges over twice as many pairs
       int32_t *pm = need<int32_t>(W.pmatch, n);
       int32_t *pg = need<int32_t>(W.pgam, n);
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
-      const int32_t n_next_p = read_i32(nnext_dev + 1, s);
-      check_err(W, s);
+      const int32_t n_next_p = read_i32_checked(W, nnext_dev + 1, s);
       if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
         HGP_HIP(hipMemcpyAsync(lmatch, pm, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
         HGP_HIP(hipMemcpyAsync(gam, pg, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));

@@ -753,8 +753,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finish(const int32_t *__restrict__ g
 
 void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta,
                        int64_t S, RoundBufs &B, int32_t *err, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s,
-                       int64_t *istar, int64_t *gstar) {
-  (void)err;
+                       int64_t *istar, int64_t *gstar, int32_t *err_bits) {
   const int qbits = bits_for(S) > 0 ? bits_for(S) : 1;
   const int pbits = bits_for(n_parts > 1 ? n_parts - 1 : 1);
   const int vshift = qbits + 2;
@@ -834,8 +833,10 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);
     HGP_LAUNCH_CHECK();
   }
+  // the result and the error bits in one round trip
   int64_t res[2];
   HGP_HIP(hipMemcpyAsync(res, B.scal + SC_ISTAR, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(err_bits, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
   *istar = res[0];
   *gstar = res[1];
