@@ -130,12 +130,13 @@ struct RoundBufs {
   int32_t *heavy = nullptr;    // [E] hedges queued for the workgroup event kernel
   int64_t *evoff = nullptr;    // [E + 1] inbound-count events per hedge, then their offsets
   int2 *contrib = nullptr;     // [P] per moving pin: in-sequence gain terms (source, destination role)
-  int64_t *esum = nullptr;     // [cap_events + 1] prefix sums of size deltas over sorted events
-  int32_t *isum = nullptr;     // [cap_events + 1] prefix sums of inbound deltas over sorted events
-  int64_t *poff = nullptr;     // [n_parts + 1] first sorted event of every part
+  int64_t *tile_e = nullptr;   // [2 cap_tiles] per tile of sorted events: size-sum aggregate, then carry
+  int32_t *tile_i = nullptr;   // [3 cap_tiles] inbound-sum aggregate, segment-start flag, carry
   DevBuf *partial = nullptr;   // per-workgroup inb(p) rows of the part-table kernel
   int64_t cap_events = 0;
+  int64_t cap_tiles = 0;
 };
+constexpr int kEventTile = 2048;  // sorted events per tile of the transition pass
 
 void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, RoundBufs &B, int32_t *err,
                        hipStream_t s);

@@ -69,7 +69,7 @@ struct Workspace {
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
   DevBuf heavy, evoff, maxin, pt, ptc, lam, solo, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
-  DevBuf contrib, esum, isum, poff, pt_partial;
+  DevBuf contrib, tile_e, tile_i, pt_partial;
   DevBuf scan_tmp, sort_tmp;
   DevBuf in_off, in_pins, in_nsrc, in_hw, in_nw, in_part;  // staging of host inputs
   DevBuf ones_e, ones_n;
@@ -118,7 +118,7 @@ struct Workspace {
                      &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2, &perm, &pin_he,   &pair,    &score,   &best,
                      &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptc,     &lam, &heavy, &evoff, &maxin, &solo,
                      &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
-                     &vdelta, &contrib, &esum, &isum, &poff, &pt_partial, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
+                     &vdelta, &contrib, &tile_e, &tile_i, &pt_partial, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
@@ -347,9 +347,9 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.gp = need<int32_t>(W.gp, (int64_t)n + 1);
   B.vdelta = need<int32_t>(W.vdelta, (int64_t)n + 1);
   B.contrib = need<int2>(W.contrib, P);
-  B.esum = need<int64_t>(W.esum, B.cap_events + 1);
-  B.isum = need<int32_t>(W.isum, B.cap_events + 1);
-  B.poff = need<int64_t>(W.poff, (int64_t)n_parts + 1);
+  B.cap_tiles = B.cap_events / kEventTile + 1;
+  B.tile_e = need<int64_t>(W.tile_e, 2 * B.cap_tiles);
+  B.tile_i = need<int32_t>(W.tile_i, 3 * B.cap_tiles);
   B.partial = &W.pt_partial;
   B.G = need<int64_t>(W.G, (int64_t)n + 1);
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);

@@ -578,82 +578,247 @@ __global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const 
   ev[base + 2 * i + 1] = (K)(((uint64_t)(uint32_t)dest[v] << vshift) | tail);
 }
 
-// poff[p] = first sorted event of part p (p = 0 .. P; poff[P] = nev).
-template <class K>
-__global__ void k_part_offsets(const K *__restrict__ ev, int64_t nev, int vshift, int32_t P,
-                               int64_t *__restrict__ poff) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p > P) return;
-  int64_t lo = 0, hi = nev;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)((uint64_t)ev[mid] >> vshift) < p) lo = mid + 1;
-    else hi = mid;
-  }
-  poff[p] = lo;
-}
+// After the sort, one pass decides every validity transition.  Deltas per
+// sorted event: a size event (type 2) adds -size(v) to the part v leaves and
+// +size(v) to the part it joins; an inbound event adds -1 (type 0) or +1
+// (type 1).  The part's size and inbound count after event i are its initial
+// values plus the prefix of the deltas within its part (a scan segmented at
+// part changes).  For a (part, position) group, invalid_after - invalid_before
+// is added to vdelta at the position: +1 where the part becomes invalid, -1
+// where it becomes valid again (invalid = size > Omega or inbound > Delta).
+// Two kernels over tiles of EVS_TILE events: per-tile aggregates of the
+// segmented sum, then (after a scan of the aggregates) the tile's own scan and
+// the group decisions.  Order within a group does not matter: only whole
+// groups are compared.
+constexpr int EVS_NT = 256;
+constexpr int EVS_IPT = 8;
+constexpr int EVS_TILE = EVS_NT * EVS_IPT;
+static_assert(EVS_TILE == kEventTile, "tile arrays are sized by kEventTile");
+constexpr int EVS_CARRY_NT = 1024;
 
-// Per sorted event: size delta (+-size(v) for the part left / joined) and
-// inbound-count delta (-1 / +1).
 template <class K>
-__global__ void k_ev_vals(const K *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
-                          const int32_t *__restrict__ seq, const int32_t *__restrict__ rho,
-                          const int32_t *__restrict__ size, int64_t *__restrict__ esum, int32_t *__restrict__ isum) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nev) return;
-  const uint64_t k = (uint64_t)ev[i];
+__device__ __forceinline__ void ev_delta(uint64_t k, int vshift, uint64_t qmask, const int32_t *__restrict__ seq,
+                                         const int32_t *__restrict__ rho, const int32_t *__restrict__ size,
+                                         int64_t &ds, int32_t &di) {
   const int type = (int)(k & 3ull);
-  int64_t ds = 0;
-  int32_t di = 0;
+  ds = 0;
+  di = 0;
   if (type == 2) {
     const int v = seq[((k >> 2) & qmask) - 1];
     ds = (uint64_t)(uint32_t)rho[v] == (k >> vshift) ? -(int64_t)size[v] : (int64_t)size[v];
   } else {
     di = type == 1 ? 1 : -1;
   }
-  esum[i] = ds;
-  isum[i] = di;
 }
 
-// At the last event of every (part, position) group: validity of the part
-// before the group (its previous position) and after it; a change adds +1
-// (valid -> invalid) or -1 to the violation delta at that position.
-template <class K>
-__global__ void k_ev_transitions(const K *__restrict__ ev, int64_t nev, int vshift, uint64_t qmask,
-                                 const int64_t *__restrict__ poff, const int32_t *__restrict__ psize,
-                                 const int32_t *__restrict__ pinb, const int64_t *__restrict__ esum,
-                                 const int32_t *__restrict__ isum, int32_t omega, int32_t delta,
-                                 int32_t *__restrict__ vdelta) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nev) return;
-  const uint64_t g = (uint64_t)ev[i] >> 2;
-  if (i + 1 < nev && ((uint64_t)ev[i + 1] >> 2) == g) return;
-  const int p = (int)((uint64_t)ev[i] >> vshift);
-  const int64_t b = poff[p];
-  int64_t lo = b, hi = i;  // first event of the group
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (((uint64_t)ev[mid] >> 2) < g) lo = mid + 1;
-    else hi = mid;
+// A segmented-sum element: f = a segment starts in it, (e, i) = the sums
+// after its last start (of all of it when f = 0).
+struct SegSum {
+  int64_t e;
+  int32_t i;
+  int32_t f;
+};
+__device__ __forceinline__ SegSum seg_combine(const SegSum &a, const SegSum &b) {
+  return b.f ? b : SegSum{a.e + b.e, a.i + b.i, a.f};
+}
+__device__ __forceinline__ SegSum seg_shfl_up(const SegSum &x, int o) {
+  return SegSum{__shfl_up(x.e, o, 64), __shfl_up(x.i, o, 64), __shfl_up(x.f, o, 64)};
+}
+// Inclusive segmented scan over a wave.
+__device__ __forceinline__ SegSum seg_wave_scan(SegSum x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const SegSum y = seg_shfl_up(x, o);
+    if (l >= o) x = seg_combine(y, x);
   }
-  const int64_t s0 = psize[p] - esum[b], i0 = (int64_t)pinb[p] - isum[b];
-  const bool valid_before = s0 + esum[lo] <= omega && i0 + isum[lo] <= delta;
-  const bool valid_after = s0 + esum[i + 1] <= omega && i0 + isum[i + 1] <= delta;
-  if (valid_before != valid_after) atomicAdd(&vdelta[g & qmask], valid_after ? -1 : 1);
+  return x;
+}
+// Exclusive segmented scan over the block (thread order); returns the
+// combination of all elements before this thread's.
+template <int NT>
+__device__ __forceinline__ SegSum seg_block_exclusive(SegSum x, SegSum *wtot) {
+  const int w = threadIdx.x >> 6, l = lane_id();
+  const SegSum inc = seg_wave_scan(x);
+  if (l == 63) wtot[w] = inc;
+  __syncthreads();
+  SegSum pre{0, 0, 0};
+  for (int q = 0; q < w; ++q) pre = seg_combine(pre, wtot[q]);
+  SegSum ex = seg_shfl_up(inc, 1);
+  if (l == 0) ex = SegSum{0, 0, 0};
+  __syncthreads();
+  return seg_combine(pre, ex);
+}
+
+template <class K>
+__global__ __launch_bounds__(EVS_NT) void k_evs_tiles(const K *__restrict__ ev, int64_t nev, int vshift,
+                                                      uint64_t qmask, const int32_t *__restrict__ seq,
+                                                      const int32_t *__restrict__ rho,
+                                                      const int32_t *__restrict__ size, int64_t *__restrict__ agg_e,
+                                                      int32_t *__restrict__ agg_i, int32_t *__restrict__ agg_f) {
+  __shared__ SegSum wtot[EVS_NT / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * EVS_TILE;
+  const int tid = threadIdx.x;
+  // contiguous items per thread, so that a thread's fold is in event order
+  SegSum x{0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < EVS_IPT; ++j) {
+    const int64_t i = t0 + (int64_t)tid * EVS_IPT + j;
+    if (i >= nev) break;
+    const uint64_t k = (uint64_t)ev[i];
+    const bool start = i == 0 || (k >> vshift) != ((uint64_t)ev[i - 1] >> vshift);
+    int64_t ds;
+    int32_t di;
+    ev_delta<K>(k, vshift, qmask, seq, rho, size, ds, di);
+    x = seg_combine(x, SegSum{ds, di, start ? 1 : 0});
+  }
+  const SegSum ex = seg_block_exclusive<EVS_NT>(x, wtot);
+  if (tid == EVS_NT - 1) {
+    const SegSum t = seg_combine(ex, x);
+    agg_e[blockIdx.x] = t.e;
+    agg_i[blockIdx.x] = t.i;
+    agg_f[blockIdx.x] = t.f;
+  }
+}
+
+// One workgroup: carry[t] = segmented sum of the tiles before t (the running
+// part sums at the start of tile t).
+__global__ __launch_bounds__(EVS_CARRY_NT) void k_evs_carry(int ntiles, const int64_t *__restrict__ agg_e,
+                                                            const int32_t *__restrict__ agg_i,
+                                                            const int32_t *__restrict__ agg_f,
+                                                            int64_t *__restrict__ carry_e,
+                                                            int32_t *__restrict__ carry_i) {
+  __shared__ SegSum wtot[EVS_CARRY_NT / 64];
+  __shared__ SegSum s_run;
+  if (threadIdx.x == 0) s_run = SegSum{0, 0, 0};
+  __syncthreads();
+  for (int c = 0; c < ntiles; c += EVS_CARRY_NT) {
+    const int t = c + (int)threadIdx.x;
+    const SegSum x = t < ntiles ? SegSum{agg_e[t], agg_i[t], agg_f[t]} : SegSum{0, 0, 0};
+    const SegSum run = s_run;
+    const SegSum ex = seg_combine(run, seg_block_exclusive<EVS_CARRY_NT>(x, wtot));
+    if (t < ntiles) {
+      carry_e[t] = ex.e;
+      carry_i[t] = ex.i;
+    }
+    if (threadIdx.x == EVS_CARRY_NT - 1) s_run = seg_combine(ex, x);
+    __syncthreads();
+  }
+}
+
+template <class K>
+__global__ __launch_bounds__(EVS_NT) void k_evs_trans(const K *__restrict__ ev, int64_t nev, int vshift,
+                                                      uint64_t qmask, const int32_t *__restrict__ seq,
+                                                      const int32_t *__restrict__ rho,
+                                                      const int32_t *__restrict__ size,
+                                                      const int64_t *__restrict__ carry_e,
+                                                      const int32_t *__restrict__ carry_i,
+                                                      const int32_t *__restrict__ psize,
+                                                      const int32_t *__restrict__ pinb, int32_t omega, int32_t delta,
+                                                      int32_t *__restrict__ vdelta) {
+  __shared__ uint64_t kk[EVS_TILE];   // the tile's keys; key >> 2 identifies a (part, position) group
+  __shared__ int8_t before[EVS_TILE];  // invalid before the group, at its first event
+  __shared__ SegSum wtot[EVS_NT / 64];
+  const int64_t t0 = (int64_t)blockIdx.x * EVS_TILE;
+  const int tid = threadIdx.x;
+  const int cnt = (int)min((int64_t)EVS_TILE, nev - t0);
+  for (int j = tid; j < cnt; j += EVS_NT) kk[j] = (uint64_t)ev[t0 + j];
+  __syncthreads();
+  const int pshift = vshift - 2;
+  // neighbours of the tile
+  const uint64_t g_prev = t0 > 0 ? ((uint64_t)ev[t0 - 1] >> 2) : ~0ull;
+  const uint64_t g_next = t0 + cnt < nev ? ((uint64_t)ev[t0 + cnt] >> 2) : ~0ull;
+  int64_t dsv[EVS_IPT];
+  int32_t div_[EVS_IPT];
+  SegSum x{0, 0, 0};
+  const int j0 = tid * EVS_IPT;
+#pragma unroll
+  for (int j = 0; j < EVS_IPT; ++j) {
+    const int lj = j0 + j;
+    dsv[j] = 0;
+    div_[j] = 0;
+    if (lj < cnt) {
+      const uint64_t k = kk[lj];
+      const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
+      const bool start = (t0 + lj == 0) || ((k >> 2) >> pshift) != (gp >> pshift);
+      ev_delta<K>(k, vshift, qmask, seq, rho, size, dsv[j], div_[j]);
+      x = seg_combine(x, SegSum{dsv[j], div_[j], start ? 1 : 0});
+    }
+  }
+  SegSum run = seg_combine(SegSum{carry_e[blockIdx.x], carry_i[blockIdx.x], 0},
+                           seg_block_exclusive<EVS_NT>(x, wtot));
+  // inclusive part sums per item; the before-state at every group start
+  int64_t inc_e[EVS_IPT];
+  int32_t inc_i[EVS_IPT];
+#pragma unroll
+  for (int j = 0; j < EVS_IPT; ++j) {
+    const int lj = j0 + j;
+    inc_e[j] = 0;
+    inc_i[j] = 0;
+    if (lj < cnt) {
+      const uint64_t g = kk[lj] >> 2;
+      const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
+      const bool pstart = (t0 + lj == 0) || (g >> pshift) != (gp >> pshift);
+      run = seg_combine(run, SegSum{dsv[j], div_[j], pstart ? 1 : 0});
+      inc_e[j] = run.e;
+      inc_i[j] = run.i;
+      if (t0 + lj == 0 || g != gp) {
+        const int p = (int)(g >> pshift);
+        const int64_t se = pstart ? 0 : run.e - dsv[j];
+        const int64_t si = pstart ? 0 : (int64_t)run.i - div_[j];
+        before[lj] = ((int64_t)psize[p] + se > omega || (int64_t)pinb[p] + si > delta) ? 1 : 0;
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t g_first = kk[0] >> 2, g_last = kk[cnt - 1] >> 2;
+#pragma unroll
+  for (int j = 0; j < EVS_IPT; ++j) {
+    const int lj = j0 + j;
+    if (lj >= cnt) continue;
+    const uint64_t g = kk[lj] >> 2;
+    const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
+    const uint64_t gn = lj + 1 < cnt ? kk[lj + 1] >> 2 : g_next;
+    const bool first = (t0 + lj == 0) || g != gp;
+    const bool last = g != gn;
+    const int q = (int)(g & qmask);
+    int d = 0;
+    if (last) {
+      const int p = (int)(g >> pshift);
+      const int after = ((int64_t)psize[p] + inc_e[j] > omega || (int64_t)pinb[p] + inc_i[j] > delta) ? 1 : 0;
+      if (g == g_first && g == g_prev) {
+        d = after;  // the group began in an earlier tile, which takes its before-state
+      } else {
+        int lo = 0, hi = lj;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((kk[mid] >> 2) < g) lo = mid + 1;
+          else hi = mid;
+        }
+        d = after - before[lo];
+      }
+    } else if (first && g == g_last && g == g_next) {
+      d = -before[lj];  // the group ends in a later tile
+    }
+    if (d) atomicAdd(&vdelta[q], d);
+  }
 }
 
 template <class K>
 static void events_after_sort(const LevelView &L, const K *keys, int64_t nev, int vshift, uint64_t qmask,
                               const int32_t *rho, int32_t n_parts, int32_t omega, int32_t delta, RoundBufs &B,
-                              DevBuf &scan_tmp, hipStream_t s) {
-  k_part_offsets<K><<<div_up((int64_t)n_parts + 1, 256), 256, 0, s>>>(keys, nev, vshift, n_parts, B.poff);
+                              hipStream_t s) {
+  (void)n_parts;
+  const int ntiles = (int)div_up(nev, EVS_TILE);
+  if ((int64_t)ntiles > B.cap_tiles) throw Error(-7, "event tile buffer overflow");
+  int64_t *agg_e = B.tile_e, *carry_e = B.tile_e + ntiles;
+  int32_t *agg_i = B.tile_i, *agg_f = B.tile_i + ntiles, *carry_i = B.tile_i + 2 * (int64_t)ntiles;
+  k_evs_tiles<K><<<ntiles, EVS_NT, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, agg_e, agg_i, agg_f);
   HGP_LAUNCH_CHECK();
-  k_ev_vals<K><<<div_up(nev, 256), 256, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, B.esum, B.isum);
+  k_evs_carry<<<1, EVS_CARRY_NT, 0, s>>>(ntiles, agg_e, agg_i, agg_f, carry_e, carry_i);
   HGP_LAUNCH_CHECK();
-  scan_i64(B.esum, B.esum, nev, B.esum + nev, scan_tmp, s);
-  scan_i32(B.isum, B.isum, nev, B.isum + nev, scan_tmp, s);
-  k_ev_transitions<K><<<div_up(nev, 256), 256, 0, s>>>(keys, nev, vshift, qmask, B.poff, B.psize, B.pinb, B.esum,
-                                                       B.isum, omega, delta, B.vdelta);
+  k_evs_trans<K><<<ntiles, EVS_NT, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, carry_e, carry_i, B.psize,
+                                           B.pinb, omega, delta, B.vdelta);
   HGP_LAUNCH_CHECK();
 }
 
@@ -826,9 +991,9 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     const uint64_t qmask = (1ull << qbits) - 1ull;
     if (nev > 0) {
       if (narrow)
-        events_after_sort<uint32_t>(L, k32, nev, vshift, qmask, rho, n_parts, omega, delta, B, scan_tmp, s);
+        events_after_sort<uint32_t>(L, k32, nev, vshift, qmask, rho, n_parts, omega, delta, B, s);
       else
-        events_after_sort<uint64_t>(L, B.keys, nev, vshift, qmask, rho, n_parts, omega, delta, B, scan_tmp, s);
+        events_after_sort<uint64_t>(L, B.keys, nev, vshift, qmask, rho, n_parts, omega, delta, B, s);
     }
     k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);
     HGP_LAUNCH_CHECK();
