@@ -402,9 +402,6 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
   return R;
 }
 
-// LDS words per id for the top-K rating of level L: 2 if the wide window fits,
-// 1 if every node's counters pack in 32 bits and the narrow window fits, else 0.
-
 struct RunStats {
   int64_t conn = 0;
   int32_t n_parts = 0, n_levels = 0, n_rounds = 0, n_fallback = 0;

@@ -401,35 +401,30 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
   add_wave_units(units, streamed);
 }
 
-// Rerate lists (mostly light nodes) use 256-thread workgroups; full ratings
-// and the new-cluster rows (long pin streams) use 1024 threads, since a
-// window of up to kTopKMaxWords words leaves room for one workgroup per CU.
-constexpr int TOPK_NT = 256;
-constexpr int TOPK_GRID = 2048;
-constexpr int TOPK_WIDE_NT = 1024;
-constexpr int TOPK_WIDE_GRID = 512;
-// window of the 1024-thread kernels: their static LDS (12.5 KB of stream
-// tables and reductions) and the window share the CU's 160 KB
+// 1024-thread workgroups: a window of up to kTopKWideMaxWords words leaves
+// room for one workgroup per CU, and 16 waves then hide the latency of the pin
+// streams (4 waves per CU with 256 threads).  Their static LDS (12.5 KB of
+// stream tables and reductions) and the window share the CU's 160 KB.
+constexpr int TOPK_NT = 1024;
+constexpr int TOPK_GRID = 512;
 constexpr int kTopKWideMaxWords = 37376;
 
 static void topk_attr() {
   // thread-safe one-time opt-in to the large dynamic LDS size
   static const bool attr_set = [] {
     HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kTopKMaxWords * 4));
-    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_WIDE_NT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kTopKWideMaxWords * 4));
-    HGP_HIP(hipFuncSetAttribute((const void *)k_tail_hist<TOPK_WIDE_NT>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kTopKWideMaxWords * 4));
+                                kTopKWideMaxWords * 4));
+    HGP_HIP(hipFuncSetAttribute((const void *)k_tail_hist<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kTopKWideMaxWords * 4));
     return true;
   }();
   (void)attr_set;
 }
 
 // LDS words of the window: the whole id range when it fits, else the maximum
-static int topk_words(int32_t n, int max_words = kTopKMaxWords) {
+static int topk_words(int32_t n) {
   const int64_t w = 2 * (int64_t)n;
-  return (int)std::max<int64_t>(2, std::min<int64_t>(max_words, (w + 1) & ~int64_t(1)));
+  return (int)std::max<int64_t>(2, std::min<int64_t>(kTopKWideMaxWords, (w + 1) & ~int64_t(1)));
 }
 
 void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, const int32_t *list,
@@ -439,18 +434,10 @@ void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, i
   KScope ks(8, s);
   topk_attr();
   const int words = topk_words(L.n);
-  if (list) {
-    const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
-    k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
-        L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, nullptr,
-        nullptr, pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr, units_ptr(8));
-  } else {
-    const int wide = topk_words(L.n, kTopKWideMaxWords);
-    const int grid = (int)(grid_nodes < TOPK_WIDE_GRID ? grid_nodes : TOPK_WIDE_GRID);
-    k_rate_topk<TOPK_WIDE_NT><<<grid, TOPK_WIDE_NT, (size_t)wide * 4, s>>>(
-        L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, nullptr,
-        nullptr, pair, score, tk.key, tk.c, tk.cnt, tk.kappa, wide, nullptr, units_ptr(8));
-  }
+  const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
+  k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
+      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, nullptr, nullptr,
+      pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr, units_ptr(8));
   HGP_LAUNCH_CHECK();
 }
 
@@ -460,22 +447,22 @@ uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_
   if (L.n <= 0 || n_rows <= 0) return nullptr;
   KScope ks(8, s);
   topk_attr();
-  const int words = topk_words(L.n, kTopKWideMaxWords);
-  // about TOPK_WIDE_GRID workgroups over the rows, at most 256 slices per row
+  const int words = topk_words(L.n);
+  // about TOPK_GRID workgroups over the rows, at most 256 slices per row
   const int slices =
-      (int)std::max<int64_t>(1, std::min<int64_t>(256, (TOPK_WIDE_GRID + n_rows - 1) / n_rows));
+      (int)std::max<int64_t>(1, std::min<int64_t>(256, (TOPK_GRID + n_rows - 1) / n_rows));
   const int64_t cells = (int64_t)n_rows * L.n;
   acc.reserve((size_t)cells * 8);
   unsigned long long *a = acc.as<unsigned long long>();
   fill_i64(reinterpret_cast<int64_t *>(a), cells, 0, s);
-  k_tail_hist<TOPK_WIDE_NT><<<n_rows * slices, TOPK_WIDE_NT, (size_t)words * 4, s>>>(
+  k_tail_hist<TOPK_NT><<<n_rows * slices, TOPK_NT, (size_t)words * 4, s>>>(
       L.n, list, n_rows, slices, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, words, a,
       units_ptr(8));
   HGP_LAUNCH_CHECK();
   // validated rows are written in place over the counters
   uint64_t *rows = reinterpret_cast<uint64_t *>(a);
-  const int grid = n_rows < TOPK_WIDE_GRID ? n_rows : TOPK_WIDE_GRID;
-  k_rate_topk<TOPK_WIDE_NT><<<grid, TOPK_WIDE_NT, (size_t)words * 4, s>>>(
+  const int grid = n_rows < TOPK_GRID ? n_rows : TOPK_GRID;
+  k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
       L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, row_slot, rows,
       pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, rows, units_ptr(8));
   HGP_LAUNCH_CHECK();

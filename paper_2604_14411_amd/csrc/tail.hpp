@@ -6,7 +6,6 @@
 namespace hgp {
 
 constexpr int kTopK = 16;            // candidates kept per node (the learned proposal needs up to 8 certain)
-constexpr int kTopKMaxWords = 38912; // LDS window of the top-K rating (32-bit words)
 constexpr int kTailRatio = 8;        // a matching with M * kTailRatio <= n starts the incremental regime
 constexpr int64_t kRowBudget = int64_t(1) << 31;  // new-cluster rows: M * n_next 64-bit entries (16 GB)
 
