@@ -303,11 +303,11 @@ int hgp_mlp_score_device(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, in
 
 /* Schedule of a batch; every knob leaves each graph's result unchanged.
  * Zero fields take the context's tuned value (hgp_batch_tune), else the
- * default (4 workers, LPT, 512, incremental). */
+ * default (4 workers, LPT, 1024, incremental). */
 typedef struct {
   int32_t workers;     /* concurrent streams, each with its own workspace: 1..16 */
   int32_t order;       /* HGP_ORDER_* */
-  int32_t rate_tile;   /* workgroup size of the rating kernel: 256 or 512 */
+  int32_t rate_tile;   /* workgroup size of the rating kernel: 256, 512 or 1024 */
   int32_t late_levels; /* HGP_LATE_* */
 } hgp_batch_sched;
 

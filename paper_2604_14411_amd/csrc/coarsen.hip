@@ -521,6 +521,8 @@ void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_
   HGP_LAUNCH_CHECK();
   if (tile == 256)
     launch_rate_nt<256>(L, total, maxin, omega, delta, pair, score, words, s);
+  else if (tile == 1024)
+    launch_rate_nt<1024>(L, total, maxin, omega, delta, pair, score, words, s);
   else
     launch_rate_nt<RATE_NT>(L, total, maxin, omega, delta, pair, score, words, s);
 }

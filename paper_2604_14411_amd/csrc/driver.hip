@@ -86,7 +86,7 @@ struct Workspace {
   std::vector<std::unique_ptr<CachedLevel>> lcache, lcache_free;
   int64_t lcache_bytes = 0;
   int64_t lcache_budget = level_cache_default();
-  int rate_tile = 512;         // rating workgroup size (schedule knob; same result)
+  int rate_tile = 1024;        // rating workgroup size (schedule knob; same result)
   DevBuf tr_xq, tr_prm, tr_mom, tr_part, tr_perm, tr_loss, tr_grad;
   DevBuf mlp, ck, cc, ccnt, coff32, ctot, ckey, ckey2, cval, cval2, cflag, cnm, csrc, cs, ccoff, ppair, pscore,
       pmatch, pgam;
@@ -1453,11 +1453,12 @@ static hgp_batch_sched sched_resolve(const hgp_ctx *ctx, const hgp_batch_sched *
   const hgp_batch_sched &t = ctx->tuned;
   if (r.workers == 0) r.workers = t.workers ? t.workers : 4;
   if (r.order == 0) r.order = t.order ? t.order : HGP_ORDER_LPT;
-  if (r.rate_tile == 0) r.rate_tile = t.rate_tile ? t.rate_tile : 512;
+  if (r.rate_tile == 0) r.rate_tile = t.rate_tile ? t.rate_tile : 1024;
   if (r.late_levels == 0) r.late_levels = t.late_levels ? t.late_levels : HGP_LATE_INCREMENTAL;
   if (r.workers < 1 || r.workers > 16) throw Error(HGP_EINVAL, "workers outside 1..16");
   if (r.order != HGP_ORDER_LPT && r.order != HGP_ORDER_INPUT) throw Error(HGP_EINVAL, "unknown order");
-  if (r.rate_tile != 256 && r.rate_tile != 512) throw Error(HGP_EINVAL, "rate_tile must be 256 or 512");
+  if (r.rate_tile != 256 && r.rate_tile != 512 && r.rate_tile != 1024)
+    throw Error(HGP_EINVAL, "rate_tile must be 256, 512 or 1024");
   if (r.late_levels != HGP_LATE_INCREMENTAL && r.late_levels != HGP_LATE_FULL)
     throw Error(HGP_EINVAL, "unknown late-level schedule");
   return r;
@@ -1587,7 +1588,7 @@ int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs,
     hgp_batch_sched cur{};
     cur.workers = 4;
     cur.order = HGP_ORDER_LPT;
-    cur.rate_tile = 512;
+    cur.rate_tile = 1024;
     cur.late_levels = HGP_LATE_INCREMENTAL;
     auto time_of = [&](const hgp_batch_sched &c) {
       const double a = now_ms();
@@ -1622,9 +1623,9 @@ int hgp_batch_tune(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs,
         cur = c;
       }
     }
-    {
+    for (int tile : {512, 256}) {
       hgp_batch_sched c = cur;
-      c.rate_tile = 256;
+      c.rate_tile = tile;
       const double t = time_of(c);
       if (t < best_t) {
         best_t = t;
