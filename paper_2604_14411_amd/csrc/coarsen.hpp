@@ -130,8 +130,8 @@ struct RoundBufs {
   int32_t *heavy = nullptr;    // [E] hedges queued for the workgroup event kernel
   int64_t *evoff = nullptr;    // [E + 1] inbound-count events per hedge, then their offsets
   int2 *contrib = nullptr;     // [P] per moving pin: in-sequence gain terms (source, destination role)
-  int64_t *tile_e = nullptr;   // [2 cap_tiles] per tile of sorted events: size-sum aggregate, then carry
-  int32_t *tile_i = nullptr;   // [3 cap_tiles] inbound-sum aggregate, segment-start flag, carry
+  int64_t *tile_e = nullptr;   // [cap_tiles] per tile of sorted events: size-sum aggregate
+  int32_t *tile_i = nullptr;   // [2 cap_tiles] inbound-sum aggregate, then the part-start flags
   DevBuf *partial = nullptr;   // per-workgroup inb(p) rows of the part-table kernel
   int64_t cap_events = 0;
   int64_t cap_tiles = 0;

@@ -348,8 +348,8 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.vdelta = need<int32_t>(W.vdelta, (int64_t)n + 1);
   B.contrib = need<int2>(W.contrib, P);
   B.cap_tiles = B.cap_events / kEventTile + 1;
-  B.tile_e = need<int64_t>(W.tile_e, 2 * B.cap_tiles);
-  B.tile_i = need<int32_t>(W.tile_i, 3 * B.cap_tiles);
+  B.tile_e = need<int64_t>(W.tile_e, B.cap_tiles);
+  B.tile_i = need<int32_t>(W.tile_i, 2 * B.cap_tiles);
   B.partial = &W.pt_partial;
   B.G = need<int64_t>(W.G, (int64_t)n + 1);
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);

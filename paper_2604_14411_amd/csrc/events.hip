@@ -587,14 +587,14 @@ __global__ void k_size_events(const int32_t *__restrict__ seq, int64_t S, const 
 // is added to vdelta at the position: +1 where the part becomes invalid, -1
 // where it becomes valid again (invalid = size > Omega or inbound > Delta).
 // Two kernels over tiles of EVS_TILE events: per-tile aggregates of the
-// segmented sum, then (after a scan of the aggregates) the tile's own scan and
-// the group decisions.  Order within a group does not matter: only whole
-// groups are compared.
+// segmented sum, then per tile its carry (a look-back over the aggregates of
+// the tiles before it, as far as the nearest one where a part starts), its own
+// scan and the group decisions.  Order within a group does not matter: only
+// whole groups are compared.
 constexpr int EVS_NT = 256;
 constexpr int EVS_IPT = 8;
 constexpr int EVS_TILE = EVS_NT * EVS_IPT;
 static_assert(EVS_TILE == kEventTile, "tile arrays are sized by kEventTile");
-constexpr int EVS_CARRY_NT = 1024;
 
 template <class K>
 __device__ __forceinline__ void ev_delta(uint64_t k, int vshift, uint64_t qmask, const int32_t *__restrict__ seq,
@@ -656,17 +656,22 @@ __global__ __launch_bounds__(EVS_NT) void k_evs_tiles(const K *__restrict__ ev, 
                                                       const int32_t *__restrict__ rho,
                                                       const int32_t *__restrict__ size, int64_t *__restrict__ agg_e,
                                                       int32_t *__restrict__ agg_i, int32_t *__restrict__ agg_f) {
+  __shared__ K kk[EVS_TILE + 1];  // kk[0]: the key before the tile
   __shared__ SegSum wtot[EVS_NT / 64];
   const int64_t t0 = (int64_t)blockIdx.x * EVS_TILE;
   const int tid = threadIdx.x;
+  const int cnt = (int)min((int64_t)EVS_TILE, nev - t0);
+  for (int j = tid; j < cnt; j += EVS_NT) kk[j + 1] = ev[t0 + j];
+  if (tid == 0) kk[0] = t0 > 0 ? ev[t0 - 1] : K(0);
+  __syncthreads();
   // contiguous items per thread, so that a thread's fold is in event order
   SegSum x{0, 0, 0};
 #pragma unroll
   for (int j = 0; j < EVS_IPT; ++j) {
-    const int64_t i = t0 + (int64_t)tid * EVS_IPT + j;
-    if (i >= nev) break;
-    const uint64_t k = (uint64_t)ev[i];
-    const bool start = i == 0 || (k >> vshift) != ((uint64_t)ev[i - 1] >> vshift);
+    const int lj = tid * EVS_IPT + j;
+    if (lj >= cnt) break;
+    const uint64_t k = (uint64_t)kk[lj + 1];
+    const bool start = (t0 + lj == 0) || (k >> vshift) != ((uint64_t)kk[lj] >> vshift);
     int64_t ds;
     int32_t di;
     ev_delta<K>(k, vshift, qmask, seq, rho, size, ds, di);
@@ -681,48 +686,47 @@ __global__ __launch_bounds__(EVS_NT) void k_evs_tiles(const K *__restrict__ ev, 
   }
 }
 
-// One workgroup: carry[t] = segmented sum of the tiles before t (the running
-// part sums at the start of tile t).
-__global__ __launch_bounds__(EVS_CARRY_NT) void k_evs_carry(int ntiles, const int64_t *__restrict__ agg_e,
-                                                            const int32_t *__restrict__ agg_i,
-                                                            const int32_t *__restrict__ agg_f,
-                                                            int64_t *__restrict__ carry_e,
-                                                            int32_t *__restrict__ carry_i) {
-  __shared__ SegSum wtot[EVS_CARRY_NT / 64];
-  __shared__ SegSum s_run;
-  if (threadIdx.x == 0) s_run = SegSum{0, 0, 0};
-  __syncthreads();
-  for (int c = 0; c < ntiles; c += EVS_CARRY_NT) {
-    const int t = c + (int)threadIdx.x;
-    const SegSum x = t < ntiles ? SegSum{agg_e[t], agg_i[t], agg_f[t]} : SegSum{0, 0, 0};
-    const SegSum run = s_run;
-    const SegSum ex = seg_combine(run, seg_block_exclusive<EVS_CARRY_NT>(x, wtot));
-    if (t < ntiles) {
-      carry_e[t] = ex.e;
-      carry_i[t] = ex.i;
-    }
-    if (threadIdx.x == EVS_CARRY_NT - 1) s_run = seg_combine(ex, x);
-    __syncthreads();
-  }
-}
-
 template <class K>
-__global__ __launch_bounds__(EVS_NT) void k_evs_trans(const K *__restrict__ ev, int64_t nev, int vshift,
+__global__ __launch_bounds__(EVS_NT, sizeof(K) == 4 ? 8 : 1) void k_evs_trans(const K *__restrict__ ev, int64_t nev, int vshift,
                                                       uint64_t qmask, const int32_t *__restrict__ seq,
                                                       const int32_t *__restrict__ rho,
                                                       const int32_t *__restrict__ size,
-                                                      const int64_t *__restrict__ carry_e,
-                                                      const int32_t *__restrict__ carry_i,
+                                                      const int64_t *__restrict__ agg_e,
+                                                      const int32_t *__restrict__ agg_i,
+                                                      const int32_t *__restrict__ agg_f,
                                                       const int32_t *__restrict__ psize,
                                                       const int32_t *__restrict__ pinb, int32_t omega, int32_t delta,
                                                       int32_t *__restrict__ vdelta) {
-  __shared__ uint64_t kk[EVS_TILE];   // the tile's keys; key >> 2 identifies a (part, position) group
+  __shared__ K kk[EVS_TILE];            // the tile's keys; key >> 2 identifies a (part, position) group
   __shared__ int8_t before[EVS_TILE];  // invalid before the group, at its first event
   __shared__ SegSum wtot[EVS_NT / 64];
+  __shared__ int64_t s_ce;
+  __shared__ int32_t s_ci;
   const int64_t t0 = (int64_t)blockIdx.x * EVS_TILE;
   const int tid = threadIdx.x;
   const int cnt = (int)min((int64_t)EVS_TILE, nev - t0);
-  for (int j = tid; j < cnt; j += EVS_NT) kk[j] = (uint64_t)ev[t0 + j];
+  for (int j = tid; j < cnt; j += EVS_NT) kk[j] = ev[t0 + j];
+  if (tid < 64) {
+    // carry: the aggregates of the tiles before this one, back to the nearest
+    // tile where a part starts (tile 0 always has one), 64 tiles per step
+    const int l = lane_id();
+    int64_t ce = 0;
+    int32_t ci = 0;
+    for (int64_t hi = blockIdx.x; hi > 0; hi -= 64) {
+      const int64_t tt = hi - 1 - l;  // lane 0: the nearest tile
+      const bool in = tt >= 0;
+      const uint64_t fm = __ballot(in && agg_f[tt] != 0);
+      const int stop = fm ? __ffsll((unsigned long long)fm) - 1 : 63;
+      const bool take = in && l <= stop;
+      ce += wave_sum<int64_t>(take ? agg_e[tt] : 0);
+      ci += wave_sum<int32_t>(take ? agg_i[tt] : 0);
+      if (fm) break;
+    }
+    if (l == 0) {
+      s_ce = ce;
+      s_ci = ci;
+    }
+  }
   __syncthreads();
   const int pshift = vshift - 2;
   // neighbours of the tile
@@ -738,61 +742,57 @@ __global__ __launch_bounds__(EVS_NT) void k_evs_trans(const K *__restrict__ ev, 
     dsv[j] = 0;
     div_[j] = 0;
     if (lj < cnt) {
-      const uint64_t k = kk[lj];
-      const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
+      const uint64_t k = (uint64_t)kk[lj];
+      const uint64_t gp = lj > 0 ? (uint64_t)kk[lj - 1] >> 2 : g_prev;
       const bool start = (t0 + lj == 0) || ((k >> 2) >> pshift) != (gp >> pshift);
       ev_delta<K>(k, vshift, qmask, seq, rho, size, dsv[j], div_[j]);
       x = seg_combine(x, SegSum{dsv[j], div_[j], start ? 1 : 0});
     }
   }
-  SegSum run = seg_combine(SegSum{carry_e[blockIdx.x], carry_i[blockIdx.x], 0},
-                           seg_block_exclusive<EVS_NT>(x, wtot));
-  // inclusive part sums per item; the before-state at every group start
-  int64_t inc_e[EVS_IPT];
-  int32_t inc_i[EVS_IPT];
+  SegSum run = seg_combine(SegSum{s_ce, s_ci, 0}, seg_block_exclusive<EVS_NT>(x, wtot));
+  // inclusive part sums per item: the before-state at every group's first
+  // event (to LDS) and the after-state at its last (bit j of after_bits)
+  uint32_t after_bits = 0;
 #pragma unroll
   for (int j = 0; j < EVS_IPT; ++j) {
     const int lj = j0 + j;
-    inc_e[j] = 0;
-    inc_i[j] = 0;
     if (lj < cnt) {
-      const uint64_t g = kk[lj] >> 2;
-      const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
+      const uint64_t g = (uint64_t)kk[lj] >> 2;
+      const uint64_t gp = lj > 0 ? (uint64_t)kk[lj - 1] >> 2 : g_prev;
+      const uint64_t gn = lj + 1 < cnt ? (uint64_t)kk[lj + 1] >> 2 : g_next;
       const bool pstart = (t0 + lj == 0) || (g >> pshift) != (gp >> pshift);
       run = seg_combine(run, SegSum{dsv[j], div_[j], pstart ? 1 : 0});
-      inc_e[j] = run.e;
-      inc_i[j] = run.i;
+      const int p = (int)(g >> pshift);
       if (t0 + lj == 0 || g != gp) {
-        const int p = (int)(g >> pshift);
         const int64_t se = pstart ? 0 : run.e - dsv[j];
         const int64_t si = pstart ? 0 : (int64_t)run.i - div_[j];
         before[lj] = ((int64_t)psize[p] + se > omega || (int64_t)pinb[p] + si > delta) ? 1 : 0;
       }
+      if (g != gn && ((int64_t)psize[p] + run.e > omega || (int64_t)pinb[p] + run.i > delta)) after_bits |= 1u << j;
     }
   }
   __syncthreads();
-  const uint64_t g_first = kk[0] >> 2, g_last = kk[cnt - 1] >> 2;
+  const uint64_t g_first = (uint64_t)kk[0] >> 2, g_last = (uint64_t)kk[cnt - 1] >> 2;
 #pragma unroll
   for (int j = 0; j < EVS_IPT; ++j) {
     const int lj = j0 + j;
     if (lj >= cnt) continue;
-    const uint64_t g = kk[lj] >> 2;
-    const uint64_t gp = lj > 0 ? kk[lj - 1] >> 2 : g_prev;
-    const uint64_t gn = lj + 1 < cnt ? kk[lj + 1] >> 2 : g_next;
+    const uint64_t g = (uint64_t)kk[lj] >> 2;
+    const uint64_t gp = lj > 0 ? (uint64_t)kk[lj - 1] >> 2 : g_prev;
+    const uint64_t gn = lj + 1 < cnt ? (uint64_t)kk[lj + 1] >> 2 : g_next;
     const bool first = (t0 + lj == 0) || g != gp;
     const bool last = g != gn;
     const int q = (int)(g & qmask);
     int d = 0;
     if (last) {
-      const int p = (int)(g >> pshift);
-      const int after = ((int64_t)psize[p] + inc_e[j] > omega || (int64_t)pinb[p] + inc_i[j] > delta) ? 1 : 0;
+      const int after = (int)((after_bits >> j) & 1u);
       if (g == g_first && g == g_prev) {
         d = after;  // the group began in an earlier tile, which takes its before-state
       } else {
         int lo = 0, hi = lj;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if ((kk[mid] >> 2) < g) lo = mid + 1;
+          if (((uint64_t)kk[mid] >> 2) < g) lo = mid + 1;
           else hi = mid;
         }
         d = after - before[lo];
@@ -811,14 +811,12 @@ static void events_after_sort(const LevelView &L, const K *keys, int64_t nev, in
   (void)n_parts;
   const int ntiles = (int)div_up(nev, EVS_TILE);
   if ((int64_t)ntiles > B.cap_tiles) throw Error(-7, "event tile buffer overflow");
-  int64_t *agg_e = B.tile_e, *carry_e = B.tile_e + ntiles;
-  int32_t *agg_i = B.tile_i, *agg_f = B.tile_i + ntiles, *carry_i = B.tile_i + 2 * (int64_t)ntiles;
+  int64_t *agg_e = B.tile_e;
+  int32_t *agg_i = B.tile_i, *agg_f = B.tile_i + ntiles;
   k_evs_tiles<K><<<ntiles, EVS_NT, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, agg_e, agg_i, agg_f);
   HGP_LAUNCH_CHECK();
-  k_evs_carry<<<1, EVS_CARRY_NT, 0, s>>>(ntiles, agg_e, agg_i, agg_f, carry_e, carry_i);
-  HGP_LAUNCH_CHECK();
-  k_evs_trans<K><<<ntiles, EVS_NT, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, carry_e, carry_i, B.psize,
-                                           B.pinb, omega, delta, B.vdelta);
+  k_evs_trans<K><<<ntiles, EVS_NT, 0, s>>>(keys, nev, vshift, qmask, B.seq, rho, L.size, agg_e, agg_i, agg_f,
+                                           B.psize, B.pinb, omega, delta, B.vdelta);
   HGP_LAUNCH_CHECK();
 }
 
