@@ -86,23 +86,17 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
 // ---------------------------------------------------------------------------
 // (node, hedge|dst) pairs in hedge order, then a stable radix sort by node:
 // every I(n) comes out ascending by hedge id, with no contended atomics.
+// Per pin j: its node id as the sort key and (hedge | dst) << 32 | j as the
+// value, so the sort by node yields inc and perm together.
 __global__ void k_expand(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
-                         uint32_t *__restrict__ key, uint32_t *__restrict__ pos, uint32_t *__restrict__ he) {
+                         uint32_t *__restrict__ key, uint64_t *__restrict__ val) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= E) return;
   for (int j = hoff[wid] + lane_id(); j < hoff[wid + 1]; j += 64) {
     const uint32_t x = hpin[j];
     key[j] = x & kIdMask;
-    pos[j] = (uint32_t)j;
-    he[j] = (uint32_t)wid | (x & kDst);
+    val[j] = ((uint64_t)((uint32_t)wid | (x & kDst)) << 32) | (uint32_t)j;
   }
-}
-
-// inc[k] = (hedge | dst) of the pin at position perm[k]
-__global__ void k_gather_inc(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ he, int64_t P,
-                             uint32_t *__restrict__ inc) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < P) inc[k] = he[perm[k]];
 }
 
 // ioff[v] = first position of node v in the sorted keys (P if none after).
@@ -454,14 +448,12 @@ static int bits_of(int64_t x) {
 
 void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
                      int32_t *ioff, uint32_t *inc, uint32_t *perm, int32_t *indeg, int32_t *total, uint32_t *tkey,
-                     uint32_t *tkey2, uint32_t *tval2, uint32_t *he, DevBuf &sort_tmp, hipStream_t s) {
+                     uint32_t *tkey2, uint64_t *tval, uint64_t *tval2, DevBuf &sort_tmp, hipStream_t s) {
   KScope ks(5, s);
   if (E > 0 && P > 0) {
-    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, perm, he);
+    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, tval);
     HGP_LAUNCH_CHECK();
-    radix_sort_u32(tkey, tkey2, perm, tval2, P, bits_of(N > 0 ? N - 1 : 0), sort_tmp, s);
-    k_gather_inc<<<div_up(P, 256), 256, 0, s>>>(perm, he, P, inc);
-    HGP_LAUNCH_CHECK();
+    radix_sort_u32_split(tkey, tkey2, tval, tval2, P, bits_of(N > 0 ? N - 1 : 0), inc, perm, sort_tmp, s);
   }
   k_offsets_from_sorted<<<div_up(P + 1, 256), 256, 0, s>>>(tkey, P, N, ioff);
   HGP_LAUNCH_CHECK();

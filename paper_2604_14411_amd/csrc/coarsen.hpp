@@ -47,10 +47,10 @@ void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, 
                   uint32_t *hpin, hipStream_t s);
 // Incidence I(n) (ascending hedge ids, destination flag in bit 31), the pin
 // position perm[k] of every incidence k, |in(n)| and total(n) of a level;
-// tkey/tkey2/tval2/he are P-element scratch.
+// tkey/tkey2/tval/tval2 are P-element scratch.
 void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
                      int32_t *ioff, uint32_t *inc, uint32_t *perm, int32_t *indeg, int32_t *total, uint32_t *tkey,
-                     uint32_t *tkey2, uint32_t *tval2, uint32_t *he, DevBuf &sort_tmp, hipStream_t s);
+                     uint32_t *tkey2, uint64_t *tval, uint64_t *tval2, DevBuf &sort_tmp, hipStream_t s);
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
                      int32_t *err, hipStream_t s);
 // maxin: one device int32 of scratch (max |in(n)| of the level)

@@ -399,6 +399,11 @@ void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *val
 // (32-bit keys: bits [lo, bits) only; keys equal on them keep their order.)
 void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
                     DevBuf &tmp, hipStream_t s, int lo = 0);
+// Sorts 32-bit keys (bits [0, bits)) with 64-bit values, stable; the sorted
+// values are written as their high halves to out_hi and low halves to out_lo
+// (the keys end sorted in keys; vals and valt are overwritten).
+void radix_sort_u32_split(uint32_t *keys, uint32_t *alt, uint64_t *vals, uint64_t *valt, int64_t n, int bits,
+                          uint32_t *out_hi, uint32_t *out_lo, DevBuf &tmp, hipStream_t s);
 
 // Fill / iota helpers.
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

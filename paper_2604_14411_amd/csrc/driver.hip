@@ -65,7 +65,7 @@ struct CachedLevel {
 struct Workspace {
   DevBuf err, sums, scal2;
   DevBuf hpin0, hoffA, hoffB, hpinA, hpinB, hoffR, hpinR, tmp_pins, cnt;
-  DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval2, perm, pin_he;
+  DevBuf ioff, inc, indeg, total, work, tkey, tkey2, tval, tval2, perm;
   DevBuf pair, score, best, up, match, rep;
   DevBuf rhoA, rhoB, used, conn;
   DevBuf heavy, evoff, maxin, pt, ptc, lam, solo, psize, pinb, dest, gain, pos, flag, seq, keys, keys2, gp, vdelta, G, viol, scal;
@@ -115,7 +115,7 @@ struct Workspace {
 
   void release_all() {
     DevBuf *all[] = {&err,  &sums,  &scal2,  &hpin0,  &hoffA,    &hoffB,  &hpinA,  &hpinB,   &hoffR,   &hpinR,
-                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval2, &perm, &pin_he,   &pair,    &score,   &best,
+                     &tmp_pins, &cnt, &ioff, &inc,  &indeg,    &total,  &work, &tkey, &tkey2, &tval, &tval2, &perm,   &pair,    &score,   &best,
                      &up,   &match, &rep,    &rhoA,   &rhoB,     &used,   &conn,   &pt,      &ptc,     &lam, &heavy, &evoff, &maxin, &solo,
                      &psize, &pinb, &dest,   &gain,   &pos,      &flag,   &seq,    &keys,    &keys2,   &gp,
                      &vdelta, &contrib, &tile_e, &tile_i, &pt_partial, &G,     &viol,   &scal,     &scan_tmp, &sort_tmp, &in_off, &in_pins,
@@ -307,10 +307,10 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   int32_t *total = need<int32_t>(W.total, n);
   uint32_t *tkey = need<uint32_t>(W.tkey, P);
   uint32_t *tkey2 = need<uint32_t>(W.tkey2, P);
-  uint32_t *tval2 = need<uint32_t>(W.tval2, P);
+  uint64_t *tval = need<uint64_t>(W.tval, P);
+  uint64_t *tval2 = need<uint64_t>(W.tval2, P);
   uint32_t *perm = need<uint32_t>(W.perm, P);
-  uint32_t *he = need<uint32_t>(W.pin_he, P);
-  build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, perm, indeg, total, tkey, tkey2, tval2, he, W.sort_tmp, s);
+  build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, perm, indeg, total, tkey, tkey2, tval, tval2, W.sort_tmp, s);
   add_units(HGP_K_INCIDENCE, P);
   LevelView L;
   L.n = n;

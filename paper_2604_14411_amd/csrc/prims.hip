@@ -270,6 +270,17 @@ __device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, 
   __syncthreads();
 }
 
+template <class VT, bool SPLIT>
+__device__ __forceinline__ void rs_put_val(VT v, int64_t pos, VT *__restrict__ ovals, uint32_t *__restrict__ ohi,
+                                           uint32_t *__restrict__ olo) {
+  if constexpr (SPLIT) {
+    ohi[pos] = (uint32_t)((uint64_t)v >> 32);
+    olo[pos] = (uint32_t)v;
+  } else {
+    ovals[pos] = v;
+  }
+}
+
 // Stable scatter of one 4096-key tile.  Each wave loads its contiguous key
 // range into registers and ranks every key within its digit among the
 // wave's earlier keys (ballot match masks and a running per-wave count in
@@ -278,28 +289,31 @@ __device__ __forceinline__ void rs_tile_bases(const int32_t *__restrict__ offs, 
 // in LDS in digit order and written out so that each digit's run goes to
 // consecutive addresses; 64-bit keys go straight to their slots.
 // offs: scanned (digit, tile) offsets within each digit; dtot: digit totals.
-template <class K, bool V, bool STAGE, int DB>
-__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const uint32_t *__restrict__ vals,
+// VT: the value word; with SPLIT (64-bit values) the values are written as
+// their high and low halves to ohi / olo instead of to ovals.
+template <class K, bool V, bool STAGE, int DB, class VT = uint32_t, bool SPLIT = false>
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys, const VT *__restrict__ vals,
                                                       int64_t n, int shift, const int32_t *__restrict__ offs,
                                                       const int32_t *__restrict__ dtot, int ntiles,
-                                                      K *__restrict__ okeys, uint32_t *__restrict__ ovals) {
+                                                      K *__restrict__ okeys, VT *__restrict__ ovals,
+                                                      uint32_t *__restrict__ ohi, uint32_t *__restrict__ olo) {
   constexpr int RADIX = 1 << DB;
   __shared__ int32_t gbase[RADIX];
   __shared__ int32_t lstart[RADIX];
   __shared__ int32_t cw[RS_NT / 64][RADIX];
   __shared__ int32_t stmp[RS_NT / 64 + 1];
   __shared__ K lkeys[STAGE ? RS_TILE : 1];
-  __shared__ uint32_t lvals[(STAGE && V) ? RS_TILE : 1];
+  __shared__ VT lvals[(STAGE && V) ? RS_TILE : 1];
   const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
   const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
   const int64_t base = tbase + w * RS_WKEYS + l;
   K kr[RS_ROUNDS];
-  uint32_t vr[V ? RS_ROUNDS : 1];
+  VT vr[V ? RS_ROUNDS : 1];
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t j = base + r * 64;
     kr[r] = j < n ? keys[j] : K(0);
-    if (V) vr[r] = j < n ? vals[j] : 0u;
+    if (V) vr[r] = j < n ? vals[j] : VT(0);
   }
   for (int i = tid; i < RS_NT / 64 * RADIX; i += RS_NT) (&cw[0][0])[i] = 0;
   rs_tile_bases<RADIX>(offs, dtot, ntiles, gbase, stmp);  // its barriers also order the zeroing above
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
     } else {
       const int64_t pos = (int64_t)gbase[d] + within;
       okeys[pos] = kr[r];
-      if (V) ovals[pos] = vr[r];
+      if (V) rs_put_val<VT, SPLIT>(vr[r], pos, ovals, ohi, olo);
     }
   }
   if (STAGE) {
@@ -354,7 +368,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K *__restrict__ keys
       const uint32_t d = (uint32_t)(key >> shift) & (uint32_t)(RADIX - 1);
       const int64_t pos = (int64_t)gbase[d] + (i - lstart[d]);
       okeys[pos] = key;
-      if (V) ovals[pos] = lvals[i];
+      if (V) rs_put_val<VT, SPLIT>(lvals[i], pos, ovals, ohi, olo);
     }
   }
 }
@@ -369,9 +383,11 @@ static void radix_pass(const K *src, const uint32_t *vs, int64_t n, int shift, i
   // 32-bit keys are staged in LDS for coalesced runs; 64-bit keys go direct
   constexpr bool kStage = sizeof(K) == 4;
   if (vs)
-    k_rs_scatter<K, true, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
+    k_rs_scatter<K, true, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd,
+                                                               nullptr, nullptr);
   else
-    k_rs_scatter<K, false, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd);
+    k_rs_scatter<K, false, kStage, DB><<<ntiles, RS_NT, 0, s>>>(src, vs, n, shift, hist, dtot, ntiles, dst, vd,
+                                                                nullptr, nullptr);
   HGP_LAUNCH_CHECK();
 }
 
@@ -411,6 +427,53 @@ void radix_sort_u64(uint64_t *keys, uint64_t *alt, uint32_t *vals, uint32_t *val
 void radix_sort_u32(uint32_t *keys, uint32_t *alt, uint32_t *vals, uint32_t *valt, int64_t n, int bits,
                     DevBuf &tmp, hipStream_t s, int lo) {
   radix_sort_impl<uint32_t>(keys, alt, vals, valt, n, lo, bits > 32 ? 32 : bits, tmp, s);
+}
+
+__global__ void k_split_u64(const uint64_t *__restrict__ v, int64_t n, uint32_t *__restrict__ hi,
+                            uint32_t *__restrict__ lo) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    hi[i] = (uint32_t)(v[i] >> 32);
+    lo[i] = (uint32_t)v[i];
+  }
+}
+
+void radix_sort_u32_split(uint32_t *keys, uint32_t *alt, uint64_t *vals, uint64_t *valt, int64_t n, int bits,
+                          uint32_t *out_hi, uint32_t *out_lo, DevBuf &tmp, hipStream_t s) {
+  if (n <= 0) return;
+  constexpr int db = 8;
+  bits = bits > 32 ? 32 : bits;
+  if (n == 1 || bits <= 0) {
+    k_split_u64<<<div_up(n, 256), 256, 0, s>>>(vals, n, out_hi, out_lo);
+    HGP_LAUNCH_CHECK();
+    return;
+  }
+  const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
+  const int64_t hn = (int64_t)(1 << db) * ntiles;
+  const size_t hist_bytes = ((size_t)hn * sizeof(int32_t) + 255) & ~size_t(255);
+  tmp.reserve(hist_bytes + 1024 * sizeof(int32_t));
+  int32_t *hist = tmp.as<int32_t>();
+  int32_t *dtot = reinterpret_cast<int32_t *>(static_cast<char *>(tmp.ptr) + hist_bytes);
+  uint32_t *src = keys, *dst = alt;
+  uint64_t *vs = vals, *vd = valt;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += db, ++passes) {
+    const bool last = shift + db >= bits;
+    k_rs_hist<uint32_t, db><<<ntiles, RS_NT, 0, s>>>(src, n, shift, hist, ntiles);
+    HGP_LAUNCH_CHECK();
+    k_rs_dscan<<<1 << db, RS_NT, 0, s>>>(hist, ntiles, dtot);
+    HGP_LAUNCH_CHECK();
+    if (last)
+      k_rs_scatter<uint32_t, true, true, db, uint64_t, true><<<ntiles, RS_NT, 0, s>>>(
+          src, vs, n, shift, hist, dtot, ntiles, dst, nullptr, out_hi, out_lo);
+    else
+      k_rs_scatter<uint32_t, true, true, db, uint64_t, false><<<ntiles, RS_NT, 0, s>>>(
+          src, vs, n, shift, hist, dtot, ntiles, dst, vd, nullptr, nullptr);
+    HGP_LAUNCH_CHECK();
+    std::swap(src, dst);
+    std::swap(vs, vd);
+  }
+  if (passes & 1) HGP_HIP(hipMemcpyAsync(keys, src, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
 }
 
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
