@@ -471,7 +471,7 @@ static void trace_level(Workspace &W, const LevelView &L, int lvl, int32_t omega
   const int32_t n = L.n;
   if (n <= 0) return;
   CandBufs CB = cand_bufs(W, n, pair, score);
-  const int64_t C = build_candidates(L, W.total.as<int32_t>(), omega, delta, kCandK, CB, W.scan_tmp, W.sort_tmp, s);
+  const int64_t C = build_candidates(L, L.total, omega, delta, kCandK, CB, W.scan_tmp, W.sort_tmp, s);
   if (C <= 0) return;
   int32_t *xq = need<int32_t>(W.tr_xq, C * kMlpF);
   launch_cand_codes(L, omega, delta, lvl, CB, C, xq, s);
@@ -517,7 +517,10 @@ static void trace_label(hgp_trace &T, int32_t N, const int32_t *part) {
 
 // Keeps level `lvl` (view L over hoff/hpin with P pins) for refinement,
 // evicting the oldest kept levels beyond the budget.
-static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, hipStream_t s) {
+// The level's buffers move into the cache entry (hoff_buf / hpin_buf: the
+// workspace buffers that hold L.hoff / L.hpin), and the entry's recycled
+// buffers take their place in the workspace, so nothing is copied.
+static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, DevBuf &hoff_buf, DevBuf &hpin_buf) {
   const int32_t n = L.n, E = L.E;
   const int64_t bytes = 4 * ((int64_t)E + 1) + 12 * P + 4 * ((int64_t)n + 1) + 8 * (int64_t)n;
   if (bytes > W.lcache_budget) return;
@@ -537,17 +540,17 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, hi
   c->n = n;
   c->P = P;
   c->bytes = bytes;
-  auto cp = [&](DevBuf &dst, const void *src, size_t b) {
-    dst.reserve(b);
-    if (b) HGP_HIP(hipMemcpyAsync(dst.ptr, src, b, hipMemcpyDeviceToDevice, s));
+  auto take = [&](DevBuf &entry, DevBuf &work, const void *held) {
+    if (work.ptr != held) throw Error(HGP_EINTERNAL, "level buffer not held by the workspace");
+    std::swap(entry, work);
   };
-  cp(c->hoff, L.hoff, 4 * ((size_t)E + 1));
-  cp(c->hpin, L.hpin, 4 * (size_t)P);
-  cp(c->ioff, L.ioff, 4 * ((size_t)n + 1));
-  cp(c->inc, L.inc, 4 * (size_t)P);
-  cp(c->perm, L.perm, 4 * (size_t)P);
-  cp(c->indeg, L.indeg, 4 * (size_t)n);
-  cp(c->total, L.total, 4 * (size_t)n);
+  take(c->hoff, hoff_buf, L.hoff);
+  take(c->hpin, hpin_buf, L.hpin);
+  take(c->ioff, W.ioff, L.ioff);
+  take(c->inc, W.inc, L.inc);
+  take(c->perm, W.perm, L.perm);
+  take(c->indeg, W.indeg, L.indeg);
+  take(c->total, W.total, L.total);
   W.lcache_bytes += bytes;
   W.lcache.push_back(std::move(c));
 }
@@ -663,7 +666,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
           // carried from the previous level)
           if (!lists_fresh) {
             path = "learned, topk";
-            launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
+            launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
             lists_ok = true;
           } else {
             path = "learned, incremental";
@@ -675,17 +678,17 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
           const int64_t C = candidate_sets(L, CB, W.scan_tmp, W.sort_tmp, s);
           score_and_select(L, omega, delta, lvl, mlp_params, CB, C, s);
         } else {
-          learned_candidates(L, W.total.as<int32_t>(), omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
+          learned_candidates(L, L.total, omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
                              W.sort_tmp, s);
           lists_ok = false;
         }
         lists_fresh = false;
       } else if (incremental && tail) {
         path = "topk";
-        launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
+        launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
         lists_ok = true;
       } else {
-        launch_rate(L, W.total.as<int32_t>(), omega, delta, pair, score, need<int32_t>(W.maxin, 1), s,
+        launch_rate(L, L.total, omega, delta, pair, score, need<int32_t>(W.maxin, 1), s,
                     W.rate_tile);
         lists_ok = false;
       }
@@ -743,8 +746,12 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       HGP_HIP(hipMemcpyAsync(Gm, gam, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
     else
       launch_project(W.lv_Gamma[lvl - 1].as<int32_t>(), gam, N, Gm, s);
-    int32_t *nh = ping ? W.hoffB.as<int32_t>() : W.hoffA.as<int32_t>();
-    uint32_t *npin = ping ? W.hpinB.as<uint32_t>() : W.hpinA.as<uint32_t>();
+    // the contracted level (at most cur_P pins) goes to the other ping-pong
+    // pair, which a cached level may have replaced by a smaller buffer
+    DevBuf &hoff_buf = ping ? W.hoffB : W.hoffA;
+    DevBuf &hpin_buf = ping ? W.hpinB : W.hpinA;
+    int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
+    uint32_t *npin = need<uint32_t>(hpin_buf, cur_P);
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
                     W.scan_tmp, s);
     add_units(HGP_K_CONTRACT, cur_P);
@@ -754,18 +761,18 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     ping ^= 1;
     ++lvl;
     L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s);
-    cache_level(W, L, lvl, cur_P, s);
+    cache_level(W, L, lvl, cur_P, hoff_buf, hpin_buf);
     tail = (int64_t)M * kTailRatio <= (int64_t)n;
     if (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget) {
       // rate level lvl incrementally from the lists of level lvl-1
       launch_new_clusters(lmatch, gam, n, n_next, nflag, newc, row_slot, W.scan_tmp, s);
       fill_i64(dcnt, 1, M, s);
-      const uint64_t *rows = launch_rate_topk_rows(L, W.total.as<int32_t>(), omega, delta, newc, dcnt, M, row_slot,
+      const uint64_t *rows = launch_rate_topk_rows(L, L.total, omega, delta, newc, dcnt, M, row_slot,
                                                    pair, score, tk_nxt, W.tail_acc, s);
       fill_i64(dcnt + 1, 1, 0, s);
       launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, learned ? opt.mlp->k : 1, tk_nxt, pair,
                          score, rerate, dcnt + 1, s);
-      launch_rate_topk(L, W.total.as<int32_t>(), omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
+      launch_rate_topk(L, L.total, omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
       have_pairs = !learned;
       lists_fresh = learned;
       lists_ok = true;
@@ -1409,7 +1416,7 @@ int hgp_level_learned(hgp_ctx *ctx, const hgp_level *lv, int32_t level, int32_t 
     int32_t *lp = need<int32_t>(W.pair, n);
     int64_t *ls = need<int64_t>(W.score, n);
     CandBufs B = cand_bufs(W, n, lp, ls);
-    const int64_t C = learned_candidates(L, W.total.as<int32_t>(), omega, delta, level, mlp->k, params, B,
+    const int64_t C = learned_candidates(L, L.total, omega, delta, level, mlp->k, params, B,
                                          W.scan_tmp, W.sort_tmp, s);
     if (C > cap) throw Error(HGP_EINVAL, "candidate capacity too small");
     HGP_HIP(hipMemcpyAsync(coff, B.coff, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
