@@ -275,27 +275,40 @@ void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, c
 // ---------------------------------------------------------------------------
 // sequence: moves sorted by (gain, id) descending (Sec. IV-A)
 // ---------------------------------------------------------------------------
-__global__ void k_move_flags(const int32_t *__restrict__ dest, int32_t N, int32_t *__restrict__ flag,
-                             int32_t *__restrict__ pos) {
+// Move flags, and the largest proposed gain into *gmax (zeroed by the caller).
+__global__ void k_move_flags(const int32_t *__restrict__ dest, const int32_t *__restrict__ gain, int32_t N,
+                             int32_t *__restrict__ flag, int32_t *__restrict__ pos,
+                             unsigned long long *__restrict__ gmax) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t g = 0;
   if (n < N) {
-    flag[n] = dest[n] >= 0 ? 1 : 0;
+    const bool mv = dest[n] >= 0;
+    flag[n] = mv ? 1 : 0;
     pos[n] = 0;
+    if (mv) g = gain[n];
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) g = max(g, __shfl_xor(g, o, 64));
+  if (lane_id() == 0 && g > 0) atomicMax(gmax, (unsigned long long)g);
 }
 
+// Sequence order (Sec. IV-B): gain descending, then node id descending; the
+// key is (gmax - gain) << idbits | (N - 1 - n), ascending.
+template <class K>
 __global__ void k_move_keys(const int32_t *__restrict__ dest, const int32_t *__restrict__ gain,
-                            const int32_t *__restrict__ off, int32_t N, int idbits, uint64_t *__restrict__ keys) {
+                            const int32_t *__restrict__ off, int32_t N, int idbits, int32_t gmax,
+                            K *__restrict__ keys) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < N && dest[n] >= 0)
-    keys[off[n]] = ((uint64_t)(uint32_t)(0x7fffffff - gain[n]) << idbits) | (uint64_t)(uint32_t)(N - 1 - n);
+    keys[off[n]] = (K)(((uint64_t)(uint32_t)(gmax - gain[n]) << idbits) | (uint64_t)(uint32_t)(N - 1 - n));
 }
 
-__global__ void k_seq_from_keys(const uint64_t *__restrict__ keys, int64_t S, int32_t N, int idbits,
+template <class K>
+__global__ void k_seq_from_keys(const K *__restrict__ keys, int64_t S, int32_t N, int idbits,
                                 int32_t *__restrict__ seq, int32_t *__restrict__ pos) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < S) {
-    const int n = N - 1 - (int)(keys[i] & ((1ull << idbits) - 1ull));
+    const int n = N - 1 - (int)((uint64_t)keys[i] & ((1ull << idbits) - 1ull));
     seq[i] = n;
     pos[n] = (int32_t)(i + 1);
   }
@@ -347,19 +360,34 @@ int bits_for(int64_t x) {
 int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s) {
   const int32_t N = L.n;
   if (N <= 0) return 0;
-  k_move_flags<<<div_up(N, 256), 256, 0, s>>>(B.dest, N, B.flag, B.pos);
+  fill_i64(B.scal + SC_GMAX, 1, 0, s);
+  k_move_flags<<<div_up(N, 256), 256, 0, s>>>(B.dest, B.gain, N, B.flag, B.pos,
+                                              reinterpret_cast<unsigned long long *>(B.scal + SC_GMAX));
   HGP_LAUNCH_CHECK();
   scan_i32(B.flag, B.flag, N, reinterpret_cast<int32_t *>(B.scal + SC_S), scan_tmp, s);
+  // |S| and the largest gain in one round trip
   int32_t S32 = 0;
+  int64_t gmax = 0;
   HGP_HIP(hipMemcpyAsync(&S32, B.scal + SC_S, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&gmax, B.scal + SC_GMAX, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
   const int64_t S = S32;
   if (S == 0) return 0;
   const int idbits = bits_for(N - 1) > 0 ? bits_for(N - 1) : 1;
-  k_move_keys<<<div_up(N, 256), 256, 0, s>>>(B.dest, B.gain, B.flag, N, idbits, B.keys);
-  HGP_LAUNCH_CHECK();
-  sort_keys(B.keys, B.keys2, S, 31 + idbits, sort_tmp, s);
-  k_seq_from_keys<<<div_up(S, 256), 256, 0, s>>>(B.keys, S, N, idbits, B.seq, B.pos);
+  const int gbits = bits_for(gmax);
+  const int bits = gbits + idbits;
+  if (bits <= 32) {
+    uint32_t *k32 = reinterpret_cast<uint32_t *>(B.keys);
+    k_move_keys<uint32_t><<<div_up(N, 256), 256, 0, s>>>(B.dest, B.gain, B.flag, N, idbits, (int32_t)gmax, k32);
+    HGP_LAUNCH_CHECK();
+    sort_keys32(k32, reinterpret_cast<uint32_t *>(B.keys2), S, bits, sort_tmp, s, 0);
+    k_seq_from_keys<uint32_t><<<div_up(S, 256), 256, 0, s>>>(k32, S, N, idbits, B.seq, B.pos);
+  } else {
+    k_move_keys<uint64_t><<<div_up(N, 256), 256, 0, s>>>(B.dest, B.gain, B.flag, N, idbits, (int32_t)gmax, B.keys);
+    HGP_LAUNCH_CHECK();
+    sort_keys(B.keys, B.keys2, S, bits, sort_tmp, s);
+    k_seq_from_keys<uint64_t><<<div_up(S, 256), 256, 0, s>>>(B.keys, S, N, idbits, B.seq, B.pos);
+  }
   HGP_LAUNCH_CHECK();
   return S;
 }
