@@ -143,6 +143,10 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // Proposals for every node, or for list[0 .. *count) when list is non-null.
 void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho, int32_t n_parts, int32_t omega,
                     RoundBufs &B, hipStream_t s, const int32_t *list = nullptr, const int64_t *count = nullptr);
+// Zeroes the round's device scalars (see k_round_reset); first launch of a
+// refinement round.
+void launch_round_reset(RoundBufs &B, int32_t E, int64_t *cnt, hipStream_t s);
+// *cnt must be zero (launch_round_reset).
 void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, const int32_t *cdest,
                         const int32_t *cgain, RoundBufs &B, int32_t *list, int64_t *cnt, hipStream_t s);
 // Builds the sequence; returns |S| (host sync).

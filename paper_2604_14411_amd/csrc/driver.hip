@@ -376,11 +376,12 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
                                 const Carry *carry = nullptr) {
   RoundBufs B = round_bufs(W, L.n, L.E, P, n_parts);
   int32_t *err = W.err.as<int32_t>();
+  int64_t *cnt = carry ? need<int64_t>(W.dev_cnt, 4) : nullptr;
+  launch_round_reset(B, L.E, cnt, s);
   launch_part_table(L, rho, n_parts, B, err, s);
   add_units(HGP_K_PARTTABLE, P);
   if (carry) {
     int32_t *list = need<int32_t>(W.split, L.n);
-    int64_t *cnt = need<int64_t>(W.dev_cnt, 4);
     launch_prop_gather(L.n, carry->match, carry->gamma, W.cdest.as<int32_t>(), W.cgain.as<int32_t>(), B, list, cnt,
                        s);
     launch_propose(L, L.total, rho, n_parts, omega, B, s, list, cnt);
@@ -869,10 +870,12 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       if (!R.applied) {
         // the state is unchanged: these proposals hold for it
         if (incremental && n > 0) {
-          HGP_HIP(hipMemcpyAsync(W.cdest.as<int32_t>(), B.dest, sizeof(int32_t) * (size_t)n,
-                                 hipMemcpyDeviceToDevice, s));
-          HGP_HIP(hipMemcpyAsync(W.cgain.as<int32_t>(), B.gain, sizeof(int32_t) * (size_t)n,
-                                 hipMemcpyDeviceToDevice, s));
+          // the round's proposal buffers become the carried ones (B.dest and
+          // B.gain are W.dest and W.gain)
+          if (B.dest != W.dest.as<int32_t>() || B.gain != W.gain.as<int32_t>())
+            throw Error(HGP_EINTERNAL, "proposal buffers");
+          std::swap(W.cdest, W.dest);
+          std::swap(W.cgain, W.gain);
         }
         break;
       }

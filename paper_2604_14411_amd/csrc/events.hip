@@ -926,11 +926,7 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   const int kbits = vshift + pbits;
   const bool narrow = kbits <= 32;
   uint32_t *k32 = reinterpret_cast<uint32_t *>(B.keys);
-  fill_i32(B.vdelta, S + 1, 0, s);
-  fill_i32(B.gp, 1, 0, s);
-  fill_i64(B.scal + SC_INVALID0, 1, 0, s);
-  fill_i64(B.scal + SC_HEAVY, 1, 0, s);
-  fill_i64(B.evoff + L.E, 1, 0, s);
+  fill_i32(B.vdelta, S + 1, 0, s);  // the round's scalars were reset by launch_round_reset
   if (S > 0) {
     KScope ks(kClsEvents, s);
     if (L.E > 0) {

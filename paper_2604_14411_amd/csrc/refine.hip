@@ -233,8 +233,7 @@ void launch_propose(const LevelView &L, const int32_t *total, const int32_t *rho
   KScope ks(1, s);
   const int grid = list ? (L.n < PROP_GRID ? L.n : PROP_GRID) : L.n;
   // heavy nodes queue into flag (free until the sequence is built)
-  int64_t *hcnt = B.scal + SC_PHEAVY;
-  fill_i64(hcnt, 1, 0, s);
+  int64_t *hcnt = B.scal + SC_PHEAVY;  // zeroed by launch_round_reset
   k_propose<PROP_NT, 4, true><<<grid, PROP_NT, (size_t)words * 4, s>>>(
       list, count, L.n, L.ioff, L.inc, L.perm, L.hoff, B.pt, B.solo, B.lam, L.hw, rho, L.size, B.psize, total, n_parts,
       omega, words, B.dest, B.gain, B.flag, reinterpret_cast<unsigned long long *>(hcnt), units_ptr(1));
@@ -264,9 +263,29 @@ __global__ void k_prop_gather(int32_t n, const int32_t *__restrict__ match, cons
   }
 }
 
+// The round's device scalars in one launch: heavy-node and heavy-hedge
+// counters, the largest gain, the initially invalid parts, g'(0), the end of
+// the event-count scan and (when given) the count of nodes to propose.
+__global__ void k_round_reset(int64_t *__restrict__ scal, int32_t *__restrict__ gp, int64_t *__restrict__ evoff_end,
+                              int64_t *__restrict__ cnt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    scal[SC_INVALID0] = 0;
+    scal[SC_HEAVY] = 0;
+    scal[SC_PHEAVY] = 0;
+    scal[SC_GMAX] = 0;
+    gp[0] = 0;
+    *evoff_end = 0;
+    if (cnt) *cnt = 0;
+  }
+}
+
+void launch_round_reset(RoundBufs &B, int32_t E, int64_t *cnt, hipStream_t s) {
+  k_round_reset<<<1, 64, 0, s>>>(B.scal, B.gp, B.evoff + E, cnt);
+  HGP_LAUNCH_CHECK();
+}
+
 void launch_prop_gather(int32_t n, const int32_t *match, const int32_t *gamma, const int32_t *cdest,
                         const int32_t *cgain, RoundBufs &B, int32_t *list, int64_t *cnt, hipStream_t s) {
-  fill_i64(cnt, 1, 0, s);
   if (n <= 0) return;
   k_prop_gather<<<div_up(n, 256), 256, 0, s>>>(n, match, gamma, cdest, cgain, B.dest, B.gain, list, cnt);
   HGP_LAUNCH_CHECK();
@@ -360,7 +379,6 @@ int bits_for(int64_t x) {
 int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s) {
   const int32_t N = L.n;
   if (N <= 0) return 0;
-  fill_i64(B.scal + SC_GMAX, 1, 0, s);
   k_move_flags<<<div_up(N, 256), 256, 0, s>>>(B.dest, B.gain, N, B.flag, B.pos,
                                               reinterpret_cast<unsigned long long *>(B.scal + SC_GMAX));
   HGP_LAUNCH_CHECK();
