@@ -211,9 +211,8 @@ __device__ __forceinline__ int rs_wave_rank(bool valid, uint32_t d, uint64_t lt,
 // waves' digit counts are combined once.
 constexpr int RS_WKEYS = RS_ROUNDS * 64;
 
-// Digit counts of one 4096-key tile, without atomics: per wave and round,
-// the last lane of each digit group (ballot match masks) adds the group's
-// size to the wave's counter.  All of the tile's loads are issued first.
+// Digit counts of one 4096-key tile: LDS atomics on per-wave counters.  All of
+// the tile's loads are issued first.
 // hist is digit-major: hist[d * ntiles + tile].
 template <class K, int DB>
 __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, int64_t n, int shift,
@@ -230,15 +229,13 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist(const K *__restrict__ keys, i
     kr[r] = j < n ? keys[j] : K(0);
   }
   __syncthreads();
-  const uint64_t lt = (l == 0) ? 0ull : ((~0ull) >> (64 - l));
+  // LDS atomics on the wave's own counters (lanes of one digit serialise in
+  // the LDS unit, but no ranks are needed here)
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const bool valid = base + r * 64 < n;
     const uint32_t d = (uint32_t)(kr[r] >> shift) & (uint32_t)(RADIX - 1);
-    int cnt;
-    const int rank = rs_wave_rank<DB>(valid, d, lt, &cnt);
-    if (valid && rank == cnt - 1) cw[w][d] += cnt;
-    wave_lds_sync();
+    if (valid) atomicAdd(&cw[w][d], 1);
   }
   __syncthreads();
   for (int d = tid; d < RADIX; d += RS_NT) {
