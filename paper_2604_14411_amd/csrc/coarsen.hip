@@ -109,18 +109,34 @@ __global__ void k_offsets_from_sorted(const uint32_t *__restrict__ key, int64_t 
   for (int64_t v = prev + 1; v <= cur; ++v) ioff[v] = (int32_t)j;
 }
 
-// |in(n)| and total(n) = sum of w(e) over I(n), one wave per node.
+// |in(n)| and total(n) = sum of w(e) over I(n), one wave per node; four
+// incidences per lane are loaded before their weights are gathered.
 __global__ void k_node_stats(const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
                              const int32_t *__restrict__ hw, int32_t N, int32_t *__restrict__ indeg,
                              int32_t *__restrict__ total) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   if (wid >= N) return;
+  const int a = ioff[wid], z = ioff[wid + 1], l = lane_id();
   int64_t s = 0;
   int d = 0;
-  for (int i = ioff[wid] + lane_id(); i < ioff[wid + 1]; i += 64) {
-    const uint32_t x = inc[i];
-    s += hw[x & kIdMask];
-    d += (int)(x >> 31);
+  for (int c = a; c < z; c += 64 * 4) {
+    uint32_t x[4];
+    int32_t we[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = c + 64 * u + l;
+      x[u] = i < z ? inc[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = c + 64 * u + l;
+      we[u] = i < z ? hw[x[u] & kIdMask] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s += we[u];
+      d += (int)(x[u] >> 31);
+    }
   }
   s = wave_sum(s);
   d = wave_sum(d);
