@@ -3,6 +3,8 @@
 // validity per prefix, the best valid prefix, projection and Eq. 1.
 #include "coarsen.hpp"
 
+#include <algorithm>
+
 namespace hgp {
 
 constexpr int PT_NT = 256;
@@ -81,6 +83,25 @@ __global__ void k_part_size(const int32_t *__restrict__ rho, const int32_t *__re
   if (n < N) atomicAdd(&psize[rho[n]], size[n]);
 }
 
+// As k_part_size for n_parts <= PS_LDS_PARTS: each workgroup sums its nodes in
+// an LDS histogram first, so a part gets one global atomic per workgroup
+// (with few parts the per-node atomics all hit the same few addresses; with
+// many, the flush of every workgroup's histogram would cost more than it saves).
+constexpr int PS_LDS_PARTS = 1024;
+constexpr int PS_GRID = 512;
+__global__ __launch_bounds__(256) void k_part_size_lds(const int32_t *__restrict__ rho,
+                                                       const int32_t *__restrict__ size, int32_t N, int32_t n_parts,
+                                                       int32_t *__restrict__ psize) {
+  extern __shared__ int32_t h[];
+  for (int p = threadIdx.x; p < n_parts; p += 256) h[p] = 0;
+  __syncthreads();
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < N; n += (int64_t)gridDim.x * 256)
+    atomicAdd(&h[rho[n]], size[n]);
+  __syncthreads();
+  for (int p = threadIdx.x; p < n_parts; p += 256)
+    if (h[p]) atomicAdd(&psize[p], h[p]);
+}
+
 void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, RoundBufs &B, int32_t *err,
                        hipStream_t s) {
   fill_i32(B.psize, n_parts, 0, s);
@@ -97,7 +118,12 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     }
   }
   if (L.n > 0 && L.size) {
-    k_part_size<<<div_up(L.n, 256), 256, 0, s>>>(rho, L.size, L.n, B.psize);
+    if (n_parts > 0 && n_parts <= PS_LDS_PARTS) {
+      const int grid = (int)std::min<int64_t>(div_up(L.n, 1024), PS_GRID);
+      k_part_size_lds<<<grid, 256, (size_t)n_parts * 4, s>>>(rho, L.size, L.n, n_parts, B.psize);
+    } else {
+      k_part_size<<<div_up(L.n, 256), 256, 0, s>>>(rho, L.size, L.n, B.psize);
+    }
     HGP_LAUNCH_CHECK();
   }
 }
