@@ -470,12 +470,25 @@ __global__ void k_cand_select(const uint64_t *__restrict__ cnm, const int32_t *_
   const uint64_t mask = (1ull << idbits) - 1ull;
   int best_m = -1;
   int32_t best_s = 0;
-  for (int64_t i = coff[n]; i < coff[n + 1]; ++i) {
-    const int m = (int)(cnm[i] & mask);
-    const int32_t s = cs[i];
-    if (best_m < 0 || s > best_s || (s == best_s && m > best_m)) {
-      best_m = m;
-      best_s = s;
+  const int64_t a = coff[n], z = coff[n + 1];
+  // four candidates' loads in flight before they are compared, in order
+  for (int64_t c = a; c < z; c += 4) {
+    uint64_t km[4];
+    int32_t ks[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      km[u] = c + u < z ? cnm[c + u] : 0ull;
+      ks[u] = c + u < z ? cs[c + u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c + u >= z) break;
+      const int m = (int)(km[u] & mask);
+      const int32_t s = ks[u];
+      if (best_m < 0 || s > best_s || (s == best_s && m > best_m)) {
+        best_m = m;
+        best_s = s;
+      }
     }
   }
   pair[n] = best_m;
