@@ -254,32 +254,60 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
     kap = (kap & 0xffffffff00000000ull) | (match[m9] == m9 ? (uint64_t)(uint32_t)gamma[m9] : 0xffffffffull);
   }
   const int c0 = old_cnt[n];
-  // surviving old candidates, renamed (already in descending key order)
+  // surviving old candidates, renamed (already in descending key order);
+  // four at a time, each round of gathers issued before the next
   int k = 0;
-  for (int q = 0; q < c0; ++q) {
-    const uint64_t key = old_key[n * kTopK + q];
-    const int m = (int)(key & 0xffffffffull);
-    if (match[m] != m) continue;
-    const uint64_t nk = (key & 0xffffffff00000000ull) | (uint64_t)(uint32_t)gamma[m];
-    const int32_t cm = old_c[n * kTopK + q];
+  for (int q0 = 0; q0 < c0; q0 += 4) {
+    uint64_t key[4];
+    int32_t cm[4], mt[4], gm[4];
 #pragma unroll
-    for (int z = 0; z < kTopK; ++z)
-      if (z == k) {
-        a[z] = nk;
-        ac[z] = cm;
-      }
-    ++k;
+    for (int u = 0; u < 4; ++u) {
+      const bool in = q0 + u < c0;
+      key[u] = in ? old_key[n * kTopK + q0 + u] : 0ull;
+      cm[u] = in ? old_c[n * kTopK + q0 + u] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mt[u] = q0 + u < c0 ? match[(int)(key[u] & 0xffffffffull)] : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = (int)(key[u] & 0xffffffffull);
+      gm[u] = (q0 + u < c0 && mt[u] == m) ? gamma[m] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = (int)(key[u] & 0xffffffffull);
+      if (q0 + u >= c0 || mt[u] != m) continue;
+      const uint64_t nk = (key[u] & 0xffffffff00000000ull) | (uint64_t)(uint32_t)gm[u];
+#pragma unroll
+      for (int z = 0; z < kTopK; ++z)
+        if (z == k) {
+          a[z] = nk;
+          ac[z] = cm[u];
+        }
+      ++k;
+    }
   }
-  // offers from the new clusters (keys above kappa only)
-  for (int j = 0; j < n_new; ++j) {
-    const uint64_t v = rows[(int64_t)j * n_coarse + nc];
-    const uint64_t h = v & 0xffffffffull;
-    if (h == 0) continue;
-    uint64_t x = cand_key(h, (uint32_t)newc[j]);
-    if (x <= kap) continue;
-    int32_t xc = (int32_t)(v >> 32);
-    list_insert<kTopK>(a, ac, x, xc);
-    if (x > kap) kap = x;  // evicted (0 if the list had room)
+  // offers from the new clusters (keys above kappa only), in cluster order,
+  // four rows loaded at a time
+  for (int j0 = 0; j0 < n_new; j0 += 4) {
+    uint64_t v[4];
+    uint32_t id[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool in = j0 + u < n_new;
+      v[u] = in ? rows[(int64_t)(j0 + u) * n_coarse + nc] : 0ull;
+      id[u] = in ? (uint32_t)newc[j0 + u] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t h = v[u] & 0xffffffffull;
+      if (h == 0) continue;  // also the slots past n_new
+      uint64_t x = cand_key(h, id[u]);
+      if (x <= kap) continue;
+      int32_t xc = (int32_t)(v[u] >> 32);
+      list_insert<kTopK>(a, ac, x, xc);
+      if (x > kap) kap = x;  // evicted (0 if the list had room)
+    }
   }
   int cnt = 0;
 #pragma unroll
