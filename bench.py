@@ -37,7 +37,7 @@ COST = {
     "part_table": ("hbm", 16.0),
     "seq_events": ("hbm", 1.0),  # units are algorithmic bytes: 4 per pin, 16 per event
     "contract": ("hbm", 16.0),
-    "incidence": ("hbm", 8.0),
+    "incidence": ("hbm", 12.0),  # pins read, incidences and their pin positions written
     "sort": ("hbm", 32.0),
     "match": ("hbm", 20.0),
     "mlp": ("hbm", 52.0),
