@@ -141,8 +141,9 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
 // is kept if gain > 0.  With DEFER, nodes of more than kPropHeavyDeg
 // incidences are only queued (hlist, *hcnt): the second launch gives each of
 // them a workgroup of many more waves, since a few such nodes (large clusters
-// at coarse levels) would otherwise decide the whole launch's duration.
-constexpr int kPropHeavyDeg = 2 * PROP_NT;
+// at coarse levels) would otherwise decide the whole launch's duration (128
+// measured best against 256 and 512 on the random and layered networks).
+constexpr int kPropHeavyDeg = PROP_NT / 2;
 template <int NT, int U, bool DEFER>
 __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list, const int64_t *__restrict__ count,
                                                 int32_t N, const int32_t *__restrict__ ioff,
