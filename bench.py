@@ -5,10 +5,12 @@ One step = one full hgp_partition_device call (coarsening + refinement +
 connectivity) on a device-resident synthetic spiking-network hypergraph.
 Prints one JSON line on stdout; progress goes to stderr.
 
-    python bench.py [--steps K] [--warmup W] [--workload rand64k] [--mlp CHECKPOINT]
+    python bench.py [--steps K] [--warmup W] [--workload conv302k] [--mlp CHECKPOINT | --plain]
 
-With --mlp the timed steps use the learned merge proposal; the plain method
-is then timed on the same input too and the line reports both connectivities.
+By default the timed steps use the learned merge proposal (the committed
+checkpoint) on the 302,400-node layered network; the plain method is then
+timed on the same input (--plain-steps runs) as the judge of its
+connectivity, and the line reports both.  --plain times the plain method.
 """
 from __future__ import annotations
 
@@ -75,21 +77,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample_n: int, mu: float, omega: int, delta: int):
-    import oracle
-    from paper_2604_14411_amd import synth
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    threads = os.cpu_count() or 1
-    oracle.set_threads(threads)
-    g = synth.random_snn(sample_n, mu, 2, 1, 16)
-    t = time.perf_counter()
-    rc, _, res, _ = oracle.partition(g, omega, delta)
-    dt = time.perf_counter() - t
-    assert rc == 0
-    return dict(value=g.n_pins / dt, unit="pins/s", cores=threads, kind="oracle",
-                sample=f"CPU oracle, whole partition of a reduced random SNN from the same generator: "
-                       f"n={sample_n}, |T_v|~Poisson({mu:g})+1, w in [1,16], seed 2, Omega={omega}, Delta={delta}; "
-                       f"{g.n_pins} pins, {res['n_levels']} levels, {dt:.1f} s")
+
+def cpu_baseline(w, mlp, threads_multi: int):
+    """The CPU oracle on a bounded sample of the benchmarked workload: the same
+    generator and bounds at a reduced size (Workload.sample), with the same
+    proposal as the timed steps; all host threads, then one thread on a
+    smaller sample.  The oracle is test infrastructure and runs only here."""
+    import oracle
+
+    sample, note, single = w.sample, w.sample_note, w.single_sample
+    g = sample()
+    oracle.set_threads(threads_multi)
+
+    def run(graph):
+        t = time.perf_counter()
+        if mlp is not None:
+            rc, _, res, _ = oracle.partition_learned(graph, w.omega, w.delta, mlp)
+        else:
+            rc, _, res, _ = oracle.partition(graph, w.omega, w.delta)
+        dt = time.perf_counter() - t
+        assert rc == 0, rc
+        return dt, res
+
+    dt, res = run(g)
+    out = dict(value=g.n_pins / dt, unit="pins/s", cores=threads_multi, kind="oracle",
+               proposal="learned" if mlp is not None else "plain",
+               sample=f"CPU oracle, whole partition of {note}: {g.n_nodes} nodes, {g.n_pins} pins, "
+                      f"sum|e|^2 {g.sum_sq():.3e}, Omega={w.omega}, Delta={w.delta}; {res['n_levels']} levels, "
+                      f"{dt:.1f} s on {threads_multi} threads",
+               seconds=dt, levels=res["n_levels"], sample_pins=g.n_pins, sample_sum_e_sq=g.sum_sq(),
+               nproc=os.cpu_count(), cpu_model=_cpu_model())
+    if single is not None:
+        g1 = single[0]()
+        oracle.set_threads(1)
+        dt1, res1 = run(g1)
+        out["single_thread"] = dict(value=g1.n_pins / dt1, unit="pins/s", cores=1, seconds=dt1,
+                                    sample=f"{single[1]}: {g1.n_nodes} nodes, {g1.n_pins} pins, "
+                                           f"{res1['n_levels']} levels")
+        oracle.set_threads(threads_multi)
+    return out
 
 
 def bench_batch(args):
@@ -147,16 +183,22 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+DEFAULT_MLP = os.path.join(ROOT, "paper_2604_14411_amd", "mlp_v2.json")
+METRIC = "pins/s (\u03a3|e|/s) partition throughput + connectivity, learned vs plain at \u03a9,\u0394"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rand64k")
-    ap.add_argument("--cpu-sample-n", type=int, default=3072)
+    ap.add_argument("--workload", default="conv302k")
+    ap.add_argument("--plain", action="store_true", help="time the plain method only (no learned proposal)")
+    ap.add_argument("--plain-steps", type=int, default=1,
+                    help="timed runs of the plain method, the judge of the learned result, on the same input")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only copy this many bytes on the device (profiling)")
-    ap.add_argument("--mlp", default=None, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
+    ap.add_argument("--mlp", default=DEFAULT_MLP, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
     args = ap.parse_args()
     if args.workload == "batch256":
         # one hardware queue per batch worker stream (HIP's default is 4);
@@ -189,15 +231,17 @@ def main():
         return bench_batch(args)
 
     w = WORKLOADS[args.workload]
+    t = time.perf_counter()
     g = w.make()
-    log(f"[bench] workload {w.name}: {w.note}; n={g.n_nodes} pins={g.n_pins}")
+    log(f"[bench] workload {w.name}: {w.note}; n={g.n_nodes} pins={g.n_pins} "
+        f"(generated in {time.perf_counter() - t:.1f} s)")
     ctx = hgp.Context(0)
     dg = hgp.DeviceHypergraph(g, "cuda:0")
     out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
 
-    def run(mlp, tag):
-        for i in range(args.warmup):
+    def run(mlp, tag, warmup, steps):
+        for i in range(warmup):
             t = time.perf_counter()
             _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, mlp=mlp)
             log(f"[bench] {tag} warmup {i}: {time.perf_counter() - t:.3f} s levels={res['n_levels']} "
@@ -205,28 +249,29 @@ def main():
         results = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, flags=hgp.FLAG_TIME_KERNELS, mlp=mlp)
             results.append(res)
-            log(f"[bench] {tag} step {i}: levels={res['n_levels']} rounds={res['n_rounds']} "
+            log(f"[bench] {tag} step {i}: levels={res['n_levels']} rounds={res['n_rounds']} parts={res['n_parts']} "
                 f"conn={res['connectivity']} fallback={res['n_fallback']}")
         torch.cuda.synchronize()
         return time.perf_counter() - t0, results
 
-    plain_cmp = None
-    if args.mlp:
+    q = None
+    if not args.plain:
         from paper_2604_14411_amd.learn import load_checkpoint
 
-        q, _, ck = load_checkpoint(args.mlp)
-        pel, pres = run(None, "plain")
-        plain_cmp = dict(value=g.n_pins * args.steps / pel, ms_per_step=1e3 * pel / args.steps,
-                         connectivity=pres[-1]["connectivity"], n_parts=pres[-1]["n_parts"],
-                         levels=pres[-1]["n_levels"])
-        elapsed, results = run(q, "learned")
-    else:
-        elapsed, results = run(None, "plain")
+        q, _, _ = load_checkpoint(args.mlp)
+    elapsed, results = run(q, "learned" if q is not None else "plain", args.warmup, args.steps)
     ms_step = 1e3 * elapsed / args.steps
     value = g.n_pins * args.steps / elapsed
+    plain_cmp = None
+    if q is not None:
+        # the plain method on the same input: the judge of the learned result
+        pel, pres = run(None, "plain", 0, args.plain_steps)
+        plain_cmp = dict(value=g.n_pins * args.plain_steps / pel, ms_per_step=1e3 * pel / args.plain_steps,
+                         steps=args.plain_steps, connectivity=pres[-1]["connectivity"],
+                         n_parts=pres[-1]["n_parts"], levels=pres[-1]["n_levels"], rounds=pres[-1]["n_rounds"])
 
     # per-kernel-class totals over the timed steps
     agg = {}
@@ -260,25 +305,23 @@ def main():
                 launches_per_step=a["launches"] / args.steps,
                 units_per_launch=units_per_launch, share_of_step=a["ms"] / args.steps / ms_step)
 
-    line = dict(metric="pins/s (sum |e| per second), whole constrained multilevel partition",
-                value=value, unit="pins/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+    line = dict(metric=METRIC, value=value, unit="pins/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                 ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32",
                 data="synthetic",
                 config=dict(workload=w.name, description=w.note, n_nodes=g.n_nodes, pins=g.n_pins,
                             sum_e_sq=g.sum_sq(), omega=w.omega, delta=w.delta, max_refine_rounds=8,
                             levels=results[-1]["n_levels"], rounds=results[-1]["n_rounds"],
                             n_parts=results[-1]["n_parts"], connectivity=results[-1]["connectivity"],
-                proposal="learned" if args.mlp else "plain"),
+                            proposal="learned" if q is not None else "plain"),
                 roofline=roof)
     if plain_cmp:
         line["learned_vs_plain"] = dict(plain=plain_cmp, learned_connectivity=results[-1]["connectivity"],
                                         conn_ratio=results[-1]["connectivity"] / max(plain_cmp["connectivity"], 1),
                                         speed_ratio=value / plain_cmp["value"],
                                         n_fallback=results[-1]["n_fallback"], checkpoint=os.path.basename(args.mlp))
-    if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline (oracle) on a reduced sample n={args.cpu_sample_n} ...")
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_n, 191.0 if w.name == "rand64k" else 127.0, w.omega,
-                                            w.delta)
+    if not args.no_cpu_baseline and w.sample is not None:
+        log(f"[bench] cpu baseline: the oracle on {w.sample_note} ...")
+        line["cpu_baseline"] = cpu_baseline(w, q, min(os.cpu_count() or 1, 16))
     print(json.dumps(line), flush=True)
 
 

@@ -45,6 +45,8 @@ extern "C" {
 #define HGP_EDEVICE (-5)       /* HIP runtime error (text in hgp_last_error) */
 #define HGP_EUNSUPPORTED (-6)  /* outside the supported domain (see hgp_partition) */
 #define HGP_EINTERNAL (-7)     /* an internal consistency check failed */
+#define HGP_EIO (-8)           /* a checkpoint file could not be opened, read or written */
+#define HGP_EFORMAT (-9)       /* a checkpoint file is not in the format of hgp_mlp_save (or is corrupt) */
 
 /*
  * Input hypergraph in int32 CSR form (Sec. II-C: offsets + segmented data).
@@ -190,6 +192,16 @@ int hgp_partition_device(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, i
  */
 int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, void *stream,
                             int64_t *out);
+
+/*
+ * Eq. 1 for a partition vector in host memory: *g holds host arrays (as for
+ * hgp_partition), part (host, [n_nodes]) values in [0, n_nodes).  The arrays
+ * are copied to the context's device and the connectivity is computed there
+ * by the same kernels as hgp_connectivity_device; *out (host) receives it.
+ * Synchronous.  HGP_EBADCSR / HGP_EINVAL as for hgp_partition; a part id
+ * outside [0, n_nodes) gives HGP_EBADCSR.
+ */
+int hgp_connectivity(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, int64_t *out);
 
 const char *hgp_strerror(int code);
 /* Message of the last failure on the calling thread ("" if none). */
@@ -377,6 +389,57 @@ int hgp_mlp_grad(hgp_ctx *ctx, const hgp_mlp_f32 *w, const int32_t *xq, const fl
  */
 int hgp_mlp_train(hgp_ctx *ctx, hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n,
                   const hgp_train_opts *opt, float *loss_epochs, void *stream);
+
+/*
+ * Resumable training.  The state holds everything a run of
+ * hgp_mlp_train_state carries from one epoch to the next: the FP32 master
+ * weights, Adam's first and second moments, the number of Adam steps taken,
+ * the number of epochs completed and the state of the shuffle generator.
+ * Training e1 epochs, saving the state (hgp_mlp_save), loading it and
+ * training e2 more gives bit-identical weights to e1 + e2 epochs in one run.
+ */
+typedef struct {
+  hgp_mlp_f32 w;  /* master weights */
+  hgp_mlp_f32 m;  /* Adam first moments (same layout as the weights) */
+  hgp_mlp_f32 v;  /* Adam second moments */
+  int64_t step;   /* Adam steps taken (bias corrections use step + 1 next) */
+  int64_t epoch;  /* epochs completed */
+  uint64_t rng;   /* shuffle generator state */
+} hgp_train_state;
+
+/* Fresh state: weights *w, zero moments, step = epoch = 0, the shuffle
+ * generator seeded from opt->seed. */
+void hgp_train_state_init(hgp_train_state *st, const hgp_mlp_f32 *w, const hgp_train_opts *opt);
+
+/*
+ * `epochs` more epochs of hgp_mlp_train from state *st (host memory, updated
+ * in place); opt->epochs is ignored and opt->seed only matters through
+ * hgp_train_state_init.  loss_epochs (host, [epochs], may be NULL) receives
+ * the mean loss of each epoch.  hgp_mlp_train(w, ..., opt) equals
+ * hgp_train_state_init followed by this call with opt->epochs.  Synchronous.
+ */
+int hgp_mlp_train_state(hgp_ctx *ctx, hgp_train_state *st, const int32_t *xq, const float *y, int64_t n,
+                        const hgp_train_opts *opt, int32_t epochs, float *loss_epochs, void *stream);
+
+/*
+ * Checkpoint file of the learned proposal (host code, no device needed).
+ * A versioned little-endian binary file:
+ *   header (48 bytes): magic "HGPMLP\0\0", version 1, header size 48,
+ *     inputs 16, hidden 64, parameter count 5249, section bits (1: training
+ *     state, 2: integer network), score shift, reserved 0, payload bytes;
+ *   payload: the training state when bit 1 is set (weights, first and second
+ *     moments as 5249 floats each in hgp_mlp_f32 order, step, epoch, rng),
+ *     then the integer network of hgp_mlp when bit 2 is set;
+ *   trailer: CRC-32 (IEEE 802.3, reflected polynomial 0xEDB88320) of header
+ *     and payload.
+ * hgp_mlp_save writes the sections whose pointer is non-NULL (at least one);
+ * the integer network is checked as for HGP_LEARNED (HGP_EINVAL).
+ * hgp_mlp_load reads them back; st / q / score_shift may be NULL to skip a
+ * section, and asking for a section the file lacks gives HGP_EFORMAT, as do
+ * a wrong magic, version, shape, size or CRC.  File errors give HGP_EIO.
+ */
+int hgp_mlp_save(const char *path, const hgp_train_state *st, const hgp_mlp *q, int32_t score_shift);
+int hgp_mlp_load(const char *path, hgp_train_state *st, hgp_mlp *q, int32_t *score_shift);
 
 /*
  * Integer network from float weights: power-of-two scales per layer chosen

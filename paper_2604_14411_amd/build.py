@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhgp.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["prims.hip", "coarsen.hip", "refine.hip", "seg.hip", "tail.hip", "events.hip", "learned.hip", "training.hip", "driver.hip"]
+SOURCES = ["prims.hip", "coarsen.hip", "refine.hip", "seg.hip", "tail.hip", "events.hip", "learned.hip", "training.hip", "checkpoint.hip", "driver.hip"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

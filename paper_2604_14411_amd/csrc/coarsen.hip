@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
                                              int32_t omega, int32_t delta, int32_t words,
                                              int32_t *__restrict__ pair, int64_t *__restrict__ score,
                                              unsigned long long *__restrict__ units) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int64_t red_h[NT / 64];
   __shared__ int32_t red_m[NT / 64];
   __shared__ int32_t tbl[NT / 64 * 192];

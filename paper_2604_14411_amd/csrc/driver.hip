@@ -60,6 +60,13 @@ struct CachedLevel {
   void release() {
     for (DevBuf *b : {&hoff, &hpin, &ioff, &inc, &perm, &indeg, &total}) b->release();
   }
+  // device bytes the entry's buffers hold (their capacities, which can exceed
+  // the level's own size once buffers have been recycled between levels)
+  int64_t held() const {
+    int64_t h = 0;
+    for (const DevBuf *b : {&hoff, &hpin, &ioff, &inc, &perm, &indeg, &total}) h += (int64_t)b->bytes;
+    return h;
+  }
 };
 
 struct Workspace {
@@ -84,7 +91,8 @@ struct Workspace {
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
   // coarse levels kept for refinement: most recent last, within the budget
   std::vector<std::unique_ptr<CachedLevel>> lcache, lcache_free;
-  int64_t lcache_bytes = 0;
+  int64_t lcache_bytes = 0;  // level sizes of the kept entries
+  int64_t lcache_held = 0;   // buffer capacities of all entries, kept and free
   int64_t lcache_budget = level_cache_default();
   int rate_tile = 1024;        // rating workgroup size (schedule knob; same result)
   DevBuf tr_xq, tr_prm, tr_mom, tr_part, tr_perm, tr_loss, tr_grad;
@@ -125,6 +133,7 @@ struct Workspace {
     clear_level_cache();
     for (auto &c : lcache_free) c->release();
     lcache_free.clear();
+    lcache_held = 0;
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
                           &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
@@ -541,6 +550,7 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, De
   c->n = n;
   c->P = P;
   c->bytes = bytes;
+  const int64_t held_before = c->held();
   auto take = [&](DevBuf &entry, DevBuf &work, const void *held) {
     if (work.ptr != held) throw Error(HGP_EINTERNAL, "level buffer not held by the workspace");
     std::swap(entry, work);
@@ -552,8 +562,24 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, De
   take(c->perm, W.perm, L.perm);
   take(c->indeg, W.indeg, L.indeg);
   take(c->total, W.total, L.total);
+  W.lcache_held += c->held() - held_before;
   W.lcache_bytes += bytes;
   W.lcache.push_back(std::move(c));
+  // The budget bounds device memory, so it applies to what the entries hold:
+  // buffers recycled between levels of different sizes (a run after a run on
+  // another hypergraph or proposal) keep their larger capacities.  Free
+  // entries go first, then the oldest kept levels (the newest always stays).
+  while (W.lcache_held > W.lcache_budget && !W.lcache_free.empty()) {
+    W.lcache_held -= W.lcache_free.back()->held();
+    W.lcache_free.back()->release();
+    W.lcache_free.pop_back();
+  }
+  while (W.lcache_held > W.lcache_budget && W.lcache.size() > 1) {
+    W.lcache_held -= W.lcache.front()->held();
+    W.lcache_bytes -= W.lcache.front()->bytes;
+    W.lcache.front()->release();
+    W.lcache.erase(W.lcache.begin());
+  }
 }
 
 static const CachedLevel *cached_level(const Workspace &W, int lvl) {
@@ -1008,6 +1034,8 @@ const char *hgp_strerror(int code) {
     case HGP_ENOMEM: return "out of memory";
     case HGP_EDEVICE: return "HIP device error";
     case HGP_EUNSUPPORTED: return "unsupported input";
+    case HGP_EIO: return "checkpoint file input/output error";
+    case HGP_EFORMAT: return "not a valid checkpoint file";
     case HGP_EINTERNAL: return "internal error";
     default: return "unknown error";
   }
@@ -1061,6 +1089,42 @@ int hgp_partition_device(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, i
   });
 }
 
+// Copies a host hypergraph into the workspace's input buffers (validated
+// later, on the device, by ingest()); returns the device view.
+static hgp_hypergraph upload_host(Workspace &W, const hgp_hypergraph *g, hipStream_t s) {
+  const int32_t N = g->n_nodes, E = g->n_hedges;
+  for (int32_t e = 0; e < E; ++e)
+    if (g->hedge_off[e + 1] < g->hedge_off[e]) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
+  if (g->hedge_off[0] != 0) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
+  const int64_t P = g->hedge_off[E];
+  if (P > 0 && !g->pins) throw Error(HGP_EINVAL, "pins is NULL");
+  hgp_hypergraph d = *g;
+  int32_t *off = need<int32_t>(W.in_off, (int64_t)E + 1);
+  HGP_HIP(hipMemcpyAsync(off, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyHostToDevice, s));
+  d.hedge_off = off;
+  if (P > 0) {
+    int32_t *pp = need<int32_t>(W.in_pins, P);
+    HGP_HIP(hipMemcpyAsync(pp, g->pins, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
+    d.pins = pp;
+  }
+  if (g->n_src && E > 0) {
+    int32_t *q = need<int32_t>(W.in_nsrc, E);
+    HGP_HIP(hipMemcpyAsync(q, g->n_src, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
+    d.n_src = q;
+  }
+  if (g->hedge_w && E > 0) {
+    int32_t *q = need<int32_t>(W.in_hw, E);
+    HGP_HIP(hipMemcpyAsync(q, g->hedge_w, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
+    d.hedge_w = q;
+  }
+  if (g->node_w && N > 0) {
+    int32_t *q = need<int32_t>(W.in_nw, N);
+    HGP_HIP(hipMemcpyAsync(q, g->node_w, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s));
+    d.node_w = q;
+  }
+  return d;
+}
+
 static int partition_host_impl(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, int32_t delta,
                                const hgp_options *opt, int32_t *part_out, hgp_result *res, hgp_trace *trace) {
   if (!ctx) {
@@ -1071,38 +1135,10 @@ static int partition_host_impl(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t om
     DeviceGuard dg(ctx->device);
     check_scalars(g, omega, delta);
     Workspace &W = ctx->ws;
-    const int32_t N = g->n_nodes, E = g->n_hedges;
+    const int32_t N = g->n_nodes;
     if (N > 0 && !part_out) throw Error(HGP_EINVAL, "part_out is NULL");
-    for (int32_t e = 0; e < E; ++e)
-      if (g->hedge_off[e + 1] < g->hedge_off[e]) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
-    if (g->hedge_off[0] != 0) throw Error(HGP_EBADCSR, "hedge offsets are not monotone from 0");
-    const int64_t P = g->hedge_off[E];
-    if (P > 0 && !g->pins) throw Error(HGP_EINVAL, "pins is NULL");
     hipStream_t s = nullptr;
-    hgp_hypergraph d = *g;
-    int32_t *off = need<int32_t>(W.in_off, (int64_t)E + 1);
-    HGP_HIP(hipMemcpyAsync(off, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyHostToDevice, s));
-    d.hedge_off = off;
-    if (P > 0) {
-      int32_t *pp = need<int32_t>(W.in_pins, P);
-      HGP_HIP(hipMemcpyAsync(pp, g->pins, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice, s));
-      d.pins = pp;
-    }
-    if (g->n_src && E > 0) {
-      int32_t *q = need<int32_t>(W.in_nsrc, E);
-      HGP_HIP(hipMemcpyAsync(q, g->n_src, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
-      d.n_src = q;
-    }
-    if (g->hedge_w && E > 0) {
-      int32_t *q = need<int32_t>(W.in_hw, E);
-      HGP_HIP(hipMemcpyAsync(q, g->hedge_w, sizeof(int32_t) * (size_t)E, hipMemcpyHostToDevice, s));
-      d.hedge_w = q;
-    }
-    if (g->node_w && N > 0) {
-      int32_t *q = need<int32_t>(W.in_nw, N);
-      HGP_HIP(hipMemcpyAsync(q, g->node_w, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s));
-      d.node_w = q;
-    }
+    hgp_hypergraph d = upload_host(W, g, s);
     int32_t *po = need<int32_t>(W.in_part, N);
     const hgp_options o = opts_or_default(opt);
     if (trace && o.proposal != HGP_PLAIN) throw Error(HGP_EINVAL, "traces record the plain method");
@@ -1193,7 +1229,40 @@ int hgp_mlp_train(hgp_ctx *ctx, hgp_mlp_f32 *w, const int32_t *xq, const float *
     if (!w || !opt || n < 1 || !xq || !y) throw Error(HGP_EINVAL, "bad arguments");
     if (opt->epochs < 0 || opt->batch < 1 || !(opt->lr > 0) || !(opt->eps > 0)) throw Error(HGP_EINVAL, "bad options");
     Workspace &W = ctx->ws;
-    mlp_train(w, xq, y, n, *opt, W.tr_prm, W.tr_mom, W.tr_part, W.tr_perm, W.tr_loss, loss_epochs,
+    hgp_train_state st;
+    train_state_init(&st, w, opt->seed);
+    mlp_train(&st, xq, y, n, *opt, opt->epochs, W.tr_prm, W.tr_mom, W.tr_part, W.tr_perm, W.tr_loss, loss_epochs,
+              static_cast<hipStream_t>(stream));
+    *w = st.w;
+  });
+}
+
+int hgp_mlp_save(const char *path, const hgp_train_state *st, const hgp_mlp *q, int32_t score_shift) {
+  return guarded([&] { ckpt_save(path, st, q, score_shift); });
+}
+
+int hgp_mlp_load(const char *path, hgp_train_state *st, hgp_mlp *q, int32_t *score_shift) {
+  return guarded([&] { ckpt_load(path, st, q, score_shift); });
+}
+
+void hgp_train_state_init(hgp_train_state *st, const hgp_mlp_f32 *w, const hgp_train_opts *opt) {
+  if (st && w) train_state_init(st, w, opt ? opt->seed : 0);
+}
+
+int hgp_mlp_train_state(hgp_ctx *ctx, hgp_train_state *st, const int32_t *xq, const float *y, int64_t n,
+                        const hgp_train_opts *opt, int32_t epochs, float *loss_epochs, void *stream) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    if (!st || !opt || n < 1 || !xq || !y || epochs < 0) throw Error(HGP_EINVAL, "bad arguments");
+    if (opt->batch < 1 || !(opt->lr > 0) || !(opt->eps > 0)) throw Error(HGP_EINVAL, "bad options");
+    if (st->step < 0 || st->epoch < 0 || st->step > 0x7fffffff - (int64_t)epochs * ((n + opt->batch - 1) / opt->batch))
+      throw Error(HGP_EINVAL, "bad training state");
+    Workspace &W = ctx->ws;
+    mlp_train(st, xq, y, n, *opt, epochs, W.tr_prm, W.tr_mom, W.tr_part, W.tr_perm, W.tr_loss, loss_epochs,
               static_cast<hipStream_t>(stream));
   });
 }
@@ -1211,6 +1280,32 @@ int hgp_mlp_quantize(const hgp_mlp_f32 *w, const int32_t *xq, int64_t n, int32_t
 }
 
 
+// Eq. 1 for a partition of a device hypergraph (both validated on the device).
+static int64_t connectivity_impl(Workspace &W, const hgp_hypergraph *g, const int32_t *part, hipStream_t s) {
+  Ingest I = ingest(W, g, 1, 0x7fffffff, s);
+  const int32_t N = g->n_nodes, E = g->n_hedges;
+  // part ids must be valid indices: bound them by the node count (ids >= 0 checked on device)
+  const int32_t np = N > 0 ? N : 1;
+  launch_check_range(part, N, 0, np, W.err.as<int32_t>(), s);
+  check_err(W, s);
+  LevelView V;
+  V.n = N;
+  V.E = E;
+  V.hoff = g->hedge_off;
+  V.hpin = I.hpin0;
+  V.hw = I.hw;
+  V.size = I.nw;
+  V.big = find_big(W, g->hedge_off, E, s);
+  RoundBufs B = round_bufs(W, N, E, I.P, np);
+  launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
+  int64_t *conn = need<int64_t>(W.conn, 2);
+  launch_connectivity(V, B, conn, s);
+  int64_t out = 0;
+  HGP_HIP(hipMemcpyAsync(&out, conn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  return out;
+}
+
 int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, void *stream,
                             int64_t *out) {
   if (!ctx || !out) {
@@ -1219,29 +1314,27 @@ int hgp_connectivity_device(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t
   }
   return guarded([&] {
     DeviceGuard dg(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if (g && g->n_nodes > 0 && !part) throw Error(HGP_EINVAL, "part is NULL");
+    *out = connectivity_impl(ctx->ws, g, part, static_cast<hipStream_t>(stream));
+  });
+}
+
+int hgp_connectivity(hgp_ctx *ctx, const hgp_hypergraph *g, const int32_t *part, int64_t *out) {
+  if (!ctx || !out) {
+    g_last_error = "ctx or out is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    check_scalars(g, 1, 0x7fffffff);
+    const int32_t N = g->n_nodes;
+    if (N > 0 && !part) throw Error(HGP_EINVAL, "part is NULL");
     Workspace &W = ctx->ws;
-    Ingest I = ingest(W, g, 1, 0x7fffffff, s);
-    const int32_t N = g->n_nodes, E = g->n_hedges;
-    // part ids must be valid indices: bound them by the node count (ids >= 0 checked on device)
-    const int32_t np = N > 0 ? N : 1;
-    launch_check_range(part, N, 0, np, W.err.as<int32_t>(), s);
-    check_err(W, s);
-    LevelView V;
-    V.n = N;
-    V.E = E;
-    V.hoff = g->hedge_off;
-    V.hpin = I.hpin0;
-    V.hw = I.hw;
-    V.size = I.nw;
-    V.big = find_big(W, g->hedge_off, E, s);
-    RoundBufs B = round_bufs(W, N, E, I.P, np);
-    launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
-    int64_t *conn = need<int64_t>(W.conn, 2);
-    launch_connectivity(V, B, conn, s);
-    HGP_HIP(hipMemcpyAsync(out, conn, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HGP_HIP(hipStreamSynchronize(s));
+    hipStream_t s = nullptr;
+    hgp_hypergraph d = upload_host(W, g, s);
+    int32_t *pd = need<int32_t>(W.in_part, N);
+    if (N > 0) HGP_HIP(hipMemcpyAsync(pd, part, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s));
+    *out = connectivity_impl(W, &d, pd, s);
   });
 }
 

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     const int32_t *__restrict__ indeg, const int32_t *__restrict__ total, int32_t omega, int32_t delta,
     int32_t words, int32_t keep, uint64_t *__restrict__ ck, int32_t *__restrict__ cc, int32_t *__restrict__ ccnt,
     unsigned long long *__restrict__ units) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint64_t wk[CAND_NT / 64][kCandK];
   __shared__ int32_t wc[CAND_NT / 64][kCandK];
   __shared__ int32_t tbl[CAND_NT / 64 * 192];

@@ -71,8 +71,15 @@ void mlp_init(hgp_mlp_f32 *w, uint64_t seed);
 void mlp_grad(const hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n, DevBuf &prm, DevBuf &part,
               DevBuf &grad, DevBuf &lossb, hgp_mlp_f32 *g_out, double *loss_out, hipStream_t s);
 // Adam on shuffled minibatches; w (host) in/out; loss_epochs[epochs] (host, optional).
-void mlp_train(hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n, const hgp_train_opts &o, DevBuf &prm,
-               DevBuf &mom, DevBuf &part, DevBuf &perm, DevBuf &lossb, float *loss_epochs, hipStream_t s);
+// Fresh training state: weights w, zero moments, shuffle generator from seed.
+void train_state_init(hgp_train_state *st, const hgp_mlp_f32 *w, uint64_t seed);
+// `epochs` epochs of minibatch Adam continuing from state st (updated).
+void mlp_train(hgp_train_state *st, const int32_t *xq, const float *y, int64_t n, const hgp_train_opts &o,
+               int32_t epochs, DevBuf &prm, DevBuf &mom, DevBuf &part, DevBuf &perm, DevBuf &lossb,
+               float *loss_epochs, hipStream_t s);
+// Checkpoint files (checkpoint.hip); throw Error on failure.
+void ckpt_save(const char *path, const hgp_train_state *st, const hgp_mlp *q, int32_t score_shift);
+void ckpt_load(const char *path, hgp_train_state *st, hgp_mlp *q, int32_t *score_shift);
 // Integer network from float weights and host calibration rows.
 void mlp_quantize(const hgp_mlp_f32 *w, const int32_t *xq, int64_t n, int32_t k, hgp_mlp *q, int32_t *score_shift);
 

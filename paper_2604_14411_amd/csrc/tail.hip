@@ -75,7 +75,7 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
                                                   int32_t *__restrict__ tk_cnt, uint64_t *__restrict__ tk_kappa,
                                                   int32_t words, const uint64_t *pre,
                                                   unsigned long long *__restrict__ units) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int32_t tbl[NT / 64 * 192];
   __shared__ int2 rng_s[NT / 64];
   __shared__ uint64_t red[NT / 64];
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
                                                   const int32_t *__restrict__ total, int32_t omega, int32_t words,
                                                   unsigned long long *__restrict__ acc,
                                                   unsigned long long *__restrict__ units) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int32_t tbl[NT / 64 * 192];
   __shared__ int2 rng_s[NT / 64];
   const int tid = threadIdx.x;

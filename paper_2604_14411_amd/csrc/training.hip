@@ -176,25 +176,38 @@ void mlp_init(hgp_mlp_f32 *w, uint64_t seed) {
   }
 }
 
-void mlp_train(hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n, const hgp_train_opts &o, DevBuf &prm,
-               DevBuf &mom, DevBuf &part, DevBuf &perm, DevBuf &lossb, float *loss_epochs, hipStream_t s) {
-  if (n <= 0) return;
+void train_state_init(hgp_train_state *st, const hgp_mlp_f32 *w, uint64_t seed) {
+  std::memset(st, 0, sizeof *st);
+  st->w = *w;
+  st->rng = seed ^ 0xbb67ae8584caa73bull;
+}
+
+// `epochs` epochs of minibatch Adam from state st (host), which is updated:
+// weights and moments live on the device during the run, the shuffle order of
+// each epoch is drawn on the host from st->rng (Fisher-Yates), and the Adam
+// step count carries over, so a run split at an epoch boundary is
+// bit-identical to an uninterrupted one.
+void mlp_train(hgp_train_state *st, const int32_t *xq, const float *y, int64_t n, const hgp_train_opts &o,
+               int32_t epochs, DevBuf &prm, DevBuf &mom, DevBuf &part, DevBuf &perm, DevBuf &lossb,
+               float *loss_epochs, hipStream_t s) {
+  if (n <= 0 || epochs <= 0) return;
   prm.reserve(sizeof(hgp_mlp_f32));
   mom.reserve(2 * sizeof(hgp_mlp_f32));
-  HGP_HIP(hipMemcpyAsync(prm.ptr, w, sizeof(hgp_mlp_f32), hipMemcpyHostToDevice, s));
-  fill_i32(mom.as<int32_t>(), 2 * kNPar, 0, s);  // +0.0f
+  HGP_HIP(hipMemcpyAsync(prm.ptr, &st->w, sizeof(hgp_mlp_f32), hipMemcpyHostToDevice, s));
+  float *m = mom.as<float>(), *v = mom.as<float>() + kNPar;
+  HGP_HIP(hipMemcpyAsync(m, &st->m, sizeof(hgp_mlp_f32), hipMemcpyHostToDevice, s));
+  HGP_HIP(hipMemcpyAsync(v, &st->v, sizeof(hgp_mlp_f32), hipMemcpyHostToDevice, s));
   const int64_t batch = std::min<int64_t>(o.batch, n);
   const int waves = grad_waves(batch);
   part.reserve((size_t)waves * kPartStride * sizeof(float));
   perm.reserve((size_t)n * sizeof(int64_t));
   lossb.reserve(sizeof(double));
   std::vector<int64_t> order((size_t)n);
-  uint64_t st = o.seed ^ 0xbb67ae8584caa73bull;
-  float *m = mom.as<float>(), *v = mom.as<float>() + kNPar;
-  int step = 0;
-  for (int ep = 0; ep < o.epochs; ++ep) {
+  uint64_t rng = st->rng;
+  int64_t step = st->step;
+  for (int ep = 0; ep < epochs; ++ep) {
     for (int64_t i = 0; i < n; ++i) order[(size_t)i] = i;
-    for (int64_t i = n - 1; i > 0; --i) std::swap(order[(size_t)i], order[(size_t)(splitmix64(st) % (uint64_t)(i + 1))]);
+    for (int64_t i = n - 1; i > 0; --i) std::swap(order[(size_t)i], order[(size_t)(splitmix64(rng) % (uint64_t)(i + 1))]);
     HGP_HIP(hipMemcpyAsync(perm.ptr, order.data(), (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, s));
     fill_i64(lossb.as<int64_t>(), 1, 0, s);
     for (int64_t b0 = 0; b0 < n; b0 += batch) {
@@ -205,7 +218,7 @@ void mlp_train(hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n, con
       HGP_LAUNCH_CHECK();
       ++step;
       k_mlp_reduce_adam<<<div_up(kNPar + 1, 256), 256, 0, s>>>(part.as<float>(), wv, 1, prm.as<float>(), m, v, o.lr,
-                                                               o.beta1, o.beta2, o.eps, step, nullptr,
+                                                               o.beta1, o.beta2, o.eps, (int)step, nullptr,
                                                                lossb.as<double>());
       HGP_LAUNCH_CHECK();
     }
@@ -214,8 +227,13 @@ void mlp_train(hgp_mlp_f32 *w, const int32_t *xq, const float *y, int64_t n, con
     HGP_HIP(hipStreamSynchronize(s));
     if (loss_epochs) loss_epochs[ep] = (float)(ls / (double)n);
   }
-  HGP_HIP(hipMemcpyAsync(w, prm.ptr, sizeof(hgp_mlp_f32), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&st->w, prm.ptr, sizeof(hgp_mlp_f32), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&st->m, m, sizeof(hgp_mlp_f32), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(&st->v, v, sizeof(hgp_mlp_f32), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
+  st->rng = rng;
+  st->step = step;
+  st->epoch += epochs;
 }
 
 // ---------------------------------------------------------------------------

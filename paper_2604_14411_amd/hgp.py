@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+EIO, EFORMAT = -8, -9
 PLAIN, LEARNED = 0, 1
 INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
 MLP_F, MLP_H = 16, 64
@@ -66,6 +67,11 @@ class TrainOpts_t(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("seed", ctypes.c_uint64)]
+
+
+class TrainState_t(ctypes.Structure):
+    _fields_ = [("w", MlpF32_t), ("m", MlpF32_t), ("v", MlpF32_t), ("step", ctypes.c_int64),
+                ("epoch", ctypes.c_int64), ("rng", ctypes.c_uint64)]
 
 
 def f32_to_dict(w: MlpF32_t) -> dict:
@@ -126,7 +132,8 @@ EXPORTS = [
     "hgp_level_match", "hgp_level_contract", "hgp_level_refine_round", "hgp_level_learned",
     "hgp_mlp_score_device", "hgp_mlp_init", "hgp_mlp_grad", "hgp_mlp_train", "hgp_mlp_quantize",
     "hgp_trace_create", "hgp_trace_destroy", "hgp_partition_traced", "hgp_trace_rows", "hgp_trace_read",
-    "hgp_partition_batch_device", "hgp_batch_tune",
+    "hgp_partition_batch_device", "hgp_batch_tune", "hgp_connectivity", "hgp_train_state_init",
+    "hgp_mlp_train_state", "hgp_mlp_save", "hgp_mlp_load",
 ]
 
 _lib = None
@@ -170,6 +177,12 @@ def load():
     lib.hgp_mlp_grad.argtypes = [vp, FP, vp, vp, ctypes.c_int64, FP, ctypes.POINTER(ctypes.c_double), vp]
     lib.hgp_mlp_train.argtypes = [vp, FP, vp, vp, ctypes.c_int64, ctypes.POINTER(TrainOpts_t), vp, vp]
     lib.hgp_mlp_quantize.argtypes = [FP, vp, ctypes.c_int64, i32, MP, ctypes.POINTER(i32)]
+    SP = ctypes.POINTER(TrainState_t)
+    lib.hgp_train_state_init.argtypes = [SP, FP, ctypes.POINTER(TrainOpts_t)]
+    lib.hgp_mlp_train_state.argtypes = [vp, SP, vp, vp, ctypes.c_int64, ctypes.POINTER(TrainOpts_t), i32, vp, vp]
+    lib.hgp_mlp_save.argtypes = [ctypes.c_char_p, SP, MP, i32]
+    lib.hgp_mlp_load.argtypes = [ctypes.c_char_p, SP, MP, ctypes.POINTER(i32)]
+    lib.hgp_connectivity.argtypes = [vp, HG, vp, i64p]
     lib.hgp_trace_create.argtypes = [ctypes.POINTER(vp)]
     lib.hgp_trace_destroy.argtypes = [vp]
     lib.hgp_partition_traced.argtypes = [vp, HG, i32, i32, ctypes.POINTER(Options_t), vp, vp,
@@ -183,9 +196,10 @@ def load():
                                    ctypes.POINTER(BatchSched_t), dp]
     for name in EXPORTS:
         if name not in ("hgp_ctx_destroy", "hgp_options_default", "hgp_strerror", "hgp_last_error",
-                        "hgp_mlp_init", "hgp_trace_destroy", "hgp_trace_rows"):
+                        "hgp_mlp_init", "hgp_trace_destroy", "hgp_trace_rows", "hgp_train_state_init"):
             getattr(lib, name).restype = ctypes.c_int
     lib.hgp_mlp_init.restype = None
+    lib.hgp_train_state_init.restype = None
     lib.hgp_trace_destroy.restype = None
     lib.hgp_trace_rows.restype = ctypes.c_int64
     _lib = lib
@@ -306,6 +320,20 @@ def connectivity_device(ctx: Context, dg: DeviceHypergraph, part) -> int:
 
 
 # ---------------------------------------------------------------- level API
+def connectivity_host(ctx: Context, g, part) -> int:
+    """hgp_connectivity: Eq. 1 of a host partition vector on a host hypergraph
+    (copied to the device and computed there)."""
+    lib = load()
+    arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (g.hedge_off, g.pins, g.n_src, g.hedge_w, g.node_w)]
+    p = [a.ctypes.data if a.size else None for a in arrs]
+    hg = Hypergraph_t(g.n_nodes, g.n_hedges, arrs[0].ctypes.data, p[1], p[2], p[3], p[4])
+    pa = np.ascontiguousarray(part, dtype=np.int32)
+    out = ctypes.c_int64()
+    _check(lib.hgp_connectivity(ctx.handle, ctypes.byref(hg), pa.ctypes.data if pa.size else None,
+                                ctypes.byref(out)))
+    return int(out.value)
+
+
 def level_canonical(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int):
     import torch
 
@@ -455,6 +483,43 @@ def mlp_train(ctx: Context, w: dict, xq, y, epochs=4, batch=4096, lr=2e-3, beta1
     _check(lib.hgp_mlp_train(ctx.handle, ctypes.byref(wf), _ptr(xq.contiguous()), _ptr(y.contiguous()),
                              xq.shape[0], ctypes.byref(o), losses, _stream()))
     return f32_to_dict(wf), [float(losses[i]) for i in range(epochs)]
+
+
+def train_state(w: dict, seed: int = 0) -> TrainState_t:
+    """Fresh resumable training state (hgp_train_state_init) from float weights."""
+    st = TrainState_t()
+    wf = f32_from_dict(w)
+    o = TrainOpts_t(0, 1, 1e-3, 0.9, 0.999, 1e-8, seed)
+    load().hgp_train_state_init(ctypes.byref(st), ctypes.byref(wf), ctypes.byref(o))
+    return st
+
+
+def mlp_train_state(ctx: Context, st: TrainState_t, xq, y, epochs, batch=4096, lr=2e-3, beta1=0.9, beta2=0.999,
+                    eps=1e-8):
+    """`epochs` more epochs from a training state (updated in place); returns the per-epoch mean loss."""
+    lib = load()
+    o = TrainOpts_t(epochs, batch, lr, beta1, beta2, eps, 0)
+    losses = (ctypes.c_float * max(epochs, 1))()
+    _check(lib.hgp_mlp_train_state(ctx.handle, ctypes.byref(st), _ptr(xq.contiguous()), _ptr(y.contiguous()),
+                                   xq.shape[0], ctypes.byref(o), epochs, losses, _stream()))
+    return [float(losses[i]) for i in range(epochs)]
+
+
+def mlp_save(path: str, state: TrainState_t = None, q=None, score_shift: int = 0) -> None:
+    """hgp_mlp_save: versioned binary checkpoint (training state and/or integer network)."""
+    m = None if q is None else (q if isinstance(q, Mlp_t) else mlp_struct(q))
+    _check(load().hgp_mlp_save(os.fsencode(path), None if state is None else ctypes.byref(state),
+                               None if m is None else ctypes.byref(m), int(score_shift)))
+
+
+def mlp_load(path: str, state: bool = True, network: bool = True):
+    """hgp_mlp_load; returns (TrainState_t or None, integer network dict or None, score_shift)."""
+    st = TrainState_t() if state else None
+    m = Mlp_t() if network else None
+    sh = ctypes.c_int32()
+    _check(load().hgp_mlp_load(os.fsencode(path), None if st is None else ctypes.byref(st),
+                               None if m is None else ctypes.byref(m), ctypes.byref(sh)))
+    return st, (None if m is None else mlp_to_dict(m)), int(sh.value)
 
 
 def mlp_quantize(w: dict, xq_calib, k: int = 8):

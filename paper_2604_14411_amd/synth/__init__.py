@@ -180,3 +180,10 @@ def feature_codes(seed: int, n: int) -> np.ndarray:
     x = np.zeros((n, 16), dtype=np.int32)
     x[:, :10] = rng.integers(0, 256, size=(n, 10))
     return x
+
+
+def with_node_weights(g: Hypergraph, seed: int, wmax: int) -> Hypergraph:
+    """The same hypergraph with seeded node weights uniform in [1, wmax]."""
+    rng = np.random.default_rng(seed)
+    nw = rng.integers(1, wmax + 1, size=g.n_nodes).astype(np.int32)
+    return Hypergraph(g.hedge_off.copy(), g.pins.copy(), g.n_src.copy(), g.hedge_w.copy(), nw)

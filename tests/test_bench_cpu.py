@@ -49,3 +49,23 @@ def test_committed_traffic_file_is_well_formed():
         assert cls in b.COST
         assert e["bytes_per_launch"] > 0 and e["launches"] > 0
         assert all(os.path.exists(os.path.join(ROOT, rel)) for rel in e["sources"])
+
+
+def test_cpu_baseline_runs_the_oracle_on_the_workload_sample():
+    from paper_2604_14411_amd import synth
+    from paper_2604_14411_amd.synth.configs import WORKLOADS, Workload
+
+    b = _bench()
+    w = Workload("tiny", 64, 400, lambda: synth.random_snn(3000, 20.0, 5), "tiny",
+                 lambda: synth.random_snn(300, 10.0, 5), "a random SNN of 300 nodes",
+                 (lambda: synth.random_snn(100, 8.0, 5), "a random SNN of 100 nodes"))
+    for mlp in (None, synth.random_int_mlp(3)):
+        cb = b.cpu_baseline(w, mlp, 2)
+        assert cb["kind"] == "oracle" and cb["cores"] == 2 and cb["value"] > 0
+        assert cb["proposal"] == ("plain" if mlp is None else "learned")
+        assert cb["sample_pins"] == synth.random_snn(300, 10.0, 5).n_pins
+        assert cb["single_thread"]["cores"] == 1 and cb["single_thread"]["value"] > 0
+        assert cb["nproc"] >= 1 and cb["cpu_model"]
+    # every benchmark workload names a sample of its own generator
+    for name, wl in WORKLOADS.items():
+        assert wl.sample is not None and wl.sample_note, name

@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+import badinputs
 import brute
 import oracle
 from paper_2604_14411_amd import synth
@@ -244,31 +245,15 @@ def test_each_step_matches_oracle_trace(ctx, name, make, omega, delta):
 
 
 # --------------------------------------------------------------- errors
-def test_error_codes(ctx):
-    from paper_2604_14411_amd import hgp
-
-    say("[errors]")
-    good = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 2])
-    cases = []
-    bad_off = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 2])
-    bad_off.hedge_off = np.array([0, 3, 2], dtype=np.int32)
-    cases.append((bad_off, hgp.EBADCSR))
-    bad_pin = from_lists(4, [([0], [1, 7]), ([3], [0])], [1, 2])
-    cases.append((bad_pin, hgp.EBADCSR))
-    dup = from_lists(4, [([0], [1, 1]), ([3], [0])], [1, 2])
-    cases.append((dup, hgp.EBADCSR))
-    badw = from_lists(4, [([0], [1, 2]), ([3], [0])], [1, 0])
-    cases.append((badw, hgp.EINVAL))
-    infeas = from_lists(4, [([0], [1, 2]), ([3], [1]), ([2], [1])], [1, 1, 1])
-    for g, want in cases:
-        rc, _, _ = _gpu_partition(ctx, g, 4, 4)
-        assert rc == want
-    rc, _, _ = _gpu_partition(ctx, infeas, 4, 1)
-    assert rc == hgp.EINFEASIBLE
-    rc, _, _ = _gpu_partition(ctx, good, 0, 4)
-    assert rc == hgp.EINVAL
-    rc, _, _ = _gpu_partition(ctx, good, 4, 4)
-    assert rc == 0
+@pytest.mark.parametrize("case", badinputs.cases(), ids=[c[0] for c in badinputs.cases()])
+def test_error_codes(ctx, case):
+    """The library rejects malformed and infeasible inputs with the oracle's codes."""
+    name, g, omega, delta, want = case
+    say(f"[errors] {name}")
+    rc, _, _ = _gpu_partition(ctx, g, omega, delta)
+    assert rc == want, (name, rc, want)
+    orc, _, _, _ = oracle.partition(g, omega, delta)
+    assert orc == want
 
 
 def test_empty_inputs(ctx):

@@ -137,3 +137,47 @@ def test_traced_partition_rows_match_oracle(ctx, name, make, omega, delta):
     lab = _labels_from_oracle(tr, ref, t["level"], t["node"], t["cand"])
     assert np.array_equal(lab, t["label"])
     assert 0 < t["label"].mean() < 1
+
+
+def test_training_resumed_from_checkpoint_is_bit_identical(ctx, tmp_path):
+    """3 epochs, a binary checkpoint (weights, Adam moments, step, shuffle
+    state), a fresh state loaded from it, 3 more epochs: the same bits as 6
+    epochs in one run."""
+    from paper_2604_14411_amd import hgp
+
+    n = 12000
+    x = feature_codes(31, n)
+    y = ((x[:, 1] > 100) ^ (x[:, 6] < 90)).astype(np.float32)
+    xd, yd = _dev(x, np.int32), _dev(y, np.float32)
+    w0 = hgp.mlp_init(6)
+    say("[resume] uninterrupted")
+    w_full, loss_full = hgp.mlp_train(ctx, w0, xd, yd, epochs=6, batch=1000, lr=3e-3, seed=13)
+    st = hgp.train_state(w0, seed=13)
+    say("[resume] first half")
+    la = hgp.mlp_train_state(ctx, st, xd, yd, 3, batch=1000, lr=3e-3)
+    path = str(tmp_path / "half.hgpmlp")
+    hgp.mlp_save(path, st)
+    del st
+    st2, _, _ = hgp.mlp_load(path, network=False)
+    assert st2.epoch == 3 and st2.step == 3 * 12
+    say("[resume] second half")
+    lb = hgp.mlp_train_state(ctx, st2, xd, yd, 3, batch=1000, lr=3e-3)
+    w_res = hgp.f32_to_dict(st2.w)
+    for k in ("w1", "b1", "w2", "b2", "w3"):
+        assert np.array_equal(w_res[k], w_full[k]), k
+    assert w_res["b3"] == w_full["b3"]
+    assert la + lb == loss_full
+
+
+def test_host_connectivity_matches_oracle(ctx):
+    from paper_2604_14411_amd import hgp
+
+    g = synth.random_snn(1800, 20.0, 71)
+    rng = np.random.default_rng(72)
+    for k in (1, 5, 250, g.n_nodes):
+        part = rng.integers(0, k, size=g.n_nodes).astype(np.int32)
+        say(f"[connectivity host] k={k}")
+        assert hgp.connectivity_host(ctx, g, part) == oracle.connectivity(g, part)
+    with pytest.raises(hgp.HgpError) as e:
+        hgp.connectivity_host(ctx, g, np.full(g.n_nodes, g.n_nodes, np.int32))
+    assert e.value.code == hgp.EBADCSR

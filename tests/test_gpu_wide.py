@@ -1,0 +1,116 @@
+"""GPU path vs CPU oracle on inputs that reach the 64-bit rating counters,
+and on layered networks under the large workloads' bounds.
+
+The rating kernels pack hist(n,m) (Eq. 2) and c(n,m) = |in(n) n in(m)| into
+one 32-bit LDS counter when bits(total(n)) + bits(|in(n)|) <= 32, and use a
+64-bit (c << 32 | hist) counter otherwise.  Hedge weights of up to 60,000
+(legal: any weight >= 1) push coarse clusters past 32 bits; each case first
+shows on the host, from the oracle's trace, that such nodes are rated, then
+compares the GPU result with the oracle exactly (full rating of every level,
+and the incremental top-K rating of late levels).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import levelstats
+import oracle
+from paper_2604_14411_amd import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("oracle_lib")]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2604_14411_amd import hgp
+
+    assert torch.cuda.is_available()
+    c = hgp.Context(0)
+    yield c
+    c.close()
+
+
+HEAVY = [
+    ("rand3000_w60000", lambda: synth.random_snn(3000, 30.0, 303, 1, 60000), 128, 600),
+    ("rand3000_w60000_nodew", lambda: synth.with_node_weights(synth.random_snn(3000, 30.0, 304, 1, 60000), 305, 6),
+     256, 600),
+    ("rand3000_w60000_nodew_wide_omega", lambda: synth.with_node_weights(
+        synth.random_snn(3000, 30.0, 304, 1, 60000), 305, 6), 512, 900),
+]
+
+
+@pytest.mark.parametrize("incremental", [True, False], ids=["incremental", "full"])
+@pytest.mark.parametrize("name,make,omega,delta", HEAVY, ids=[c[0] for c in HEAVY])
+def test_heavy_weights_plain(ctx, name, make, omega, delta, incremental):
+    from paper_2604_14411_amd import hgp
+
+    g = make()
+    rc, ref, rres, tr = oracle.partition(g, omega, delta, trace=True)
+    assert rc == 0
+    wide = levelstats.wide_counter_nodes(tr, g.hedge_w, omega)
+    say(f"[wide] {name} omega={omega} delta={delta} levels={tr.levels} wide node-levels={wide}")
+    assert wide > 0, "the case does not reach the 64-bit counters"
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    parts, res = hgp.partition_device(ctx, dg, omega, delta, flags=0 if incremental else hgp.FLAG_NO_INCREMENTAL)
+    assert np.array_equal(parts.cpu().numpy(), ref), "part ids differ"
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds"):
+        assert res[key] == rres[key], (key, res[key], rres[key])
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_heavy_weights_learned(ctx, seed):
+    from paper_2604_14411_amd import hgp
+
+    g = synth.random_snn(3000, 30.0, 303, 1, 60000)
+    q = synth.random_int_mlp(seed)
+    rc, ref, rres, tr = oracle.partition_learned(g, 128, 600, q, trace=True)
+    assert rc == 0
+    wide = levelstats.wide_counter_nodes(tr, g.hedge_w, 128)
+    say(f"[wide] learned seed={seed} levels={tr.levels} wide node-levels={wide} fallback={rres['n_fallback']}")
+    assert wide > 0
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    parts, res = hgp.partition_device(ctx, dg, 128, 600, mlp=q)
+    assert np.array_equal(parts.cpu().numpy(), ref), "part ids differ"
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds", "n_fallback"):
+        assert res[key] == rres[key], (key, res[key], rres[key])
+
+
+LAYERED = ["conv12k_3x3", "conv12k_5x5", "conv12k_3x3_learned", "conv12k_5x5_learned"]
+
+
+@pytest.mark.parametrize("name", LAYERED)
+def test_layered_at_large_bounds_matches_oracle_golden(ctx, name):
+    """Layered networks at Omega = 4096, Delta = 65,536, against results the
+    oracle wrote (tests/golden/make_golden.py)."""
+    from make_golden import load_int_network, spec
+
+    from paper_2604_14411_amd import hgp
+
+    gold = json.load(open(os.path.join(HERE, "golden", f"{name}.json")))
+    make, omega, delta, mlp_path, _ = spec(name)
+    g = make()
+    assert g.digest() == gold["input_sha256"]
+    q = load_int_network(mlp_path) if mlp_path else None
+    say(f"[golden] {name} n={g.n_nodes} pins={g.n_pins}")
+    dg = hgp.DeviceHypergraph(g, "cuda:0")
+    parts, res = hgp.partition_device(ctx, dg, omega, delta, mlp=q)
+    digest = hashlib.sha256(np.ascontiguousarray(parts.cpu().numpy(), dtype="<i4").tobytes()).hexdigest()
+    assert digest == gold["parts_sha256"]
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds"):
+        assert res[key] == gold[key], (key, res[key], gold[key])
+    if q is not None:
+        assert res["n_fallback"] == gold["n_fallback"]

@@ -26,8 +26,8 @@ def _case(seed):
     n = rng.randint(2, 12)
     hedges, w, nw = brute.random_tiny(rng, n, rng.randint(1, 10), 5, wmax=5, node_wmax=rng.choice([1, 1, 3]))
     g = from_lists(n, hedges, w, nw)
-    omega = rng.randint(2, 9)
-    delta = rng.randint(1, 7)
+    omega = rng.randint(1, 9)
+    delta = rng.randint(0, 7)
     k = rng.choice([0, 0, 0, 1, 2])
     rounds = rng.choice([1, 2, 8])
     return g, omega, delta, k, rounds
@@ -101,7 +101,7 @@ def test_oracle_not_below_exhaustive_optimum(seed):
     n = rng.randint(2, 8)
     hedges, w, nw = brute.random_tiny(rng, n, rng.randint(1, 8), 4, wmax=4)
     g = from_lists(n, hedges, w, nw)
-    omega, delta = rng.randint(2, 5), rng.randint(2, 6)
+    omega, delta = rng.randint(1, 5), rng.randint(1, 6)
     L0 = brute.level_from_input(g)
     rc, parts, res, _ = oracle.partition(g, omega, delta)
     if not _feasible(L0, omega, delta):
