@@ -80,6 +80,9 @@ typedef struct {
 /* hgp_options.flags */
 #define HGP_FLAG_TIME_KERNELS 1   /* time kernel classes with HIP events on the call's stream */
 #define HGP_FLAG_NO_INCREMENTAL 2 /* rate every level and propose every round from scratch (same result) */
+#define HGP_FLAG_EXACT_MATCHING 4 /* plain proposal: exact maximum-weight matching of the pairing
+                                     pseudo-forest (hgp_level_match_ex, HGP_MATCH_EXACT) instead of
+                                     the two traversals of Sec. III-A; changes the result */
 
 /* kernel classes reported in hgp_result.ms_kernel / n_kernel / units_kernel */
 #define HGP_K_RATE 0       /* candidate rating + selection; unit: pin-pair visit (sum |e|^2 per level) */
@@ -140,7 +143,10 @@ typedef struct {
   int32_t flags;             /* HGP_FLAG_* bits, 0 by default */
   const hgp_mlp *mlp;        /* host memory; required with HGP_LEARNED, read during the call */
   int32_t constraint;        /* HGP_INBOUND (default), HGP_OUTBOUND or HGP_INCIDENT */
-  int32_t reserved;          /* 0 */
+  int32_t time_classes;      /* with HGP_FLAG_TIME_KERNELS: bit c set times class c (HGP_K_*) with
+                                HIP events and counts its units, 0 does so for every class; each timed
+                                launch records two events on the stream and the counting kernels add
+                                atomics, so timing fewer classes perturbs the run less */
 } hgp_options;
 
 typedef struct {
@@ -152,7 +158,8 @@ typedef struct {
   double ms_coarsen;    /* host wall-clock of the coarsening phase */
   double ms_refine;     /* host wall-clock of the refinement phase */
   /* with HGP_FLAG_TIME_KERNELS: summed kernel time, launches and algorithmic
-     units per kernel class (HGP_K_*); zero otherwise */
+     units per kernel class (HGP_K_*) of the timed classes (time_classes);
+     zero otherwise (units counted on the host may appear for every class) */
   double ms_kernel[HGP_NKERNEL];
   int64_t n_kernel[HGP_NKERNEL];
   int64_t units_kernel[HGP_NKERNEL];
@@ -256,6 +263,25 @@ int hgp_level_rate(hgp_ctx *ctx, const hgp_level *lv, int32_t omega, int32_t del
  */
 int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, void *stream,
                     int32_t *match_out, int32_t *gamma_out, int32_t *n_next);
+
+/*
+ * Matching rules.  HGP_MATCH_TRAVERSAL is hgp_level_match above (Sec. III-A).
+ * HGP_MATCH_EXACT is the dynamic-programming formulation Sec. VI names as
+ * future work: a maximum-weight matching of the pairing edges {n, pair(n)}
+ * (weight score(n)) in each component, by the tree recursion
+ *   children(v) = {c : pair(c) = v} without v's 2-cycle partner,
+ *   g(v) = sum of f(c) over the children, d(v) = max over the children of
+ *   g(c) + score(c) - f(c) (argmax c*(v) by value, then larger id),
+ *   f(v) = g(v) + max(0, d(v)); v takes c*(v) when d(v) >= 0 and it is not
+ *   matched upward; a 2-cycle {a, b} matches iff
+ *   g(a) + g(b) + score(a) >= f(a) + f(b).
+ * Scores of nodes with a candidate must lie in [0, 2^31) (HGP_EINVAL).
+ * Outputs as hgp_level_match.
+ */
+#define HGP_MATCH_TRAVERSAL 0
+#define HGP_MATCH_EXACT 1
+int hgp_level_match_ex(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, int32_t rule,
+                       void *stream, int32_t *match_out, int32_t *gamma_out, int32_t *n_next);
 
 /*
  * Coarse hypergraph (Sec. III-B): hedge pins mapped through gamma and

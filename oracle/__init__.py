@@ -80,6 +80,12 @@ def _load():
         lib.hgpo_partition_role.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(_Res),
                                             ctypes.c_void_p]
+        lib.hgpo_partition_ex.restype = ctypes.c_int
+        lib.hgpo_partition_ex.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(_Res), ctypes.c_void_p]
+        lib.hgpo_match.restype = ctypes.c_int
+        lib.hgpo_match.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         lib.hgpo_partition_learned.restype = ctypes.c_int
         lib.hgpo_partition_learned.argtypes = [ctypes.POINTER(_HG), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.POINTER(_MLP), ctypes.c_void_p,
@@ -153,10 +159,13 @@ class Trace:
 
 
 INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
+MATCH_TRAVERSAL, MATCH_EXACT = 0, 1
 
 
-def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace: bool = False, role: int = INBOUND):
-    """Run the oracle (role: which pins' hedges count toward Delta).
+def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace: bool = False, role: int = INBOUND,
+              matching: int = MATCH_TRAVERSAL):
+    """Run the oracle (role: which pins' hedges count toward Delta; matching:
+    the paper's two traversals or the exact tree recursion).
     Returns (rc, parts, result dict, Trace or None)."""
     lib = _load()
     keep = []
@@ -164,8 +173,8 @@ def partition(g, omega: int, delta: int, k: int = 0, max_rounds: int = 8, trace:
     parts = np.zeros(max(g.n_nodes, 1), dtype=np.int32)
     res = _Res()
     tr = Trace() if trace else None
-    rc = lib.hgpo_partition_role(ctypes.byref(hg), omega, delta, k, max_rounds, role, parts.ctypes.data,
-                                 ctypes.byref(res), tr.ptr if tr else None)
+    rc = lib.hgpo_partition_ex(ctypes.byref(hg), omega, delta, k, max_rounds, role, matching, parts.ctypes.data,
+                               ctypes.byref(res), tr.ptr if tr else None)
     out = dict(connectivity=res.connectivity, n_parts=res.n_parts, n_levels=res.n_levels, n_rounds=res.n_rounds)
     return rc, parts[:g.n_nodes], out, tr
 
@@ -185,6 +194,18 @@ def partition_learned(g, omega: int, delta: int, mlp, k: int = 0, max_rounds: in
     out = dict(connectivity=res.connectivity, n_parts=res.n_parts, n_levels=res.n_levels, n_rounds=res.n_rounds,
                n_fallback=res.n_fallback)
     return rc, parts[:g.n_nodes], out, tr
+
+
+def match(pair, score, matching: int = MATCH_TRAVERSAL) -> np.ndarray:
+    """One matching of the pairing pseudo-forest (pair: -1 = none)."""
+    lib = _load()
+    p = np.ascontiguousarray(pair, dtype=np.int32)
+    sc = np.ascontiguousarray(score, dtype=np.int64)
+    out = np.zeros(max(len(p), 1), dtype=np.int32)
+    rc = lib.hgpo_match(len(p), p.ctypes.data, sc.ctypes.data, matching, out.ctypes.data)
+    if rc != OK:
+        raise ValueError(f"hgpo_match rc={rc}")
+    return out[:len(p)]
 
 
 def mlp_score(mlp, xq) -> np.ndarray:

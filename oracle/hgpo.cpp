@@ -23,6 +23,7 @@
 #include <map>
 #include <new>
 #include <utility>
+#include <stdexcept>
 #include <vector>
 
 #ifdef _OPENMP
@@ -235,6 +236,81 @@ void match_pairs(const std::vector<int32_t> &pair, const std::vector<int64_t> &s
       match[n] = pair[n];
     else if (best[n] >= 0 && up[best[n]] == 1)
       match[n] = best[n];
+    else
+      match[n] = n;
+  }
+}
+
+/*
+ * Exact matching on the pairing pseudo-forest: the dynamic-programming
+ * formulation the paper names as future work (Sec. VI), replacing the
+ * two-traversal heuristic of Sec. III-A.  Each component is a tree hanging
+ * from a 2-cycle, or from a node without candidate; its edges are the pairing
+ * edges {n, pair(n)} of weight score(n).  The textbook tree recursion gives a
+ * maximum-weight matching:
+ *   children(v) = {c : pair(c) = v}, without v's 2-cycle partner
+ *   g(v) = sum of f(c) over the children      (v left free for its parent)
+ *   d(v) = max over the children of g(c) + score(c) - f(c), argmax c*(v)
+ *          by (value, id), larger id on ties; no children: no d(v)
+ *   f(v) = g(v) + max(0, d(v))                (best matching of v's subtree)
+ *   v is matched to c*(v) unless matched upward, when d(v) >= 0
+ * A 2-cycle {a, b} is matched iff g(a) + g(b) + score(a) >= f(a) + f(b).
+ * Ties favour matching (d(v) = 0 still takes c*(v)), which fixes one
+ * matching among those of maximum weight.  Whether a node is matched to its
+ * parent follows the recursion of match_pairs with best = c* and the 2-cycle
+ * decision.
+ */
+void match_exact(const std::vector<int32_t> &pair, const std::vector<int64_t> &score, std::vector<int32_t> &match) {
+  const int32_t N = (int32_t)pair.size();
+  auto root = [&](int32_t v) { return pair[v] < 0 || pair[pair[v]] == v; };
+  /* children lists, and the nodes in an order where children come first
+   * (reverse of a breadth-first order from the roots) */
+  std::vector<std::vector<int32_t>> kids((size_t)N);
+  for (int32_t c = 0; c < N; ++c)
+    if (!root(c)) kids[(size_t)pair[c]].push_back(c);
+  std::vector<int32_t> order;
+  for (int32_t v = 0; v < N; ++v)
+    if (root(v)) order.push_back(v);
+  for (size_t i = 0; i < order.size(); ++i)
+    for (int32_t c : kids[(size_t)order[i]]) order.push_back(c);
+  if ((int32_t)order.size() != N) throw std::logic_error("pairing graph has a cycle longer than two");
+  std::vector<int64_t> g((size_t)N, 0), f((size_t)N, 0);
+  std::vector<int32_t> cstar((size_t)N, -1);
+  for (size_t i = order.size(); i-- > 0;) {
+    const int32_t v = order[i];
+    int64_t gv = 0, best = 0;
+    int32_t bc = -1;
+    for (int32_t c : kids[(size_t)v]) {
+      gv += f[c];
+      const int64_t val = g[c] + score[c] - f[c];
+      if (bc < 0 || val > best || (val == best && c > bc)) {
+        best = val;
+        bc = c;
+      }
+    }
+    g[v] = gv;
+    f[v] = gv + (bc >= 0 && best > 0 ? best : 0);
+    if (bc >= 0 && best >= 0) cstar[v] = bc;
+  }
+  /* up(v): matched to pair(v) */
+  std::vector<int8_t> up((size_t)N, 0);
+  for (int32_t v : order) {
+    const int32_t p = pair[v];
+    if (p < 0) {
+      up[v] = 0;
+    } else if (pair[p] == v) {
+      const int32_t a = std::min(v, p), b = std::max(v, p);
+      up[v] = (g[a] + g[b] + score[a] >= f[a] + f[b]) ? 1 : 0;
+    } else {
+      up[v] = (cstar[p] == v && up[p] == 0) ? 1 : 0; /* the parent comes earlier in `order` */
+    }
+  }
+  match.assign((size_t)N, 0);
+  for (int32_t n = 0; n < N; ++n) {
+    if (up[n] == 1)
+      match[n] = pair[n];
+    else if (cstar[n] >= 0 && up[cstar[n]] == 1)
+      match[n] = cstar[n];
     else
       match[n] = n;
   }
@@ -841,7 +917,8 @@ int hgpo_connectivity(const hgpo_hypergraph *g, const int32_t *part, int64_t *ou
  * initial-part id, skipping emptied parts.
  */
 static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
-                          const hgpo_mlp *mlp, int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+                          const hgpo_mlp *mlp, int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace,
+                          int32_t matching = HGPO_MATCH_TRAVERSAL) {
   int rc = validate(g, omega, delta, k, max_rounds);
   if (rc != HGPO_OK) return rc;
   if (!part_out && g->n_nodes > 0) return HGPO_EINVAL;
@@ -896,7 +973,10 @@ static int partition_impl(const hgpo_hypergraph *g, int32_t omega, int32_t delta
       std::vector<int64_t> score;
       if (!mlp) {
         rate_select(L, w, omega, delta, pair, score);
-        match_pairs(pair, score, match);
+        if (matching == HGPO_MATCH_EXACT)
+          match_exact(pair, score, match);
+        else
+          match_pairs(pair, score, match);
         if (trace) record_candidates(L, l, w, omega, delta, trace);
       } else {
         learned_level(L, l, w, omega, delta, *mlp, pair, score, match, n_fallback, trace);
@@ -990,6 +1070,32 @@ int hgpo_partition_role(const hgpo_hypergraph *g, int32_t omega, int32_t delta, 
                         int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
   if (role != HGPO_INBOUND && role != HGPO_OUTBOUND && role != HGPO_INCIDENT) return HGPO_EINVAL;
   return partition_impl(g, omega, delta, k, max_rounds, nullptr, role, part_out, res, trace);
+}
+
+int hgpo_partition_ex(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                      int32_t role, int32_t matching, int32_t *part_out, hgpo_result *res, hgpo_trace *trace) {
+  if (role != HGPO_INBOUND && role != HGPO_OUTBOUND && role != HGPO_INCIDENT) return HGPO_EINVAL;
+  if (matching != HGPO_MATCH_TRAVERSAL && matching != HGPO_MATCH_EXACT) return HGPO_EINVAL;
+  return partition_impl(g, omega, delta, k, max_rounds, nullptr, role, part_out, res, trace, matching);
+}
+
+int hgpo_match(int32_t n, const int32_t *pair, const int64_t *score, int32_t matching, int32_t *match_out) {
+  if (n < 0 || (n > 0 && (!pair || !score || !match_out))) return HGPO_EINVAL;
+  if (matching != HGPO_MATCH_TRAVERSAL && matching != HGPO_MATCH_EXACT) return HGPO_EINVAL;
+  for (int32_t v = 0; v < n; ++v)
+    if (pair[v] < -1 || pair[v] >= n || pair[v] == v) return HGPO_EINVAL;
+  try {
+    std::vector<int32_t> p(pair, pair + n), m;
+    std::vector<int64_t> sc(score, score + n);
+    if (matching == HGPO_MATCH_EXACT)
+      match_exact(p, sc, m);
+    else
+      match_pairs(p, sc, m);
+    std::copy(m.begin(), m.end(), match_out);
+  } catch (const std::logic_error &) {
+    return HGPO_EINVAL;
+  }
+  return HGPO_OK;
 }
 
 int hgpo_partition_learned(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,

@@ -132,6 +132,19 @@ enum { HGPO_INBOUND = 0, HGPO_OUTBOUND = 1, HGPO_INCIDENT = 2 };
 int hgpo_partition_role(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                         int32_t role, int32_t *part_out, hgpo_result *res, hgpo_trace *trace);
 
+/* Matching rules over the pairing pseudo-forest: the two traversals of
+ * Sec. III-A (the paper's), or the exact maximum-weight matching by the tree
+ * recursion of the dynamic-programming formulation of Sec. VI. */
+enum { HGPO_MATCH_TRAVERSAL = 0, HGPO_MATCH_EXACT = 1 };
+
+/* As hgpo_partition_role with the given matching rule (plain method). */
+int hgpo_partition_ex(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
+                      int32_t role, int32_t matching, int32_t *part_out, hgpo_result *res, hgpo_trace *trace);
+
+/* One matching of n nodes from pair[n] (-1: none; no self pairs, cycles of
+ * length two only) and score[n]: match_out[n] (n itself if unmatched). */
+int hgpo_match(int32_t n, const int32_t *pair, const int64_t *score, int32_t matching, int32_t *match_out);
+
 /* As hgpo_partition with the learned merge proposal (mlp non-NULL). */
 int hgpo_partition_learned(const hgpo_hypergraph *g, int32_t omega, int32_t delta, int32_t k, int32_t max_rounds,
                            const hgpo_mlp *mlp, int32_t *part_out, hgpo_result *res, hgpo_trace *trace);

@@ -345,6 +345,113 @@ __global__ void k_up(const int32_t *__restrict__ pair, const unsigned long long 
   up[n] = (uint8_t)((uint32_t)r ^ parity);
 }
 
+// ---------------------------------------------------------------------------
+// exact matching: the tree recursion over the pairing pseudo-forest
+// ---------------------------------------------------------------------------
+// Components hang from 2-cycles or from nodes without candidate; a node's
+// children are its proposers other than its 2-cycle partner.  With f(v) the
+// best matching weight in v's subtree and g(v) that with v left free:
+//   g(v) = sum of f(c) over the children,
+//   d(v) = max over the children of g(c) + score(c) - f(c) (by value, id),
+//   f(v) = g(v) + max(0, d(v)), and v takes c*(v) when d(v) >= 0;
+// a 2-cycle {a, b} is matched iff g(a) + g(b) + score(a) >= f(a) + f(b).
+// Bottom-up without waiting: a thread starts at every leaf; at each node it
+// adds f to the parent's g, offers (d-candidate, id) to the parent's packed
+// maximum, and the last child to arrive (counter) carries on with the parent,
+// whose sums are then complete.  Scores lie in [0, 2^31), so every
+// d-candidate lies in (-2^31, 2^31) and packs as (value + 2^31) << 32 | id.
+__global__ void k_dp_children(const int32_t *__restrict__ pair, const int64_t *__restrict__ score, int32_t N,
+                              int32_t *__restrict__ nchild, int32_t *err) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int32_t p = pair[n];
+  if (p < 0) return;
+  const int64_t sc = score[n];
+  if (sc < 0 || sc > 2147483647LL) atomicOr(err, kErrWeight);
+  if (pair[p] != (int32_t)n) atomicAdd(&nchild[p], 1);
+}
+
+__global__ void k_dp_climb(const int32_t *__restrict__ pair, const int64_t *__restrict__ score, int32_t N,
+                           const int32_t *__restrict__ nchild, int32_t *__restrict__ arrived,
+                           unsigned long long *__restrict__ gsum, unsigned long long *__restrict__ dkey,
+                           int64_t *__restrict__ f, int32_t *err) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N || nchild[n] != 0) return;
+  int v = (int)n;
+  for (int64_t step = 0; step <= N; ++step) {
+    // every child of v has arrived: its sums are final (read at device scope)
+    const int64_t gv = (int64_t)atomicAdd(&gsum[v], 0ull);
+    const unsigned long long dk = atomicAdd(&dkey[v], 0ull);
+    const int64_t d = dk ? (int64_t)(dk >> 32) - (int64_t(1) << 31) : 0;
+    const int64_t fv = gv + (d > 0 ? d : 0);
+    f[v] = fv;
+    const int32_t p = pair[v];
+    if (p < 0 || pair[p] == v) return;
+    atomicAdd(&gsum[p], (unsigned long long)fv);
+    const int64_t val = gv + score[v] - fv;
+    atomicMax(&dkey[p], ((unsigned long long)(val + (int64_t(1) << 31)) << 32) | (unsigned long long)(uint32_t)v);
+    __threadfence();
+    if (atomicAdd(&arrived[p], 1) + 1 != nchild[p]) return;
+    __threadfence();
+    v = p;
+  }
+  atomicOr(err, kErrInternal);
+}
+
+// best(v) = c*(v) (flag bit 32 set) when d(v) >= 0, else 0; root(v) = 1 on a
+// 2-cycle the recursion matches.
+__global__ void k_dp_decide(const int32_t *__restrict__ pair, const int64_t *__restrict__ score, int32_t N,
+                            const unsigned long long *__restrict__ gsum, const unsigned long long *__restrict__ dkey,
+                            const int64_t *__restrict__ f, unsigned long long *__restrict__ best,
+                            uint8_t *__restrict__ root) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const unsigned long long dk = dkey[n];
+  const int64_t d = dk ? (int64_t)(dk >> 32) - (int64_t(1) << 31) : -1;
+  best[n] = (dk && d >= 0) ? ((1ull << 32) | (dk & 0xffffffffull)) : 0ull;
+  const int32_t p = pair[n];
+  uint8_t r = 0;
+  if (p >= 0 && pair[p] == (int32_t)n) {
+    const int32_t a = min((int32_t)n, p), b = max((int32_t)n, p);
+    r = ((int64_t)gsum[a] + (int64_t)gsum[b] + score[a] >= f[a] + f[b]) ? 1 : 0;
+  }
+  root[n] = r;
+}
+
+// up(n) as in k_up, with best = c* and a 2-cycle matched only when the
+// recursion says so.
+__global__ void k_up_exact(const int32_t *__restrict__ pair, const unsigned long long *__restrict__ best,
+                           const uint8_t *__restrict__ root, int32_t N, uint8_t *__restrict__ up, int32_t *err) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  int u = (int)n;
+  uint32_t parity = 0;
+  int r = -1;
+  for (int64_t step = 0; step <= N; ++step) {
+    const int p = pair[u];
+    if (p < 0) {
+      r = 0;
+      break;
+    }
+    if (pair[p] == u) {
+      r = root[u];
+      break;
+    }
+    const unsigned long long b = best[p];
+    if (!b || (int)(b & 0xffffffffull) != u) {
+      r = 0;
+      break;
+    }
+    parity ^= 1u;
+    u = p;
+  }
+  if (r < 0) {
+    atomicOr(err, kErrInternal);
+    r = 0;
+  }
+  up[n] = (uint8_t)((uint32_t)r ^ parity);
+}
+
 __global__ void k_match(const int32_t *__restrict__ pair, const unsigned long long *__restrict__ best,
                         const uint8_t *__restrict__ up, int32_t N, int32_t *__restrict__ match,
                         int32_t *__restrict__ rep) {
@@ -422,15 +529,6 @@ __global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__
     }
   }
   if (threadIdx.x == 0) cnt[e] = kept;
-}
-
-// Copy each hedge's survivors from the oversized layout to the packed one.
-__global__ void k_pack(const int32_t *__restrict__ old_off, const int32_t *__restrict__ new_off, int32_t E,
-                       const uint32_t *__restrict__ src, uint32_t *__restrict__ dst) {
-  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wid >= E) return;
-  const int a = old_off[wid], b = new_off[wid], len = new_off[wid + 1] - b;
-  for (int j = lane_id(); j < len; j += 64) dst[b + j] = src[a + j];
 }
 
 // ---------------------------------------------------------------------------
@@ -554,6 +652,32 @@ void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned
   HGP_LAUNCH_CHECK();
 }
 
+void launch_match_exact(const int32_t *pair, const int64_t *score, int32_t N, const MatchScratch &m,
+                        unsigned long long *best, uint8_t *up, int32_t *match, int32_t *gamma, int32_t *rep,
+                        int32_t *n_next_dev, int32_t *err, DevBuf &scan_tmp, hipStream_t s) {
+  if (N <= 0) return;
+  KScope ks(7, s);
+  add_units(7, N);
+  fill_i32(m.nchild, N, 0, s);
+  fill_i32(m.arrived, N, 0, s);
+  fill_i64(reinterpret_cast<int64_t *>(m.gsum), N, 0, s);
+  fill_i64(reinterpret_cast<int64_t *>(m.dkey), N, 0, s);
+  const int g = div_up(N, 256);
+  k_dp_children<<<g, 256, 0, s>>>(pair, score, N, m.nchild, err);
+  HGP_LAUNCH_CHECK();
+  k_dp_climb<<<g, 256, 0, s>>>(pair, score, N, m.nchild, m.arrived, m.gsum, m.dkey, m.f, err);
+  HGP_LAUNCH_CHECK();
+  k_dp_decide<<<g, 256, 0, s>>>(pair, score, N, m.gsum, m.dkey, m.f, best, m.root);
+  HGP_LAUNCH_CHECK();
+  k_up_exact<<<g, 256, 0, s>>>(pair, best, m.root, N, up, err);
+  HGP_LAUNCH_CHECK();
+  k_match<<<g, 256, 0, s>>>(pair, best, up, N, match, rep);
+  HGP_LAUNCH_CHECK();
+  scan_i32(rep, gamma, N, n_next_dev, scan_tmp, s);
+  k_gamma<<<g, 256, 0, s>>>(match, N, gamma);
+  HGP_LAUNCH_CHECK();
+}
+
 void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
                          hipStream_t s) {
   if (N <= 0) return;
@@ -563,20 +687,19 @@ void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32
 
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
                      int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
-                     hipStream_t s) {
+                     int32_t *list_buf, hipStream_t s) {
   if (E <= 0) {
     fill_i32(new_hoff, 1, 0, s);
     return;
   }
   KScope ks(4, s);
-  launch_contract_wave(hoff, hpin, E, map, tmp_pins, cnt, s);
+  launch_contract_split(hoff, hpin, E, map, tmp_pins, cnt, list_buf, s);
   if (big.n > 0) {
     k_contract<<<big.n, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, big.list);
     HGP_LAUNCH_CHECK();
   }
   scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);
-  k_pack<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, new_hoff, E, tmp_pins, new_hpin);
-  HGP_LAUNCH_CHECK();
+  launch_pack_split(hoff, new_hoff, E, tmp_pins, new_hpin, list_buf, s);
 }
 
 __global__ void k_check_range(const int32_t *__restrict__ a, int64_t n, int32_t lo, int32_t hi, int32_t *err) {

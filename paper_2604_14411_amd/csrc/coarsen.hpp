@@ -17,6 +17,14 @@ constexpr int32_t kErrInternal = 128;  // internal consistency check
 
 // Hedges longer than kWaveSegMax pins, handled by workgroup-per-hedge kernels.
 constexpr int kWaveSegMax = 1024;
+// Hedges of at most kThreadSegMax pins get their part tables from one thread each.
+constexpr int kThreadSegMax = 16;
+// A level's hedges with kThreadSegMax < |e| <= kWaveSegMax: list[0 .. *count)
+// on the device (null list: every hedge, filtered by length in the kernel).
+struct MidHedges {
+  const int32_t *list = nullptr;
+  const int32_t *count = nullptr;
+};
 struct BigHedges {
   const int32_t *list = nullptr;
   int32_t n = 0;
@@ -37,6 +45,7 @@ struct LevelView {
   const int32_t *total = nullptr;  // [n] sum of w(e) over I(n)
   const int32_t *hw = nullptr;     // [E]
   BigHedges big;                   // hedges longer than kWaveSegMax (a superset is fine)
+  MidHedges mid;                   // this level's hedges for the wave part-table kernel
 };
 
 // --- coarsen.hip ---
@@ -59,20 +68,53 @@ void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,
                   int32_t *match, int32_t *gamma, int32_t *rep, int32_t *n_next_dev, int32_t *err,
                   DevBuf &scan_tmp, hipStream_t s);
+// Scratch of the exact matching, N elements each.
+struct MatchScratch {
+  int32_t *nchild = nullptr;
+  int32_t *arrived = nullptr;
+  unsigned long long *gsum = nullptr;
+  unsigned long long *dkey = nullptr;
+  int64_t *f = nullptr;
+  uint8_t *root = nullptr;
+};
+// Exact maximum-weight matching over the pairing pseudo-forest (tree
+// recursion; outputs as launch_match).  A score outside [0, 2^31) of a node
+// with a candidate sets kErrWeight.
+void launch_match_exact(const int32_t *pair, const int64_t *score, int32_t N, const MatchScratch &m,
+                        unsigned long long *best, uint8_t *up, int32_t *match, int32_t *gamma, int32_t *rep,
+                        int32_t *n_next_dev, int32_t *err, DevBuf &scan_tmp, hipStream_t s);
 void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
                          hipStream_t s);
+// list_buf: E + 1 ints of scratch.
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
                      int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
-                     hipStream_t s);
+                     int32_t *list_buf, hipStream_t s);
 // --- seg.hip ---
-void launch_contract_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
-                          int32_t *cnt, hipStream_t s);
 // Part tables of hedges with at most kWaveSegMax pins and inb(p) of their
 // entries: pinb[0 .. n_parts) is written (not accumulated).  partial: scratch.
 // max_len: an upper bound of the hedge lengths (selects the kernel variant).
-void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int32_t *pt,
-                            uint32_t *ptc, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
-                            int32_t max_len, DevBuf &partial, hipStream_t s);
+// Hedges are list[0 .. *list_n) if list is non-null, else all E (those of at
+// most kThreadSegMax pins are skipped: launch_part_table_thread covers them).
+void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *list,
+                            const int32_t *list_n, const int32_t *rho, int32_t *pt, uint32_t *ptc, int32_t *lam,
+                            uint8_t *solo, int32_t *pinb, int32_t n_parts, int32_t max_len, DevBuf &partial,
+                            hipStream_t s);
+// Part tables of the hedges of at most kThreadSegMax pins; inb(p) counts are
+// added to pinb.
+void launch_part_table_thread(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *rho, int32_t *pt,
+                              uint32_t *ptc, int32_t *lam, uint8_t *solo, int32_t *pinb, int32_t n_parts,
+                              hipStream_t s);
+// list[0 .. *count) = the hedges with lo < |e| <= hi (default: the wave
+// part-table kernel's range kThreadSegMax < |e| <= kWaveSegMax).
+void launch_mid_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s,
+                       int32_t lo = kThreadSegMax, int32_t hi = kWaveSegMax);
+// Coarse pins of every hedge of at most kWaveSegMax pins: short hedges by one
+// thread each, the others by one wave each over a list built here in
+// list_buf (E + 1 ints, count first; reused by launch_pack_split).
+void launch_contract_split(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *out,
+                           int32_t *cnt, int32_t *list_buf, hipStream_t s);
+void launch_pack_split(const int32_t *old_off, const int32_t *new_off, int32_t E, const uint32_t *src, uint32_t *dst,
+                       const int32_t *list_buf, hipStream_t s);
 // list[0 .. count[0]) = hedges longer than kWaveSegMax; count[1] = the
 // longest hedge's length.
 void launch_big_hedges(const int32_t *hoff, int32_t E, int32_t *list, int32_t *count, hipStream_t s);

@@ -343,6 +343,7 @@ __host__ __device__ inline int next_pow2(int x) {
 constexpr int kNKClass = 10;
 struct KTimer {
   bool on = false;
+  uint32_t mask = ~0u;  // classes timed while on; kernels count their own units only for these
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {
@@ -366,7 +367,7 @@ struct KScope {
   int cls;
   hipStream_t s;
   bool on;
-  KScope(int c, hipStream_t st) : cls(c), s(st), on(g_ktimer && g_ktimer->on) {
+  KScope(int c, hipStream_t st) : cls(c), s(st), on(g_ktimer && g_ktimer->on && ((g_ktimer->mask >> c) & 1u)) {
     if (on) g_ktimer->begin(s);
   }
   ~KScope() {
@@ -376,9 +377,12 @@ struct KScope {
 inline void add_units(int cls, int64_t u) {
   if (g_ktimer && g_ktimer->on) g_ktimer->units[cls] += u;
 }
-// Device counter for kernels that count their own algorithmic units.
+// Device counter for kernels that count their own algorithmic units (per
+// wave, atomics on one address: only for the classes being timed).
 inline unsigned long long *units_ptr(int cls) {
-  return (g_ktimer && g_ktimer->on && g_ktimer->units_dev) ? g_ktimer->units_dev + cls : nullptr;
+  return (g_ktimer && g_ktimer->on && g_ktimer->units_dev && ((g_ktimer->mask >> cls) & 1u))
+             ? g_ktimer->units_dev + cls
+             : nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -86,7 +86,8 @@ struct Workspace {
   DevBuf units_dev;
   // incremental late levels
   DevBuf tkA_key, tkA_c, tkA_cnt, tkA_kap, tkB_key, tkB_c, tkB_cnt, tkB_kap, newc, row_slot, nflag, rerate, dev_cnt;
-  DevBuf split, cdest, cgain, maxbits, biglist, tail_acc;
+  DevBuf split, cdest, cgain, maxbits, biglist, midlist, longlist, tail_acc;
+  DevBuf dp_nchild, dp_arrived, dp_g, dp_key, dp_f, dp_root;  // exact matching
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
   // coarse levels kept for refinement: most recent last, within the budget
@@ -135,7 +136,7 @@ struct Workspace {
     lcache_free.clear();
     lcache_held = 0;
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     clear_levels();
@@ -305,6 +306,27 @@ static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStrea
   return b;
 }
 
+// Scratch of the exact matching for n nodes.
+static MatchScratch match_scratch(Workspace &W, int32_t n) {
+  MatchScratch m;
+  m.nchild = need<int32_t>(W.dp_nchild, n);
+  m.arrived = need<int32_t>(W.dp_arrived, n);
+  m.gsum = need<unsigned long long>(W.dp_g, n);
+  m.dkey = need<unsigned long long>(W.dp_key, n);
+  m.f = need<int64_t>(W.dp_f, n);
+  m.root = need<uint8_t>(W.dp_root, n);
+  return m;
+}
+
+// The level's hedges for the wave part-table kernel (list kept in W.midlist,
+// count on the device): built once per level, used by every round.
+static void set_mid(Workspace &W, LevelView &V, hipStream_t s) {
+  int32_t *buf = need<int32_t>(W.midlist, (int64_t)V.E + 1);
+  launch_mid_hedges(V.hoff, V.E, buf + 1, buf, s);
+  V.mid.list = buf + 1;
+  V.mid.count = buf;
+}
+
 // `size_cap` is the element capacity of the buffer behind `size` (checked).
 static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *hoff, const uint32_t *hpin,
                            int64_t P, const int32_t *size, size_t size_cap, const int32_t *hw, const BigHedges &big,
@@ -424,9 +446,10 @@ struct RunStats {
 // Installs the context's kernel timer for the duration of one call.
 struct TimerGuard {
   Workspace &W;
-  TimerGuard(Workspace &w, bool on, hipStream_t s) : W(w) {
+  TimerGuard(Workspace &w, bool on, hipStream_t s, int32_t classes = 0) : W(w) {
     W.timer.reset();
     W.timer.on = on;
+    W.timer.mask = classes ? (uint32_t)classes : ~0u;
     g_ktimer = &W.timer;
     if (on) {
       W.units_dev.reserve(HGP_NKERNEL * sizeof(int64_t));
@@ -606,6 +629,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   if (opt.proposal != HGP_PLAIN && opt.proposal != HGP_LEARNED) throw Error(HGP_EINVAL, "unknown proposal");
   const bool learned = opt.proposal == HGP_LEARNED;
   if (learned) check_mlp(opt.mlp);
+  const bool exact = (opt.flags & HGP_FLAG_EXACT_MATCHING) != 0;
+  if (exact && learned) throw Error(HGP_EINVAL, "exact matching applies to the plain proposal");
   const double t0 = now_ms();
   if (opt.constraint != HGP_INBOUND && opt.constraint != HGP_OUTBOUND && opt.constraint != HGP_INCIDENT)
     throw Error(HGP_EINVAL, "unknown constraint");
@@ -726,7 +751,11 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     W.lv_match.emplace_back();
     int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
     int32_t *lmatch = need<int32_t>(W.lv_match[lvl], n);
-    launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
+    if (exact)
+      launch_match_exact(pair, score, n, match_scratch(W, n), best, up, lmatch, gam, rep, nnext_dev,
+                         W.err.as<int32_t>(), W.scan_tmp, s);
+    else
+      launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
     int32_t n_next = read_i32_checked(W, nnext_dev, s);
     if (learned) {
       // fallback: the plain pairs' matching, used if it merges over twice as many pairs
@@ -780,7 +809,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
     uint32_t *npin = need<uint32_t>(hpin_buf, cur_P);
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
-                    W.scan_tmp, s);
+                    W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1), s);
     add_units(HGP_K_CONTRACT, cur_P);
     cur_P = read_i32(nh + E, s);
     cur_hoff = nh;
@@ -868,7 +897,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
         uint32_t *rp = need<uint32_t>(W.hpinR, P);
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
-                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, s);
+                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1), s);
         add_units(HGP_K_CONTRACT, P);
         Pl = read_i32(rh + E, s);
         h = rh;
@@ -876,6 +905,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       }
       if (!c) V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, big, s);
     }
+    set_mid(W, V, s);
     bool last_applied = false;
     int ran = 0;
     for (int r = 0; r < opt.max_refine_rounds; ++r) {
@@ -1006,8 +1036,10 @@ static LevelView level_view_from(Workspace &W, const hgp_level *lv, hipStream_t 
   launch_check_level(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), lv->n_hedges, lv->n_nodes, err, s);
   check_err(W, s);
   const BigHedges big = find_big(W, lv->hoff, lv->n_hedges, s);
-  return make_view(W, lv->n_nodes, lv->n_hedges, lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), P,
-                   lv->size, (size_t)lv->n_nodes, lv->hedge_w, big, s);
+  LevelView V = make_view(W, lv->n_nodes, lv->n_hedges, lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), P,
+                          lv->size, (size_t)lv->n_nodes, lv->hedge_w, big, s);
+  set_mid(W, V, s);
+  return V;
 }
 
 }  // namespace hgp
@@ -1081,7 +1113,7 @@ int hgp_partition_device(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, i
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (g && g->n_nodes > 0 && !part_out) throw Error(HGP_EINVAL, "part_out is NULL");
     const hgp_options o = opts_or_default(opt);
-    TimerGuard tg(ctx->ws, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+    TimerGuard tg(ctx->ws, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s, o.time_classes);
     RunStats st = run_partition(ctx->ws, g, omega, delta, o, s, part_out);
     tg.collect(st, s);
     HGP_HIP(hipStreamSynchronize(s));
@@ -1142,7 +1174,7 @@ static int partition_host_impl(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t om
     int32_t *po = need<int32_t>(W.in_part, N);
     const hgp_options o = opts_or_default(opt);
     if (trace && o.proposal != HGP_PLAIN) throw Error(HGP_EINVAL, "traces record the plain method");
-    TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+    TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s, o.time_classes);
     struct TraceGuard {
       Workspace &W;
       ~TraceGuard() { W.trace = nullptr; }
@@ -1296,6 +1328,7 @@ static int64_t connectivity_impl(Workspace &W, const hgp_hypergraph *g, const in
   V.hw = I.hw;
   V.size = I.nw;
   V.big = find_big(W, g->hedge_off, E, s);
+  set_mid(W, V, s);
   RoundBufs B = round_bufs(W, N, E, I.P, np);
   launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
   int64_t *conn = need<int64_t>(W.conn, 2);
@@ -1383,8 +1416,8 @@ int hgp_level_rate(hgp_ctx *ctx, const hgp_level *lv, int32_t omega, int32_t del
   });
 }
 
-int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, void *stream,
-                    int32_t *match_out, int32_t *gamma_out, int32_t *n_next) {
+static int level_match_impl(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, int32_t rule,
+                            void *stream, int32_t *match_out, int32_t *gamma_out, int32_t *n_next) {
   if (!ctx || !n_next) {
     g_last_error = "ctx or n_next is NULL";
     return HGP_EINVAL;
@@ -1393,6 +1426,7 @@ int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t 
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (n < 0) throw Error(HGP_EINVAL, "negative count");
+    if (rule != HGP_MATCH_TRAVERSAL && rule != HGP_MATCH_EXACT) throw Error(HGP_EINVAL, "unknown matching rule");
     if (n > 0 && (!pair || !score || !match_out || !gamma_out)) throw Error(HGP_EINVAL, "NULL array");
     Workspace &W = ctx->ws;
     if (n == 0) {
@@ -1407,10 +1441,24 @@ int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t 
     int32_t *nn = need<int32_t>(W.scal2, 4);
     launch_check_range(pair, n, -1, n, W.err.as<int32_t>(), s);
     check_err(W, s);
-    launch_match(pair, score, n, best, up, match_out, gamma_out, rep, nn, W.err.as<int32_t>(), W.scan_tmp, s);
+    if (rule == HGP_MATCH_EXACT)
+      launch_match_exact(pair, score, n, match_scratch(W, n), best, up, match_out, gamma_out, rep, nn,
+                         W.err.as<int32_t>(), W.scan_tmp, s);
+    else
+      launch_match(pair, score, n, best, up, match_out, gamma_out, rep, nn, W.err.as<int32_t>(), W.scan_tmp, s);
     *n_next = read_i32(nn, s);
     check_err(W, s);
   });
+}
+
+int hgp_level_match(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, void *stream,
+                    int32_t *match_out, int32_t *gamma_out, int32_t *n_next) {
+  return level_match_impl(ctx, n, pair, score, HGP_MATCH_TRAVERSAL, stream, match_out, gamma_out, n_next);
+}
+
+int hgp_level_match_ex(hgp_ctx *ctx, int32_t n, const int32_t *pair, const int64_t *score, int32_t rule,
+                       void *stream, int32_t *match_out, int32_t *gamma_out, int32_t *n_next) {
+  return level_match_impl(ctx, n, pair, score, rule, stream, match_out, gamma_out, n_next);
 }
 
 int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, int32_t n_next, void *stream,
@@ -1439,7 +1487,8 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
     int32_t *cnt = need<int32_t>(W.cnt, E);
     const BigHedges big = find_big(W, lv->hoff, E, s);
     launch_contract(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, gamma, tmp, cnt, hoff_out,
-                    reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, s);
+                    reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1),
+                    s);
     // cluster sizes: sum of member sizes (atomics over the fine nodes)
     fill_i32(size_out, n_next, 0, s);
     launch_cluster_size_sum(gamma, lv->size, lv->n_nodes, size_out, s);
@@ -1615,7 +1664,7 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
         if (i >= n) break;
         const int32_t g = order[(size_t)i];
         const double a = now_ms() - t0;
-        TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s);
+        TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s, o.time_classes);
         RunStats st = run_partition(W, &graphs[g], omega[g], delta[g], o, s, part_out[g]);
         tg.collect(st, s);
         HGP_HIP(hipStreamSynchronize(s));

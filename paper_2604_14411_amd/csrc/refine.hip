@@ -108,14 +108,17 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   KScope ks(2, s);
   add_units(2, 0);
   if (!B.partial) throw Error(-7, "part-table scratch missing");
-  launch_part_table_wave(L.hoff, L.hpin, L.E, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, n_parts, L.big.max_len,
-                         *B.partial, s);
+  // pinb is written by the wave kernel's reduction (or zeroed by it), then
+  // the workgroup and thread kernels add their hedges' counts
+  launch_part_table_wave(L.hoff, L.hpin, L.E, L.mid.list, L.mid.count, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb,
+                         n_parts, L.big.max_len, *B.partial, s);
   if (L.E > 0) {
     if (L.big.n > 0) {
       k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
                                              L.big.list);
       HGP_LAUNCH_CHECK();
     }
+    launch_part_table_thread(L.hoff, L.hpin, L.E, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, n_parts, s);
   }
   if (L.n > 0 && L.size) {
     if (n_parts > 0 && n_parts <= PS_LDS_PARTS) {

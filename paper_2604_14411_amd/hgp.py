@@ -21,6 +21,8 @@ INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
 MLP_F, MLP_H = 16, 64
 FLAG_TIME_KERNELS = 1
 FLAG_NO_INCREMENTAL = 2
+FLAG_EXACT_MATCHING = 4
+MATCH_TRAVERSAL, MATCH_EXACT = 0, 1
 KERNEL_CLASSES = ["rate", "propose", "part_table", "seq_events", "contract", "incidence", "sort", "match",
                   "rate_tail", "mlp"]
 NK = len(KERNEL_CLASSES)
@@ -111,7 +113,7 @@ class BatchSched_t(ctypes.Structure):
 class Options_t(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("max_refine_rounds", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32), ("mlp", ctypes.POINTER(Mlp_t)),
-                ("constraint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("constraint", ctypes.c_int32), ("time_classes", ctypes.c_int32)]
 
 
 class Result_t(ctypes.Structure):
@@ -133,7 +135,7 @@ EXPORTS = [
     "hgp_mlp_score_device", "hgp_mlp_init", "hgp_mlp_grad", "hgp_mlp_train", "hgp_mlp_quantize",
     "hgp_trace_create", "hgp_trace_destroy", "hgp_partition_traced", "hgp_trace_rows", "hgp_trace_read",
     "hgp_partition_batch_device", "hgp_batch_tune", "hgp_connectivity", "hgp_train_state_init",
-    "hgp_mlp_train_state", "hgp_mlp_save", "hgp_mlp_load",
+    "hgp_mlp_train_state", "hgp_mlp_save", "hgp_mlp_load", "hgp_level_match_ex",
 ]
 
 _lib = None
@@ -166,6 +168,7 @@ def load():
     lib.hgp_level_canonical.argtypes = [vp, HG, i32, i32, vp, vp, vp]
     lib.hgp_level_rate.argtypes = [vp, LV, i32, i32, vp, vp, vp]
     lib.hgp_level_match.argtypes = [vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32)]
+    lib.hgp_level_match_ex.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, ctypes.POINTER(i32)]
     lib.hgp_level_contract.argtypes = [vp, LV, vp, i32, vp, vp, vp, vp]
     lib.hgp_level_refine_round.argtypes = [vp, LV, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64p]
     MP = ctypes.POINTER(Mlp_t)
@@ -240,13 +243,15 @@ class Context:
         self.close()
 
 
-def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0, mlp=None, constraint: int = 0):
+def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 0, mlp=None, constraint: int = 0,
+            time_classes: int = 0):
     """hgp_options; with an integer network dict `mlp` the learned proposal is selected.
     Returns (Options_t, keep-alive object)."""
     o = Options_t()
     load().hgp_options_default(ctypes.byref(o))
     o.k, o.max_refine_rounds, o.seed, o.flags = k, max_refine_rounds, seed, flags
     o.constraint = constraint
+    o.time_classes = time_classes
     m = None
     if mlp is not None:
         m = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
@@ -296,7 +301,8 @@ def partition_host(ctx: Context, g, omega: int, delta: int, k: int = 0, max_refi
 
 
 def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int, k: int = 0,
-                     max_refine_rounds: int = 8, out=None, flags: int = 0, mlp=None, constraint: int = 0):
+                     max_refine_rounds: int = 8, out=None, flags: int = 0, mlp=None, constraint: int = 0,
+                     time_classes: int = 0):
     """hgp_partition_device; returns (parts tensor on device, result dict)."""
     import torch
 
@@ -305,7 +311,7 @@ def partition_device(ctx: Context, dg: DeviceHypergraph, omega: int, delta: int,
         out = torch.empty(max(dg.n_nodes, 1), dtype=torch.int32, device=dg.hedge_off.device)
     hg = dg.struct()
     res = Result_t()
-    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp, constraint=constraint)
+    o, _keep = options(k, max_refine_rounds, 0, flags, mlp=mlp, constraint=constraint, time_classes=time_classes)
     _check(lib.hgp_partition_device(ctx.handle, ctypes.byref(hg), omega, delta, ctypes.byref(o), _stream(),
                                     out.data_ptr(), ctypes.byref(res)))
     return out[:dg.n_nodes], _result_dict(res)
@@ -363,7 +369,9 @@ def level_rate(ctx: Context, n, hoff, hpin, size, hw, omega: int, delta: int):
     return pair[:n], score[:n]
 
 
-def level_match(ctx: Context, pair, score):
+def level_match(ctx: Context, pair, score, rule: int = MATCH_TRAVERSAL):
+    """hgp_level_match_ex on device pair (int32) and score (int64) tensors;
+    returns (match, gamma, number of clusters)."""
     import torch
 
     lib = load()
@@ -371,8 +379,8 @@ def level_match(ctx: Context, pair, score):
     match = torch.empty(max(n, 1), dtype=torch.int32, device=pair.device)
     gamma = torch.empty(max(n, 1), dtype=torch.int32, device=pair.device)
     nn = ctypes.c_int32()
-    _check(lib.hgp_level_match(ctx.handle, n, _ptr(pair), _ptr(score), _stream(), match.data_ptr(),
-                               gamma.data_ptr(), ctypes.byref(nn)))
+    _check(lib.hgp_level_match_ex(ctx.handle, n, _ptr(pair), _ptr(score), rule, _stream(), match.data_ptr(),
+                                  gamma.data_ptr(), ctypes.byref(nn)))
     return match[:n], gamma[:n], nn.value
 
 

@@ -315,3 +315,48 @@ def pair_features(L: Lvl, level, omega, delta, n, m, hist, c):
     f = [hist, c, L.size[a], L.size[b], uni, len(L.I(a)), len(L.I(b)), level, omega - L.size[a] - L.size[b],
          delta - uni]
     return [qlog_closed(x) for x in f] + [0] * 6
+
+
+def pairing_edges(pair, score):
+    """The edges {n, pair(n)} of a pairing pseudo-forest with their weight
+    score(n) (a 2-cycle gives one edge)."""
+    edges = {}
+    for n, p in enumerate(pair):
+        if p >= 0:
+            key = (min(n, p), max(n, p))
+            edges[key] = int(score[n])
+    return edges
+
+
+def max_weight_matching(pair, score):
+    """Weight of a maximum-weight matching over the pairing edges, by trying
+    every subset of edges (tiny inputs only)."""
+    edges = list(pairing_edges(pair, score).items())
+    best = 0
+    for r in range(len(edges) + 1):
+        for sub in itertools.combinations(edges, r):
+            used = set()
+            ok = True
+            for (a, b), _ in sub:
+                if a in used or b in used:
+                    ok = False
+                    break
+                used.add(a)
+                used.add(b)
+            if ok:
+                best = max(best, sum(x for _, x in sub))
+    return best
+
+
+def matching_weight(pair, score, match):
+    """Total weight of a matching given as match[n] (n if unmatched); checks it
+    is an involution over pairing edges."""
+    edges = pairing_edges(pair, score)
+    tot = 0
+    for n, m in enumerate(match):
+        m = int(m)
+        assert int(match[m]) == n, "matching is not an involution"
+        if m > n:
+            assert (n, m) in edges, "matched pair is not a pairing edge"
+            tot += edges[(n, m)]
+    return tot
