@@ -330,6 +330,22 @@ int hgp_level_learned(hgp_ctx *ctx, const hgp_level *lv, int32_t level, int32_t 
 int hgp_mlp_score_device(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score,
                          void *stream);
 
+/*
+ * hgp_mlp_score_device for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments and results, but the staged copy of the network
+ * and the intermediate int32 scores live in a fixed scratch array of the
+ * library instead of context buffers, so the call makes no device allocation.
+ * The array holds HGP_NOALLOC_MAX_ROWS rows (about 16 MiB); every device the
+ * library runs on keeps its own copy until the process ends.  n above
+ * HGP_NOALLOC_MAX_ROWS gives HGP_EUNSUPPORTED (nothing is launched).  All
+ * calls on one device share that device's scratch: calls that overlap on a
+ * device (other streams or threads) race, and the caller must order them.
+ */
+#define HGP_NOALLOC_MAX_ROWS (1 << 22)
+int hgp_mlp_score_device_noalloc(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score,
+                                 void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batches of independent hypergraphs
  * ------------------------------------------------------------------------- */

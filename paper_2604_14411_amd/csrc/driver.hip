@@ -155,6 +155,7 @@ struct hgp_trace {
 
 struct hgp_ctx {
   int device = 0;
+  void *noalloc_scratch = nullptr;  // device address of the scoring scratch on `device`
   hgp::Workspace ws;
   // batch workers: one workspace and one stream each
   std::vector<std::unique_ptr<hgp::Workspace>> pool;
@@ -1087,8 +1088,10 @@ int hgp_ctx_create(hgp_ctx **ctx, int device) {
     if (device < 0 || device >= count) throw Error(HGP_EINVAL, "no such device");
     DeviceGuard dg(device);
     HGP_HIP(hipFree(nullptr));
+    void *scratch = noalloc_scratch_init(device);
     hgp_ctx *c = new hgp_ctx();
     c->device = device;
+    c->noalloc_scratch = scratch;
     *ctx = c;
   });
 }
@@ -1593,6 +1596,22 @@ int hgp_mlp_score_device(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, in
     int32_t *tmp = need<int32_t>(W.cs, n);
     launch_mlp_score_codes(xq, n, params, tmp, s);
     launch_widen_scores(tmp, n, score, s);
+  });
+}
+
+int hgp_mlp_score_device_noalloc(hgp_ctx *ctx, const hgp_mlp *mlp, const int32_t *xq, int64_t n, int64_t *score,
+                                 void *stream) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    if (n < 0 || (n > 0 && (!xq || !score))) throw Error(HGP_EINVAL, "bad arguments");
+    check_mlp(mlp);
+    if (n > HGP_NOALLOC_MAX_ROWS)
+      throw Error(HGP_EUNSUPPORTED, "more than HGP_NOALLOC_MAX_ROWS rows for the allocation-free scoring");
+    mlp_score_noalloc(ctx->noalloc_scratch, mlp, xq, n, score, static_cast<hipStream_t>(stream));
   });
 }
 

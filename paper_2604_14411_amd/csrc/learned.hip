@@ -14,6 +14,8 @@
 // activations in 0..255) and every partial sum stays below 2^24 in magnitude,
 // so the FP32 accumulation of v_mfma_f32_32x32x8_bf16 is exact in any order
 // and the scores are bit-identical for (n, m) and (m, n).
+#include <mutex>
+
 #include "learned.hpp"
 
 namespace hgp {
@@ -669,6 +671,52 @@ void launch_cand_ids(const CandBufs &B, int64_t C, int32_t N, int32_t *ids, hipS
   const int idbits = std::max(1, bits_for(N - 1));
   k_cand_ids<<<div_up(C, 256), 256, 0, s>>>(B.cnm, C, idbits, ids);
   HGP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// scoring without device allocation
+// ---------------------------------------------------------------------------
+// The scratch of hgp_mlp_score_device_noalloc: the integer network staged
+// from host memory, then the int32 scores of up to HGP_NOALLOC_MAX_ROWS rows
+// before they are widened.  One copy per device (each device that loads the
+// library's code object holds its own), kept until the process ends.  Host
+// code must not pass `scratch` itself to a kernel: its name on the host is a
+// stand-in, not a device address.  noalloc_scratch_init looks the address up
+// once per device, with that device current, and later calls use it.
+constexpr size_t kNoAllocParamBytes = (sizeof(hgp_mlp) + 255) & ~size_t(255);
+constexpr size_t kNoAllocBytes = kNoAllocParamBytes + (size_t)HGP_NOALLOC_MAX_ROWS * sizeof(int32_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void *noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error(HGP_EUNSUPPORTED, "device id beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    HGP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(HGP_EDEVICE, "no device address for the scoring scratch");
+    g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
+void mlp_score_noalloc(void *scratch_dev, const hgp_mlp *q, const int32_t *xq, int64_t n, int64_t *score,
+                       hipStream_t s) {
+  if (!scratch_dev) throw Error(HGP_EINTERNAL, "scoring scratch not set up");
+  if (n > HGP_NOALLOC_MAX_ROWS) throw Error(HGP_EUNSUPPORTED, "more rows than the allocation-free scratch holds");
+  if (n <= 0) return;
+  // every byte read below is written first: the network by the copy, the
+  // int32 scores by the scoring kernel, so nothing needs clearing
+  unsigned char *base = static_cast<unsigned char *>(scratch_dev);
+  HGP_HIP(hipMemcpyAsync(base, q, sizeof(hgp_mlp), hipMemcpyHostToDevice, s));
+  int32_t *tmp = reinterpret_cast<int32_t *>(base + kNoAllocParamBytes);
+  launch_mlp_score_codes(xq, n, reinterpret_cast<const int32_t *>(base), tmp, s);
+  launch_widen_scores(tmp, n, score, s);
 }
 
 }  // namespace hgp

@@ -77,6 +77,11 @@ void train_state_init(hgp_train_state *st, const hgp_mlp_f32 *w, uint64_t seed);
 void mlp_train(hgp_train_state *st, const int32_t *xq, const float *y, int64_t n, const hgp_train_opts &o,
                int32_t epochs, DevBuf &prm, DevBuf &mom, DevBuf &part, DevBuf &perm, DevBuf &lossb,
                float *loss_epochs, hipStream_t s);
+// Allocation-free scoring: the per-device scratch address (looked up once per
+// device, with that device current) and the scoring on it.
+void *noalloc_scratch_init(int device);
+void mlp_score_noalloc(void *scratch_dev, const hgp_mlp *q, const int32_t *xq, int64_t n, int64_t *score,
+                       hipStream_t s);
 // Checkpoint files (checkpoint.hip); throw Error on failure.
 void ckpt_save(const char *path, const hgp_train_state *st, const hgp_mlp *q, int32_t score_shift);
 void ckpt_load(const char *path, hgp_train_state *st, hgp_mlp *q, int32_t *score_shift);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhgp.so")
 
 OK, EINVAL, EBADCSR, EINFEASIBLE, ENOMEM, EDEVICE, EUNSUPPORTED, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 EIO, EFORMAT = -8, -9
+NOALLOC_MAX_ROWS = 1 << 22
 PLAIN, LEARNED = 0, 1
 INBOUND, OUTBOUND, INCIDENT = 0, 1, 2
 MLP_F, MLP_H = 16, 64
@@ -135,7 +136,7 @@ EXPORTS = [
     "hgp_mlp_score_device", "hgp_mlp_init", "hgp_mlp_grad", "hgp_mlp_train", "hgp_mlp_quantize",
     "hgp_trace_create", "hgp_trace_destroy", "hgp_partition_traced", "hgp_trace_rows", "hgp_trace_read",
     "hgp_partition_batch_device", "hgp_batch_tune", "hgp_connectivity", "hgp_train_state_init",
-    "hgp_mlp_train_state", "hgp_mlp_save", "hgp_mlp_load", "hgp_level_match_ex",
+    "hgp_mlp_train_state", "hgp_mlp_save", "hgp_mlp_load", "hgp_mlp_score_device_noalloc", "hgp_level_match_ex",
 ]
 
 _lib = None
@@ -175,6 +176,7 @@ def load():
     lib.hgp_level_learned.argtypes = [vp, LV, i32, i32, i32, MP, vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp,
                                       i64p]
     lib.hgp_mlp_score_device.argtypes = [vp, MP, vp, ctypes.c_int64, vp, vp]
+    lib.hgp_mlp_score_device_noalloc.argtypes = [vp, MP, vp, ctypes.c_int64, vp, vp]
     FP = ctypes.POINTER(MlpF32_t)
     lib.hgp_mlp_init.argtypes = [FP, ctypes.c_uint64]
     lib.hgp_mlp_grad.argtypes = [vp, FP, vp, vp, ctypes.c_int64, FP, ctypes.POINTER(ctypes.c_double), vp]
@@ -463,6 +465,21 @@ def mlp_score_device(ctx: Context, mlp, xq):
 
 
 # ---------------------------------------------------------------- training
+def mlp_score_device_noalloc(ctx: Context, mlp, xq, out=None):
+    """hgp_mlp_score_device_noalloc: the network on device rows xq [n,16]
+    without device allocation in the library (out: int64 [n] device tensor;
+    allocated here by torch when not given)."""
+    import torch
+
+    m = mlp if isinstance(mlp, Mlp_t) else mlp_struct(mlp)
+    n = int(xq.shape[0])
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.int64, device=xq.device)
+    _check(load().hgp_mlp_score_device_noalloc(ctx.handle, ctypes.byref(m), _ptr(xq.contiguous()), n, _ptr(out),
+                                               _stream()))
+    return out[:n]
+
+
 def mlp_init(seed: int) -> dict:
     """Seeded initial float weights (hgp_mlp_init)."""
     w = MlpF32_t()
