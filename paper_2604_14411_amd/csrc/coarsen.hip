@@ -492,14 +492,10 @@ __global__ void k_cluster_size(const int32_t *__restrict__ match, const int32_t 
 // One workgroup per hedge: map pins through `map`, sort (id << 1 | dst),
 // keep the last key of every id run (its low bit is the OR of the run's
 // destination flags), write the survivors at the hedge's old offset.
-__global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__ hoff,
-                                                     const uint32_t *__restrict__ hpin,
-                                                     const int32_t *__restrict__ map, uint32_t *__restrict__ out,
-                                                     int32_t *__restrict__ cnt, const int32_t *__restrict__ list) {
-  __shared__ uint32_t key[kSegCap];
-  __shared__ int32_t pos[kSegCap];
-  __shared__ int32_t tmp[SEG_NT / 64 + 1];
-  const int e = list[blockIdx.x];
+__device__ __forceinline__ void contract_block(int e, const int32_t *__restrict__ hoff,
+                                               const uint32_t *__restrict__ hpin, const int32_t *__restrict__ map,
+                                               uint32_t *__restrict__ out, int32_t *__restrict__ cnt, uint32_t *key,
+                                               int32_t *pos, int32_t *tmp) {
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
   if (len <= 0) {
@@ -529,6 +525,23 @@ __global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__
     }
   }
   if (threadIdx.x == 0) cnt[e] = kept;
+}
+
+// Workgroup per hedge, grid-stride over list[0 .. count): count from the
+// device when list_n is set, else n_fixed.
+__global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__ hoff,
+                                                     const uint32_t *__restrict__ hpin,
+                                                     const int32_t *__restrict__ map, uint32_t *__restrict__ out,
+                                                     int32_t *__restrict__ cnt, const int32_t *__restrict__ list,
+                                                     const int32_t *__restrict__ list_n, int32_t n_fixed) {
+  __shared__ uint32_t key[kSegCap];
+  __shared__ int32_t pos[kSegCap];
+  __shared__ int32_t tmp[SEG_NT / 64 + 1];
+  const int count = list_n ? *list_n : n_fixed;
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    contract_block(list[t], hoff, hpin, map, out, cnt, key, pos, tmp);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -695,7 +708,10 @@ void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const
   KScope ks(4, s);
   launch_contract_split(hoff, hpin, E, map, tmp_pins, cnt, list_buf, s);
   if (big.n > 0) {
-    k_contract<<<big.n, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, big.list);
+    // this level's hedges above kWaveSegMax (the level-0 list is a superset)
+    int32_t *bl = list_buf + E + 1;
+    launch_mid_hedges(hoff, E, bl + 1, bl, s, kWaveSegMax, 0x7fffffff);
+    k_contract<<<std::min<int>(big.n, 2048), SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, bl + 1, bl, 0);
     HGP_LAUNCH_CHECK();
   }
   scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);

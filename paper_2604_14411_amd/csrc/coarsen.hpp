@@ -19,11 +19,16 @@ constexpr int32_t kErrInternal = 128;  // internal consistency check
 constexpr int kWaveSegMax = 1024;
 // Hedges of at most kThreadSegMax pins get their part tables from one thread each.
 constexpr int kThreadSegMax = 16;
-// A level's hedges with kThreadSegMax < |e| <= kWaveSegMax: list[0 .. *count)
-// on the device (null list: every hedge, filtered by length in the kernel).
+// A level's hedges by length class, lists on the device with device counts:
+// list[0 .. *count) with kThreadSegMax < |e| <= kWaveSegMax, and
+// big_list[0 .. *big_count) with |e| > kWaveSegMax.  A null list means every
+// hedge, filtered by length in the kernel (mid), or the level-0 superset
+// BigHedges (big).
 struct MidHedges {
   const int32_t *list = nullptr;
   const int32_t *count = nullptr;
+  const int32_t *big_list = nullptr;
+  const int32_t *big_count = nullptr;
 };
 struct BigHedges {
   const int32_t *list = nullptr;
@@ -85,7 +90,7 @@ void launch_match_exact(const int32_t *pair, const int64_t *score, int32_t N, co
                         int32_t *n_next_dev, int32_t *err, DevBuf &scan_tmp, hipStream_t s);
 void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32_t *size, int32_t N, int32_t *csize,
                          hipStream_t s);
-// list_buf: E + 1 ints of scratch.
+// list_buf: 2 (E + 1) ints of scratch.
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
                      int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
                      int32_t *list_buf, hipStream_t s);

@@ -101,24 +101,30 @@ struct Workspace {
       pmatch, pgam;
   std::vector<DevBuf> lv_match;
 
-  // Entries go back in level order and are taken from the front, so a
-  // repeated run on the same hypergraph gets each level's own buffers back
-  // (no reallocation, hence no device-wide synchronisation in hipFree).
+  // A run starts without kept levels.  Entries recycled from an earlier run
+  // would hand the workspace buffers sized for other levels, and every
+  // reallocation's hipFree synchronises the device (a repeated conv302k
+  // partition took 10.2 s against 8.2 s for the first); a run that creates
+  // its entries sizes every buffer for its own level.
   void clear_level_cache() {
-    for (auto &c : lcache) lcache_free.push_back(std::move(c));
+    for (auto &c : lcache) c->release();
+    for (auto &c : lcache_free) c->release();
     lcache.clear();
+    lcache_free.clear();
     lcache_bytes = 0;
+    lcache_held = 0;
   }
 
-  void clear_levels() {
-    for (auto &b : lv_size) b.release();
-    for (auto &b : lv_gamma) b.release();
-    for (auto &b : lv_Gamma) b.release();
-    for (auto &b : lv_match) b.release();
-    lv_match.clear();
-    lv_size.clear();
-    lv_gamma.clear();
-    lv_Gamma.clear();
+  // Per-level buffers (sizes, cluster maps, matches) are kept for the next
+  // run: it reuses them level by level, growing only those that are too small
+  // (thousands of levels would otherwise cost a hipFree and a hipMalloc each).
+  void clear_levels() { lv_n.clear(); }
+
+  void release_levels() {
+    for (auto *v : {&lv_size, &lv_gamma, &lv_Gamma, &lv_match}) {
+      for (auto &b : *v) b.release();
+      v->clear();
+    }
     lv_n.clear();
   }
 
@@ -132,14 +138,11 @@ struct Workspace {
     for (DevBuf *b : all) b->release();
     units_dev.release();
     clear_level_cache();
-    for (auto &c : lcache_free) c->release();
-    lcache_free.clear();
-    lcache_held = 0;
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
                           &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
-    clear_levels();
+    release_levels();
   }
 };
 
@@ -307,6 +310,11 @@ static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStrea
   return b;
 }
 
+// Makes v[i] exist (per-level buffers are reused across runs).
+static void level_slot(std::vector<DevBuf> &v, size_t i) {
+  if (v.size() <= i) v.resize(i + 1);
+}
+
 // Scratch of the exact matching for n nodes.
 static MatchScratch match_scratch(Workspace &W, int32_t n) {
   MatchScratch m;
@@ -322,10 +330,17 @@ static MatchScratch match_scratch(Workspace &W, int32_t n) {
 // The level's hedges for the wave part-table kernel (list kept in W.midlist,
 // count on the device): built once per level, used by every round.
 static void set_mid(Workspace &W, LevelView &V, hipStream_t s) {
-  int32_t *buf = need<int32_t>(W.midlist, (int64_t)V.E + 1);
+  int32_t *buf = need<int32_t>(W.midlist, 2 * ((int64_t)V.E + 1));
+  int32_t *bbuf = buf + V.E + 1;
   launch_mid_hedges(V.hoff, V.E, buf + 1, buf, s);
   V.mid.list = buf + 1;
   V.mid.count = buf;
+  if (V.big.n > 0) {
+    // the level's own long hedges (the level-0 list is only a superset)
+    launch_mid_hedges(V.hoff, V.E, bbuf + 1, bbuf, s, kWaveSegMax, 0x7fffffff);
+    V.mid.big_list = bbuf + 1;
+    V.mid.big_count = bbuf;
+  }
 }
 
 // `size_cap` is the element capacity of the buffer behind `size` (checked).
@@ -644,7 +659,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const int32_t *mlp_params = learned ? upload_mlp(W.mlp, opt.mlp, s) : nullptr;
   W.clear_levels();
   W.clear_level_cache();
-  W.lv_size.emplace_back();
+  level_slot(W.lv_size, 0);
   W.lv_n.push_back(N);
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
   if (N > 0)
@@ -748,8 +763,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     }
     have_pairs = false;
     if (W.trace) trace_level(W, L, lvl, omega, delta, pair, score, s);
-    W.lv_gamma.emplace_back();
-    W.lv_match.emplace_back();
+    level_slot(W.lv_gamma, (size_t)lvl);
+    level_slot(W.lv_match, (size_t)lvl);
     int32_t *gam = need<int32_t>(W.lv_gamma[lvl], n);
     int32_t *lmatch = need<int32_t>(W.lv_match[lvl], n);
     if (exact)
@@ -793,11 +808,11 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       break;
     }
     const int32_t M = n - n_next;
-    W.lv_size.emplace_back();
+    level_slot(W.lv_size, (size_t)lvl + 1);
     W.lv_n.push_back(n_next);
     int32_t *csize = need<int32_t>(W.lv_size[lvl + 1], n_next);
     launch_cluster_size(lmatch, gam, W.lv_size[lvl].as<int32_t>(), n, csize, s);
-    W.lv_Gamma.emplace_back();  // lv_Gamma[k]: level 0 -> level k+1
+    level_slot(W.lv_Gamma, (size_t)lvl);  // lv_Gamma[k]: level 0 -> level k+1
     int32_t *Gm = need<int32_t>(W.lv_Gamma[lvl], N);
     if (lvl == 0)
       HGP_HIP(hipMemcpyAsync(Gm, gam, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
@@ -810,7 +825,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
     uint32_t *npin = need<uint32_t>(hpin_buf, cur_P);
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
-                    W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1), s);
+                    W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), s);
     add_units(HGP_K_CONTRACT, cur_P);
     cur_P = read_i32(nh + E, s);
     cur_hoff = nh;
@@ -898,7 +913,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
         uint32_t *rp = need<uint32_t>(W.hpinR, P);
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
-                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1), s);
+                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), s);
         add_units(HGP_K_CONTRACT, P);
         Pl = read_i32(rh + E, s);
         h = rh;
@@ -1490,7 +1505,7 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
     int32_t *cnt = need<int32_t>(W.cnt, E);
     const BigHedges big = find_big(W, lv->hoff, E, s);
     launch_contract(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, gamma, tmp, cnt, hoff_out,
-                    reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, need<int32_t>(W.longlist, (int64_t)E + 1),
+                    reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)),
                     s);
     // cluster sizes: sum of member sizes (atomics over the fine nodes)
     fill_i32(size_out, n_next, 0, s);

@@ -25,16 +25,13 @@ __device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int n, uint32_
 // ---------------------------------------------------------------------------
 // part table: pins(p,e), pins_in(p,e) (Sec. IV-B, counting pins per partition)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict__ hoff,
-                                                      const uint32_t *__restrict__ hpin,
-                                                      const int32_t *__restrict__ rho, int32_t *__restrict__ pt,
-                                                      uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
-                                                      uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
-                                                      int32_t *err, const int32_t *__restrict__ list) {
-  __shared__ uint32_t key[kSegCap];
-  __shared__ int32_t first[kSegCap];
-  __shared__ int32_t tmp[PT_NT / 64 + 1];
-  const int e = list[blockIdx.x];
+// Part table of one hedge of at most kSegCap pins by a workgroup (LDS sort).
+__device__ __forceinline__ void part_table_block(int e, const int32_t *__restrict__ hoff,
+                                                 const uint32_t *__restrict__ hpin, const int32_t *__restrict__ rho,
+                                                 int32_t *__restrict__ pt, uint32_t *__restrict__ ptc,
+                                                 int32_t *__restrict__ lam, uint8_t *__restrict__ solo,
+                                                 int32_t *__restrict__ pinb, int32_t *err, uint32_t *key,
+                                                 int32_t *first, int32_t *tmp) {
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
   if (len <= 0 || len > kSegCap) {
@@ -77,6 +74,25 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
   }
 }
 
+// Workgroup per hedge, grid-stride over list[0 .. count).
+__global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict__ hoff,
+                                                      const uint32_t *__restrict__ hpin,
+                                                      const int32_t *__restrict__ rho, int32_t *__restrict__ pt,
+                                                      uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
+                                                      uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
+                                                      int32_t *err, const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ list_n, int32_t n_fixed) {
+  __shared__ uint32_t key[kSegCap];
+  __shared__ int32_t first[kSegCap];
+  __shared__ int32_t tmp[PT_NT / 64 + 1];
+  // grid-stride over list[0 .. count): count from the device when list_n is set
+  const int count = list_n ? *list_n : n_fixed;
+  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+    part_table_block(list[t], hoff, hpin, rho, pt, ptc, lam, solo, pinb, err, key, first, tmp);
+    __syncthreads();
+  }
+}
+
 __global__ void k_part_size(const int32_t *__restrict__ rho, const int32_t *__restrict__ size, int32_t N,
                             int32_t *__restrict__ psize) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,8 +130,14 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
                          n_parts, L.big.max_len, *B.partial, s);
   if (L.E > 0) {
     if (L.big.n > 0) {
-      k_part_table<<<L.big.n, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
-                                             L.big.list);
+      // the level's own long hedges when listed (fewer than level 0's at coarse levels)
+      const int grid = std::min<int>(L.big.n, 2048);
+      if (L.mid.big_list)
+        k_part_table<<<grid, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
+                                            L.mid.big_list, L.mid.big_count, 0);
+      else
+        k_part_table<<<grid, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
+                                            L.big.list, nullptr, L.big.n);
       HGP_LAUNCH_CHECK();
     }
     launch_part_table_thread(L.hoff, L.hpin, L.E, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, n_parts, s);
