@@ -15,7 +15,7 @@ __global__ void k_check_offsets(const int32_t *__restrict__ off, int32_t E, int3
   if (e < E) {
     const int32_t a = off[e], b = off[e + 1];
     if (b < a) atomicOr(err, kErrCsr);
-    else if (b - a > kSegCap) atomicOr(err, kErrBigHedge);
+    else if (b - a > kHugeCap) atomicOr(err, kErrBigHedge);
   }
 }
 
@@ -46,14 +46,11 @@ __global__ void k_check_weights(const int32_t *__restrict__ hw, int32_t E, const
 // Bit 31 of a canonical pin marks the pins whose hedges count toward Delta
 // for their part: destinations (inbound, Sec. II-A), sources (outbound) or
 // every pin (incident); `role` is HGP_INBOUND / HGP_OUTBOUND / HGP_INCIDENT.
-__global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                  const int32_t *__restrict__ nsrc, int32_t N, int32_t role,
-                                                  int32_t *err, uint32_t *__restrict__ hpin) {
-  __shared__ uint32_t key[kSegCap];
-  const int e = blockIdx.x;
-  const int b = off[e];
-  const int len = off[e + 1] - b;
-  if (len <= 0) return;
+// Hedges above kSegCap pins sort their keys in global scratch (huge_keys at
+// twice the hedge's pin offset: next_pow2(|e|) < 2|e| words).
+__device__ __forceinline__ void canon_hedge(int e, int b, int len, const int32_t *__restrict__ pins,
+                                            const int32_t *__restrict__ nsrc, int32_t N, int32_t role, int32_t *err,
+                                            uint32_t *__restrict__ hpin, uint32_t *key) {
   const int ns = nsrc ? nsrc[e] : 1;
   if (threadIdx.x == 0 && (ns < 0 || ns > len)) atomicOr(err, kErrNsrc);
   const int np = next_pow2(len);
@@ -81,6 +78,24 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
   }
 }
 
+__global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                  const int32_t *__restrict__ nsrc, int32_t N, int32_t role,
+                                                  int32_t *err, uint32_t *__restrict__ hpin,
+                                                  uint32_t *__restrict__ huge_keys) {
+  __shared__ uint32_t key[kSegCap];
+  const int e = blockIdx.x;
+  const int b = off[e];
+  const int len = off[e + 1] - b;
+  if (len <= 0) return;
+  if (len <= kSegCap) {
+    canon_hedge(e, b, len, pins, nsrc, N, role, err, hpin, key);
+  } else if (huge_keys && len <= kHugeCap) {
+    canon_hedge(e, b, len, pins, nsrc, N, role, err, hpin, huge_keys + 2 * (int64_t)b);
+  } else if (threadIdx.x == 0) {
+    atomicOr(err, kErrInternal);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // incidence transpose: I(n) with the destination flag, |in(n)|, total(n)
 // ---------------------------------------------------------------------------
@@ -88,6 +103,7 @@ __global__ __launch_bounds__(SEG_NT) void k_canon(const int32_t *__restrict__ of
 // every I(n) comes out ascending by hedge id, with no contended atomics.
 // Per pin j: its node id as the sort key and (hedge | dst) << 32 | j as the
 // value, so the sort by node yields inc and perm together.
+// (node, hedge|dst) pairs in hedge order, one wave per hedge.
 __global__ void k_expand(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, int32_t E,
                          uint32_t *__restrict__ key, uint64_t *__restrict__ val) {
   const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -96,6 +112,44 @@ __global__ void k_expand(const int32_t *__restrict__ hoff, const uint32_t *__res
     const uint32_t x = hpin[j];
     key[j] = x & kIdMask;
     val[j] = ((uint64_t)((uint32_t)wid | (x & kDst)) << 32) | (uint32_t)j;
+  }
+}
+
+// A wave takes 64 consecutive hedges: each lane writes the pins of its own
+// hedge when it has at most kThreadSegMax of them (coarse levels: most
+// hedges), then the wave writes the longer ones together, one at a time.
+// Levels of long hedges use k_expand (a wave per hedge): with 64 long hedges
+// per wave the loads in flight would be too few.
+__global__ __launch_bounds__(256) void k_expand_lanes(const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin,
+                                                int32_t E, uint32_t *__restrict__ key, uint64_t *__restrict__ val) {
+  const int64_t e0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6;
+  if (e0 >= E) return;
+  const int l = lane_id();
+  const int64_t e = e0 + l;
+  int b = 0, len = 0;
+  if (e < E) {
+    b = hoff[e];
+    len = hoff[e + 1] - b;
+  }
+  const bool mine = len <= kThreadSegMax;
+  if (mine) {
+    for (int j = 0; j < len; ++j) {
+      const uint32_t x = hpin[b + j];
+      key[b + j] = x & kIdMask;
+      val[b + j] = ((uint64_t)((uint32_t)e | (x & kDst)) << 32) | (uint32_t)(b + j);
+    }
+  }
+  uint64_t rest = __ballot(!mine);
+  while (rest) {
+    const int i = __ffsll((long long)rest) - 1;
+    rest &= rest - 1ull;
+    const int hb = __shfl(b, i, 64), hl = __shfl(len, i, 64);
+    const uint32_t he = (uint32_t)(e0 + i);
+    for (int j = l; j < hl; j += 64) {
+      const uint32_t x = hpin[hb + j];
+      key[hb + j] = x & kIdMask;
+      val[hb + j] = ((uint64_t)(he | (x & kDst)) << 32) | (uint32_t)(hb + j);
+    }
   }
 }
 
@@ -143,6 +197,71 @@ __global__ void k_node_stats(const int32_t *__restrict__ ioff, const uint32_t *_
   if (lane_id() == 0) {
     total[wid] = (int32_t)s;
     indeg[wid] = d;
+  }
+}
+
+// |in(n)| and total(n) = sum of w(e) over I(n).  A wave takes 64
+// consecutive nodes: a lane sums its own node's incidences when there are at
+// most kThreadSegMax of them, then the wave sums each larger node together
+// (four incidences per lane loaded before their weights are gathered).
+// Levels of high-degree nodes use k_node_stats (a wave per node).
+__global__ __launch_bounds__(256) void k_node_stats_lanes(const int32_t *__restrict__ ioff,
+                                                    const uint32_t *__restrict__ inc,
+                                                    const int32_t *__restrict__ hw, int32_t N,
+                                                    int32_t *__restrict__ indeg, int32_t *__restrict__ total) {
+  const int64_t v0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6;
+  if (v0 >= N) return;
+  const int l = lane_id();
+  const int64_t v = v0 + l;
+  int a = 0, z = 0;
+  if (v < N) {
+    a = ioff[v];
+    z = ioff[v + 1];
+  }
+  const bool mine = v < N && z - a <= kThreadSegMax;
+  if (mine) {
+    int64_t s = 0;
+    int d = 0;
+    for (int i = a; i < z; ++i) {
+      const uint32_t x = inc[i];
+      s += hw[x & kIdMask];
+      d += (int)(x >> 31);
+    }
+    total[v] = (int32_t)s;
+    indeg[v] = d;
+  }
+  uint64_t rest = __ballot(v < N && !mine);
+  while (rest) {
+    const int i0 = __ffsll((long long)rest) - 1;
+    rest &= rest - 1ull;
+    const int na = __shfl(a, i0, 64), nz = __shfl(z, i0, 64);
+    int64_t s = 0;
+    int d = 0;
+    for (int c = na; c < nz; c += 64 * 4) {
+      uint32_t x[4];
+      int32_t we[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = c + 64 * u + l;
+        x[u] = i < nz ? inc[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = c + 64 * u + l;
+        we[u] = i < nz ? hw[x[u] & kIdMask] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s += we[u];
+        d += (int)(x[u] >> 31);
+      }
+    }
+    s = wave_sum(s);
+    d = wave_sum(d);
+    if (l == 0) {
+      total[v0 + i0] = (int32_t)s;
+      indeg[v0 + i0] = d;
+    }
   }
 }
 
@@ -529,17 +648,29 @@ __device__ __forceinline__ void contract_block(int e, const int32_t *__restrict_
 
 // Workgroup per hedge, grid-stride over list[0 .. count): count from the
 // device when list_n is set, else n_fixed.
+// Hedges above kSegCap pins use the global scratch (keys at twice the pin
+// offset in huge_i, run flags at the pin offset in huge_k).
 __global__ __launch_bounds__(SEG_NT) void k_contract(const int32_t *__restrict__ hoff,
                                                      const uint32_t *__restrict__ hpin,
                                                      const int32_t *__restrict__ map, uint32_t *__restrict__ out,
                                                      int32_t *__restrict__ cnt, const int32_t *__restrict__ list,
-                                                     const int32_t *__restrict__ list_n, int32_t n_fixed) {
+                                                     const int32_t *__restrict__ list_n, int32_t n_fixed,
+                                                     uint64_t *__restrict__ huge_k, int32_t *__restrict__ huge_i,
+                                                     int32_t *err) {
   __shared__ uint32_t key[kSegCap];
   __shared__ int32_t pos[kSegCap];
   __shared__ int32_t tmp[SEG_NT / 64 + 1];
   const int count = list_n ? *list_n : n_fixed;
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    contract_block(list[t], hoff, hpin, map, out, cnt, key, pos, tmp);
+    const int e = list[t];
+    const int b = hoff[e], len = hoff[e + 1] - b;
+    if (len <= kSegCap)
+      contract_block(e, hoff, hpin, map, out, cnt, key, pos, tmp);
+    else if (huge_k && len <= kHugeCap)
+      contract_block(e, hoff, hpin, map, out, cnt, reinterpret_cast<uint32_t *>(huge_i) + 2 * (int64_t)b,
+                     reinterpret_cast<int32_t *>(huge_k) + b, tmp);
+    else if (threadIdx.x == 0)
+      atomicOr(err, kErrInternal);
     __syncthreads();
   }
 }
@@ -561,9 +692,9 @@ void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32
 }
 
 void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t role, int32_t *err,
-                  uint32_t *hpin, hipStream_t s) {
+                  uint32_t *hpin, uint32_t *huge_keys, hipStream_t s) {
   if (E <= 0) return;
-  k_canon<<<E, SEG_NT, 0, s>>>(off, pins, nsrc, N, role, err, hpin);
+  k_canon<<<E, SEG_NT, 0, s>>>(off, pins, nsrc, N, role, err, hpin, huge_keys);
   HGP_LAUNCH_CHECK();
 }
 
@@ -578,14 +709,21 @@ void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32
                      uint32_t *tkey2, uint64_t *tval, uint64_t *tval2, DevBuf &sort_tmp, hipStream_t s) {
   KScope ks(5, s);
   if (E > 0 && P > 0) {
-    k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, tval);
+    // lanes take whole hedges when they are short on average (coarse levels)
+    if (P <= (int64_t)kThreadSegMax * E)
+      k_expand_lanes<<<div_up(E, 256), 256, 0, s>>>(hoff, hpin, E, tkey, tval);
+    else
+      k_expand<<<div_up((int64_t)E * 64, 256), 256, 0, s>>>(hoff, hpin, E, tkey, tval);
     HGP_LAUNCH_CHECK();
     radix_sort_u32_split(tkey, tkey2, tval, tval2, P, bits_of(N > 0 ? N - 1 : 0), inc, perm, sort_tmp, s);
   }
   k_offsets_from_sorted<<<div_up(P + 1, 256), 256, 0, s>>>(tkey, P, N, ioff);
   HGP_LAUNCH_CHECK();
   if (N > 0) {
-    k_node_stats<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
+    if (P <= (int64_t)kThreadSegMax * N)
+      k_node_stats_lanes<<<div_up(N, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
+    else
+      k_node_stats<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
     HGP_LAUNCH_CHECK();
   }
 }
@@ -700,7 +838,7 @@ void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32
 
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
                      int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
-                     int32_t *list_buf, hipStream_t s) {
+                     int32_t *list_buf, int32_t *err, hipStream_t s) {
   if (E <= 0) {
     fill_i32(new_hoff, 1, 0, s);
     return;
@@ -711,7 +849,8 @@ void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const
     // this level's hedges above kWaveSegMax (the level-0 list is a superset)
     int32_t *bl = list_buf + E + 1;
     launch_mid_hedges(hoff, E, bl + 1, bl, s, kWaveSegMax, 0x7fffffff);
-    k_contract<<<std::min<int>(big.n, 2048), SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, bl + 1, bl, 0);
+    k_contract<<<std::min<int>(big.n, 2048), SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, bl + 1, bl, 0,
+                                                             big.huge_k, big.huge_i, err);
     HGP_LAUNCH_CHECK();
   }
   scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);

@@ -12,7 +12,7 @@ constexpr int32_t kErrDup = 4;         // duplicate pin within a hedge
 constexpr int32_t kErrNsrc = 8;        // n_src outside [0, |e|]
 constexpr int32_t kErrWeight = 16;     // weight < 1
 constexpr int32_t kErrInfeasible = 32; // node exceeding Omega or Delta on its own
-constexpr int32_t kErrBigHedge = 64;   // hedge larger than kSegCap pins
+constexpr int32_t kErrBigHedge = 64;   // hedge larger than kHugeCap pins
 constexpr int32_t kErrInternal = 128;  // internal consistency check
 
 // Hedges longer than kWaveSegMax pins, handled by workgroup-per-hedge kernels.
@@ -34,6 +34,11 @@ struct BigHedges {
   const int32_t *list = nullptr;
   int32_t n = 0;
   int32_t max_len = 0x7fffffff;  // bound of the hedge lengths (coarse hedges only shrink)
+  // Global scratch of the workgroup kernels for hedges above kSegCap pins
+  // (null when the input has none), oversized at each hedge's pin offset b:
+  // huge_k[4b .. 4b + 4|e|) 64-bit words, huge_i[2b .. 2b + 2|e|) 32-bit words.
+  uint64_t *huge_k = nullptr;
+  int32_t *huge_i = nullptr;
 };
 
 // One hierarchy level resident on the device.
@@ -57,8 +62,9 @@ struct LevelView {
 void launch_check_offsets(const int32_t *off, int32_t E, int32_t *err, hipStream_t s);
 void launch_check_weights(const int32_t *hw, int32_t E, const int32_t *nw, int32_t N, int32_t *err,
                           unsigned long long *sums, hipStream_t s);
+// huge_keys: 2 P words of scratch when some hedge exceeds kSegCap pins, else null.
 void launch_canon(const int32_t *off, const int32_t *pins, const int32_t *nsrc, int32_t E, int32_t N, int32_t role, int32_t *err,
-                  uint32_t *hpin, hipStream_t s);
+                  uint32_t *hpin, uint32_t *huge_keys, hipStream_t s);
 // Incidence I(n) (ascending hedge ids, destination flag in bit 31), the pin
 // position perm[k] of every incidence k, |in(n)| and total(n) of a level;
 // tkey/tkey2/tval/tval2 are P-element scratch.
@@ -93,7 +99,7 @@ void launch_cluster_size(const int32_t *match, const int32_t *gamma, const int32
 // list_buf: 2 (E + 1) ints of scratch.
 void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const int32_t *map, uint32_t *tmp_pins,
                      int32_t *cnt, int32_t *new_hoff, uint32_t *new_hpin, const BigHedges &big, DevBuf &scan_tmp,
-                     int32_t *list_buf, hipStream_t s);
+                     int32_t *list_buf, int32_t *err, hipStream_t s);
 // --- seg.hip ---
 // Part tables of hedges with at most kWaveSegMax pins and inb(p) of their
 // entries: pinb[0 .. n_parts) is written (not accumulated).  partial: scratch.

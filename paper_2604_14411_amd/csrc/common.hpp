@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -16,6 +17,10 @@ constexpr uint32_t kIdMask = 0x7fffffffu;
 
 // Largest hedge handled by the LDS-resident per-hedge kernels (pins).
 constexpr int kSegCap = 4096;
+// Largest hedge supported at all: longer than kSegCap, the per-hedge
+// workgroup kernels sort in global scratch; pin positions within a hedge
+// then still fit 15 bits and pin counts the 16-bit fields of the part tables.
+constexpr int kHugeCap = 32767;
 
 struct Error : std::runtime_error {
   int code;
@@ -33,6 +38,9 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line);
 #define HGP_LAUNCH_CHECK() HGP_HIP(hipGetLastError())
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Counts of DevBuf device allocations and frees (diagnostics).
+extern std::atomic<int64_t> g_dev_allocs, g_dev_frees;
 
 // Grow-only device buffer owned by a context.
 struct DevBuf {

@@ -86,7 +86,7 @@ struct Workspace {
   DevBuf units_dev;
   // incremental late levels
   DevBuf tkA_key, tkA_c, tkA_cnt, tkA_kap, tkB_key, tkB_c, tkB_cnt, tkB_kap, newc, row_slot, nflag, rerate, dev_cnt;
-  DevBuf split, cdest, cgain, maxbits, biglist, midlist, longlist, tail_acc;
+  DevBuf split, cdest, cgain, maxbits, biglist, midlist, longlist, huge_k, huge_i, tail_acc;
   DevBuf dp_nchild, dp_arrived, dp_g, dp_key, dp_f, dp_root;  // exact matching
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
@@ -101,17 +101,21 @@ struct Workspace {
       pmatch, pgam;
   std::vector<DevBuf> lv_match;
 
-  // A run starts without kept levels.  Entries recycled from an earlier run
-  // would hand the workspace buffers sized for other levels, and every
-  // reallocation's hipFree synchronises the device (a repeated conv302k
-  // partition took 10.2 s against 8.2 s for the first); a run that creates
-  // its entries sizes every buffer for its own level.
+  // Kept levels become free entries at the start of a run; their buffers are
+  // recycled (cache_level hands the workspace the largest free entry's
+  // buffers), so a repeated run allocates and frees nothing.  Every hipFree
+  // synchronises the device: releasing the ~1,500 kept levels of a conv302k
+  // partition at each run cost 2 s.
   void clear_level_cache() {
-    for (auto &c : lcache) c->release();
-    for (auto &c : lcache_free) c->release();
+    for (auto &c : lcache) lcache_free.push_back(std::move(c));
     lcache.clear();
-    lcache_free.clear();
     lcache_bytes = 0;
+  }
+
+  void release_level_cache() {
+    clear_level_cache();
+    for (auto &c : lcache_free) c->release();
+    lcache_free.clear();
     lcache_held = 0;
   }
 
@@ -137,9 +141,9 @@ struct Workspace {
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
-    clear_level_cache();
+    release_level_cache();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &huge_k, &huge_i, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     release_levels();
@@ -244,8 +248,31 @@ static void check_scalars(const hgp_hypergraph *g, int32_t omega, int32_t delta)
   if (g->n_nodes >= (1 << 30)) throw Error(HGP_EUNSUPPORTED, "more than 2^30 - 1 nodes");
 }
 
+// Hedges of `hoff` longer than kWaveSegMax pins (list kept in W.biglist),
+// and the global scratch of the workgroup kernels when some hedge is longer
+// than kSegCap (sized for the P pins of the level it is found on: coarser
+// levels only have fewer).
+static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStream_t s, int64_t P = -1) {
+  BigHedges b;
+  int32_t *list = need<int32_t>(W.biglist, (int64_t)E + 2);
+  launch_big_hedges(hoff, E, list + 2, list, s);
+  int32_t hdr[2];
+  HGP_HIP(hipMemcpyAsync(hdr, list, sizeof hdr, hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  b.n = hdr[0];
+  b.max_len = hdr[1];
+  b.list = list + 2;
+  if (b.max_len > kSegCap) {
+    if (P < 0) P = read_i32(hoff + E, s);
+    b.huge_k = need<uint64_t>(W.huge_k, 4 * P + 16);
+    b.huge_i = need<int32_t>(W.huge_i, 2 * P + 16);
+  }
+  return b;
+}
+
 struct Ingest {
   int64_t P = 0;
+  BigHedges big;  // level-0 long hedges (a superset for every coarser level)
   int64_t wsum_nodes = 0;
   const int32_t *hw = nullptr;
   const int32_t *nw = nullptr;
@@ -270,7 +297,9 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
   unsigned long long *sums = need<unsigned long long>(W.sums, 2);
   fill_i64(reinterpret_cast<int64_t *>(sums), 2, 0, s);
   launch_check_weights(g->hedge_w, E, g->node_w, N, err, sums, s);
-  launch_canon(g->hedge_off, g->pins, g->n_src, E, N, role, err, I.hpin0, s);
+  I.big = find_big(W, g->hedge_off, E, s, I.P);
+  launch_canon(g->hedge_off, g->pins, g->n_src, E, N, role, err, I.hpin0,
+               reinterpret_cast<uint32_t *>(I.big.huge_i), s);
   unsigned long long hs[2] = {0, 0};
   HGP_HIP(hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, s));
   check_err(W, s, kErrCsr | kErrPin | kErrNsrc | kErrWeight);
@@ -295,20 +324,6 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
   return I;
 }
 
-// Incidence I(n) with destination flags, |in(n)| and total(n) of a level.
-// Hedges of `hoff` longer than kWaveSegMax pins (list kept in W.biglist).
-static BigHedges find_big(Workspace &W, const int32_t *hoff, int32_t E, hipStream_t s) {
-  BigHedges b;
-  int32_t *list = need<int32_t>(W.biglist, (int64_t)E + 2);
-  launch_big_hedges(hoff, E, list + 2, list, s);
-  int32_t hdr[2];
-  HGP_HIP(hipMemcpyAsync(hdr, list, sizeof hdr, hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipStreamSynchronize(s));
-  b.n = hdr[0];
-  b.max_len = hdr[1];
-  b.list = list + 2;
-  return b;
-}
 
 // Makes v[i] exist (per-level buffers are reused across runs).
 static void level_slot(std::vector<DevBuf> &v, size_t i) {
@@ -578,12 +593,27 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, De
     W.lcache_free.push_back(std::move(W.lcache.front()));
     W.lcache.erase(W.lcache.begin());
   }
+  // The entry's buffers go to the workspace, which builds the next (smaller)
+  // level in them: take the free entry holding the least memory among those
+  // whose every buffer fits this level, so the workspace needs no
+  // reallocation and the kept levels hold buffers of about their own size (a
+  // repeated run on the same hypergraph gets back the entry each level had).
   std::unique_ptr<CachedLevel> c;
-  if (!W.lcache_free.empty()) {
-    c = std::move(W.lcache_free.front());
-    W.lcache_free.erase(W.lcache_free.begin());
-  } else {
-    c.reset(new CachedLevel());
+  {
+    const size_t nb = 4 * ((size_t)n + 1), pb = 4 * (size_t)P, eb = 4 * ((size_t)E + 1);
+    size_t pick = W.lcache_free.size();
+    for (size_t i = 0; i < W.lcache_free.size(); ++i) {
+      const CachedLevel &f = *W.lcache_free[i];
+      const bool fits = f.hoff.bytes >= eb && f.hpin.bytes >= pb && f.inc.bytes >= pb && f.perm.bytes >= pb &&
+                        f.ioff.bytes >= nb && f.indeg.bytes >= nb && f.total.bytes >= nb;
+      if (fits && (pick == W.lcache_free.size() || f.held() < W.lcache_free[pick]->held())) pick = i;
+    }
+    if (pick < W.lcache_free.size()) {
+      c = std::move(W.lcache_free[pick]);
+      W.lcache_free.erase(W.lcache_free.begin() + (ptrdiff_t)pick);
+    } else {
+      c.reset(new CachedLevel());
+    }
   }
   c->lvl = lvl;
   c->n = n;
@@ -604,16 +634,21 @@ static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, De
   W.lcache_held += c->held() - held_before;
   W.lcache_bytes += bytes;
   W.lcache.push_back(std::move(c));
-  // The budget bounds device memory, so it applies to what the entries hold:
-  // buffers recycled between levels of different sizes (a run after a run on
-  // another hypergraph or proposal) keep their larger capacities.  Free
-  // entries go first, then the oldest kept levels (the newest always stays).
-  while (W.lcache_held > W.lcache_budget && !W.lcache_free.empty()) {
+  // The budget bounds device memory, so it also applies to what the entries
+  // hold: buffers recycled between levels of different sizes (a run after a
+  // run on another hypergraph or proposal) keep their larger capacities.
+  // Beyond a quarter over the budget, free entries go first, then the oldest
+  // kept levels (the newest always stays).  The slack absorbs the shift of
+  // one level's worth that each entry takes on in a repeated run (entry l
+  // ends up holding level l-1's buffers), so a repeated run on the same
+  // hypergraph allocates and frees nothing here.
+  const int64_t cap = W.lcache_budget + W.lcache_budget / 4;
+  while (W.lcache_held > cap && !W.lcache_free.empty()) {
     W.lcache_held -= W.lcache_free.back()->held();
     W.lcache_free.back()->release();
     W.lcache_free.pop_back();
   }
-  while (W.lcache_held > W.lcache_budget && W.lcache.size() > 1) {
+  while (W.lcache_held > cap && W.lcache.size() > 1) {
     W.lcache_held -= W.lcache.front()->held();
     W.lcache_bytes -= W.lcache.front()->bytes;
     W.lcache.front()->release();
@@ -641,6 +676,15 @@ static double now_ms() {
 static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32_t delta,
                               const hgp_options &opt, hipStream_t s, int32_t *part_out) {
   RunStats st;
+  const int64_t allocs0 = g_dev_allocs.load(), frees0 = g_dev_frees.load();
+  struct AllocLog {
+    int64_t a0, f0;
+    ~AllocLog() {
+      if (log_on())
+        fprintf(stderr, "[hgp] partition: %lld device allocations, %lld frees\n",
+                (long long)(g_dev_allocs.load() - a0), (long long)(g_dev_frees.load() - f0));
+    }
+  } alloc_log{allocs0, frees0};
   if (opt.k < 0 || opt.max_refine_rounds < 0) throw Error(HGP_EINVAL, "k < 0 or max_refine_rounds < 0");
   if (opt.proposal != HGP_PLAIN && opt.proposal != HGP_LEARNED) throw Error(HGP_EINVAL, "unknown proposal");
   const bool learned = opt.proposal == HGP_LEARNED;
@@ -664,7 +708,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
   if (N > 0)
     HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
-  const BigHedges big = find_big(W, hoff0, E, s);  // coarse hedges only shrink: valid for every level
+  const BigHedges big = I.big;  // coarse hedges only shrink: valid for every level
   LevelView L = make_view(W, N, E, hoff0, hpin0, P, size0, W.lv_size[0].bytes / 4, hw, big, s);
   launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
   check_err(W, s);
@@ -772,14 +816,23 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
                          W.err.as<int32_t>(), W.scan_tmp, s);
     else
       launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
-    int32_t n_next = read_i32_checked(W, nnext_dev, s);
-    if (learned) {
-      // fallback: the plain pairs' matching, used if it merges over twice as many pairs
+    int32_t n_next = 0;
+    if (!learned) {
+      n_next = read_i32_checked(W, nnext_dev, s);
+    } else {
+      // fallback: the plain pairs' matching, used if it merges over twice as
+      // many pairs (both counts read back together)
       int32_t *pm = need<int32_t>(W.pmatch, n);
       int32_t *pg = need<int32_t>(W.pgam, n);
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
-      const int32_t n_next_p = read_i32_checked(W, nnext_dev + 1, s);
+      int32_t v[3] = {0, 0, 0};
+      HGP_HIP(hipMemcpyAsync(v, nnext_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGP_HIP(hipMemcpyAsync(&v[2], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGP_HIP(hipStreamSynchronize(s));
+      raise_err(v[2]);
+      n_next = v[0];
+      const int32_t n_next_p = v[1];
       if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
         HGP_HIP(hipMemcpyAsync(lmatch, pm, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
         HGP_HIP(hipMemcpyAsync(gam, pg, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
@@ -825,7 +878,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
     uint32_t *npin = need<uint32_t>(hpin_buf, cur_P);
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
-                    W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), s);
+                    W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
     add_units(HGP_K_CONTRACT, cur_P);
     cur_P = read_i32(nh + E, s);
     cur_hoff = nh;
@@ -913,7 +966,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
         uint32_t *rp = need<uint32_t>(W.hpinR, P);
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
-                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), s);
+                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
         add_units(HGP_K_CONTRACT, P);
         Pl = read_i32(rh + E, s);
         h = rh;
@@ -1345,7 +1398,7 @@ static int64_t connectivity_impl(Workspace &W, const hgp_hypergraph *g, const in
   V.hpin = I.hpin0;
   V.hw = I.hw;
   V.size = I.nw;
-  V.big = find_big(W, g->hedge_off, E, s);
+  V.big = I.big;
   set_mid(W, V, s);
   RoundBufs B = round_bufs(W, N, E, I.P, np);
   launch_part_table(V, part, np, B, W.err.as<int32_t>(), s);
@@ -1404,8 +1457,7 @@ int hgp_level_canonical(hgp_ctx *ctx, const hgp_hypergraph *g, int32_t omega, in
     if (I.P > 0 && !hpin_out) throw Error(HGP_EINVAL, "hpin_out is NULL");
     int32_t *size0 = need<int32_t>(W.rhoB, N);
     if (N > 0) HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
-    const BigHedges big = find_big(W, g->hedge_off, E, s);
-    LevelView L = make_view(W, N, E, g->hedge_off, I.hpin0, I.P, size0, W.rhoB.bytes / 4, I.hw, big, s);
+    LevelView L = make_view(W, N, E, g->hedge_off, I.hpin0, I.P, size0, W.rhoB.bytes / 4, I.hw, I.big, s);
     launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
     check_err(W, s);
     HGP_HIP(hipMemcpyAsync(hoff_out, g->hedge_off, sizeof(int32_t) * ((size_t)E + 1), hipMemcpyDeviceToDevice, s));
@@ -1506,7 +1558,7 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
     const BigHedges big = find_big(W, lv->hoff, E, s);
     launch_contract(lv->hoff, reinterpret_cast<const uint32_t *>(lv->hpin), E, gamma, tmp, cnt, hoff_out,
                     reinterpret_cast<uint32_t *>(hpin_out), big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)),
-                    s);
+                    W.err.as<int32_t>(), s);
     // cluster sizes: sum of member sizes (atomics over the fine nodes)
     fill_i32(size_out, n_next, 0, s);
     launch_cluster_size_sum(gamma, lv->size, lv->n_nodes, size_out, s);

@@ -453,6 +453,7 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
   for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
     const int e = heavy[h];
     const int b = hoff[e], len = hoff[e + 1] - b;
+    if (len > kSegCap) continue;  // k_ev_huge's
     if (tid == 0) s_cnt = 0;
     __syncthreads();
     for (int i = tid; i < len; i += EVB_NT) {
@@ -529,6 +530,96 @@ __global__ __launch_bounds__(EVB_NT) void k_ev_block(
       const uint64_t q = (k >> 14) & qmask;
       evpad[o++] = (KP)(((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull));
     }
+    __syncthreads();
+  }
+}
+
+// Queued hedges of more than kSegCap pins (at most kHugeCap): the events of
+// k_ev_block built in global scratch (keys at four times the pin offset in
+// gkey, their deltas at twice it in gdl).  The key carries the pin's
+// position within the hedge instead of a slot, 16 bits wide:
+// part << (qbits + 18) | position << 18 | pin << 2 | role << 1 | dst; keys
+// are distinct (a node has one pin per hedge), so no slot is needed, and
+// the hedge's inbound events take their places by an LDS counter (their
+// order within the hedge's region does not matter: they are sorted later).
+template <class KP>
+__global__ __launch_bounds__(EVB_NT) void k_ev_huge(
+    const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+    const int32_t *__restrict__ rho, const int32_t *__restrict__ dest, const int32_t *__restrict__ pos,
+    const int32_t *__restrict__ pt, const uint32_t *__restrict__ ptc, const int32_t *__restrict__ lam, int qbits,
+    int2 *__restrict__ contrib, KP *__restrict__ evpad, int64_t *__restrict__ evcnt,
+    const int64_t *__restrict__ scal, const int32_t *__restrict__ heavy, uint64_t *__restrict__ gkey,
+    int32_t *__restrict__ gdl) {
+  __shared__ int32_t tmp[EVB_NT / 64 + 1];
+  __shared__ int32_t s_cnt, s_out;
+  const int tid = threadIdx.x;
+  const int hshift = qbits + 18;
+  const uint64_t qmask = (1ull << qbits) - 1ull;
+  const int vshift = qbits + 2;
+  const int64_t nh = scal[SC_HEAVY];
+  for (int64_t h = blockIdx.x; h < nh; h += gridDim.x) {
+    const int e = heavy[h];
+    const int b = hoff[e], len = hoff[e + 1] - b;
+    if (len <= kSegCap) continue;  // k_ev_block's
+    uint64_t *key = gkey + 4 * (int64_t)b;
+    int32_t *dl = gdl + 2 * (int64_t)b;
+    if (tid == 0) {
+      s_cnt = 0;
+      s_out = 0;
+    }
+    __syncthreads();
+    for (int i = tid; i < len; i += EVB_NT) {
+      const uint32_t x = hpin[b + i];
+      const int v = (int)(x & kIdMask);
+      const int q = pos[v];
+      if (q > 0) {
+        const int slot = atomicAdd(&s_cnt, 1);
+        const uint64_t tail = ((uint64_t)q << 18) | ((uint64_t)i << 2) | (uint64_t)(x >> 31);
+        key[2 * slot] = ((uint64_t)(uint32_t)rho[v] << hshift) | tail;
+        key[2 * slot + 1] = ((uint64_t)(uint32_t)dest[v] << hshift) | tail | 2ull;
+      }
+    }
+    __syncthreads();
+    const int nev = 2 * s_cnt;
+    const int np = next_pow2(nev);
+    for (int i = nev + tid; i < np; i += EVB_NT) key[i] = ~0ull;
+    __syncthreads();
+    block_bitonic_sort<uint64_t, EVB_NT>(key, np);
+    for (int i = tid; i < nev; i += EVB_NT) {
+      const uint64_t k = key[i];
+      const int sgn = (k & 2ull) ? 1 : -1;
+      dl[i] = sgn + ((k & 1ull) ? sgn * 65536 : 0);
+    }
+    __syncthreads();
+    block_exclusive_scan<int32_t, EVB_NT>(dl, nev, tmp);
+    const int32_t we = hw[e];
+    const int plen = lam[e];
+    for (int i = tid; i < nev; i += EVB_NT) {
+      const uint64_t k = key[i];
+      const uint64_t part = k >> hshift;
+      int lo = 0, hi = i;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((key[mid] >> hshift) < part) lo = mid + 1;
+        else hi = mid;
+      }
+      const int2 before = unpack_delta(dl[i] - dl[lo]);
+      const int2 c0 = pt_lookup(pt, ptc, b, plen, (int)part);
+      const bool dst_role = (k & 2ull) != 0;
+      int2 *cp = &contrib[b + (int)((k >> 2) & 0xffffull)];
+      if (dst_role) cp->y = (c0.x + before.x == 0) ? -we : 0;
+      else cp->x = (c0.x + before.x == 1) ? we : 0;
+      if (k & 1ull) {
+        const int bin = c0.y + before.y;
+        if ((!dst_role && bin == 1) || (dst_role && bin == 0)) {
+          const int o = atomicAdd(&s_out, 1);
+          const uint64_t q = (k >> 18) & qmask;
+          evpad[2 * (int64_t)b + o] = (KP)(((k >> hshift) << vshift) | (q << 2) | ((k >> 1) & 1ull));
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) evcnt[e] = s_out;
     __syncthreads();
   }
 }
@@ -920,7 +1011,7 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   const int qbits = bits_for(S) > 0 ? bits_for(S) : 1;
   const int pbits = bits_for(n_parts > 1 ? n_parts - 1 : 1);
   const int vshift = qbits + 2;
-  if (pbits + qbits + 14 > 64) throw Error(-6, "sequence too long for the 64-bit event keys");
+  if (pbits + qbits + (L.big.huge_k ? 18 : 14) > 64) throw Error(-6, "sequence too long for the 64-bit event keys");
   // keys of at most 32 bits are packed and sorted as 32-bit words (half the
   // traffic): keys (as uint32) then holds them, keys2 is the sort's other half
   const int kbits = vshift + pbits;
@@ -947,6 +1038,12 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
         k_ev_block<KP><<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam,
                                                    qbits, B.contrib, evpad, B.evoff, B.scal, B.heavy);
         HGP_LAUNCH_CHECK();
+        if (L.big.huge_k) {
+          k_ev_huge<KP><<<EVB_GRID, EVB_NT, 0, s>>>(L.hoff, L.hpin, L.hw, rho, B.dest, B.pos, B.pt, B.ptc, B.lam,
+                                                    qbits, B.contrib, evpad, B.evoff, B.scal, B.heavy,
+                                                    L.big.huge_k, L.big.huge_i);
+          HGP_LAUNCH_CHECK();
+        }
         scan_i64(B.evoff, B.evoff, (int64_t)L.E + 1, nullptr, scan_tmp, s);
         k_ev_compact<KP><<<div_up((int64_t)L.E, 4), 256, 0, s>>>(L.hoff, L.E, B.evoff, evpad, ev);
         HGP_LAUNCH_CHECK();

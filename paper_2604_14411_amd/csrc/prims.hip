@@ -1,6 +1,8 @@
 // Device-wide primitives: exclusive scans, stable LSD radix sort, fills.
 #include "common.hpp"
 
+#include <atomic>
+
 #include <cstdio>
 
 namespace hgp {
@@ -57,10 +59,15 @@ void KTimer::destroy() {
   recs.clear();
 }
 
+// Device allocations and frees made through DevBuf (diagnostics: printed per
+// partition with HGP_LOG=1).
+std::atomic<int64_t> g_dev_allocs{0}, g_dev_frees{0};
+
 void DevBuf::reserve(size_t need) {
   if (need <= bytes) return;
   const size_t old = bytes;
   release();
+  g_dev_allocs.fetch_add(1, std::memory_order_relaxed);
   // grow by at least a quarter: fewer reallocations (each hipFree
   // synchronises the device)
   size_t b = need < 256 ? 256 : need;
@@ -77,7 +84,10 @@ void DevBuf::reserve(size_t need) {
 }
 
 void DevBuf::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) {
+    (void)hipFree(ptr);
+    g_dev_frees.fetch_add(1, std::memory_order_relaxed);
+  }
   ptr = nullptr;
   bytes = 0;
 }

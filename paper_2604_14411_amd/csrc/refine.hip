@@ -34,10 +34,10 @@ __device__ __forceinline__ void part_table_block(int e, const int32_t *__restric
                                                  int32_t *first, int32_t *tmp) {
   const int b = hoff[e];
   const int len = hoff[e + 1] - b;
-  if (len <= 0 || len > kSegCap) {
+  if (len <= 0 || len > kHugeCap) {
     if (threadIdx.x == 0) {
       lam[e] = 0;
-      if (len > kSegCap) atomicOr(err, kErrInternal);
+      if (len > kHugeCap) atomicOr(err, kErrInternal);
     }
     return;
   }
@@ -81,14 +81,22 @@ __global__ __launch_bounds__(PT_NT) void k_part_table(const int32_t *__restrict_
                                                       uint32_t *__restrict__ ptc, int32_t *__restrict__ lam,
                                                       uint8_t *__restrict__ solo, int32_t *__restrict__ pinb,
                                                       int32_t *err, const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ list_n, int32_t n_fixed) {
+                                                      const int32_t *__restrict__ list_n, int32_t n_fixed,
+                                                      uint64_t *__restrict__ huge_k, int32_t *__restrict__ huge_i) {
   __shared__ uint32_t key[kSegCap];
   __shared__ int32_t first[kSegCap];
   __shared__ int32_t tmp[PT_NT / 64 + 1];
   // grid-stride over list[0 .. count): count from the device when list_n is set
   const int count = list_n ? *list_n : n_fixed;
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
-    part_table_block(list[t], hoff, hpin, rho, pt, ptc, lam, solo, pinb, err, key, first, tmp);
+    const int e = list[t];
+    const int b = hoff[e], len = hoff[e + 1] - b;
+    if (len <= kSegCap || !huge_k)
+      part_table_block(e, hoff, hpin, rho, pt, ptc, lam, solo, pinb, err, key, first, tmp);
+    else  // keys at twice the pin offset, run flags at the pin offset of the global scratch
+      part_table_block(e, hoff, hpin, rho, pt, ptc, lam, solo, pinb, err,
+                       reinterpret_cast<uint32_t *>(huge_i) + 2 * (int64_t)b,
+                       reinterpret_cast<int32_t *>(huge_k) + b, tmp);
     __syncthreads();
   }
 }
@@ -134,10 +142,10 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
       const int grid = std::min<int>(L.big.n, 2048);
       if (L.mid.big_list)
         k_part_table<<<grid, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
-                                            L.mid.big_list, L.mid.big_count, 0);
+                                            L.mid.big_list, L.mid.big_count, 0, L.big.huge_k, L.big.huge_i);
       else
         k_part_table<<<grid, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
-                                            L.big.list, nullptr, L.big.n);
+                                            L.big.list, nullptr, L.big.n, L.big.huge_k, L.big.huge_i);
       HGP_LAUNCH_CHECK();
     }
     launch_part_table_thread(L.hoff, L.hpin, L.E, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, n_parts, s);

@@ -307,9 +307,52 @@ def test_hedges_longer_than_a_wave(ctx):
     _compare(ctx, g, 64, 2000, label="big hedges")
     from paper_2604_14411_amd import hgp
 
-    too_big = from_lists(5000, [([0], list(range(1, 4098)))])
+    # one hedge just past the LDS kernels' capacity (4096 pins), and the
+    # supported maximum (32767 pins) exceeded by one
+    base = synth.random_snn(5000, 10.0, 5)
+    hedges = []
+    for e in range(base.n_hedges):
+        b, en, ns = int(base.hedge_off[e]), int(base.hedge_off[e + 1]), int(base.n_src[e])
+        pins = [int(x) for x in base.pins[b:en]]
+        hedges.append((pins[:ns], pins[ns:]))
+    hedges.append(([0], list(range(1, 4098))))
+    g = from_lists(5000, hedges, [int(x) for x in base.hedge_w] + [7])
+    _compare(ctx, g, 64, 4500, label="4097-pin hedge")
+    too_big = from_lists(33000, [([0], list(range(1, 32768)))])
     rc, _, _ = _gpu_partition(ctx, too_big, 64, 4000)
     assert rc == hgp.EUNSUPPORTED
+
+
+def test_hedges_of_ten_thousand_pins(ctx):
+    """Hub hedges of 10,000 pins (above the LDS kernels' 4096): ingest,
+    contraction, part tables and in-sequence events run in global scratch.
+    The oracle's trace shows rounds where more than 256 pins of such a hedge
+    move (the workgroup event path for long hedges)."""
+    g = _with_big_hedges(12000, 12.0, 3, 10000, 77)
+    rc, ref, rres, tr = oracle.partition(g, 256, 20000, trace=True)
+    assert rc == 0
+    heavy = 0
+    first_hub = g.n_hedges - 3
+    for r in range(tr.rounds):
+        info = tr.get(oracle.RD_INFO, r)
+        lv, S = int(info[0]), int(info[1])
+        if S == 0:
+            continue
+        hoff = tr.get(oracle.LV_HOFF, lv)
+        hpin = tr.get(oracle.LV_HPIN, lv) & 0x7FFFFFFF
+        moving = np.zeros(len(tr.get(oracle.LV_SIZE, lv)), bool)
+        moving[tr.get(oracle.RD_SEQ, r)] = True
+        for e in range(first_hub, g.n_hedges):
+            pins = hpin[hoff[e]:hoff[e + 1]]
+            if len(pins) > 4096 and moving[pins].sum() > 256:
+                heavy += 1
+    say(f"[parity] 10k-pin hubs: {heavy} rounds x hubs with more than 256 moving pins")
+    assert heavy > 0
+    grc, got, gres = _gpu_partition(ctx, g, 256, 20000)
+    assert grc == 0
+    assert np.array_equal(got, ref), "part ids differ"
+    for key in ("connectivity", "n_parts", "n_levels", "n_rounds"):
+        assert gres[key] == rres[key], (key, gres[key], rres[key])
 
 
 def test_connectivity_entry_point(ctx):
