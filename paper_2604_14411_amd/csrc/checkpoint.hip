@@ -1,4 +1,5 @@
-// Checkpoint files of the learned proposal's network (host code only).
+// Checkpoint files of the learned proposal's network and the check of an
+// integer network's domain (host code only).
 //
 // Layout (little-endian), version 1:
 //   header, 48 bytes: magic "HGPMLP\0\0", u32 version, u32 header size,
@@ -65,6 +66,26 @@ struct FileCloser {
 };
 
 }  // namespace
+
+// The integer network's domain (see hgp_mlp): the ranges that keep every
+// partial sum exact in FP32 on the MFMA path.
+void check_mlp(const hgp_mlp *q) {
+  if (!q) throw Error(HGP_EINVAL, "learned proposal without a network");
+  if (q->k < 1) throw Error(HGP_EINVAL, "network k < 1");
+  if (q->k > kCandK) throw Error(HGP_EUNSUPPORTED, "network k > 8");
+  if (q->r1 < 0 || q->r1 > 30 || q->r2 < 0 || q->r2 > 30) throw Error(HGP_EINVAL, "shift outside 0..30");
+  const int64_t bmax = int64_t(1) << 22;
+  for (int i = 0; i < kMlpF * kMlpH; ++i)
+    if (q->w1[i] < -255 || q->w1[i] > 255) throw Error(HGP_EINVAL, "w1 outside -255..255");
+  for (int i = 0; i < kMlpH * kMlpH; ++i)
+    if (q->w2[i] < -255 || q->w2[i] > 255) throw Error(HGP_EINVAL, "w2 outside -255..255");
+  for (int i = 0; i < kMlpH; ++i) {
+    if (q->w3[i] < -255 || q->w3[i] > 255) throw Error(HGP_EINVAL, "w3 outside -255..255");
+    if (q->b1[i] < -bmax || q->b1[i] > bmax || q->b2[i] < -bmax || q->b2[i] > bmax)
+      throw Error(HGP_EINVAL, "bias outside -2^22..2^22");
+  }
+  if (q->b3 < -bmax || q->b3 > bmax) throw Error(HGP_EINVAL, "bias outside -2^22..2^22");
+}
 
 void ckpt_save(const char *path, const hgp_train_state *st, const hgp_mlp *q, int32_t score_shift) {
   if (!path) throw Error(HGP_EINVAL, "path is NULL");

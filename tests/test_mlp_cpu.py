@@ -129,3 +129,40 @@ def test_plain_trace_candidates_match_brute(seed):
             for j, m in enumerate(ids):
                 h, c = C[v][m]
                 assert list(feat[coff[v] + j]) == brute.pair_features(L, l, omega, delta, v, m, h, c)
+
+
+def test_trained_checkpoint_score_error_on_held_out_rows():
+    """The committed network (mlp_v2.json): its integer scores against its own
+    float weights (float64 forward of oracle/mlp_ref.py) on candidate rows of
+    a held-out layered network (8 x (16x10x10), 5x5 window, seed 302; no
+    training graph has this shape or seed), every level's candidates as the
+    plain oracle records them."""
+    from paper_2604_14411_amd import synth
+    from paper_2604_14411_amd.learn import load_checkpoint
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    q, w, ck = load_checkpoint(os.path.join(root, "paper_2604_14411_amd", "mlp_v2.json"))
+    g = synth.layered_conv(8, 16, 10, 10, 5, 0.1, 302)
+    rc, _, _, tr = oracle.partition(g, 4096, 65536, trace=True)
+    assert rc == 0
+    rows = [tr.get(oracle.LV_FEAT, l).reshape(-1, 16) for l in range(0, tr.levels, 25)]
+    x = np.concatenate(rows)
+    x = np.unique(x, axis=0)
+    assert len(x) > 1000
+    z = mlp_ref.forward(w, x)["z"]
+    s = oracle.mlp_score(q, x).astype(np.float64) / 2.0 ** ck["score_shift"]
+    err = np.abs(s - z)
+    spread = z.max() - z.min()
+    print(f"held-out rows {len(x)}: max |int - float| {err.max():.4f} (mean {err.mean():.4f}), "
+          f"float score range {spread:.3f}, relative {err.max() / spread:.4f}")
+    rng = np.random.default_rng(3)
+    i = rng.integers(0, len(x), 20000)
+    j = rng.integers(0, len(x), 20000)
+    differ = z[i] != z[j]
+    agree = np.mean(np.sign(z[i] - z[j])[differ] == np.sign(s[i] - s[j])[differ])
+    print(f"pairs ordered alike by the integer and float scores: {agree:.4f}")
+    # measured: max error 7.9% of the float range, mean 1.1%; 97.3% of pairs ordered alike
+    assert err.max() < 0.09 * spread and err.mean() < 0.02 * spread
+    assert agree > 0.97
+    clear = np.abs(z[i] - z[j]) > 2 * err.max()
+    assert np.all(np.sign(z[i] - z[j])[clear] == np.sign(s[i] - s[j])[clear])
