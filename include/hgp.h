@@ -155,6 +155,8 @@ typedef struct {
   int32_t n_levels;     /* hypergraph levels built (1 + contractions) */
   int32_t n_rounds;     /* refinement rounds run, all levels */
   int32_t n_fallback;   /* HGP_LEARNED: levels that used the plain matching */
+  int32_t n_kept;       /* coarse levels refinement found kept in device memory (the others
+                           were rebuilt from level 0; see hgp_set_level_cache) */
   double ms_coarsen;    /* host wall-clock of the coarsening phase */
   double ms_refine;     /* host wall-clock of the refinement phase */
   /* with HGP_FLAG_TIME_KERNELS: summed kernel time, launches and algorithmic
@@ -171,6 +173,23 @@ typedef struct hgp_ctx hgp_ctx;
 int hgp_ctx_create(hgp_ctx **ctx, int device);
 /* Free a context and all its device scratch.  NULL is ignored. */
 void hgp_ctx_destroy(hgp_ctx *ctx);
+
+/*
+ * Device memory the context may keep coarse levels in between coarsening and
+ * refinement (Sec. II-B: refinement visits the levels coarsening built, from
+ * the coarsest down).  Kept levels (the most recent ones that fit) are read
+ * back directly; the others are rebuilt from level 0 by the composed cluster
+ * map when refinement reaches them, so the partition does not depend on the
+ * budget, only the time does.  bytes = 0 keeps no level; bytes < 0 restores
+ * the default (HGP_LEVEL_CACHE_GB in the environment, else 48 GiB).  The
+ * memory is one device allocation, made by the next partition that needs it
+ * and reused by later ones; it is released here when the budget falls below
+ * it, and by hgp_ctx_destroy.  *held (may be NULL) receives the bytes the
+ * context holds for it after the call.  Applies to hgp_partition and
+ * hgp_partition_device; batch workers share it (see
+ * hgp_partition_batch_device).  HGP_EINVAL if ctx is NULL.
+ */
+int hgp_set_level_cache(hgp_ctx *ctx, int64_t bytes, int64_t *held);
 
 /* Fill *opt with the defaults: k = 0, max_refine_rounds = 8, seed = 0, plain. */
 void hgp_options_default(hgp_options *opt);
@@ -370,10 +389,14 @@ typedef struct {
  * (graphs[i] as for hgp_partition_device, with its own omega[i], delta[i]).
  * part_out[i] (device, [graphs[i].n_nodes]) receives graph i's part ids,
  * identical to a single hgp_partition_device call on it.  res (host,
- * [n_graphs]) and t_start_ms / t_end_ms (host, [n_graphs]: wall-clock ms from
- * the batch start to graph i's start and completion) may be NULL.  `stream`
- * is synchronised before the batch starts; the call returns when every graph
- * is done.  The first failing graph's error is returned.
+ * [n_graphs]) and t_start_ms / t_end_ms (host, [n_graphs]: ms from the batch
+ * start to graph i's start and completion, read from the device's constant-
+ * rate wall clock by stamps on the streams that run the graphs) may be NULL.
+ * `stream` is synchronised before the batch starts; the call returns when
+ * every graph is done.  The first failing graph's error is returned.  Each
+ * worker keeps coarse levels in a ring of its own, sized once per batch for
+ * the largest graph within an equal share of the context's level budget
+ * (hgp_set_level_cache).
  */
 int hgp_partition_batch_device(hgp_ctx *ctx, int32_t n_graphs, const hgp_hypergraph *graphs, const int32_t *omega,
                                const int32_t *delta, const hgp_options *opt, const hgp_batch_sched *sched,

@@ -3,6 +3,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <algorithm>
 #include <atomic>
 #include <memory>
@@ -50,22 +51,34 @@ static int64_t level_cache_default() {
 }
 
 // A coarse level kept in HBM between coarsening and refinement (its hedge
-// CSR and incidence), so refinement need not rebuild it from level 0.
+// CSR and incidence), so refinement need not rebuild it from level 0.  Its
+// arrays lie in one range of the workspace's level ring.
 struct CachedLevel {
   int lvl = -1;
   int32_t n = 0;
   int64_t P = 0;
-  int64_t bytes = 0;
-  DevBuf hoff, hpin, ioff, inc, perm, indeg, total;
-  void release() {
-    for (DevBuf *b : {&hoff, &hpin, &ioff, &inc, &perm, &indeg, &total}) b->release();
-  }
-  // device bytes the entry's buffers hold (their capacities, which can exceed
-  // the level's own size once buffers have been recycled between levels)
-  int64_t held() const {
-    int64_t h = 0;
-    for (const DevBuf *b : {&hoff, &hpin, &ioff, &inc, &perm, &indeg, &total}) h += (int64_t)b->bytes;
-    return h;
+  size_t off = 0, bytes = 0;  // range in the ring
+  int32_t *hoff = nullptr, *ioff = nullptr, *indeg = nullptr, *total = nullptr;
+  uint32_t *hpin = nullptr, *inc = nullptr, *perm = nullptr;
+};
+
+// The kept levels share one device allocation used as a ring: a new level
+// goes right after the newest one (back to the start when it would run past
+// the end) and evicts the oldest levels it overlaps, so the most recent
+// levels within the budget stay.  The allocation is made once and reused by
+// every run (it grows between runs when the last run wanted more): a level
+// costs a copy of its hedge CSR (its incidence is built in place), never a
+// device allocation or free, each of which would synchronise the device.
+struct LevelRing {
+  DevBuf arena;
+  std::deque<CachedLevel> kept;  // oldest first
+  size_t head = 0;               // end of the newest level
+  int64_t want = 0;              // bytes of every coarse level of the current run
+  int64_t want_last = 0;         // ... of the previous run
+  int64_t kept_bytes() const {
+    int64_t b = 0;
+    for (const CachedLevel &c : kept) b += (int64_t)c.bytes;
+    return b;
   }
 };
 
@@ -90,10 +103,8 @@ struct Workspace {
   DevBuf dp_nchild, dp_arrived, dp_g, dp_key, dp_f, dp_root;  // exact matching
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
-  // coarse levels kept for refinement: most recent last, within the budget
-  std::vector<std::unique_ptr<CachedLevel>> lcache, lcache_free;
-  int64_t lcache_bytes = 0;  // level sizes of the kept entries
-  int64_t lcache_held = 0;   // buffer capacities of all entries, kept and free
+  // coarse levels kept for refinement: the most recent, within the budget
+  LevelRing ring;
   int64_t lcache_budget = level_cache_default();
   int rate_tile = 1024;        // rating workgroup size (schedule knob; same result)
   DevBuf tr_xq, tr_prm, tr_mom, tr_part, tr_perm, tr_loss, tr_grad;
@@ -101,22 +112,10 @@ struct Workspace {
       pmatch, pgam;
   std::vector<DevBuf> lv_match;
 
-  // Kept levels become free entries at the start of a run; their buffers are
-  // recycled (cache_level hands the workspace the largest free entry's
-  // buffers), so a repeated run allocates and frees nothing.  Every hipFree
-  // synchronises the device: releasing the ~1,500 kept levels of a conv302k
-  // partition at each run cost 2 s.
-  void clear_level_cache() {
-    for (auto &c : lcache) lcache_free.push_back(std::move(c));
-    lcache.clear();
-    lcache_bytes = 0;
-  }
-
   void release_level_cache() {
-    clear_level_cache();
-    for (auto &c : lcache_free) c->release();
-    lcache_free.clear();
-    lcache_held = 0;
+    ring.kept.clear();
+    ring.head = 0;
+    ring.arena.release();
   }
 
   // Per-level buffers (sizes, cluster maps, matches) are kept for the next
@@ -168,8 +167,10 @@ struct hgp_ctx {
   std::vector<std::unique_ptr<hgp::Workspace>> pool;
   std::vector<hipStream_t> pool_streams;
   hgp_batch_sched tuned{};  // zero until hgp_batch_tune ran
+  hgp::DevBuf batch_stamps;  // device clock at each batch graph's start and end
   ~hgp_ctx() {
     ws.release_all();
+    batch_stamps.release();
     for (auto &w : pool) w->release_all();
     for (hipStream_t st : pool_streams) (void)hipStreamDestroy(st);
   }
@@ -359,19 +360,22 @@ static void set_mid(Workspace &W, LevelView &V, hipStream_t s) {
 }
 
 // `size_cap` is the element capacity of the buffer behind `size` (checked).
+// The level's incidence is built in the workspace, or in the ring range of
+// `keep` when the level is kept.
 static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *hoff, const uint32_t *hpin,
                            int64_t P, const int32_t *size, size_t size_cap, const int32_t *hw, const BigHedges &big,
-                           hipStream_t s) {
+                           hipStream_t s, const CachedLevel *keep = nullptr) {
   if ((size_t)n > size_cap) throw Error(HGP_EINTERNAL, "node-size buffer smaller than the level");
-  int32_t *ioff = need<int32_t>(W.ioff, (int64_t)n + 1);
-  uint32_t *inc = need<uint32_t>(W.inc, P);
-  int32_t *indeg = need<int32_t>(W.indeg, n);
-  int32_t *total = need<int32_t>(W.total, n);
+  if (keep && (keep->n != n || keep->P != P)) throw Error(HGP_EINTERNAL, "kept level shape");
+  int32_t *ioff = keep ? keep->ioff : need<int32_t>(W.ioff, (int64_t)n + 1);
+  uint32_t *inc = keep ? keep->inc : need<uint32_t>(W.inc, P);
+  int32_t *indeg = keep ? keep->indeg : need<int32_t>(W.indeg, n);
+  int32_t *total = keep ? keep->total : need<int32_t>(W.total, n);
   uint32_t *tkey = need<uint32_t>(W.tkey, P);
   uint32_t *tkey2 = need<uint32_t>(W.tkey2, P);
   uint64_t *tval = need<uint64_t>(W.tval, P);
   uint64_t *tval2 = need<uint64_t>(W.tval2, P);
-  uint32_t *perm = need<uint32_t>(W.perm, P);
+  uint32_t *perm = keep ? keep->perm : need<uint32_t>(W.perm, P);
   build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, perm, indeg, total, tkey, tkey2, tval, tval2, W.sort_tmp, s);
   add_units(HGP_K_INCIDENCE, P);
   LevelView L;
@@ -467,7 +471,7 @@ static RoundResult refine_round(Workspace &W, const LevelView &L, int64_t P, int
 
 struct RunStats {
   int64_t conn = 0;
-  int32_t n_parts = 0, n_levels = 0, n_rounds = 0, n_fallback = 0;
+  int32_t n_parts = 0, n_levels = 0, n_rounds = 0, n_fallback = 0, n_kept = 0;
   double ms_coarsen = 0, ms_refine = 0;
   double ms_kernel[HGP_NKERNEL] = {};
   int64_t n_kernel[HGP_NKERNEL] = {};
@@ -579,86 +583,88 @@ static void trace_label(hgp_trace &T, int32_t N, const int32_t *part) {
   }
 }
 
-// Keeps level `lvl` (view L over hoff/hpin with P pins) for refinement,
-// evicting the oldest kept levels beyond the budget.
-// The level's buffers move into the cache entry (hoff_buf / hpin_buf: the
-// workspace buffers that hold L.hoff / L.hpin), and the entry's recycled
-// buffers take their place in the workspace, so nothing is copied.
-static void cache_level(Workspace &W, const LevelView &L, int lvl, int64_t P, DevBuf &hoff_buf, DevBuf &hpin_buf) {
-  const int32_t n = L.n, E = L.E;
-  const int64_t bytes = 4 * ((int64_t)E + 1) + 12 * P + 4 * ((int64_t)n + 1) + 8 * (int64_t)n;
-  if (bytes > W.lcache_budget) return;
-  while (!W.lcache.empty() && W.lcache_bytes + bytes > W.lcache_budget) {
-    W.lcache_bytes -= W.lcache.front()->bytes;
-    W.lcache_free.push_back(std::move(W.lcache.front()));
-    W.lcache.erase(W.lcache.begin());
-  }
-  // The entry's buffers go to the workspace, which builds the next (smaller)
-  // level in them: take the free entry holding the least memory among those
-  // whose every buffer fits this level, so the workspace needs no
-  // reallocation and the kept levels hold buffers of about their own size (a
-  // repeated run on the same hypergraph gets back the entry each level had).
-  std::unique_ptr<CachedLevel> c;
-  {
-    const size_t nb = 4 * ((size_t)n + 1), pb = 4 * (size_t)P, eb = 4 * ((size_t)E + 1);
-    size_t pick = W.lcache_free.size();
-    for (size_t i = 0; i < W.lcache_free.size(); ++i) {
-      const CachedLevel &f = *W.lcache_free[i];
-      const bool fits = f.hoff.bytes >= eb && f.hpin.bytes >= pb && f.inc.bytes >= pb && f.perm.bytes >= pb &&
-                        f.ioff.bytes >= nb && f.indeg.bytes >= nb && f.total.bytes >= nb;
-      if (fits && (pick == W.lcache_free.size() || f.held() < W.lcache_free[pick]->held())) pick = i;
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Ring size of a batch worker in level-0 sizes: the coarse levels of the
+// random networks add up to about 35 times level 0 (their hedges barely
+// shrink), those of the layered ones to about 7 times.
+constexpr int64_t kBatchRingLevels = 40;
+
+// Ring bytes of a level with n nodes, E hedges and P pins: hoff, hpin, ioff,
+// inc, perm, indeg and total, each starting on a 256-byte boundary.
+static size_t level_bytes(int32_t n, int32_t E, int64_t P) {
+  const size_t pb = align256(4 * (size_t)P), nb = align256(4 * ((size_t)n + 1));
+  return align256(4 * ((size_t)E + 1)) + 3 * pb + 3 * nb;
+}
+
+// Starts a run's level cache: the ring is emptied and, if the previous run
+// wanted more than it holds (or, on a first run, 32 times level 0's size),
+// reallocated at up to the budget (halving on failure).
+static void ring_begin(Workspace &W, int32_t N, int32_t E, int64_t P) {
+  LevelRing &R = W.ring;
+  if (R.want > 0) R.want_last = R.want;
+  R.kept.clear();
+  R.head = 0;
+  R.want = 0;
+  const int64_t budget = std::max<int64_t>(W.lcache_budget, 0);
+  int64_t desired = std::min<int64_t>(budget, std::max<int64_t>(R.want_last, 32 * (int64_t)level_bytes(N, E, P)));
+  desired &= ~int64_t(255);  // within the budget
+  if ((int64_t)R.arena.bytes > budget) R.arena.release();
+  if ((int64_t)R.arena.bytes >= desired) return;
+  R.arena.release();
+  while (desired >= (int64_t(1) << 20)) {
+    try {
+      R.arena.reserve((size_t)desired);
+      return;
+    } catch (const Error &e) {
+      if (e.code != HGP_ENOMEM) throw;
+      desired = (desired / 2) & ~int64_t(255);
     }
-    if (pick < W.lcache_free.size()) {
-      c = std::move(W.lcache_free[pick]);
-      W.lcache_free.erase(W.lcache_free.begin() + (ptrdiff_t)pick);
-    } else {
-      c.reset(new CachedLevel());
-    }
-  }
-  c->lvl = lvl;
-  c->n = n;
-  c->P = P;
-  c->bytes = bytes;
-  const int64_t held_before = c->held();
-  auto take = [&](DevBuf &entry, DevBuf &work, const void *held) {
-    if (work.ptr != held) throw Error(HGP_EINTERNAL, "level buffer not held by the workspace");
-    std::swap(entry, work);
-  };
-  take(c->hoff, hoff_buf, L.hoff);
-  take(c->hpin, hpin_buf, L.hpin);
-  take(c->ioff, W.ioff, L.ioff);
-  take(c->inc, W.inc, L.inc);
-  take(c->perm, W.perm, L.perm);
-  take(c->indeg, W.indeg, L.indeg);
-  take(c->total, W.total, L.total);
-  W.lcache_held += c->held() - held_before;
-  W.lcache_bytes += bytes;
-  W.lcache.push_back(std::move(c));
-  // The budget bounds device memory, so it also applies to what the entries
-  // hold: buffers recycled between levels of different sizes (a run after a
-  // run on another hypergraph or proposal) keep their larger capacities.
-  // Beyond a quarter over the budget, free entries go first, then the oldest
-  // kept levels (the newest always stays).  The slack absorbs the shift of
-  // one level's worth that each entry takes on in a repeated run (entry l
-  // ends up holding level l-1's buffers), so a repeated run on the same
-  // hypergraph allocates and frees nothing here.
-  const int64_t cap = W.lcache_budget + W.lcache_budget / 4;
-  while (W.lcache_held > cap && !W.lcache_free.empty()) {
-    W.lcache_held -= W.lcache_free.back()->held();
-    W.lcache_free.back()->release();
-    W.lcache_free.pop_back();
-  }
-  while (W.lcache_held > cap && W.lcache.size() > 1) {
-    W.lcache_held -= W.lcache.front()->held();
-    W.lcache_bytes -= W.lcache.front()->bytes;
-    W.lcache.front()->release();
-    W.lcache.erase(W.lcache.begin());
   }
 }
 
+// Places level `lvl` (n nodes, E hedges, P pins) in the ring, evicting the
+// oldest kept levels in its way; nullptr (nothing evicted) if the level is
+// larger than the ring.  Coarsening reads a level's incidence only until the
+// next level's is built, so the level just before may be evicted too.
+static const CachedLevel *ring_place(Workspace &W, int lvl, int32_t n, int32_t E, int64_t P) {
+  LevelRing &R = W.ring;
+  const size_t b = level_bytes(n, E, P);
+  R.want += (int64_t)b;
+  if (b > R.arena.bytes) return nullptr;
+  size_t off = R.head;
+  if (off + b > R.arena.bytes) {
+    // wrap: the levels between the head and the end are the oldest
+    while (!R.kept.empty() && R.kept.front().off >= R.head) R.kept.pop_front();
+    off = 0;
+  }
+  while (!R.kept.empty() && R.kept.front().off < off + b && R.kept.front().off + R.kept.front().bytes > off)
+    R.kept.pop_front();
+  CachedLevel c;
+  c.lvl = lvl;
+  c.n = n;
+  c.P = P;
+  c.off = off;
+  c.bytes = b;
+  char *p = R.arena.as<char>() + off;
+  const size_t pb = align256(4 * (size_t)P), nb = align256(4 * ((size_t)n + 1));
+  c.hoff = reinterpret_cast<int32_t *>(p);
+  p += align256(4 * ((size_t)E + 1));
+  c.hpin = reinterpret_cast<uint32_t *>(p);
+  c.inc = reinterpret_cast<uint32_t *>(p + pb);
+  c.perm = reinterpret_cast<uint32_t *>(p + 2 * pb);
+  p += 3 * pb;
+  c.ioff = reinterpret_cast<int32_t *>(p);
+  c.indeg = reinterpret_cast<int32_t *>(p + nb);
+  c.total = reinterpret_cast<int32_t *>(p + 2 * nb);
+  R.head = off + b;
+  R.kept.push_back(c);
+  return &R.kept.back();
+}
+
 static const CachedLevel *cached_level(const Workspace &W, int lvl) {
-  for (const auto &c : W.lcache)
-    if (c->lvl == lvl) return c.get();
+  for (const CachedLevel &c : W.ring.kept)
+    if (c.lvl == lvl) return &c;
   return nullptr;
 }
 
@@ -702,7 +708,6 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const int32_t *hw = I.hw;
   const int32_t *mlp_params = learned ? upload_mlp(W.mlp, opt.mlp, s) : nullptr;
   W.clear_levels();
-  W.clear_level_cache();
   level_slot(W.lv_size, 0);
   W.lv_n.push_back(N);
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
@@ -735,6 +740,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   need<uint32_t>(W.hpinB, P);
   need<uint32_t>(W.tmp_pins, P);
   need<int32_t>(W.cnt, E);
+  // after the level-0 buffers, which the ring must not crowd out
+  ring_begin(W, N, E, P);
 
   // ---- coarsening ----
   // Late levels that merge few pairs are rated incrementally (tail.hip):
@@ -871,8 +878,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       HGP_HIP(hipMemcpyAsync(Gm, gam, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
     else
       launch_project(W.lv_Gamma[lvl - 1].as<int32_t>(), gam, N, Gm, s);
-    // the contracted level (at most cur_P pins) goes to the other ping-pong
-    // pair, which a cached level may have replaced by a smaller buffer
+    // the contracted level (at most cur_P pins) goes to the other ping-pong pair
     DevBuf &hoff_buf = ping ? W.hoffB : W.hoffA;
     DevBuf &hpin_buf = ping ? W.hpinB : W.hpinA;
     int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
@@ -885,8 +891,13 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     cur_hpin = npin;
     ping ^= 1;
     ++lvl;
-    L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s);
-    cache_level(W, L, lvl, cur_P, hoff_buf, hpin_buf);
+    const CachedLevel *keep = ring_place(W, lvl, n_next, E, cur_P);
+    if (keep) {
+      HGP_HIP(hipMemcpyAsync(keep->hoff, cur_hoff, 4 * ((size_t)E + 1), hipMemcpyDeviceToDevice, s));
+      if (cur_P > 0)
+        HGP_HIP(hipMemcpyAsync(keep->hpin, cur_hpin, 4 * (size_t)cur_P, hipMemcpyDeviceToDevice, s));
+    }
+    L = make_view(W, n_next, E, cur_hoff, cur_hpin, cur_P, csize, W.lv_size[lvl].bytes / 4, hw, big, s, keep);
     tail = (int64_t)M * kTailRatio <= (int64_t)n;
     if (incremental && lists_ok && tail && (int64_t)M * n_next <= kRowBudget) {
       // rate level lvl incrementally from the lists of level lvl-1
@@ -942,17 +953,18 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       const CachedLevel *c = lv > 0 ? cached_level(W, lv) : nullptr;
       if (log_on())
         fprintf(stderr, "[hgp] refine level %d view %s (%zu levels kept, %.2f GB)\n", lv, c ? "kept" : "rebuilt",
-                W.lcache.size(), W.lcache_bytes / 1e9);
+                W.ring.kept.size(), W.ring.kept_bytes() / 1e9);
       if (c) {
+        ++st.n_kept;
         V.n = n;
         V.E = E;
-        V.hoff = c->hoff.as<int32_t>();
-        V.hpin = c->hpin.as<uint32_t>();
-        V.ioff = c->ioff.as<int32_t>();
-        V.inc = c->inc.as<uint32_t>();
-        V.perm = c->perm.as<uint32_t>();
-        V.indeg = c->indeg.as<int32_t>();
-        V.total = c->total.as<int32_t>();
+        V.hoff = c->hoff;
+        V.hpin = c->hpin;
+        V.ioff = c->ioff;
+        V.inc = c->inc;
+        V.perm = c->perm;
+        V.indeg = c->indeg;
+        V.total = c->total;
         V.size = W.lv_size[lv].as<int32_t>();
         V.hw = hw;
         V.big = big;
@@ -1082,6 +1094,7 @@ static void fill_result(hgp_result *res, const RunStats &st) {
   res->n_levels = st.n_levels;
   res->n_rounds = st.n_rounds;
   res->n_fallback = st.n_fallback;
+  res->n_kept = st.n_kept;
   res->ms_coarsen = st.ms_coarsen;
   res->ms_refine = st.ms_refine;
   for (int c = 0; c < HGP_NKERNEL; ++c) {
@@ -1161,6 +1174,22 @@ int hgp_ctx_create(hgp_ctx **ctx, int device) {
     c->device = device;
     c->noalloc_scratch = scratch;
     *ctx = c;
+  });
+}
+
+int hgp_set_level_cache(hgp_ctx *ctx, int64_t bytes, int64_t *held) {
+  if (!ctx) {
+    g_last_error = "ctx is NULL";
+    return HGP_EINVAL;
+  }
+  return guarded([&] {
+    DeviceGuard dg(ctx->device);
+    ctx->ws.lcache_budget = bytes < 0 ? level_cache_default() : bytes;
+    if ((int64_t)ctx->ws.ring.arena.bytes > ctx->ws.lcache_budget) {
+      HGP_HIP(hipDeviceSynchronize());  // a partition on another stream may still read the levels
+      ctx->ws.release_level_cache();
+    }
+    if (held) *held = (int64_t)ctx->ws.ring.arena.bytes;
   });
 }
 
@@ -1707,25 +1736,46 @@ static int64_t pins_of(const hgp_hypergraph &g, hipStream_t s) {
   return read_i32(g.hedge_off + g.n_hedges, s);
 }
 
+// Device wall-clock stamp (the constant-rate counter read by wall_clock64).
+__global__ void k_stamp(unsigned long long *slot) { *slot = (unsigned long long)wall_clock64(); }
+
 // Runs every graph once on `sc.workers` concurrent streams (one workspace
-// each), taking graphs in the schedule's order.  Times are host wall clock
-// in ms from the batch start.
+// each), taking graphs in the schedule's order.  Each graph's start and end
+// are stamped on its stream by the device clock; times are ms from a stamp
+// taken on the caller's stream before any graph starts.
 static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, const int32_t *omega,
                       const int32_t *delta, const hgp_options &opt, const hgp_batch_sched &sc, hipStream_t caller,
                       int32_t *const *part_out, hgp_result *res, double *t_start, double *t_end) {
   while ((int)ctx->pool.size() < sc.workers) {
     ctx->pool.emplace_back(new Workspace());
-    // no level cache in batch workers: graphs of different sizes would
-    // reallocate its buffers, and every hipFree synchronises the device
-    // across all workers
-    ctx->pool.back()->lcache_budget = 0;
     hipStream_t st = nullptr;
     HGP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     ctx->pool_streams.push_back(st);
   }
   HGP_HIP(hipStreamSynchronize(caller));
   std::vector<int64_t> pins((size_t)n);
-  for (int32_t i = 0; i < n; ++i) pins[(size_t)i] = pins_of(graphs[i], caller);
+  int64_t ring_need = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    pins[(size_t)i] = pins_of(graphs[i], caller);
+    ring_need = std::max<int64_t>(
+        ring_need, kBatchRingLevels * (int64_t)level_bytes(graphs[i].n_nodes, graphs[i].n_hedges, pins[(size_t)i]));
+  }
+  // Each worker keeps its graphs' coarse levels in a ring sized once for the
+  // largest graph of the batch (a share of the context's budget), so no
+  // worker reallocates it mid-batch: a hipFree would stall every worker.
+  const int64_t share = std::max<int64_t>(ctx->ws.lcache_budget, 0) / std::max(sc.workers, 1);
+  for (int w = 0; w < sc.workers; ++w) {
+    Workspace &W = *ctx->pool[(size_t)w];
+    W.lcache_budget = std::min(share, ring_need);
+    W.ring.want_last = std::max(W.ring.want_last, W.lcache_budget);
+  }
+  unsigned long long *stamps = need<unsigned long long>(ctx->batch_stamps, 2 * (int64_t)n + 1);
+  int khz = 0;
+  HGP_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+  if (khz <= 0) throw Error(HGP_EDEVICE, "device wall-clock rate unknown");
+  k_stamp<<<1, 1, 0, caller>>>(stamps + 2 * (int64_t)n);
+  HGP_HIP(hipGetLastError());
+  HGP_HIP(hipStreamSynchronize(caller));
   std::vector<int32_t> order((size_t)n);
   std::iota(order.begin(), order.end(), 0);
   if (sc.order == HGP_ORDER_LPT)
@@ -1749,16 +1799,17 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
         const int32_t i = next.fetch_add(1);
         if (i >= n) break;
         const int32_t g = order[(size_t)i];
-        const double a = now_ms() - t0;
+        k_stamp<<<1, 1, 0, s>>>(stamps + 2 * (int64_t)g);
+        HGP_HIP(hipGetLastError());
         TimerGuard tg(W, (o.flags & HGP_FLAG_TIME_KERNELS) != 0, s, o.time_classes);
         RunStats st = run_partition(W, &graphs[g], omega[g], delta[g], o, s, part_out[g]);
         tg.collect(st, s);
+        k_stamp<<<1, 1, 0, s>>>(stamps + 2 * (int64_t)g + 1);
+        HGP_HIP(hipGetLastError());
         HGP_HIP(hipStreamSynchronize(s));
-        const double b = now_ms() - t0;
-        if (t_start) t_start[g] = a;
-        if (t_end) t_end[g] = b;
         if (log_batch_on())
-          fprintf(stderr, "[hgp] batch graph %d (n=%d) done at %.0f ms by worker %d\n", g, graphs[g].n_nodes, b, w);
+          fprintf(stderr, "[hgp] batch graph %d (n=%d) done at %.0f ms (host) by worker %d\n", g, graphs[g].n_nodes,
+                  now_ms() - t0, w);
         if (res) fill_result(&res[g], st);
       }
     } catch (const Error &e) {
@@ -1779,6 +1830,16 @@ static void run_batch(hgp_ctx *ctx, int32_t n, const hgp_hypergraph *graphs, con
   for (int w = 0; w < sc.workers; ++w) th.emplace_back(work, w);
   for (auto &t : th) t.join();
   if (failed.load()) throw Error(err_code, err_msg);
+  if (n > 0 && (t_start || t_end)) {
+    std::vector<unsigned long long> h(2 * (size_t)n + 1);
+    HGP_HIP(hipMemcpy(h.data(), stamps, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+    const unsigned long long base = h[2 * (size_t)n];
+    const double per_ms = (double)khz;  // ticks per ms
+    for (int32_t g = 0; g < n; ++g) {
+      if (t_start) t_start[g] = (double)(long long)(h[2 * (size_t)g] - base) / per_ms;
+      if (t_end) t_end[g] = (double)(long long)(h[2 * (size_t)g + 1] - base) / per_ms;
+    }
+  }
 }
 
 static void check_batch_args(int32_t n, const hgp_hypergraph *graphs, const int32_t *omega, const int32_t *delta,

@@ -119,7 +119,8 @@ class Options_t(ctypes.Structure):
 
 class Result_t(ctypes.Structure):
     _fields_ = [("connectivity", ctypes.c_int64), ("n_parts", ctypes.c_int32), ("n_levels", ctypes.c_int32),
-                ("n_rounds", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("ms_coarsen", ctypes.c_double),
+                ("n_rounds", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("n_kept", ctypes.c_int32),
+                ("ms_coarsen", ctypes.c_double),
                 ("ms_refine", ctypes.c_double), ("ms_kernel", ctypes.c_double * NK),
                 ("n_kernel", ctypes.c_int64 * NK), ("units_kernel", ctypes.c_int64 * NK)]
 
@@ -130,7 +131,7 @@ class Level_t(ctypes.Structure):
 
 
 EXPORTS = [
-    "hgp_ctx_create", "hgp_ctx_destroy", "hgp_options_default", "hgp_partition", "hgp_partition_device",
+    "hgp_ctx_create", "hgp_ctx_destroy", "hgp_set_level_cache", "hgp_options_default", "hgp_partition", "hgp_partition_device",
     "hgp_connectivity_device", "hgp_strerror", "hgp_last_error", "hgp_level_canonical", "hgp_level_rate",
     "hgp_level_match", "hgp_level_contract", "hgp_level_refine_round", "hgp_level_learned",
     "hgp_mlp_score_device", "hgp_mlp_init", "hgp_mlp_grad", "hgp_mlp_train", "hgp_mlp_quantize",
@@ -157,6 +158,7 @@ def load():
     lib.hgp_ctx_destroy.argtypes = [vp]
     lib.hgp_ctx_destroy.restype = None
     lib.hgp_options_default.argtypes = [ctypes.POINTER(Options_t)]
+    lib.hgp_set_level_cache.argtypes = [vp, ctypes.c_int64, i64p]
     lib.hgp_options_default.restype = None
     lib.hgp_partition.argtypes = [vp, HG, i32, i32, ctypes.POINTER(Options_t), vp, ctypes.POINTER(Result_t)]
     lib.hgp_partition_device.argtypes = [vp, HG, i32, i32, ctypes.POINTER(Options_t), vp, vp,
@@ -236,6 +238,13 @@ class Context:
         self.handle = h
         self.device = device
 
+    def set_level_cache(self, nbytes: int) -> int:
+        """Device bytes the context may keep coarse levels in (0: none, -1:
+        the default); returns the bytes it holds for them now."""
+        held = ctypes.c_int64(0)
+        _check(self._lib.hgp_set_level_cache(self.handle, int(nbytes), ctypes.byref(held)))
+        return held.value
+
     def close(self):
         if getattr(self, "handle", None):
             self._lib.hgp_ctx_destroy(self.handle)
@@ -264,7 +273,7 @@ def options(k: int = 0, max_refine_rounds: int = 8, seed: int = 0, flags: int = 
 
 def _result_dict(r: Result_t) -> dict:
     return dict(connectivity=r.connectivity, n_parts=r.n_parts, n_levels=r.n_levels, n_rounds=r.n_rounds,
-                n_fallback=r.n_fallback, ms_coarsen=r.ms_coarsen, ms_refine=r.ms_refine,
+                n_fallback=r.n_fallback, n_kept=r.n_kept, ms_coarsen=r.ms_coarsen, ms_refine=r.ms_refine,
                 kernels={name: dict(ms=r.ms_kernel[i], launches=r.n_kernel[i], units=r.units_kernel[i])
                          for i, name in enumerate(KERNEL_CLASSES)})
 

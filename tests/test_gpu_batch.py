@@ -1,6 +1,7 @@
 """Batches of independent hypergraphs: every schedule gives each graph the
 result of a single call (and of the oracle)."""
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -67,11 +68,18 @@ def test_batch_matches_single_calls(ctx, singles, sched):
 
     gs, om, de, dgs, ref = singles
     say(f"[batch] schedule {sched}")
+    wall = time.perf_counter()
     parts, res, t0, t1 = hgp.partition_batch_device(ctx, dgs, om, de, sched=sched)
+    wall = (time.perf_counter() - wall) * 1e3
     for i in range(len(gs)):
         assert np.array_equal(parts[i].cpu().numpy(), ref[i][0]), i
         assert res[i]["connectivity"] == ref[i][1] and res[i]["n_parts"] == ref[i][2]
-    assert np.all(t0 >= 0) and np.all(t1 >= t0)
+        if res[i]["n_levels"] >= 3:
+            assert res[i]["n_kept"] > 0, i  # the workers keep coarse levels
+    # device-clock stamps: inside the call, and one after another on one worker
+    assert np.all(t0 >= 0) and np.all(t1 > t0) and t1.max() <= wall * 1.05 + 5.0
+    if sched and sched.get("workers") == 1 and sched.get("order") == 2:
+        assert np.all(t0[1:] >= t1[:-1])
 
 
 def test_batch_matches_oracle(singles):
