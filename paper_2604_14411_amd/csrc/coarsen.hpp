@@ -186,6 +186,7 @@ struct RoundBufs {
   int64_t *tile_e = nullptr;   // [cap_tiles] per tile of sorted events: size-sum aggregate
   int32_t *tile_i = nullptr;   // [2 cap_tiles] inbound-sum aggregate, then the part-start flags
   DevBuf *partial = nullptr;   // per-workgroup inb(p) rows of the part-table kernel
+  int64_t *hbox = nullptr;     // pinned host words for the round's read-backs
   int64_t cap_events = 0;
   int64_t cap_tiles = 0;
 };

@@ -42,6 +42,17 @@ inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Counts of DevBuf device allocations and frees (diagnostics).
 extern std::atomic<int64_t> g_dev_allocs, g_dev_frees;
 
+// Pinned host words for small device-to-host reads.  A copy into pageable
+// memory is staged and blocks the host copy by copy; into pinned memory it is
+// a plain asynchronous copy, so the reads of one step share a single stream
+// synchronisation.
+struct HostBox {
+  static constexpr int kWords = 64;
+  int64_t *p = nullptr;
+  int64_t *get();  // allocated on first use
+  void release();
+};
+
 // Grow-only device buffer owned by a context.
 struct DevBuf {
   void *ptr = nullptr;

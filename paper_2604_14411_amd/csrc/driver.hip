@@ -97,6 +97,7 @@ struct Workspace {
   std::vector<int32_t> lv_n;
   KTimer timer;
   DevBuf units_dev;
+  HostBox hbox;  // pinned words for read-backs
   // incremental late levels
   DevBuf tkA_key, tkA_c, tkA_cnt, tkA_kap, tkB_key, tkB_c, tkB_cnt, tkB_kap, newc, row_slot, nflag, rerate, dev_cnt;
   DevBuf split, cdest, cgain, maxbits, biglist, midlist, longlist, huge_k, huge_i, tail_acc;
@@ -140,6 +141,7 @@ struct Workspace {
                      &in_nsrc, &in_hw, &in_nw, &in_part, &ones_e, &ones_n};
     for (DevBuf *b : all) b->release();
     units_dev.release();
+    hbox.release();
     release_level_cache();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
                           &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &huge_k, &huge_i, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
@@ -221,6 +223,14 @@ static int32_t read_i32(const int32_t *dptr, hipStream_t s) {
   return v;
 }
 
+// As read_i32, through the workspace's pinned words (the per-level reads).
+static int32_t read_i32(Workspace &W, const int32_t *dptr, hipStream_t s) {
+  int32_t *h = reinterpret_cast<int32_t *>(W.hbox.get());
+  HGP_HIP(hipMemcpyAsync(h, dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipStreamSynchronize(s));
+  return h[0];
+}
+
 static void raise_err(int32_t bits) {
   const char *msg = "";
   const int rc = map_err(bits, &msg);
@@ -228,12 +238,12 @@ static void raise_err(int32_t bits) {
 }
 
 static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
-  raise_err(read_i32(W.err.as<int32_t>(), s) & mask);
+  raise_err(read_i32(W, W.err.as<int32_t>(), s) & mask);
 }
 
 // *dptr and the error bits in one round trip; throws on an error
 static int32_t read_i32_checked(Workspace &W, const int32_t *dptr, hipStream_t s) {
-  int32_t v[2] = {0, 0};
+  int32_t *v = reinterpret_cast<int32_t *>(W.hbox.get());
   HGP_HIP(hipMemcpyAsync(&v[0], dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipMemcpyAsync(&v[1], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
@@ -422,6 +432,7 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.scal = need<int64_t>(W.scal, 8);
   B.heavy = need<int32_t>(W.heavy, E);
   B.evoff = need<int64_t>(W.evoff, (int64_t)E + 1);
+  B.hbox = W.hbox.get();
   return B;
 }
 
@@ -530,6 +541,8 @@ static CandBufs cand_bufs(Workspace &W, int32_t n, int32_t *pair, int64_t *score
   B.score = score;
   B.ppair = need<int32_t>(W.ppair, n);
   B.pscore = need<int64_t>(W.pscore, n);
+  B.best = need<unsigned long long>(W.best, n);  // the matching refills it
+  B.hbox = W.hbox.get();
   return B;
 }
 
@@ -833,7 +846,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       int32_t *pg = need<int32_t>(W.pgam, n);
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
-      int32_t v[3] = {0, 0, 0};
+      int32_t *v = reinterpret_cast<int32_t *>(W.hbox.get());
       HGP_HIP(hipMemcpyAsync(v, nnext_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGP_HIP(hipMemcpyAsync(&v[2], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
       HGP_HIP(hipStreamSynchronize(s));
@@ -886,7 +899,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
                     W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
     add_units(HGP_K_CONTRACT, cur_P);
-    cur_P = read_i32(nh + E, s);
+    cur_P = read_i32(W, nh + E, s);
     cur_hoff = nh;
     cur_hpin = npin;
     ping ^= 1;
@@ -980,7 +993,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
                         W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
         add_units(HGP_K_CONTRACT, P);
-        Pl = read_i32(rh + E, s);
+        Pl = read_i32(W, rh + E, s);
         h = rh;
         p = rp;
       }

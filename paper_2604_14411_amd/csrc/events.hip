@@ -1054,9 +1054,9 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     k_move_gain<<<div_up(S, 4), 256, 0, s>>>(B.seq, S, L.ioff, L.perm, B.contrib, B.gp);
     HGP_LAUNCH_CHECK();
   }
-  int64_t nin = 0;
-  HGP_HIP(hipMemcpyAsync(&nin, B.evoff + L.E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(B.hbox, B.evoff + L.E, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
+  const int64_t nin = B.hbox[0];
   const int64_t nev = nin + 2 * S;
   if (nev > B.cap_events) throw Error(-7, "event buffer overflow");
   add_units(kClsEvents, 16 * nev);  // algorithmic bytes: an 8-byte event key written and read once
@@ -1090,12 +1090,12 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
     HGP_LAUNCH_CHECK();
   }
   // the result and the error bits in one round trip
-  int64_t res[2];
-  HGP_HIP(hipMemcpyAsync(res, B.scal + SC_ISTAR, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipMemcpyAsync(err_bits, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_ISTAR, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(B.hbox + 2, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
-  *istar = res[0];
-  *gstar = res[1];
+  *istar = B.hbox[0];
+  *gstar = B.hbox[1];
+  *err_bits = *reinterpret_cast<const int32_t *>(B.hbox + 2);
 }
 
 }  // namespace hgp

@@ -9,7 +9,7 @@
 //   3. k_cand_score: exact integer features of the unordered pair, their
 //      8-bit codes and the fixed-point network (two 64-unit ReLU layers on
 //      MFMA, a 64-term integer dot product for the output);
-//   4. k_cand_select: pair(n) = argmax over C(n) of (score, id).
+//   4. k_cand_best / k_cand_pick: pair(n) = argmax over C(n) of (score, id).
 // The network's values are integers carried in BF16 (|w| <= 255, codes and
 // activations in 0..255) and every partial sum stays below 2^24 in magnitude,
 // so the FP32 accumulation of v_mfma_f32_32x32x8_bf16 is exact in any order
@@ -462,39 +462,42 @@ __global__ void k_cand_codes(CandCodes cf, int64_t C, int32_t *__restrict__ xq) 
 // pair(n) = argmax over C(n) of (score, id); the matching key is score + 2^31
 // (order-preserving, in [0, 2^32)).  ppair / pscore: the plain pair (first
 // kept candidate) and its hist.
-__global__ void k_cand_select(const uint64_t *__restrict__ cnm, const int32_t *__restrict__ cs,
-                              const int64_t *__restrict__ coff, int32_t N, int idbits,
-                              const uint64_t *__restrict__ ck, const int32_t *__restrict__ ccnt,
-                              int32_t *__restrict__ pair, int64_t *__restrict__ score, int32_t *__restrict__ ppair,
-                              int64_t *__restrict__ pscore) {
+// pair(n) = the candidate m maximising (score, id), as the packed key
+// (score + 2^31) << 32 | m (scores stay far above -2^31, so a key is never 0,
+// the value of a node without candidates).  One lane per candidate of the
+// node-sorted array: a segmented maximum over the wave's runs of equal n and
+// one atomicMax per run, so a node that is in the candidate sets of
+// thousands of others costs a few hundred atomics, not a serial scan.
+__global__ void k_cand_best(const uint64_t *__restrict__ cnm, const int32_t *__restrict__ cs, int64_t C, int idbits,
+                            unsigned long long *__restrict__ best) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < C;
+  const uint64_t e = in ? cnm[i] : 0ull;
+  const int64_t n = in ? (int64_t)(e >> idbits) : -1 - (int64_t)lane_id();  // lanes past C: runs of their own
+  unsigned long long key =
+      in ? ((unsigned long long)((int64_t)cs[i] + 2147483648LL) << 32) | (e & ((1ull << idbits) - 1ull)) : 0ull;
+  const int l = lane_id();
+  // the array is sorted by n, so equal n are contiguous lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long k2 = __shfl_up(key, o, 64);
+    const int64_t n2 = __shfl_up(n, o, 64);
+    if (l >= o && n2 == n && k2 > key) key = k2;
+  }
+  const int64_t nn = __shfl_down(n, 1, 64);
+  if (in && (l == 63 || nn != n)) atomicMax(&best[n], key);
+}
+
+// Unpacks the selection and records the plain pair (the first candidate of
+// the rating).
+__global__ void k_cand_pick(const unsigned long long *__restrict__ best, int32_t N, const uint64_t *__restrict__ ck,
+                            const int32_t *__restrict__ ccnt, int32_t *__restrict__ pair, int64_t *__restrict__ score,
+                            int32_t *__restrict__ ppair, int64_t *__restrict__ pscore) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  const uint64_t mask = (1ull << idbits) - 1ull;
-  int best_m = -1;
-  int32_t best_s = 0;
-  const int64_t a = coff[n], z = coff[n + 1];
-  // four candidates' loads in flight before they are compared, in order
-  for (int64_t c = a; c < z; c += 4) {
-    uint64_t km[4];
-    int32_t ks[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      km[u] = c + u < z ? cnm[c + u] : 0ull;
-      ks[u] = c + u < z ? cs[c + u] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (c + u >= z) break;
-      const int m = (int)(km[u] & mask);
-      const int32_t s = ks[u];
-      if (best_m < 0 || s > best_s || (s == best_s && m > best_m)) {
-        best_m = m;
-        best_s = s;
-      }
-    }
-  }
-  pair[n] = best_m;
-  score[n] = best_m < 0 ? 0 : (int64_t)best_s + 2147483648LL;
+  const unsigned long long b = best[n];
+  pair[n] = b ? (int32_t)(b & 0xffffffffull) : -1;
+  score[n] = b ? (int64_t)(b >> 32) : 0;
   const uint64_t k0 = ck[n * kCandK];
   const bool any = ccnt[n] > 0;
   ppair[n] = any ? (int)(k0 & 0xffffffffull) : -1;
@@ -558,9 +561,9 @@ int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf
   {
     KScope ks(HGP_K_MLP, s);
     scan_i32(B.ccnt, B.coff32, N, B.tot32, scan_tmp, s);
-    int32_t kept = 0;
-    HGP_HIP(hipMemcpyAsync(&kept, B.tot32, sizeof kept, hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipMemcpyAsync(B.hbox, B.tot32, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGP_HIP(hipStreamSynchronize(s));
+    const int32_t kept = *reinterpret_cast<const int32_t *>(B.hbox);
     M = 2 * (int64_t)kept;
     if (M > 0) {
       k_cand_mirror<<<div_up((int64_t)N * kCandK, 256), 256, 0, s>>>(B.ck, B.ccnt, B.coff32, N, idbits, B.key,
@@ -576,10 +579,9 @@ int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf
     scan_i32(B.flag, B.flag, M, B.tot32 + 1, scan_tmp, s);
     k_cand_compact<<<div_up(M, 256), 256, 0, s>>>(B.key, B.val, M, B.flag, B.cnm, B.csrc);
     HGP_LAUNCH_CHECK();
-    int32_t c32 = 0;
-    HGP_HIP(hipMemcpyAsync(&c32, B.tot32 + 1, sizeof c32, hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipMemcpyAsync(B.hbox, B.tot32 + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGP_HIP(hipStreamSynchronize(s));
-    C = c32;
+    C = *reinterpret_cast<const int32_t *>(B.hbox);
   }
   k_cand_offsets<<<div_up((int64_t)N + 1, 256), 256, 0, s>>>(B.cnm, C, N, idbits, B.coff);
   HGP_LAUNCH_CHECK();
@@ -598,8 +600,12 @@ void score_and_select(const LevelView &L, int32_t omega, int32_t delta, int leve
     k_cand_score<<<grid_for_tiles(C), MLP_NT, 0, s>>>(cf, C, params, B.cs);
     HGP_LAUNCH_CHECK();
   }
-  k_cand_select<<<div_up(N, 256), 256, 0, s>>>(B.cnm, B.cs, B.coff, N, idbits, B.ck, B.ccnt, B.pair, B.score,
-                                               B.ppair, B.pscore);
+  fill_i64(reinterpret_cast<int64_t *>(B.best), N, 0, s);
+  if (C > 0) {
+    k_cand_best<<<div_up(C, 256), 256, 0, s>>>(B.cnm, B.cs, C, idbits, B.best);
+    HGP_LAUNCH_CHECK();
+  }
+  k_cand_pick<<<div_up(N, 256), 256, 0, s>>>(B.best, N, B.ck, B.ccnt, B.pair, B.score, B.ppair, B.pscore);
   HGP_LAUNCH_CHECK();
 }
 

@@ -33,6 +33,8 @@ struct CandBufs {
   int64_t *score = nullptr;  // [N] matching key score + 2^31
   int32_t *ppair = nullptr;  // [N] plain pair
   int64_t *pscore = nullptr; // [N] its hist
+  unsigned long long *best = nullptr;  // [N] selection scratch: best packed (score, id) per node
+  int64_t *hbox = nullptr;             // pinned host words for read-backs
 };
 
 // Validates a network (HGP_EINVAL / HGP_EUNSUPPORTED) and copies it to buf.

@@ -83,6 +83,20 @@ void DevBuf::reserve(size_t need) {
   bytes = b;
 }
 
+int64_t *HostBox::get() {
+  if (!p) {
+    void *q = nullptr;
+    HGP_HIP(hipHostMalloc(&q, kWords * sizeof(int64_t), hipHostMallocDefault));
+    p = static_cast<int64_t *>(q);
+  }
+  return p;
+}
+
+void HostBox::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+}
+
 void DevBuf::release() {
   if (ptr) {
     (void)hipFree(ptr);

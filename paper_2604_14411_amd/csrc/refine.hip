@@ -444,12 +444,11 @@ int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBu
   HGP_LAUNCH_CHECK();
   scan_i32(B.flag, B.flag, N, reinterpret_cast<int32_t *>(B.scal + SC_S), scan_tmp, s);
   // |S| and the largest gain in one round trip
-  int32_t S32 = 0;
-  int64_t gmax = 0;
-  HGP_HIP(hipMemcpyAsync(&S32, B.scal + SC_S, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipMemcpyAsync(&gmax, B.scal + SC_GMAX, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_S, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(B.hbox + 1, B.scal + SC_GMAX, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
-  const int64_t S = S32;
+  const int64_t S = *reinterpret_cast<const int32_t *>(B.hbox);
+  const int64_t gmax = B.hbox[1];
   if (S == 0) return 0;
   const int idbits = bits_for(N - 1) > 0 ? bits_for(N - 1) : 1;
   const int gbits = bits_for(gmax);
