@@ -327,7 +327,7 @@ __global__ __launch_bounds__(NT) void k_rate(int32_t N, const int32_t *__restric
       // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
       streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
         constexpr int MODE = decltype(mode)::value;
-        return stream_segments<NT / 64, 4, true, uint32_t>(
+        return stream_segments<NT / 64, kRateU, true, uint32_t>(
             i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
             [&](uint32_t y, uint32_t info) {
               const int m = (int)(y & kIdMask);
@@ -762,6 +762,13 @@ static void launch_rate_nt(const LevelView &L, const int32_t *total, const int32
   (void)attr_set;
   k_rate<NT><<<xcd_grid(L.n), NT, (size_t)words * 4, s>>>(L.n, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
                                                 maxin, omega, delta, words, pair, score, units_ptr(0));
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_max_i32(const int32_t *a, int32_t n, int32_t *out, hipStream_t s) {
+  fill_i32(out, 1, 0, s);
+  if (n <= 0) return;
+  k_max_i32<<<std::min(div_up(n, 2048), 256), 256, 0, s>>>(a, n, out);
   HGP_LAUNCH_CHECK();
 }
 

@@ -53,6 +53,7 @@ struct LevelView {
   const int32_t *size = nullptr;   // [n]
   const int32_t *indeg = nullptr;  // [n]
   const int32_t *total = nullptr;  // [n] sum of w(e) over I(n)
+  const int32_t *maxin = nullptr;  // [1] largest indeg of the level (set for the levels coarsening rates)
   const int32_t *hw = nullptr;     // [E]
   BigHedges big;                   // hedges longer than kWaveSegMax (a superset is fine)
   MidHedges mid;                   // this level's hedges for the wave part-table kernel
@@ -74,6 +75,8 @@ void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32
 void launch_feasible(const int32_t *size, const int32_t *indeg, int32_t N, int32_t omega, int32_t delta,
                      int32_t *err, hipStream_t s);
 // maxin: one device int32 of scratch (max |in(n)| of the level)
+// *out = max(0, a[0 .. n)).
+void launch_max_i32(const int32_t *a, int32_t n, int32_t *out, hipStream_t s);
 void launch_rate(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, int32_t *pair,
                  int64_t *score, int32_t *maxin, hipStream_t s, int tile = 512);
 void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned long long *best, uint8_t *up,

@@ -89,6 +89,68 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Slots of the LDS hash set of inbound_common for a node with `din` inbound
+// hedges: the power of two at least twice din (at least 64).
+__host__ __device__ inline int inbound_slots(uint32_t din) {
+  int s = 64;
+  while ((uint32_t)s < 2u * din) s <<= 1;
+  return s;
+}
+
+// c(n, m) = |in(n) ∩ in(m)| (hedges holding both nodes as destinations) for
+// the candidates m = key[r] & 0xffffffff, r < cnt, into c[r]: n's inbound
+// hedges go into an open-addressing hash set of `slots` LDS words (a power
+// of two, at least twice their number: probes always end), then one wave per
+// candidate looks up the candidate's inbound hedges.  Block-wide; the caller
+// synchronises before the table's words are reused.
+template <int NT>
+__device__ void inbound_common(int n, const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
+                               uint32_t *table, int slots, const uint64_t *key, int32_t *c, int cnt) {
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  const uint32_t mask = (uint32_t)slots - 1u, empty = 0xffffffffu;
+  for (int i = tid; i < slots; i += NT) table[i] = empty;
+  __syncthreads();
+  for (int i = ioff[n] + tid; i < ioff[n + 1]; i += NT) {
+    const uint32_t v = inc[i];
+    if (!(v >> 31)) continue;  // n is a source of this hedge
+    const uint32_t e = v & kIdMask;
+    for (uint32_t h = (e * 2654435761u) & mask;; h = (h + 1u) & mask) {
+      const uint32_t old = atomicCAS(&table[h], empty, e);
+      if (old == empty || old == e) break;
+    }
+  }
+  __syncthreads();
+  constexpr int B = 8;  // incidences loaded per lane before they are looked up
+  for (int r = w; r < cnt; r += NT / 64) {
+    const int m = (int)(key[r] & 0xffffffffull);
+    const int j1 = ioff[m + 1];
+    int k = 0;
+    for (int j0 = ioff[m]; j0 < j1; j0 += 64 * B) {
+      uint32_t v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int j = j0 + u * 64 + l;
+        v[u] = j < j1 ? inc[j] : 0u;  // 0: not a destination, skipped
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (!(v[u] >> 31)) continue;
+        const uint32_t e = v[u] & kIdMask;
+        for (uint32_t h = (e * 2654435761u) & mask;; h = (h + 1u) & mask) {
+          const uint32_t t = table[h];
+          if (t == e) {
+            ++k;
+            break;
+          }
+          if (t == empty) break;
+        }
+      }
+    }
+    k = wave_sum(k);
+    if (l == 0) c[r] = k;
+  }
+}
+
 // Block-wide exclusive scan of a[0..n) in place (any address space).  Each
 // thread scans a contiguous chunk; chunk totals are scanned by wave shuffles.
 // `tmp` must hold NT/64 + 1 elements of shared memory.  Returns the total.
@@ -165,6 +227,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 // each segment is first narrowed by binary search to the entries whose id
 // lies in [clip_lo, clip_hi): a rating over several LDS windows then streams
 // each pin once instead of once per window.
+// Loads in flight per lane in the ratings' pin streams: each round of U
+// loads waits out one cache latency before its LDS updates, so the pin rate
+// of a latency-bound stream grows with U.
+constexpr int kRateU = 16;
+
 template <int NW, int U, bool LEN_FROM_END, class V, class Load, class Apply>
 __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_t *__restrict__ inc,
                                                    const int32_t *__restrict__ soff, const int32_t *__restrict__ slen,

@@ -388,6 +388,8 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   uint32_t *perm = keep ? keep->perm : need<uint32_t>(W.perm, P);
   build_incidence(hoff, hpin, E, n, P, hw, ioff, inc, perm, indeg, total, tkey, tkey2, tval, tval2, W.sort_tmp, s);
   add_units(HGP_K_INCIDENCE, P);
+  int32_t *maxin = need<int32_t>(W.maxin, 1);  // the ratings' test of whether Delta can bind
+  launch_max_i32(indeg, n, maxin, s);
   LevelView L;
   L.n = n;
   L.E = E;
@@ -399,6 +401,7 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   L.size = size;
   L.indeg = indeg;
   L.total = total;
+  L.maxin = maxin;
   L.hw = hw;
   L.big = big;
   return L;
@@ -780,7 +783,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int32_t *row_slot = need<int32_t>(W.row_slot, N);
   int32_t *nflag = need<int32_t>(W.nflag, N);
   int32_t *rerate = need<int32_t>(W.rerate, N);
-  int64_t *dcnt = need<int64_t>(W.dev_cnt, 4);
+  int64_t *dcnt = need<int64_t>(W.dev_cnt, 8);  // [4..7]: re-rating diagnostics (HGP_LOG)
   bool have_pairs = false;  // pair/score of the current level already computed
   bool lists_ok = false;    // tk_cur holds exact lists for the current level
   bool lists_fresh = false; // ... carried to it incrementally (learned: first k entries certain)
@@ -918,19 +921,24 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       fill_i64(dcnt, 1, M, s);
       const uint64_t *rows = launch_rate_topk_rows(L, L.total, omega, delta, newc, dcnt, M, row_slot,
                                                    pair, score, tk_nxt, W.tail_acc, s);
-      fill_i64(dcnt + 1, 1, 0, s);
+      if (log_on()) fill_i64(dcnt + 4, 4, 0, s);
+      // re-rated nodes: flags in nflag (free after the new clusters' list),
+      // count in dcnt[1] (dcnt[2] holds the scan total)
       launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, learned ? opt.mlp->k : 1, tk_nxt, pair,
-                         score, rerate, dcnt + 1, s);
+                         score, nflag, rerate, dcnt + 1, W.scan_tmp, s, log_on() ? dcnt + 4 : nullptr);
       launch_rate_topk(L, L.total, omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
       have_pairs = !learned;
       lists_fresh = learned;
       lists_ok = true;
       path = "incremental";
       if (log_on()) {
-        int64_t rr = 0;
-        HGP_HIP(hipMemcpyAsync(&rr, dcnt + 1, sizeof rr, hipMemcpyDeviceToHost, s));
+        int64_t rr[8] = {};
+        HGP_HIP(hipMemcpyAsync(rr, dcnt, sizeof rr, hipMemcpyDeviceToHost, s));
         HGP_HIP(hipStreamSynchronize(s));
-        fprintf(stderr, "[hgp]   level %d: %d new clusters rated, %lld nodes re-rated\n", lvl, M, (long long)rr);
+        fprintf(stderr,
+                "[hgp]   level %d: %d new clusters rated, %lld nodes re-rated (hist-only bound %lld, short list "
+                "%lld, need-th key at or below the bound %lld; bound's node merged at %lld nodes)\n",
+                lvl, M, (long long)rr[1], (long long)rr[4], (long long)rr[5], (long long)rr[6], (long long)rr[7]);
       }
     } else {
       lists_ok = false;

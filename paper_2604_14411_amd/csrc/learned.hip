@@ -65,14 +65,17 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
 __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     int32_t N, const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
     const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw, const int32_t *__restrict__ size,
-    const int32_t *__restrict__ indeg, const int32_t *__restrict__ total, int32_t omega, int32_t delta,
-    int32_t words, int32_t keep, uint64_t *__restrict__ ck, int32_t *__restrict__ cc, int32_t *__restrict__ ccnt,
-    unsigned long long *__restrict__ units) {
+    const int32_t *__restrict__ indeg, const int32_t *__restrict__ total, const int32_t *__restrict__ maxin,
+    int32_t omega, int32_t delta, int32_t words, int32_t keep, uint64_t *__restrict__ ck, int32_t *__restrict__ cc,
+    int32_t *__restrict__ ccnt, unsigned long long *__restrict__ units) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint64_t wk[CAND_NT / 64][kCandK];
   __shared__ int32_t wc[CAND_NT / 64][kCandK];
   __shared__ int32_t tbl[CAND_NT / 64 * 192];
   __shared__ int2 rng_s[CAND_NT / 64];
+  __shared__ uint64_t selk[kCandK];
+  __shared__ int32_t selc[kCandK];
+  __shared__ int32_t selcnt;
   const int n = xcd_node((int)blockIdx.x, N);
   if (n < 0) return;
   const int tid = threadIdx.x;
@@ -86,14 +89,18 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
   }
   int64_t streamed = 0;
   const int64_t sn = size[n];
+  const uint32_t din = (uint32_t)indeg[n];
+  bool half = false;
   if (sn < omega) {
     const uint32_t tot = (uint32_t)total[n];
-    const uint32_t din = (uint32_t)indeg[n];
     const int hb = tot ? 32 - __clz(tot) : 0;
     const int cb = din ? 32 - __clz(din) : 0;
     const bool packed = hb + cb <= 32;
+    // hist alone in 16-bit halves when it fits and no candidate can break
+    // Delta (c is then counted afterwards for the kept candidates only)
+    half = maxin && hb <= 16 && (int64_t)din + (int64_t)(*maxin) <= (int64_t)delta && inbound_slots(din) <= words;
     const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
-    const int R = packed ? words : (words >> 1);
+    const int R = half ? 2 * words : (packed ? words : (words >> 1));
     const int i0 = ioff[n], i1 = ioff[n + 1];
     uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
     // windows over the neighbours' id range only
@@ -101,12 +108,13 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     const uint32_t *clip = ((int64_t)rg.y - rg.x >= R) ? hpin : nullptr;  // several windows
     for (int lo = rg.x; lo <= rg.y; lo += R) {
       const int span = min(R, rg.y + 1 - lo);
-      const int zw = packed ? span : 2 * span;
+      const int zw = half ? (span + 1) >> 1 : (packed ? span : 2 * span);
       for (int i = tid; i < zw; i += CAND_NT) lds[i] = 0u;
       __syncthreads();
-      streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
+      // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
+      streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
         constexpr int MODE = decltype(mode)::value;
-        return stream_segments<CAND_NT / 64, 4, true, uint32_t>(
+        return stream_segments<CAND_NT / 64, kRateU, true, uint32_t>(
             i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
             [&](uint32_t y, uint32_t info) {
               const int m = (int)(y & kIdMask);
@@ -114,7 +122,9 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
               if ((m != n) & (rel < (uint32_t)span)) {
                 const uint32_t we = info & kIdMask;
                 const uint32_t both = (info & y) >> 31;
-                if constexpr (MODE == 1)
+                if constexpr (MODE == 0)
+                  atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
+                else if constexpr (MODE == 1)
                   atomicAdd(&lds[rel], we + (both << hb));
                 else
                   atomicAdd((unsigned long long *)&lds64[rel],
@@ -124,6 +134,22 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
             clip, lo, lo + span);
       });
       __syncthreads();
+      if (half) {
+        // Delta holds for every candidate here, whatever c is
+        for (int i = tid; i < zw; i += CAND_NT) {
+          const uint32_t v = lds[i];
+          if (!v) continue;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            const uint64_t h = hh ? (v >> 16) : (v & 0xffffu);
+            const int m = lo + 2 * i + hh;
+            const uint64_t key = (h << 32) | (uint32_t)m;
+            if (h && key > kk[kCandK - 1] && sn + size[m] <= omega) cand_insert(kk, kc, key, 0);
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       for (int i = tid; i < span; i += CAND_NT) {
         uint64_t h, c;
         if (packed) {
@@ -177,18 +203,27 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
     for (int r = 0; r < kCandK; ++r) {
       const uint64_t best = wave_max_u64(e);
       if (best != 0 && e == best) {
-        ck[(int64_t)n * kCandK + r] = best;
-        cc[(int64_t)n * kCandK + r] = ec;
+        selk[r] = best;
+        selc[r] = ec;
         e = 0;
       }
       if (best == 0 && l == 0) {
-        ck[(int64_t)n * kCandK + r] = 0;
-        cc[(int64_t)n * kCandK + r] = 0;
+        selk[r] = 0;
+        selc[r] = 0;
       }
       cnt += best != 0 ? 1 : 0;
     }
-    if (l == 0) ccnt[n] = cnt < keep ? cnt : keep;
+    if (l == 0) selcnt = cnt;
   }
+  __syncthreads();
+  // c(n, m) of the kept candidates (the window's LDS is free now)
+  if (half) inbound_common<CAND_NT>(n, ioff, inc, lds, inbound_slots(din), selk, selc, selcnt);
+  __syncthreads();
+  if (tid < kCandK) {
+    ck[(int64_t)n * kCandK + tid] = selk[tid];
+    cc[(int64_t)n * kCandK + tid] = selc[tid];
+  }
+  if (tid == 0) ccnt[n] = selcnt < keep ? selcnt : keep;
 }
 
 // ---------------------------------------------------------------------------
@@ -545,9 +580,9 @@ int64_t build_candidates(const LevelView &L, const int32_t *total, int32_t omega
     int words = N <= max_words / 2 ? 2 * N : max_words;
     words = (words + 1) & ~1;
     KScope ks(HGP_K_RATE, s);
-    k_rate_cand<<<xcd_grid(N), CAND_NT, (size_t)words * 4, s>>>(N, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total,
-                                                      omega, delta, words, keep, B.ck, B.cc, B.ccnt,
-                                                      units_ptr(HGP_K_RATE));
+    k_rate_cand<<<xcd_grid(N), CAND_NT, (size_t)words * 4, s>>>(N, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size,
+                                                                 L.indeg, total, L.maxin, omega, delta, words, keep,
+                                                                 B.ck, B.cc, B.ccnt, units_ptr(HGP_K_RATE));
     HGP_LAUNCH_CHECK();
   }
   return candidate_sets(L, B, scan_tmp, sort_tmp, s);

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
                                                   const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
                                                   const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
                                                   const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
-                                                  const int32_t *__restrict__ total, int32_t omega, int32_t delta,
+                                                  const int32_t *__restrict__ total, const int32_t *__restrict__ maxin,
+                                                  int32_t omega, int32_t delta,
                                                   const int32_t *__restrict__ row_slot, uint64_t *rows,
                                                   int32_t *__restrict__ pair, int64_t *__restrict__ score,
                                                   uint64_t *__restrict__ tk_key, int32_t *__restrict__ tk_c,
@@ -93,6 +94,11 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
     const int hb = tot ? 32 - __clz(tot) : 0;
     const int cb = din ? 32 - __clz(din) : 0;
     const bool packed = hb + cb <= 32;
+    // hist alone in 16-bit halves when it fits and no candidate can break
+    // Delta (then c is not needed to select; it is counted afterwards for
+    // the listed candidates only)
+    const bool half = !pre && maxin && hb <= 16 && (int64_t)din + (int64_t)(*maxin) <= (int64_t)delta &&
+                      inbound_slots(din) <= words;
     const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
     // each thread keeps the TK+1 largest valid keys of its counters, descending
     uint64_t top[kTopK + 1];
@@ -125,17 +131,18 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
       }
     } else if (sn < omega) {
       const int i0 = ioff[n], i1 = ioff[n + 1];
-      const int R = packed ? words : (words >> 1);
+      const int R = half ? 2 * words : (packed ? words : (words >> 1));
       const int2 rg = neighbour_range<NT>(i0, i1, inc, hoff, hpin, rng_s);
       const uint32_t *clip = ((int64_t)rg.y - rg.x >= R) ? hpin : nullptr;  // several windows
       for (int lo = rg.x; lo <= rg.y; lo += R) {
         const int span = min(R, rg.y + 1 - lo);
-        const int zw = packed ? span : 2 * span;
+        const int zw = half ? (span + 1) >> 1 : (packed ? span : 2 * span);
         for (int i = tid; i < zw; i += NT) lds[i] = 0u;
         __syncthreads();
-        streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
+        // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
+        streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
           constexpr int MODE = decltype(mode)::value;
-          return stream_segments<NT / 64, 4, true, uint32_t>(
+          return stream_segments<NT / 64, kRateU, true, uint32_t>(
               i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
               [&](uint32_t y, uint32_t info) {
                 const int m = (int)(y & kIdMask);
@@ -143,7 +150,9 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
                 if ((m != n) & (rel < (uint32_t)span)) {
                   const uint32_t we = info & kIdMask;
                   const uint32_t both = (info & y) >> 31;
-                  if constexpr (MODE == 1)
+                  if constexpr (MODE == 0)
+                  atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
+                else if constexpr (MODE == 1)
                     atomicAdd(&lds[rel], we + (both << hb));
                   else
                     atomicAdd((unsigned long long *)&lds64[rel],
@@ -153,6 +162,17 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
               clip, lo, lo + span);
         });
         __syncthreads();
+        if (half) {
+          // Delta holds for every candidate here, whatever c is
+          for (int i = tid; i < zw; i += NT) {
+            const uint32_t v = lds[i];
+            if (!v) continue;
+            offer(v & 0xffffu, 0, lo + 2 * i);
+            offer(v >> 16, 0, lo + 2 * i + 1);
+          }
+          __syncthreads();
+          continue;
+        }
         for (int i = tid; i < span; i += NT) {
           uint64_t h, c;
           if (packed) {
@@ -205,6 +225,11 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
       }
     }
     __syncthreads();
+    if (half) {
+      // c(n, m) of the listed candidates (the window's LDS is free now)
+      inbound_common<NT>(n, ioff, inc, lds, inbound_slots(din), found, foundc, nf < kTopK ? nf : kTopK);
+      __syncthreads();
+    }
     if (tid == 0) {
       const int keep = nf < kTopK ? nf : kTopK;
       for (int q = 0; q < kTopK; ++q) {
@@ -224,8 +249,22 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
 // Carry the lists of unmerged level-l nodes to level l+1 and offer the new
 // clusters (one thread per level-l node).  rows[j * n_coarse + m] = hist |
 // c << 32 of new cluster j and node m (0 if not a valid pair).  Nodes whose
-// first `need` entries are not certain are queued in rerate[] (count in
-// *rerate_cnt).
+// first `need` entries are not certain get rflag = 1 (rflag zeroed by the
+// caller), from which the caller builds their list in id order.
+// list[pos[i]] = i for the flagged i, given pos = the exclusive scan of the
+// 0/1 flags and *total their sum; *count = *total.
+__global__ void k_list_from_scan(const int32_t *__restrict__ pos, int32_t n, const int32_t *__restrict__ total,
+                                 int32_t *__restrict__ list, int64_t *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = pos[i], q = i + 1 < n ? pos[i + 1] : *total;
+  if (q > p) list[p] = (int32_t)i;
+  if (i == 0) *count = *total;
+}
+
+// Nodes below a merged bound node searched for a representative.
+constexpr int kBoundScan = 64;
+
 __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match, const int32_t *__restrict__ gamma,
                               const uint64_t *__restrict__ old_key, const int32_t *__restrict__ old_c,
                               const int32_t *__restrict__ old_cnt, const uint64_t *__restrict__ old_kappa,
@@ -233,8 +272,8 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
                               int32_t n_coarse, int32_t need, uint64_t *__restrict__ tk_key,
                               int32_t *__restrict__ tk_c, int32_t *__restrict__ tk_cnt,
                               uint64_t *__restrict__ tk_kappa, int32_t *__restrict__ pair,
-                              int64_t *__restrict__ score, int32_t *__restrict__ rerate,
-                              int64_t *__restrict__ rerate_cnt) {
+                              int64_t *__restrict__ score, int32_t *__restrict__ rflag,
+                              int64_t *__restrict__ why) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= n_fine || match[n] != n) return;
   const int nc = gamma[n];
@@ -246,12 +285,30 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
     ac[q] = 0;
   }
   // key bound of the candidates left off the list, in the new numbering
-  // (an id part of all ones marks a hist-only bound: it stays as it is)
+  // (an id part of all ones marks a hist-only bound: it stays as it is).
+  // The hidden candidates that stay unmerged keep their keys; those with the
+  // bound's hist h have old ids below the bound's node m9.  If m9 stays
+  // unmerged its new id bounds theirs.  If it merged, every unmerged node
+  // below m9 is a representative at most r, the largest representative
+  // below m9, so new ids are at most gamma(r): (h, gamma(r)) still bounds
+  // every hidden key, and (h, 0) does when no representative is below m9.
+  // (Hidden candidates that merged are offered again as new clusters.)
   uint64_t kap = old_kappa[n];
   const uint32_t k9 = (uint32_t)(kap & 0xffffffffull);
   if (kap && k9 != 0xffffffffu) {
     const int m9 = (int)k9;  // a node of the finer level, 0 <= m9 < n_fine
-    kap = (kap & 0xffffffff00000000ull) | (match[m9] == m9 ? (uint64_t)(uint32_t)gamma[m9] : 0xffffffffull);
+    const uint64_t h = kap & 0xffffffff00000000ull;
+    if (match[m9] == m9) {
+      kap = h | (uint64_t)(uint32_t)gamma[m9];
+    } else {
+      if (why) atomicAdd((unsigned long long *)(why + 3), 1ull);
+      // representatives: unmerged nodes and the smaller node of each pair
+      int r = m9 - 1;
+      for (int step = 0; step < kBoundScan && r >= 0 && match[r] < r; ++step) --r;
+      if (r < 0) kap = h;
+      else if (match[r] >= r) kap = h | (uint64_t)(uint32_t)gamma[r];
+      else kap = h | 0xffffffffull;  // none found within the scan: hist-only bound
+    }
   }
   const int c0 = old_cnt[n];
   // surviving old candidates, renamed (already in descending key order);
@@ -326,7 +383,12 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
     if (z == need - 1) kneed = a[z];
   const bool certain = kap == 0 || (cnt >= need && kneed > kap);
   if (!certain) {
-    rerate[atomicAdd((unsigned long long *)rerate_cnt, 1ull)] = nc;
+    rflag[nc] = 1;
+    // diagnostics: why the node is re-rated (hist-only bound, short list,
+    // need-th key not above the bound)
+    if (why)
+      atomicAdd((unsigned long long *)(why + ((kap & 0xffffffffull) == 0xffffffffull ? 0 : cnt < need ? 1 : 2)),
+                1ull);
   } else {
     pair[nc] = cnt ? (int32_t)(a[0] & 0xffffffffull) : -1;
     score[nc] = cnt ? (int64_t)(a[0] >> 32) : 0;
@@ -396,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
     __syncthreads();
     streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
       constexpr int MODE = decltype(mode)::value;
-      return stream_segments<NT / 64, 4, true, uint32_t>(
+      return stream_segments<NT / 64, kRateU, true, uint32_t>(
           a, z, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
           [&](uint32_t y, uint32_t info) {
             const int m = (int)(y & kIdMask);
@@ -462,9 +524,10 @@ void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, i
   KScope ks(8, s);
   topk_attr();
   const int words = topk_words(L.n);
-  const int grid = (int)(grid_nodes < TOPK_GRID ? grid_nodes : TOPK_GRID);
+  const int grid = (int)std::min<int64_t>(TOPK_GRID, xcd_grid((int)std::min<int64_t>(grid_nodes, TOPK_GRID)));
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
-      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, nullptr, nullptr,
+      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, L.maxin, omega, delta, nullptr,
+      nullptr,
       pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr, units_ptr(8));
   HGP_LAUNCH_CHECK();
 }
@@ -489,9 +552,10 @@ uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_
   HGP_LAUNCH_CHECK();
   // validated rows are written in place over the counters
   uint64_t *rows = reinterpret_cast<uint64_t *>(a);
-  const int grid = n_rows < TOPK_GRID ? n_rows : TOPK_GRID;
+  const int grid = std::min(TOPK_GRID, xcd_grid(std::min(n_rows, TOPK_GRID)));
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
-      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, delta, row_slot, rows,
+      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, L.maxin, omega, delta, row_slot,
+      rows,
       pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, rows, units_ptr(8));
   HGP_LAUNCH_CHECK();
   return rows;
@@ -499,13 +563,21 @@ uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_
 
 void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gamma, const TopK &old_tk,
                         int32_t n_new, const int32_t *newc, const uint64_t *rows, int32_t n_coarse, int32_t need,
-                        TopK &tk, int32_t *pair, int64_t *score, int32_t *rerate, int64_t *rerate_cnt,
-                        hipStream_t s) {
-  if (n_fine <= 0) return;
+                        TopK &tk, int32_t *pair, int64_t *score, int32_t *rflag, int32_t *rerate,
+                        int64_t *rerate_cnt, DevBuf &scan_tmp, hipStream_t s, int64_t *why) {
+  fill_i64(rerate_cnt, 1, 0, s);
+  if (n_fine <= 0 || n_coarse <= 0) return;
   KScope ks(8, s);
+  fill_i32(rflag, n_coarse, 0, s);
   k_rate_update<<<div_up(n_fine, 256), 256, 0, s>>>(n_fine, match, gamma, old_tk.key, old_tk.c, old_tk.cnt,
                                                     old_tk.kappa, n_new, newc, rows, n_coarse, need, tk.key, tk.c,
-                                                    tk.cnt, tk.kappa, pair, score, rerate, rerate_cnt);
+                                                    tk.cnt, tk.kappa, pair, score, rflag, why);
+  HGP_LAUNCH_CHECK();
+  // the re-rated nodes in id order: nearby ids share hedges, and the rating
+  // gives each XCD a contiguous part of the list
+  int32_t *total = reinterpret_cast<int32_t *>(rerate_cnt + 1);
+  scan_i32(rflag, rflag, n_coarse, total, scan_tmp, s);
+  k_list_from_scan<<<div_up(n_coarse, 256), 256, 0, s>>>(rflag, n_coarse, total, rerate, rerate_cnt);
   HGP_LAUNCH_CHECK();
 }
 
