@@ -196,6 +196,9 @@ def main():
     ap.add_argument("--plain", action="store_true", help="time the plain method only (no learned proposal)")
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="timed runs of the plain method, the judge of the learned result, on the same input")
+    ap.add_argument("--exact", action="store_true",
+                    help="with --plain: the exact maximum-weight matching of the pairing pseudo-forest "
+                         "instead of the two traversals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only copy this many bytes on the device (profiling)")
     ap.add_argument("--mlp", default=DEFAULT_MLP, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
@@ -240,17 +243,23 @@ def main():
     out = torch.empty(g.n_nodes, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
 
+    match_flags = hgp.FLAG_EXACT_MATCHING if args.exact else 0
+    if args.exact and not args.plain:
+        log("[bench] --exact applies to the plain method: add --plain")
+        sys.exit(2)
+
     def run(mlp, tag, warmup, steps, time_classes=0):
         for i in range(warmup):
             t = time.perf_counter()
-            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, mlp=mlp)
+            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, mlp=mlp, flags=match_flags)
             log(f"[bench] {tag} warmup {i}: {time.perf_counter() - t:.3f} s levels={res['n_levels']} "
                 f"rounds={res['n_rounds']} parts={res['n_parts']} conn={res['connectivity']}")
         results = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(steps):
-            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out, flags=hgp.FLAG_TIME_KERNELS, mlp=mlp,
+            _, res = hgp.partition_device(ctx, dg, w.omega, w.delta, out=out,
+                                          flags=hgp.FLAG_TIME_KERNELS | match_flags, mlp=mlp,
                                           time_classes=time_classes)
             results.append(res)
             log(f"[bench] {tag} step {i}: levels={res['n_levels']} rounds={res['n_rounds']} parts={res['n_parts']} "
@@ -293,7 +302,7 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     value = g.n_pins * args.steps / elapsed
     plain_cmp = None
-    if q is not None:
+    if q is not None and args.plain_steps > 0:
         # the plain method on the same input: the judge of the learned result
         pel, pres = run(None, "plain", 0, args.plain_steps, time_classes=dom_bit)
         plain_cmp = dict(value=g.n_pins * args.plain_steps / pel, ms_per_step=1e3 * pel / args.plain_steps,
@@ -329,7 +338,8 @@ def main():
                             sum_e_sq=g.sum_sq(), omega=w.omega, delta=w.delta, max_refine_rounds=8,
                             levels=results[-1]["n_levels"], rounds=results[-1]["n_rounds"],
                             n_parts=results[-1]["n_parts"], connectivity=results[-1]["connectivity"],
-                            proposal="learned" if q is not None else "plain"),
+                            proposal="learned" if q is not None else "plain",
+                            matching="exact" if args.exact else "two traversals"),
                 roofline=roof)
     if plain_cmp:
         line["learned_vs_plain"] = dict(plain=plain_cmp, learned_connectivity=results[-1]["connectivity"],

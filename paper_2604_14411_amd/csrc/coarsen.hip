@@ -163,108 +163,6 @@ __global__ void k_offsets_from_sorted(const uint32_t *__restrict__ key, int64_t 
   for (int64_t v = prev + 1; v <= cur; ++v) ioff[v] = (int32_t)j;
 }
 
-// |in(n)| and total(n) = sum of w(e) over I(n), one wave per node; four
-// incidences per lane are loaded before their weights are gathered.
-__global__ void k_node_stats(const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
-                             const int32_t *__restrict__ hw, int32_t N, int32_t *__restrict__ indeg,
-                             int32_t *__restrict__ total) {
-  const int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  if (wid >= N) return;
-  const int a = ioff[wid], z = ioff[wid + 1], l = lane_id();
-  int64_t s = 0;
-  int d = 0;
-  for (int c = a; c < z; c += 64 * 4) {
-    uint32_t x[4];
-    int32_t we[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = c + 64 * u + l;
-      x[u] = i < z ? inc[i] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = c + 64 * u + l;
-      we[u] = i < z ? hw[x[u] & kIdMask] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      s += we[u];
-      d += (int)(x[u] >> 31);
-    }
-  }
-  s = wave_sum(s);
-  d = wave_sum(d);
-  if (lane_id() == 0) {
-    total[wid] = (int32_t)s;
-    indeg[wid] = d;
-  }
-}
-
-// |in(n)| and total(n) = sum of w(e) over I(n).  A wave takes 64
-// consecutive nodes: a lane sums its own node's incidences when there are at
-// most kThreadSegMax of them, then the wave sums each larger node together
-// (four incidences per lane loaded before their weights are gathered).
-// Levels of high-degree nodes use k_node_stats (a wave per node).
-__global__ __launch_bounds__(256) void k_node_stats_lanes(const int32_t *__restrict__ ioff,
-                                                    const uint32_t *__restrict__ inc,
-                                                    const int32_t *__restrict__ hw, int32_t N,
-                                                    int32_t *__restrict__ indeg, int32_t *__restrict__ total) {
-  const int64_t v0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6;
-  if (v0 >= N) return;
-  const int l = lane_id();
-  const int64_t v = v0 + l;
-  int a = 0, z = 0;
-  if (v < N) {
-    a = ioff[v];
-    z = ioff[v + 1];
-  }
-  const bool mine = v < N && z - a <= kThreadSegMax;
-  if (mine) {
-    int64_t s = 0;
-    int d = 0;
-    for (int i = a; i < z; ++i) {
-      const uint32_t x = inc[i];
-      s += hw[x & kIdMask];
-      d += (int)(x >> 31);
-    }
-    total[v] = (int32_t)s;
-    indeg[v] = d;
-  }
-  uint64_t rest = __ballot(v < N && !mine);
-  while (rest) {
-    const int i0 = __ffsll((long long)rest) - 1;
-    rest &= rest - 1ull;
-    const int na = __shfl(a, i0, 64), nz = __shfl(z, i0, 64);
-    int64_t s = 0;
-    int d = 0;
-    for (int c = na; c < nz; c += 64 * 4) {
-      uint32_t x[4];
-      int32_t we[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = c + 64 * u + l;
-        x[u] = i < nz ? inc[i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = c + 64 * u + l;
-        we[u] = i < nz ? hw[x[u] & kIdMask] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        s += we[u];
-        d += (int)(x[u] >> 31);
-      }
-    }
-    s = wave_sum(s);
-    d = wave_sum(d);
-    if (l == 0) {
-      total[v0 + i0] = (int32_t)s;
-      indeg[v0 + i0] = d;
-    }
-  }
-}
-
 __global__ void k_feasible(const int32_t *__restrict__ size, const int32_t *__restrict__ indeg, int32_t N,
                            int32_t omega, int32_t delta, int32_t *err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -704,6 +602,39 @@ static int bits_of(int64_t x) {
   return b;
 }
 
+// |in(n)| and total(n) = sum of w(e) over I(n) from the node-sorted
+// incidences (node[i] = node of incidence i): one lane per incidence, a
+// segmented sum over each wave's runs of equal nodes and one atomic add per
+// run, so a coarse cluster with a hundred thousand incidences costs the same
+// per incidence as any node (a wave per node left it on one wave).
+// indeg and total are zeroed by the caller.
+__global__ __launch_bounds__(256) void k_node_stats_seg(const uint32_t *__restrict__ node,
+                                                        const uint32_t *__restrict__ inc,
+                                                        const int32_t *__restrict__ hw, int64_t P,
+                                                        int32_t *__restrict__ indeg, int32_t *__restrict__ total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = lane_id();
+  const bool in = i < P;
+  const uint32_t x = in ? inc[i] : 0u;
+  const int64_t v = in ? (int64_t)node[i] : -1 - (int64_t)l;  // lanes past P: runs of their own
+  int32_t s = in ? hw[x & kIdMask] : 0;
+  int32_t d = (int32_t)(x >> 31);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t s2 = __shfl_up(s, o, 64), d2 = __shfl_up(d, o, 64);
+    const int64_t v2 = __shfl_up(v, o, 64);
+    if (l >= o && v2 == v) {
+      s += s2;
+      d += d2;
+    }
+  }
+  const int64_t vn = __shfl_down(v, 1, 64);
+  if (in && (l == 63 || vn != v)) {
+    atomicAdd(&total[v], s);
+    if (d) atomicAdd(&indeg[v], d);
+  }
+}
+
 void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32_t N, int64_t P, const int32_t *hw,
                      int32_t *ioff, uint32_t *inc, uint32_t *perm, int32_t *indeg, int32_t *total, uint32_t *tkey,
                      uint32_t *tkey2, uint64_t *tval, uint64_t *tval2, DevBuf &sort_tmp, hipStream_t s) {
@@ -720,11 +651,13 @@ void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32
   k_offsets_from_sorted<<<div_up(P + 1, 256), 256, 0, s>>>(tkey, P, N, ioff);
   HGP_LAUNCH_CHECK();
   if (N > 0) {
-    if (P <= (int64_t)kThreadSegMax * N)
-      k_node_stats_lanes<<<div_up(N, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
-    else
-      k_node_stats<<<div_up((int64_t)N * 64, 256), 256, 0, s>>>(ioff, inc, hw, N, indeg, total);
-    HGP_LAUNCH_CHECK();
+    fill_i32(indeg, N, 0, s);
+    fill_i32(total, N, 0, s);
+    if (P > 0) {
+      // tkey holds the sorted node of every incidence
+      k_node_stats_seg<<<div_up(P, 256), 256, 0, s>>>(tkey, inc, hw, P, indeg, total);
+      HGP_LAUNCH_CHECK();
+    }
   }
 }
 
@@ -848,17 +781,20 @@ void launch_contract(const int32_t *hoff, const uint32_t *hpin, int32_t E, const
                      int32_t *list_buf, int32_t *err, hipStream_t s) {
   if (E <= 0) {
     fill_i32(new_hoff, 1, 0, s);
+    fill_i32(list_buf + 1, 1, 0, s);  // no long hedges (list_buf[E + 1])
     return;
   }
   KScope ks(4, s);
   launch_contract_split(hoff, hpin, E, map, tmp_pins, cnt, list_buf, s);
-  if (big.n > 0) {
+  int32_t *bl = list_buf + E + 1;
+  const int grid = std::min(std::min(big.n, big.bound), 2048);
+  if (grid > 0) {
     // this level's hedges above kWaveSegMax (the level-0 list is a superset)
-    int32_t *bl = list_buf + E + 1;
     launch_mid_hedges(hoff, E, bl + 1, bl, s, kWaveSegMax, 0x7fffffff);
-    k_contract<<<std::min<int>(big.n, 2048), SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, bl + 1, bl, 0,
-                                                             big.huge_k, big.huge_i, err);
+    k_contract<<<grid, SEG_NT, 0, s>>>(hoff, hpin, map, tmp_pins, cnt, bl + 1, bl, 0, big.huge_k, big.huge_i, err);
     HGP_LAUNCH_CHECK();
+  } else {
+    fill_i32(bl, 1, 0, s);  // the count the caller may read back
   }
   scan_i32(cnt, new_hoff, E, new_hoff + E, scan_tmp, s);
   launch_pack_split(hoff, new_hoff, E, tmp_pins, new_hpin, list_buf, s);

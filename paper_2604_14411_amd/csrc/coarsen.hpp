@@ -34,6 +34,10 @@ struct BigHedges {
   const int32_t *list = nullptr;
   int32_t n = 0;
   int32_t max_len = 0x7fffffff;  // bound of the hedge lengths (coarse hedges only shrink)
+  // bound of this level's count of hedges above kWaveSegMax (n at level 0,
+  // the finer level's count below it: coarse hedges only shrink); sizes the
+  // grids of the long-hedge kernels, which skip the level when it is 0
+  int32_t bound = 0x7fffffff;
   // Global scratch of the workgroup kernels for hedges above kSegCap pins
   // (null when the input has none), oversized at each hedge's pin offset b:
   // huge_k[4b .. 4b + 4|e|) 64-bit words, huge_i[2b .. 2b + 2|e|) 32-bit words.

@@ -345,13 +345,23 @@ template <int NT>
 __device__ int2 neighbour_range(int i0, int i1, const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
                                 const uint32_t *__restrict__ hpin, int2 *red) {
   int lo = 0x7fffffff, hi = -1;
-  for (int i = i0 + (int)threadIdx.x; i < i1; i += NT) {
-    const int e = (int)(inc[i] & kIdMask);
-    const int b = hoff[e], en = hoff[e + 1];
-    if (en > b) {
-      lo = min(lo, (int)(hpin[b] & kIdMask));
-      hi = max(hi, (int)(hpin[en - 1] & kIdMask));
+  // four incidences per thread in flight through the three dependent loads
+  // (a coarse cluster has tens of thousands of incidences)
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += 4 * NT) {
+    int e[4], b[4], en[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e[u] = i + u * NT < i1 ? (int)(inc[i + u * NT] & kIdMask) : -1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      b[u] = e[u] >= 0 ? hoff[e[u]] : 0;
+      en[u] = e[u] >= 0 ? hoff[e[u] + 1] : 0;
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (en[u] > b[u]) {
+        lo = min(lo, (int)(hpin[b[u]] & kIdMask));
+        hi = max(hi, (int)(hpin[en[u] - 1] & kIdMask));
+      }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {

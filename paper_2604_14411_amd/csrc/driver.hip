@@ -95,6 +95,7 @@ struct Workspace {
   DevBuf ones_e, ones_n;
   std::vector<DevBuf> lv_size, lv_gamma, lv_Gamma;
   std::vector<int32_t> lv_n;
+  std::vector<int32_t> lv_bigb;  // per level: bound of its long-hedge count (BigHedges::bound)
   KTimer timer;
   DevBuf units_dev;
   HostBox hbox;  // pinned words for read-backs
@@ -361,7 +362,7 @@ static void set_mid(Workspace &W, LevelView &V, hipStream_t s) {
   launch_mid_hedges(V.hoff, V.E, buf + 1, buf, s);
   V.mid.list = buf + 1;
   V.mid.count = buf;
-  if (V.big.n > 0) {
+  if (V.big.n > 0 && V.big.bound > 0) {
     // the level's own long hedges (the level-0 list is only a superset)
     launch_mid_hedges(V.hoff, V.E, bbuf + 1, bbuf, s, kWaveSegMax, 0x7fffffff);
     V.mid.big_list = bbuf + 1;
@@ -729,7 +730,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
   if (N > 0)
     HGP_HIP(hipMemcpyAsync(size0, I.nw, sizeof(int32_t) * (size_t)N, hipMemcpyDeviceToDevice, s));
-  const BigHedges big = I.big;  // coarse hedges only shrink: valid for every level
+  BigHedges big = I.big;  // coarse hedges only shrink: valid for every level
+  big.bound = big.n;
+  W.lv_bigb.assign(1, big.bound);
   LevelView L = make_view(W, N, E, hoff0, hpin0, P, size0, W.lv_size[0].bytes / 4, hw, big, s);
   launch_feasible(size0, L.indeg, N, omega, delta, W.err.as<int32_t>(), s);
   check_err(W, s);
@@ -899,10 +902,21 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     DevBuf &hpin_buf = ping ? W.hpinB : W.hpinA;
     int32_t *nh = need<int32_t>(hoff_buf, (int64_t)E + 1);
     uint32_t *npin = need<uint32_t>(hpin_buf, cur_P);
+    int32_t *longlist = need<int32_t>(W.longlist, 2 * ((int64_t)E + 1));
     launch_contract(cur_hoff, cur_hpin, E, gam, W.tmp_pins.as<uint32_t>(), W.cnt.as<int32_t>(), nh, npin, big,
-                    W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
+                    W.scan_tmp, longlist, W.err.as<int32_t>(), s);
     add_units(HGP_K_CONTRACT, cur_P);
-    cur_P = read_i32(W, nh + E, s);
+    {
+      // the contracted pin count, and this level's count of long hedges:
+      // a bound for the next level's
+      int32_t *h = reinterpret_cast<int32_t *>(W.hbox.get());
+      HGP_HIP(hipMemcpyAsync(h, nh + E, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGP_HIP(hipMemcpyAsync(h + 1, longlist + E + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HGP_HIP(hipStreamSynchronize(s));
+      cur_P = h[0];
+      big.bound = std::min(big.bound, h[1]);
+    }
+    W.lv_bigb.push_back(big.bound);
     cur_hoff = nh;
     cur_hpin = npin;
     ping ^= 1;
@@ -972,6 +986,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       const int32_t *h = nullptr;
       const uint32_t *p = nullptr;
       const CachedLevel *c = lv > 0 ? cached_level(W, lv) : nullptr;
+      BigHedges vbig = I.big;  // level 0's long hedges, bounded by this level's count
+      vbig.bound = W.lv_bigb[(size_t)lv];
       if (log_on())
         fprintf(stderr, "[hgp] refine level %d view %s (%zu levels kept, %.2f GB)\n", lv, c ? "kept" : "rebuilt",
                 W.ring.kept.size(), W.ring.kept_bytes() / 1e9);
@@ -988,7 +1004,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         V.total = c->total;
         V.size = W.lv_size[lv].as<int32_t>();
         V.hw = hw;
-        V.big = big;
+        V.big = vbig;
         Pl = c->P;
         if (c->n != n) throw Error(HGP_EINTERNAL, "cached level size");
       } else if (lv == 0) {
@@ -999,13 +1015,14 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         int32_t *rh = need<int32_t>(W.hoffR, (int64_t)E + 1);
         uint32_t *rp = need<uint32_t>(W.hpinR, P);
         launch_contract(hoff0, hpin0, E, W.lv_Gamma[lv - 1].as<int32_t>(), W.tmp_pins.as<uint32_t>(),
-                        W.cnt.as<int32_t>(), rh, rp, big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)), W.err.as<int32_t>(), s);
+                        W.cnt.as<int32_t>(), rh, rp, I.big, W.scan_tmp, need<int32_t>(W.longlist, 2 * ((int64_t)E + 1)),
+                        W.err.as<int32_t>(), s);
         add_units(HGP_K_CONTRACT, P);
         Pl = read_i32(W, rh + E, s);
         h = rh;
         p = rp;
       }
-      if (!c) V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, big, s);
+      if (!c) V = make_view(W, n, E, h, p, Pl, W.lv_size[lv].as<int32_t>(), W.lv_size[lv].bytes / 4, hw, vbig, s);
     }
     set_mid(W, V, s);
     bool last_applied = false;

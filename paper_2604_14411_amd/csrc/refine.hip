@@ -108,10 +108,12 @@ __global__ void k_part_size(const int32_t *__restrict__ rho, const int32_t *__re
 }
 
 // As k_part_size for n_parts <= PS_LDS_PARTS: each workgroup sums its nodes in
-// an LDS histogram first, so a part gets one global atomic per workgroup
-// (with few parts the per-node atomics all hit the same few addresses; with
-// many, the flush of every workgroup's histogram would cost more than it saves).
-constexpr int PS_LDS_PARTS = 1024;
+// an LDS histogram first and flushes its non-zero bins, so a part gets one
+// global atomic per workgroup (at coarse levels a part can hold thousands of
+// nodes, whose per-node atomics serialise on one address; with many more
+// parts, clearing and scanning every workgroup's histogram would cost more
+// than it saves).
+constexpr int PS_LDS_PARTS = 8192;
 constexpr int PS_GRID = 512;
 __global__ __launch_bounds__(256) void k_part_size_lds(const int32_t *__restrict__ rho,
                                                        const int32_t *__restrict__ size, int32_t N, int32_t n_parts,
@@ -137,9 +139,9 @@ void launch_part_table(const LevelView &L, const int32_t *rho, int32_t n_parts, 
   launch_part_table_wave(L.hoff, L.hpin, L.E, L.mid.list, L.mid.count, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb,
                          n_parts, L.big.max_len, *B.partial, s);
   if (L.E > 0) {
-    if (L.big.n > 0) {
+    const int grid = std::min(std::min(L.big.n, L.big.bound), 2048);
+    if (grid > 0) {
       // the level's own long hedges when listed (fewer than level 0's at coarse levels)
-      const int grid = std::min<int>(L.big.n, 2048);
       if (L.mid.big_list)
         k_part_table<<<grid, PT_NT, 0, s>>>(L.hoff, L.hpin, rho, B.pt, B.ptc, B.lam, B.solo, B.pinb, err,
                                             L.mid.big_list, L.mid.big_count, 0, L.big.huge_k, L.big.huge_i);
@@ -206,10 +208,24 @@ __global__ __launch_bounds__(NT) void k_propose(const int32_t *__restrict__ list
       if (tid == 0) hlist[atomicAdd(hcnt, 1ull)] = n;
       continue;
     }
-    // saving(n): hedges where n is the only pin of p_s
+    // saving(n): hedges where n is the only pin of p_s; eight incidences
+    // per thread in flight (a coarse cluster has tens of thousands)
     int64_t sav = 0;
-    for (int i = i0 + tid; i < i1; i += NT)
-      if (solo[perm[i]]) sav += hw[inc[i] & kIdMask];
+    for (int i = i0 + tid; i < i1; i += 8 * NT) {
+      uint32_t pp[8], x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = i + u * NT;
+        pp[u] = j < i1 ? perm[j] : 0u;
+        x[u] = j < i1 ? inc[j] : 0u;
+      }
+      uint8_t so[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) so[u] = i + u * NT < i1 ? solo[pp[u]] : (uint8_t)0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (so[u]) sav += hw[x[u] & kIdMask];
+    }
     sav = wave_sum(sav);
     if (l == 0) red[w] = sav;
     __syncthreads();

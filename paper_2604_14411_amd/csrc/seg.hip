@@ -145,6 +145,11 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
   __shared__ uint32_t sbuf[4][64 * MAXKPL];
   extern __shared__ int32_t hist[];
   const bool local = partial != nullptr;
+  const int count = list ? *list_n : E;
+  // workgroups past the list (the grid is sized for every hedge; a coarse
+  // level lists few) neither clear nor flush a histogram row: k_pinb_reduce
+  // reads the rows of the first ceil(count / 4) workgroups only
+  if ((int64_t)blockIdx.x * 4 >= count) return;
   if (local) {
     for (int i = threadIdx.x; i < n_parts; i += 256) hist[i] = 0;
     __syncthreads();
@@ -152,7 +157,6 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
   int32_t *cnt = local ? hist : pinb;
   const int w = threadIdx.x >> 6;
   uint32_t *s = sbuf[w];
-  const int count = list ? *list_n : E;
   for (int t = (int)(blockIdx.x * 4 + w); t < count; t += (int)(gridDim.x * 4)) {
     const int e = list ? list[t] : t;
     const int b = hoff[e], len = hoff[e + 1] - b;
@@ -171,13 +175,18 @@ __global__ __launch_bounds__(256) void k_part_table_wave(const int32_t *__restri
 }
 static_assert(kWaveSegMax == 1024, "k_part_table_wave<16> covers the wave-path hedge lengths");
 
-// pinb[p] = sum over the rows of partial.  A workgroup covers 64 parts (one
-// per lane); its PR_W waves sum interleaved rows, 8 loads in flight each.
+// pinb[p] = sum over the rows of partial written by the wave kernel: those of
+// its first ceil(count / 4) workgroups (count = *list_n, or E without a
+// list), at most `rows`.  A workgroup covers 64 parts (one per lane); its
+// PR_W waves sum interleaved rows, 8 loads in flight each.
 constexpr int PR_W = 16;
 
-__global__ __launch_bounds__(64 * PR_W) void k_pinb_reduce(const int32_t *__restrict__ partial, int rows,
+__global__ __launch_bounds__(64 * PR_W) void k_pinb_reduce(const int32_t *__restrict__ partial, int grid_rows,
+                                                           const int32_t *__restrict__ list_n, int32_t E,
                                                            int32_t n_parts, int32_t *__restrict__ pinb) {
   __shared__ int32_t red[PR_W][64];
+  const int count = list_n ? *list_n : E;
+  const int rows = (int)min((int64_t)grid_rows, ((int64_t)count + 3) / 4);
   const int l = lane_id(), w = (int)(threadIdx.x >> 6);
   const int p = (int)(blockIdx.x * 64) + l;
   int32_t t = 0;
@@ -236,7 +245,8 @@ void launch_part_table_wave(const int32_t *hoff, const uint32_t *hpin, int32_t E
   else
     launch_ptw<16>(grid, lds, hoff, hpin, E, list, list_n, rho, pt, ptc, lam, solo, pinb, n_parts, rows, s);
   if (local) {
-    k_pinb_reduce<<<div_up(n_parts, 64), 64 * PR_W, 0, s>>>(rows, grid, n_parts, pinb);
+    k_pinb_reduce<<<div_up(n_parts, 64), 64 * PR_W, 0, s>>>(rows, grid, list ? list_n : nullptr, E, n_parts,
+                                                           pinb);
     HGP_LAUNCH_CHECK();
   }
 }
