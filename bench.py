@@ -219,6 +219,17 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] copied {args.copy_probe} bytes 3 times")
+        # achieved copy bandwidth (read + write), HIP events on the copies' stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps(dict(probe="device copy", bytes=args.copy_probe, ms_per_copy=ms,
+                              read_write_gbs=2 * args.copy_probe / ms / 1e6, peak_gbs=HBM_PEAK_GBS)))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path",

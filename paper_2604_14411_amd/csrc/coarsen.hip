@@ -495,6 +495,81 @@ __global__ void k_gamma(const int32_t *__restrict__ match, int32_t N, int32_t *_
   if (m < n) gamma[n] = gamma[m];
 }
 
+// The whole matching of a small level in one workgroup (the coarse levels
+// that merge a few pairs each): the phases of k_best, k_up, k_match, the
+// scan of the representative flags and k_gamma, separated by barriers
+// instead of launches, with the same results.  *n_next = the number of
+// clusters.
+constexpr int MATCH_SMALL_NT = 1024;
+constexpr int kMatchSmallMax = 8192;
+
+__global__ __launch_bounds__(MATCH_SMALL_NT) void k_match_small(const int32_t *__restrict__ pair,
+                                                                const int64_t *__restrict__ score, int32_t N,
+                                                                unsigned long long *best, uint8_t *up, int32_t *match,
+                                                                int32_t *rep, int32_t *gamma, int32_t *n_next,
+                                                                int32_t *err) {
+  __shared__ int32_t tmp[MATCH_SMALL_NT / 64 + 1];
+  const int tid = threadIdx.x;
+  for (int n = tid; n < N; n += MATCH_SMALL_NT) best[n] = 0ull;
+  __syncthreads();
+  for (int n = tid; n < N; n += MATCH_SMALL_NT) {
+    const int32_t p = pair[n];
+    if (p >= 0) atomicMax(&best[p], ((unsigned long long)score[n] << 32) | (unsigned long long)n);
+  }
+  __syncthreads();
+  for (int n = tid; n < N; n += MATCH_SMALL_NT) {
+    int u = n;
+    uint32_t parity = 0;
+    int r = -1;
+    for (int64_t step = 0; step <= N; ++step) {
+      const int p = pair[u];
+      if (p < 0) {
+        r = 0;
+        break;
+      }
+      if (pair[p] == u) {
+        r = 1;
+        break;
+      }
+      if ((int)(best[p] & 0xffffffffull) != u) {
+        r = 0;
+        break;
+      }
+      parity ^= 1u;
+      u = p;
+    }
+    if (r < 0) {
+      atomicOr(err, kErrInternal);
+      r = 0;
+    }
+    up[n] = (uint8_t)((uint32_t)r ^ parity);
+  }
+  __syncthreads();
+  for (int n = tid; n < N; n += MATCH_SMALL_NT) {
+    int m = n;
+    if (up[n]) {
+      m = pair[n];
+    } else {
+      const unsigned long long b = best[n];
+      if (b) {
+        const int c = (int)(b & 0xffffffffull);
+        if (up[c]) m = c;
+      }
+    }
+    match[n] = m;
+    rep[n] = (m >= n) ? 1 : 0;
+    gamma[n] = rep[n];
+  }
+  __syncthreads();
+  const int32_t total = block_exclusive_scan<int32_t, MATCH_SMALL_NT>(gamma, N, tmp);
+  // representatives hold their rank now; the others take their partner's
+  for (int n = tid; n < N; n += MATCH_SMALL_NT) {
+    const int m = match[n];
+    if (m < n) gamma[n] = gamma[m];
+  }
+  if (tid == 0) *n_next = total;
+}
+
 // ---------------------------------------------------------------------------
 // contraction (Sec. III-B)
 // ---------------------------------------------------------------------------
@@ -730,6 +805,11 @@ void launch_match(const int32_t *pair, const int64_t *score, int32_t N, unsigned
   if (N <= 0) return;
   KScope ks(7, s);
   add_units(7, N);
+  if (N <= kMatchSmallMax) {
+    k_match_small<<<1, MATCH_SMALL_NT, 0, s>>>(pair, score, N, best, up, match, rep, gamma, n_next_dev, err);
+    HGP_LAUNCH_CHECK();
+    return;
+  }
   fill_i64(reinterpret_cast<int64_t *>(best), N, 0, s);
   const int g = div_up(N, 256);
   k_best<<<g, 256, 0, s>>>(pair, score, N, best);
