@@ -165,6 +165,22 @@ __global__ __launch_bounds__(SC_NT) void k_tile_scan(const T *in, T *out, int64_
   if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
 }
 
+// Exclusive scan of up to SC_ONE_MAX elements by one workgroup (one launch
+// where the tiled scan takes three): in is copied to out, then scanned in
+// place, each thread owning a contiguous chunk.
+constexpr int SC_ONE_NT = 1024;
+constexpr int64_t SC_ONE_MAX = 16384;
+
+template <class T>
+__global__ __launch_bounds__(SC_ONE_NT) void k_scan_one(const T *in, T *out, int n, T *total) {
+  __shared__ T tmp[SC_ONE_NT / 64 + 1];
+  if (in != out)
+    for (int i = threadIdx.x; i < n; i += SC_ONE_NT) out[i] = in[i];
+  __syncthreads();
+  const T tot = block_exclusive_scan<T, SC_ONE_NT>(out, n, tmp);
+  if (total && threadIdx.x == 0) *total = tot;
+}
+
 template <class T>
 static void scan_impl(const T *in, T *out, int64_t n, T *total, T *tmp, hipStream_t s) {
   if (n <= 0) {
@@ -175,6 +191,11 @@ static void scan_impl(const T *in, T *out, int64_t n, T *total, T *tmp, hipStrea
     return;
   }
   const int64_t nb = (n + SC_TILE - 1) / SC_TILE;
+  if (nb > 1 && n <= SC_ONE_MAX) {
+    k_scan_one<T><<<1, SC_ONE_NT, 0, s>>>(in, out, (int)n, total);
+    HGP_LAUNCH_CHECK();
+    return;
+  }
   if (nb == 1) {
     k_tile_scan<T><<<1, SC_NT, 0, s>>>(in, out, n, nullptr, total);
     HGP_LAUNCH_CHECK();
