@@ -938,7 +938,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       if (log_on()) fill_i64(dcnt + 4, 4, 0, s);
       // re-rated nodes: flags in nflag (free after the new clusters' list),
       // count in dcnt[1] (dcnt[2] holds the scan total)
-      launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, learned ? opt.mlp->k : 1, tk_nxt, pair,
+      launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, L.size, L.indeg, omega, delta,
+                         learned ? opt.mlp->k : 1, tk_nxt, pair,
                          score, nflag, rerate, dcnt + 1, W.scan_tmp, s, log_on() ? dcnt + 4 : nullptr);
       launch_rate_topk(L, L.total, omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
       have_pairs = !learned;

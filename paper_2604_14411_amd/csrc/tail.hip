@@ -269,7 +269,9 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
                               const uint64_t *__restrict__ old_key, const int32_t *__restrict__ old_c,
                               const int32_t *__restrict__ old_cnt, const uint64_t *__restrict__ old_kappa,
                               int32_t n_new, const int32_t *__restrict__ newc, const uint64_t *__restrict__ rows,
-                              int32_t n_coarse, int32_t need, uint64_t *__restrict__ tk_key,
+                              int32_t n_coarse, const int32_t *__restrict__ csize,
+                              const int32_t *__restrict__ cindeg, int32_t omega, int32_t delta, int32_t need,
+                              uint64_t *__restrict__ tk_key,
                               int32_t *__restrict__ tk_c, int32_t *__restrict__ tk_cnt,
                               uint64_t *__restrict__ tk_kappa, int32_t *__restrict__ pair,
                               int64_t *__restrict__ score, int32_t *__restrict__ rflag,
@@ -344,8 +346,11 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
       ++k;
     }
   }
-  // offers from the new clusters (keys above kappa only), in cluster order,
-  // four rows loaded at a time
+  // offers from the new clusters (valid pairs with keys above kappa only), in
+  // cluster order, four rows loaded at a time; the rows hold the raw
+  // counters hist | c << 32 of every node against each new cluster
+  const int64_t sn = csize[nc];
+  const int64_t dn = cindeg[nc];
   for (int j0 = 0; j0 < n_new; j0 += 4) {
     uint64_t v[4];
     uint32_t id[4];
@@ -362,6 +367,7 @@ __global__ void k_rate_update(int32_t n_fine, const int32_t *__restrict__ match,
       uint64_t x = cand_key(h, id[u]);
       if (x <= kap) continue;
       int32_t xc = (int32_t)(v[u] >> 32);
+      if (sn + csize[id[u]] > omega || dn + cindeg[id[u]] - xc > delta) continue;  // not a valid pair
       list_insert<kTopK>(a, ac, x, xc);
       if (x > kap) kap = x;  // evicted (0 if the list had room)
     }
@@ -550,19 +556,22 @@ uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_
       L.n, list, n_rows, slices, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, omega, words, a,
       units_ptr(8));
   HGP_LAUNCH_CHECK();
-  // validated rows are written in place over the counters
+  // the rows stay raw counters: k_rate_update tests each offer's validity
+  // itself, so they are not written back validated (a dense row set is
+  // gigabytes at the early levels)
   uint64_t *rows = reinterpret_cast<uint64_t *>(a);
   const int grid = std::min(TOPK_GRID, xcd_grid(std::min(n_rows, TOPK_GRID)));
   k_rate_topk<TOPK_NT><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
-      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, L.maxin, omega, delta, row_slot,
-      rows,
+      L.n, list, count, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg, total, L.maxin, omega, delta, nullptr,
+      nullptr,
       pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, rows, units_ptr(8));
   HGP_LAUNCH_CHECK();
   return rows;
 }
 
 void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gamma, const TopK &old_tk,
-                        int32_t n_new, const int32_t *newc, const uint64_t *rows, int32_t n_coarse, int32_t need,
+                        int32_t n_new, const int32_t *newc, const uint64_t *rows, int32_t n_coarse,
+                        const int32_t *csize, const int32_t *cindeg, int32_t omega, int32_t delta, int32_t need,
                         TopK &tk, int32_t *pair, int64_t *score, int32_t *rflag, int32_t *rerate,
                         int64_t *rerate_cnt, DevBuf &scan_tmp, hipStream_t s, int64_t *why) {
   fill_i64(rerate_cnt, 1, 0, s);
@@ -570,7 +579,8 @@ void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gam
   KScope ks(8, s);
   fill_i32(rflag, n_coarse, 0, s);
   k_rate_update<<<div_up(n_fine, 256), 256, 0, s>>>(n_fine, match, gamma, old_tk.key, old_tk.c, old_tk.cnt,
-                                                    old_tk.kappa, n_new, newc, rows, n_coarse, need, tk.key, tk.c,
+                                                    old_tk.kappa, n_new, newc, rows, n_coarse, csize, cindeg, omega,
+                                                    delta, need, tk.key, tk.c,
                                                     tk.cnt, tk.kappa, pair, score, rflag, why);
   HGP_LAUNCH_CHECK();
   // the re-rated nodes in id order: nearby ids share hedges, and the rating

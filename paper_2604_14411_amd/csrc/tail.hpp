@@ -31,7 +31,8 @@ uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_
 // Carries the lists to the next level; nodes whose first `need` entries are
 // not certain go to rerate (need 1: the plain head; k: the learned proposal).
 void launch_rate_update(int32_t n_fine, const int32_t *match, const int32_t *gamma, const TopK &old_tk,
-                        int32_t n_new, const int32_t *newc, const uint64_t *rows, int32_t n_coarse, int32_t need,
+                        int32_t n_new, const int32_t *newc, const uint64_t *rows, int32_t n_coarse,
+                        const int32_t *csize, const int32_t *cindeg, int32_t omega, int32_t delta, int32_t need,
                         TopK &tk, int32_t *pair, int64_t *score, int32_t *rflag, int32_t *rerate,
                         int64_t *rerate_cnt, DevBuf &scan_tmp, hipStream_t s, int64_t *why = nullptr);
 void launch_new_clusters(const int32_t *match, const int32_t *gamma, int32_t n_fine, int32_t n_coarse,
