@@ -799,9 +799,12 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       if (learned) {
         path = "learned";
         CandBufs CB = cand_bufs(W, n, pair, score);
-        if (lists_fresh || (incremental && tail)) {
+        if (lists_fresh || incremental) {
           // candidate lists from the top-K lists (rated in full here unless
-          // carried from the previous level)
+          // carried from the previous level); every level keeps lists so
+          // that the next one can be rated incrementally (on the layered
+          // networks the top-K rating is also faster than the candidate
+          // rating of k_rate_cand: conv302k 3.65 to 3.27 s per partition)
           if (!lists_fresh) {
             path = "learned, topk";
             launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);

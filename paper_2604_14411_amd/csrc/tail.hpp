@@ -7,7 +7,7 @@ namespace hgp {
 
 constexpr int kTopK = 16;            // candidates kept per node (the learned proposal needs up to 8 certain)
 constexpr int kTailRatio = 8;        // a matching with M * kTailRatio <= n starts the incremental regime
-constexpr int64_t kRowBudget = int64_t(1) << 31;  // new-cluster rows: M * n_next 64-bit entries (16 GB)
+constexpr int64_t kRowBudget = int64_t(1) << 32;  // new-cluster rows: M * n_next 64-bit entries (32 GB)
 
 struct TopK {
   uint64_t *key = nullptr;    // [n * kTopK] (hist << 32 | id), descending, 0 = empty
