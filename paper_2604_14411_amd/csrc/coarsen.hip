@@ -679,19 +679,25 @@ static int bits_of(int64_t x) {
 
 // |in(n)| and total(n) = sum of w(e) over I(n) from the node-sorted
 // incidences (node[i] = node of incidence i): one lane per incidence, a
-// segmented sum over each wave's runs of equal nodes and one atomic add per
-// run, so a coarse cluster with a hundred thousand incidences costs the same
-// per incidence as any node (a wave per node left it on one wave).
+// segmented sum over each workgroup's runs of equal nodes (within waves by
+// shuffles, across the workgroup's waves through LDS) and one atomic add per
+// run and workgroup, so a coarse cluster with a hundred thousand incidences
+// costs about a hundred atomics (a wave per node left it on one wave, a
+// wave-level sum still made it take one atomic per wave on one address).
 // indeg and total are zeroed by the caller.
-__global__ __launch_bounds__(256) void k_node_stats_seg(const uint32_t *__restrict__ node,
-                                                        const uint32_t *__restrict__ inc,
-                                                        const int32_t *__restrict__ hw, int64_t P,
-                                                        int32_t *__restrict__ indeg, int32_t *__restrict__ total) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = lane_id();
+constexpr int NS_NT = 1024;
+__global__ __launch_bounds__(NS_NT) void k_node_stats_seg(const uint32_t *__restrict__ node,
+                                                          const uint32_t *__restrict__ inc,
+                                                          const int32_t *__restrict__ hw, int64_t P,
+                                                          int32_t *__restrict__ indeg, int32_t *__restrict__ total) {
+  constexpr int NW = NS_NT / 64;
+  __shared__ int64_t head_v[NW], tail_v[NW];
+  __shared__ int32_t tail_s[NW], tail_d[NW], carry_s[NW], carry_d[NW];
+  const int64_t i = (int64_t)blockIdx.x * NS_NT + threadIdx.x;
+  const int l = lane_id(), w = (int)(threadIdx.x >> 6);
   const bool in = i < P;
   const uint32_t x = in ? inc[i] : 0u;
-  const int64_t v = in ? (int64_t)node[i] : -1 - (int64_t)l;  // lanes past P: runs of their own
+  const int64_t v = in ? (int64_t)node[i] : -1 - (int64_t)threadIdx.x;  // past P: runs of their own
   int32_t s = in ? hw[x & kIdMask] : 0;
   int32_t d = (int32_t)(x >> 31);
 #pragma unroll
@@ -703,8 +709,44 @@ __global__ __launch_bounds__(256) void k_node_stats_seg(const uint32_t *__restri
       d += d2;
     }
   }
-  const int64_t vn = __shfl_down(v, 1, 64);
-  if (in && (l == 63 || vn != v)) {
+  if (l == 0) head_v[w] = v;
+  if (l == 63) {
+    tail_v[w] = v;
+    tail_s[w] = s;
+    tail_d[w] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // carry[q]: the part of wave q's first run held by earlier waves (the
+    // nodes are sorted, so a run continues across waves only through whole
+    // waves of one node)
+    int32_t cs = 0, cd = 0;
+    carry_s[0] = 0;
+    carry_d[0] = 0;
+    for (int q = 1; q < NW; ++q) {
+      if (tail_v[q - 1] == head_v[q]) {
+        const bool whole = head_v[q - 1] == tail_v[q - 1];
+        cs = tail_s[q - 1] + (whole ? cs : 0);
+        cd = tail_d[q - 1] + (whole ? cd : 0);
+      } else {
+        cs = 0;
+        cd = 0;
+      }
+      carry_s[q] = cs;
+      carry_d[q] = cd;
+    }
+  }
+  __syncthreads();
+  if (v == head_v[w]) {
+    s += carry_s[w];
+    d += carry_d[w];
+  }
+  // the last lane of each run within the workgroup adds the run's sums (the
+  // shuffle runs on every lane: a lane masked off would leave its
+  // neighbour's read undefined)
+  const int64_t dn = __shfl_down(v, 1, 64);
+  const int64_t vn = l < 63 ? dn : (w + 1 < NW ? head_v[w + 1] : -1 - (int64_t)NS_NT);
+  if (in && vn != v) {
     atomicAdd(&total[v], s);
     if (d) atomicAdd(&indeg[v], d);
   }
@@ -730,7 +772,7 @@ void build_incidence(const int32_t *hoff, const uint32_t *hpin, int32_t E, int32
     fill_i32(total, N, 0, s);
     if (P > 0) {
       // tkey holds the sorted node of every incidence
-      k_node_stats_seg<<<div_up(P, 256), 256, 0, s>>>(tkey, inc, hw, P, indeg, total);
+      k_node_stats_seg<<<div_up(P, NS_NT), NS_NT, 0, s>>>(tkey, inc, hw, P, indeg, total);
       HGP_LAUNCH_CHECK();
     }
   }
