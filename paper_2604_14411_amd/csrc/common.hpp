@@ -227,12 +227,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // each segment is first narrowed by binary search to the entries whose id
 // lies in [clip_lo, clip_hi): a rating over several LDS windows then streams
 // each pin once instead of once per window.
+// With PASS_OK, apply(v, info, ok) is called for every lane of every round,
+// ok false for the lanes past the end (their v and info repeat the last
+// entry), so that a caller can fold the mask into its update instead of
+// branching around it.
 // Loads in flight per lane in the ratings' pin streams: each round of U
 // loads waits out one cache latency before its LDS updates, so the pin rate
 // of a latency-bound stream grows with U.
 constexpr int kRateU = 16;
 
-template <int NW, int U, bool LEN_FROM_END, class V, class Load, class Apply>
+template <int NW, int U, bool LEN_FROM_END, class V, bool PASS_OK = false, class Load, class Apply>
 __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_t *__restrict__ inc,
                                                    const int32_t *__restrict__ soff, const int32_t *__restrict__ slen,
                                                    const int32_t *__restrict__ hw, int32_t *tbl, Load load,
@@ -307,8 +311,12 @@ __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_
 #pragma unroll
       for (int u = 0; u < U; ++u) vv[u] = load(jj[u]);
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (ok[u]) apply(vv[u], ii[u]);
+      for (int u = 0; u < U; ++u) {
+        if constexpr (PASS_OK)
+          apply(vv[u], ii[u], ok[u]);
+        else if (ok[u])
+          apply(vv[u], ii[u]);
+      }
     }
     wave_lds_sync();
   }

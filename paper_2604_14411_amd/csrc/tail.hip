@@ -56,6 +56,40 @@ __device__ __forceinline__ void list_insert(uint64_t (&k)[L], int32_t (&kc)[L], 
   }
 }
 
+// One pin of a rated node's hedge added to its window counter rel (layout
+// MODE: 0 = hist in 16-bit halves, 1 = hist | c << hb in 32 bits, 2 = hist |
+// c << 32 in 64 bits), weight we and co-destination bit both.  Every pin a
+// rating streams lies in its window (the window spans the node's neighbour
+// id range, or the segments were clipped to it), so no range test is needed;
+// masked lanes add zero.  The node's own pin is counted too and its counter
+// cleared afterwards (window_clear_self): its count, total(n) | indeg(n) <<
+// hb, fits the layout by the same bounds as every other counter.
+template <int MODE>
+__device__ __forceinline__ void window_add(uint32_t *lds, uint64_t *lds64, uint32_t rel, uint32_t we, uint32_t both,
+                                           int hb) {
+  if constexpr (MODE == 0)
+    atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
+  else if constexpr (MODE == 1)
+    atomicAdd(&lds[rel], we + (both << hb));
+  else
+    atomicAdd((unsigned long long *)&lds64[rel], (unsigned long long)we | ((unsigned long long)both << 32));
+}
+
+// Clears the rated node's own counter (relative id rn) in a window of span
+// ids after a stream (block-wide; the caller's barrier precedes it, one
+// follows it).
+__device__ __forceinline__ void window_clear_self(uint32_t *lds, uint64_t *lds64, int mode, int rn, int span) {
+  if (threadIdx.x == 0 && (uint32_t)rn < (uint32_t)span) {
+    if (mode == 0)
+      lds[rn >> 1] &= ~(0xffffu << ((rn & 1) << 4));
+    else if (mode == 1)
+      lds[rn] = 0u;
+    else
+      lds64[rn] = 0ull;
+  }
+  __syncthreads();
+}
+
 // Full rating with top-(TK+1) selection of the nodes in list[0 .. *count)
 // (or of every node when list is null).  With pre non-null, node t's counters
 // are row t of pre (N 64-bit counters hist | c << 32, from k_tail_hist)
@@ -142,26 +176,16 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
         // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
         streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
           constexpr int MODE = decltype(mode)::value;
-          return stream_segments<NT / 64, kRateU, true, uint32_t>(
+          return stream_segments<NT / 64, kRateU, true, uint32_t, true>(
               i0, i1, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-              [&](uint32_t y, uint32_t info) {
-                const int m = (int)(y & kIdMask);
-                const uint32_t rel = (uint32_t)(m - lo);
-                if ((m != n) & (rel < (uint32_t)span)) {
-                  const uint32_t we = info & kIdMask;
-                  const uint32_t both = (info & y) >> 31;
-                  if constexpr (MODE == 0)
-                  atomicAdd(&lds[rel >> 1], we << ((rel & 1u) << 4));
-                else if constexpr (MODE == 1)
-                    atomicAdd(&lds[rel], we + (both << hb));
-                  else
-                    atomicAdd((unsigned long long *)&lds64[rel],
-                              (unsigned long long)we | ((unsigned long long)both << 32));
-                }
+              [&](uint32_t y, uint32_t info, bool ok) {
+                window_add<MODE>(lds, lds64, (y & kIdMask) - (uint32_t)lo, ok ? info & kIdMask : 0u,
+                                 ok ? (info & y) >> 31 : 0u, hb);
               },
               clip, lo, lo + span);
         });
         __syncthreads();
+        window_clear_self(lds, lds64, half ? 0 : (packed ? 1 : 2), n - lo, span);
         if (half) {
           // Delta holds for every candidate here, whatever c is
           for (int i = tid; i < zw; i += NT) {
@@ -464,24 +488,16 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
     __syncthreads();
     streamed += with_mode(packed ? 1 : 2, [&](auto mode) {
       constexpr int MODE = decltype(mode)::value;
-      return stream_segments<NT / 64, kRateU, true, uint32_t>(
+      return stream_segments<NT / 64, kRateU, true, uint32_t, true>(
           a, z, inc, hoff, nullptr, hw, tbl, [&](int j) { return hpin[j]; },
-          [&](uint32_t y, uint32_t info) {
-            const int m = (int)(y & kIdMask);
-            const uint32_t rel = (uint32_t)(m - lo);
-            if ((m != n) & (rel < (uint32_t)span)) {
-              const uint32_t we = info & kIdMask;
-              const uint32_t both = (info & y) >> 31;
-              if constexpr (MODE == 1)
-                atomicAdd(&lds[rel], we + (both << hb));
-              else
-                atomicAdd((unsigned long long *)&lds64[rel],
-                          (unsigned long long)we | ((unsigned long long)both << 32));
-            }
+          [&](uint32_t y, uint32_t info, bool ok) {
+            window_add<MODE>(lds, lds64, (y & kIdMask) - (uint32_t)lo, ok ? info & kIdMask : 0u,
+                             ok ? (info & y) >> 31 : 0u, hb);
           },
           clip, lo, lo + span);
     });
     __syncthreads();
+    window_clear_self(lds, lds64, packed ? 1 : 2, n - lo, span);
     for (int i = tid; i < span; i += NT) {
       unsigned long long v;
       if (packed) {
