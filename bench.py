@@ -187,6 +187,51 @@ DEFAULT_MLP = os.path.join(ROOT, "paper_2604_14411_amd", "mlp_v2.json")
 METRIC = "pins/s (\u03a3|e|/s) partition throughput + connectivity, learned vs plain at \u03a9,\u0394"
 
 
+def lds_probe():
+    """The LDS atomic-add rate of the whole device (the peak that the ratings'
+    and proposals' histograms are priced against): 512 workgroups of 1024
+    threads, 8 adds per thread and iteration.  The counters are checked
+    against their closed forms."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    path = os.path.join(ROOT, "paper_2604_14411_amd", "libhgp_probe.so")
+    if not os.path.exists(path):
+        raise SystemExit(f"{path} is not built (python __graft_entry__.py build)")
+    lib = ctypes.CDLL(path)
+    lib.hgp_probe_lds_atomics.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_float)]
+    lib.hgp_probe_lds_atomics.restype = ctypes.c_int
+    grid, iters, words = 512, 8192, 8192
+    out = torch.empty(grid * words, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    res = {}
+    for random in (0, 1):
+        ms = ctypes.c_float(0.0)
+        best = None
+        for _ in range(4):  # the first launch also loads the code object
+            rc = lib.hgp_probe_lds_atomics(random, grid, iters, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream),
+                                           ctypes.byref(ms))
+            if rc != 0:
+                raise SystemExit(f"hgp_probe_lds_atomics returned {rc}")
+            best = ms.value if best is None else min(best, ms.value)
+        cnt = out.cpu().numpy().view(np.uint32).reshape(grid, words)
+        tri = (iters * (iters + 1) // 2) % 2**32
+        if random:
+            ok = bool(np.all(cnt.astype(np.uint64).sum(axis=1) % 2**32 == (words * tri) % 2**32))
+        else:
+            ok = bool(np.all(cnt == tri))
+        ops = grid * 1024 * 8 * iters
+        key = "random" if random else "conflict_free"
+        res[key] = dict(ms=best, tops=ops / best / 1e9, frac=ops / best / 1e9 / LDS_ATOMIC_PEAK_TOPS, counters_ok=ok)
+        log(f"[bench] LDS atomics {key}: {best:.3f} ms for {ops:.3e} adds, {ops / best / 1e9:.2f} T/s, counters ok={ok}")
+    print(json.dumps(dict(probe="LDS atomic add (u32, no return)", grid=grid, threads=1024, iters=iters,
+                          adds_per_launch=grid * 1024 * 8 * iters, peak_tops=LDS_ATOMIC_PEAK_TOPS, **res)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +246,8 @@ def main():
                          "instead of the two traversals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, help="only copy this many bytes on the device (profiling)")
+    ap.add_argument("--lds-probe", action="store_true",
+                    help="only measure the device's LDS atomic-add rate (libhgp_probe.so), conflict-free and random")
     ap.add_argument("--mlp", default=DEFAULT_MLP, help="checkpoint of the learned proposal (paper_2604_14411_amd/learn.py)")
     args = ap.parse_args()
     if args.workload == "batch256":
@@ -230,6 +277,9 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         print(json.dumps(dict(probe="device copy", bytes=args.copy_probe, ms_per_copy=ms,
                               read_write_gbs=2 * args.copy_probe / ms / 1e6, peak_gbs=HBM_PEAK_GBS)))
+        return
+    if args.lds_probe:
+        lds_probe()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path",

@@ -1,4 +1,5 @@
-"""Build libhgp.so (hipcc, gfx950) and the synthetic-input generator in-tree."""
+"""Build libhgp.so (hipcc, gfx950), the LDS-atomic micro-benchmark
+libhgp_probe.so and the synthetic-input generator in-tree."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhgp.so")
+PROBE_LIB = os.path.join(HERE, "libhgp_probe.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["prims.hip", "coarsen.hip", "refine.hip", "seg.hip", "tail.hip", "events.hip", "learned.hip", "training.hip", "checkpoint.hip", "driver.hip"]
@@ -43,11 +45,24 @@ def build_lib() -> str:
     return LIB
 
 
+def build_probe() -> str:
+    """The micro-benchmark of LDS atomic adds (bench.py --lds-probe)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *HIP_FLAGS, "-shared", os.path.join(CSRC, "probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on probe.hip:\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build_all() -> None:
     from paper_2604_14411_amd import synth
 
     synth.build(force=True)
     build_lib()
+    build_probe()
 
 
 if __name__ == "__main__":

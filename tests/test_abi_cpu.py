@@ -50,3 +50,21 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(hgp, "_lib", None)
     with pytest.raises(RuntimeError):
         hgp.load()
+
+
+def test_probe_library_exports_its_entry_and_checks_arguments():
+    """The LDS-atomic micro-benchmark (bench.py --lds-probe) is a library of
+    its own; argument errors return -1 before any HIP call."""
+    path = os.path.join(ROOT, "paper_2604_14411_amd", "libhgp_probe.so")
+    if not os.path.exists(path):
+        pytest.skip("libhgp_probe.so not built")
+    lib = ctypes.CDLL(path)
+    f = lib.hgp_probe_lds_atomics
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.POINTER(ctypes.c_float)]
+    f.restype = ctypes.c_int
+    ms = ctypes.c_float(0.0)
+    assert f(0, 0, 1, ctypes.c_void_p(1), None, ctypes.byref(ms)) == -1
+    assert f(0, 1, 0, ctypes.c_void_p(1), None, ctypes.byref(ms)) == -1
+    assert f(1, 1, 1, None, None, ctypes.byref(ms)) == -1
+    assert f(1, 1, 1, ctypes.c_void_p(1), None, None) == -1
