@@ -143,7 +143,10 @@ void launch_check_level(const int32_t *hoff, const uint32_t *hpin, int32_t E, in
 
 
 // device scalars of a refinement round (RoundBufs::scal)
-enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4, SC_HEAVY = 5, SC_PHEAVY = 6, SC_GMAX = 7 };
+// (SC_ERR: the error bits, copied there at the end of the round so that they
+// are read back with the round's result)
+enum { SC_S = 0, SC_EVENTS = 1, SC_ISTAR = 2, SC_GSTAR = 3, SC_INVALID0 = 4, SC_HEAVY = 5, SC_PHEAVY = 6, SC_GMAX = 7,
+       SC_ERR = 8, SC_COUNT = 9 };
 
 // (pins, pins_in) of part p in the sorted part table of a hedge: part ids
 // pt[b .. b+len), counts ptc (pins | pins_in << 16).
@@ -186,7 +189,8 @@ struct RoundBufs {
   int32_t *vdelta = nullptr;   // [n+1] violation deltas per position
   int64_t *G = nullptr;        // [n+1]
   int32_t *viol = nullptr;     // [n+1]
-  int64_t *scal = nullptr;     // [8] device scalars: S, events, istar, Gstar, init_invalid, heavy hedges, heavy nodes, max gain
+  int64_t *scal = nullptr;     // [SC_COUNT] device scalars: S, events, istar, Gstar, init_invalid, heavy hedges,
+                               // heavy nodes, max gain, error bits
   int32_t *heavy = nullptr;    // [E] hedges queued for the workgroup event kernel
   int64_t *evoff = nullptr;    // [E + 1] inbound-count events per hedge, then their offsets
   int2 *contrib = nullptr;     // [P] per moving pin: in-sequence gain terms (source, destination role)

@@ -242,14 +242,26 @@ static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
   raise_err(read_i32(W, W.err.as<int32_t>(), s) & mask);
 }
 
-// *dptr and the error bits in one round trip; throws on an error
-static int32_t read_i32_checked(Workspace &W, const int32_t *dptr, hipStream_t s) {
+// The error word buffer (W.err): word 0 holds the error bits, the words after
+// it the per-level scalars that are read back with them in one copy.
+constexpr int kErrWords = 16;
+constexpr int kErrNnext = 4;     // matching: nodes of the next level (learned, plain pairs)
+constexpr int kErrContract = 8;  // contraction: pins of the next level, long hedges
+
+// err[0 .. n) in one round trip; throws on an error.
+static const int32_t *read_err_words(Workspace &W, int n, hipStream_t s) {
   int32_t *v = reinterpret_cast<int32_t *>(W.hbox.get());
-  HGP_HIP(hipMemcpyAsync(&v[0], dptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipMemcpyAsync(&v[1], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HGP_HIP(hipMemcpyAsync(v, W.err.ptr, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
-  raise_err(v[1]);
-  return v[0];
+  raise_err(v[0]);
+  return v;
+}
+
+__global__ void k_pick2(int32_t *__restrict__ dst, const int32_t *__restrict__ a, const int32_t *__restrict__ b) {
+  if (threadIdx.x == 0) {
+    dst[0] = *a;
+    dst[1] = *b;
+  }
 }
 
 static void check_scalars(const hgp_hypergraph *g, int32_t omega, int32_t delta) {
@@ -298,7 +310,7 @@ static Ingest ingest(Workspace &W, const hgp_hypergraph *g, int32_t omega, int32
   check_scalars(g, omega, delta);
   Ingest I;
   const int32_t N = g->n_nodes, E = g->n_hedges;
-  int32_t *err = need<int32_t>(W.err, 4);
+  int32_t *err = need<int32_t>(W.err, kErrWords);
   fill_i32(err, 1, 0, s);
   launch_check_offsets(g->hedge_off, E, err, s);
   const int32_t P32 = read_i32(g->hedge_off + E, s);
@@ -433,7 +445,7 @@ static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32
   B.partial = &W.pt_partial;
   B.G = need<int64_t>(W.G, (int64_t)n + 1);
   B.viol = need<int32_t>(W.viol, (int64_t)n + 1);
-  B.scal = need<int64_t>(W.scal, 8);
+  B.scal = need<int64_t>(W.scal, SC_COUNT);
   B.heavy = need<int32_t>(W.heavy, E);
   B.evoff = need<int64_t>(W.evoff, (int64_t)E + 1);
   B.hbox = W.hbox.get();
@@ -750,7 +762,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   uint8_t *up = need<uint8_t>(W.up, N);
   int32_t *match = need<int32_t>(W.match, N);
   int32_t *rep = need<int32_t>(W.rep, N);
-  int32_t *nnext_dev = need<int32_t>(W.scal2, 4);
+  int32_t *nnext_dev = need<int32_t>(W.err, kErrWords) + kErrNnext;
   int32_t *rho = need<int32_t>(W.rhoA, N);
   int32_t *rho2 = need<int32_t>(W.rhoB, N);
   need<int32_t>(W.hoffA, (int64_t)E + 1);
@@ -816,8 +828,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
             KScope ks(HGP_K_RATE, s);
             launch_cand_from_lists(n, opt.mlp->k, tk_cur, CB.ck, CB.cc, CB.ccnt, s);
           }
-          const int64_t C = candidate_sets(L, CB, W.scan_tmp, W.sort_tmp, s);
-          score_and_select(L, omega, delta, lvl, mlp_params, CB, C, s);
+          const int64_t Cb = candidate_sets_dev(L, CB, opt.mlp->k, W.scan_tmp, W.sort_tmp, s);
+          score_and_select(L, omega, delta, lvl, mlp_params, CB, Cb, s);
         } else {
           learned_candidates(L, L.total, omega, delta, lvl, opt.mlp->k, mlp_params, CB, W.scan_tmp,
                              W.sort_tmp, s);
@@ -847,7 +859,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
     int32_t n_next = 0;
     if (!learned) {
-      n_next = read_i32_checked(W, nnext_dev, s);
+      n_next = read_err_words(W, kErrNnext + 1, s)[kErrNnext];
     } else {
       // fallback: the plain pairs' matching, used if it merges over twice as
       // many pairs (both counts read back together)
@@ -855,13 +867,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       int32_t *pg = need<int32_t>(W.pgam, n);
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
-      int32_t *v = reinterpret_cast<int32_t *>(W.hbox.get());
-      HGP_HIP(hipMemcpyAsync(v, nnext_dev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HGP_HIP(hipMemcpyAsync(&v[2], W.err.as<int32_t>(), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HGP_HIP(hipStreamSynchronize(s));
-      raise_err(v[2]);
-      n_next = v[0];
-      const int32_t n_next_p = v[1];
+      const int32_t *v = read_err_words(W, kErrNnext + 2, s);
+      n_next = v[kErrNnext];
+      const int32_t n_next_p = v[kErrNnext + 1];
       if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
         HGP_HIP(hipMemcpyAsync(lmatch, pm, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
         HGP_HIP(hipMemcpyAsync(gam, pg, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
@@ -912,10 +920,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     {
       // the contracted pin count, and this level's count of long hedges:
       // a bound for the next level's
-      int32_t *h = reinterpret_cast<int32_t *>(W.hbox.get());
-      HGP_HIP(hipMemcpyAsync(h, nh + E, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HGP_HIP(hipMemcpyAsync(h + 1, longlist + E + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HGP_HIP(hipStreamSynchronize(s));
+      k_pick2<<<1, 64, 0, s>>>(W.err.as<int32_t>() + kErrContract, nh + E, longlist + E + 1);
+      HGP_LAUNCH_CHECK();
+      const int32_t *h = read_err_words(W, kErrContract + 2, s) + kErrContract;
       cur_P = h[0];
       big.bound = std::min(big.bound, h[1]);
     }
@@ -1153,7 +1160,7 @@ static LevelView level_view_from(Workspace &W, const hgp_level *lv, hipStream_t 
   const int64_t P = read_i32(lv->hoff + lv->n_hedges, s);
   if (P > 0 && !lv->hpin) throw Error(HGP_EINVAL, "bad level");
   *P_out = P;
-  int32_t *err = need<int32_t>(W.err, 4);
+  int32_t *err = need<int32_t>(W.err, kErrWords);
   fill_i32(err, 1, 0, s);
   launch_check_offsets(lv->hoff, lv->n_hedges, err, s);
   check_err(W, s);
@@ -1574,7 +1581,7 @@ static int level_match_impl(hgp_ctx *ctx, int32_t n, const int32_t *pair, const 
       *n_next = 0;
       return;
     }
-    need<int32_t>(W.err, 4);
+    need<int32_t>(W.err, kErrWords);
     fill_i32(W.err.as<int32_t>(), 1, 0, s);
     unsigned long long *best = need<unsigned long long>(W.best, n);
     uint8_t *up = need<uint8_t>(W.up, n);
@@ -1617,7 +1624,7 @@ int hgp_level_contract(hgp_ctx *ctx, const hgp_level *lv, const int32_t *gamma, 
     const int32_t E = lv->n_hedges;
     const int64_t P = read_i32(lv->hoff + E, s);
     if (P > 0 && (!hpin_out || !lv->hpin)) throw Error(HGP_EINVAL, "NULL array");
-    int32_t *err = need<int32_t>(W.err, 4);
+    int32_t *err = need<int32_t>(W.err, kErrWords);
     fill_i32(err, 1, 0, s);
     launch_check_offsets(lv->hoff, E, err, s);
     check_err(W, s);

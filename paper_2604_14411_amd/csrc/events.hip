@@ -924,7 +924,7 @@ __global__ void k_init_invalid(const int32_t *__restrict__ psize, const int32_t 
 constexpr int FIN_NT = 1024;
 __global__ __launch_bounds__(FIN_NT) void k_finish(const int32_t *__restrict__ gp, const int32_t *__restrict__ vdelta,
                                                    int64_t S, int64_t *__restrict__ G, int32_t *__restrict__ viol,
-                                                   int64_t *__restrict__ scal) {
+                                                   int64_t *__restrict__ scal, const int32_t *__restrict__ err) {
   __shared__ int64_t wsum[FIN_NT / 64];
   __shared__ int32_t wvs[FIN_NT / 64];
   __shared__ int64_t s_carry_g;
@@ -1001,6 +1001,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finish(const int32_t *__restrict__ g
       }
     scal[SC_ISTAR] = my_i;
     scal[SC_GSTAR] = my_i >= 0 ? my_g : 0;
+    scal[SC_ERR] = *err;
   }
 }
 
@@ -1086,16 +1087,16 @@ void evaluate_sequence(const LevelView &L, const int32_t *rho, int32_t n_parts, 
       else
         events_after_sort<uint64_t>(L, B.keys, nev, vshift, qmask, rho, n_parts, omega, delta, B, s);
     }
-    k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal);
+    k_finish<<<1, FIN_NT, 0, s>>>(B.gp, B.vdelta, S, B.G, B.viol, B.scal, err);
     HGP_LAUNCH_CHECK();
   }
-  // the result and the error bits in one round trip
-  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_ISTAR, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipMemcpyAsync(B.hbox + 2, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  // the result and the error bits (copied beside it by k_finish) in one copy
+  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_ISTAR, (SC_ERR - SC_ISTAR + 1) * sizeof(int64_t),
+                         hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
   *istar = B.hbox[0];
-  *gstar = B.hbox[1];
-  *err_bits = *reinterpret_cast<const int32_t *>(B.hbox + 2);
+  *gstar = B.hbox[SC_GSTAR - SC_ISTAR];
+  *err_bits = (int32_t)B.hbox[SC_ERR - SC_ISTAR];
 }
 
 }  // namespace hgp

@@ -230,12 +230,21 @@ __global__ __launch_bounds__(CAND_NT) void k_rate_cand(
 // 2. symmetric candidate sets
 // ---------------------------------------------------------------------------
 // Both orientations of every kept pair: key n << idbits | m, value = slot of
-// the pair in ck / cc.  off[n] = exclusive prefix of ccnt.
+// the pair in ck / cc.  off[n] = exclusive prefix of ccnt.  With kept (the
+// device count of kept pairs), the entries from 2 *kept up to the bound
+// Mb get the key of all ones over 2 idbits bits, which no pair has (n != m),
+// so that they sort last.
 __global__ void k_cand_mirror(const uint64_t *__restrict__ ck, const int32_t *__restrict__ ccnt,
                               const int32_t *__restrict__ off, int32_t N, int idbits, uint64_t *__restrict__ key,
-                              uint32_t *__restrict__ val) {
+                              uint32_t *__restrict__ val, const int32_t *__restrict__ kept, int64_t Mb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)N * kCandK) return;
+  if (kept) {
+    const int64_t M = 2 * (int64_t)*kept;
+    const uint64_t pad = (1ull << (2 * idbits)) - 1ull;
+    if (2 * t >= M && 2 * t < Mb) key[2 * t] = pad;
+    if (2 * t + 1 >= M && 2 * t + 1 < Mb) key[2 * t + 1] = pad;
+  }
   const int n = (int)(t / kCandK), j = (int)(t % kCandK);
   if (j >= ccnt[n]) return;
   const uint64_t m = ck[t] & 0xffffffffull;
@@ -246,15 +255,20 @@ __global__ void k_cand_mirror(const uint64_t *__restrict__ ck, const int32_t *__
   val[p + 1] = (uint32_t)t;
 }
 
-__global__ void k_cand_first(const uint64_t *__restrict__ key, int64_t M, int32_t *__restrict__ flag) {
+// First entry of each distinct key among the first M (2 *kept when kept is
+// given; the entries up to the bound Mb are padding).
+__global__ void k_cand_first(const uint64_t *__restrict__ key, int64_t Mb, const int32_t *__restrict__ kept,
+                             int32_t *__restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < M) flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+  const int64_t M = kept ? 2 * (int64_t)*kept : Mb;
+  if (i < Mb) flag[i] = (i < M && (i == 0 || key[i] != key[i - 1])) ? 1 : 0;
 }
 
-__global__ void k_cand_compact(const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t M,
-                               const int32_t *__restrict__ pos, uint64_t *__restrict__ cnm,
-                               uint32_t *__restrict__ csrc) {
+__global__ void k_cand_compact(const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t Mb,
+                               const int32_t *__restrict__ kept, const int32_t *__restrict__ pos,
+                               uint64_t *__restrict__ cnm, uint32_t *__restrict__ csrc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t M = kept ? 2 * (int64_t)*kept : Mb;
   if (i >= M) return;
   if (i == 0 || key[i] != key[i - 1]) {
     cnm[pos[i]] = key[i];
@@ -262,13 +276,15 @@ __global__ void k_cand_compact(const uint64_t *__restrict__ key, const uint32_t 
   }
 }
 
-// coff[n] = first entry of node n (n = 0 .. N; coff[N] = C)
-__global__ void k_cand_offsets(const uint64_t *__restrict__ cnm, int64_t C, int32_t N, int idbits,
-                               int64_t *__restrict__ coff) {
+// coff[n] = first entry of node n (n = 0 .. N; coff[N] = C; C = *cdev if given,
+// and then added to *units when that is non-null: the network's rows)
+__global__ void k_cand_offsets(const uint64_t *__restrict__ cnm, int64_t C, const int32_t *__restrict__ cdev,
+                               int32_t N, int idbits, int64_t *__restrict__ coff, unsigned long long *units) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n > N) return;
+  if (n == 0 && cdev && units) atomicAdd(units, (unsigned long long)*cdev);
   const uint64_t x = (uint64_t)n << idbits;
-  int64_t lo = 0, hi = C;
+  int64_t lo = 0, hi = cdev ? (int64_t)*cdev : C;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if (cnm[mid] < x) lo = mid + 1;
@@ -475,10 +491,10 @@ struct CandCodes {
   }
 };
 
-__global__ __launch_bounds__(MLP_NT) void k_cand_score(CandCodes cf, int64_t C, const int32_t *__restrict__ params,
-                                                       int32_t *__restrict__ out) {
+__global__ __launch_bounds__(MLP_NT) void k_cand_score(CandCodes cf, int64_t C, const int32_t *__restrict__ cdev,
+                                                       const int32_t *__restrict__ params, int32_t *__restrict__ out) {
   __shared__ int32_t tiles[MLP_NT / 64][32 * MLP_LD];
-  mlp_tiles(C, params, cf, out, tiles[threadIdx.x >> 6]);
+  mlp_tiles(cdev ? (int64_t)*cdev : C, params, cf, out, tiles[threadIdx.x >> 6]);
 }
 
 // Codes only (for the level API): the same feature function, written out.
@@ -503,10 +519,10 @@ __global__ void k_cand_codes(CandCodes cf, int64_t C, int32_t *__restrict__ xq) 
 // node-sorted array: a segmented maximum over the wave's runs of equal n and
 // one atomicMax per run, so a node that is in the candidate sets of
 // thousands of others costs a few hundred atomics, not a serial scan.
-__global__ void k_cand_best(const uint64_t *__restrict__ cnm, const int32_t *__restrict__ cs, int64_t C, int idbits,
-                            unsigned long long *__restrict__ best) {
+__global__ void k_cand_best(const uint64_t *__restrict__ cnm, const int32_t *__restrict__ cs, int64_t C,
+                            const int32_t *__restrict__ cdev, int idbits, unsigned long long *__restrict__ best) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = i < C;
+  const bool in = i < (cdev ? (int64_t)*cdev : C);
   const uint64_t e = in ? cnm[i] : 0ull;
   const int64_t n = in ? (int64_t)(e >> idbits) : -1 - (int64_t)lane_id();  // lanes past C: runs of their own
   unsigned long long key =
@@ -602,25 +618,55 @@ int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf
     M = 2 * (int64_t)kept;
     if (M > 0) {
       k_cand_mirror<<<div_up((int64_t)N * kCandK, 256), 256, 0, s>>>(B.ck, B.ccnt, B.coff32, N, idbits, B.key,
-                                                                      B.val);
+                                                                      B.val, nullptr, M);
       HGP_LAUNCH_CHECK();
     }
   }
   if (M > 1) radix_sort_u64(B.key, B.key2, B.val, B.val2, M, 2 * idbits, sort_tmp, s);
   KScope ks(HGP_K_MLP, s);
   if (M > 0) {
-    k_cand_first<<<div_up(M, 256), 256, 0, s>>>(B.key, M, B.flag);
+    k_cand_first<<<div_up(M, 256), 256, 0, s>>>(B.key, M, nullptr, B.flag);
     HGP_LAUNCH_CHECK();
     scan_i32(B.flag, B.flag, M, B.tot32 + 1, scan_tmp, s);
-    k_cand_compact<<<div_up(M, 256), 256, 0, s>>>(B.key, B.val, M, B.flag, B.cnm, B.csrc);
+    k_cand_compact<<<div_up(M, 256), 256, 0, s>>>(B.key, B.val, M, nullptr, B.flag, B.cnm, B.csrc);
     HGP_LAUNCH_CHECK();
     HGP_HIP(hipMemcpyAsync(B.hbox, B.tot32 + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HGP_HIP(hipStreamSynchronize(s));
     C = *reinterpret_cast<const int32_t *>(B.hbox);
   }
-  k_cand_offsets<<<div_up((int64_t)N + 1, 256), 256, 0, s>>>(B.cnm, C, N, idbits, B.coff);
+  k_cand_offsets<<<div_up((int64_t)N + 1, 256), 256, 0, s>>>(B.cnm, C, nullptr, N, idbits, B.coff, nullptr);
   HGP_LAUNCH_CHECK();
+  B.cdev = nullptr;
   return C;
+}
+
+int64_t candidate_sets_dev(const LevelView &L, CandBufs &B, int keep, DevBuf &scan_tmp, DevBuf &sort_tmp,
+                           hipStream_t s) {
+  const int32_t N = L.n;
+  B.cdev = nullptr;
+  if (N <= 0) return 0;
+  if (keep < 1 || keep > kCandK) throw Error(HGP_EINVAL, "candidates per node outside 1..8");
+  const int idbits = std::max(1, bits_for(N - 1));
+  const int64_t Mb = 2 * (int64_t)N * keep;  // every node keeps at most `keep` pairs
+  {
+    KScope ks(HGP_K_MLP, s);
+    scan_i32(B.ccnt, B.coff32, N, B.tot32, scan_tmp, s);
+    k_cand_mirror<<<div_up((int64_t)N * kCandK, 256), 256, 0, s>>>(B.ck, B.ccnt, B.coff32, N, idbits, B.key, B.val,
+                                                                    B.tot32, Mb);
+    HGP_LAUNCH_CHECK();
+  }
+  if (Mb > 1) radix_sort_u64(B.key, B.key2, B.val, B.val2, Mb, 2 * idbits, sort_tmp, s);
+  KScope ks(HGP_K_MLP, s);
+  k_cand_first<<<div_up(Mb, 256), 256, 0, s>>>(B.key, Mb, B.tot32, B.flag);
+  HGP_LAUNCH_CHECK();
+  scan_i32(B.flag, B.flag, Mb, B.tot32 + 1, scan_tmp, s);
+  k_cand_compact<<<div_up(Mb, 256), 256, 0, s>>>(B.key, B.val, Mb, B.tot32, B.flag, B.cnm, B.csrc);
+  HGP_LAUNCH_CHECK();
+  k_cand_offsets<<<div_up((int64_t)N + 1, 256), 256, 0, s>>>(B.cnm, 0, B.tot32 + 1, N, idbits, B.coff,
+                                                              units_ptr(HGP_K_MLP));
+  HGP_LAUNCH_CHECK();
+  B.cdev = B.tot32 + 1;
+  return Mb;
 }
 
 void score_and_select(const LevelView &L, int32_t omega, int32_t delta, int level, const int32_t *params,
@@ -631,13 +677,13 @@ void score_and_select(const LevelView &L, int32_t omega, int32_t delta, int leve
   const int idbits = std::max(1, bits_for(N - 1));
   CandCodes cf{B.cnm, B.csrc, B.ck, B.cc, L.size, L.indeg, L.ioff, idbits, level, omega, delta};
   if (C > 0) {
-    add_units(HGP_K_MLP, C);
-    k_cand_score<<<grid_for_tiles(C), MLP_NT, 0, s>>>(cf, C, params, B.cs);
+    if (!B.cdev) add_units(HGP_K_MLP, C);
+    k_cand_score<<<grid_for_tiles(C), MLP_NT, 0, s>>>(cf, C, B.cdev, params, B.cs);
     HGP_LAUNCH_CHECK();
   }
   fill_i64(reinterpret_cast<int64_t *>(B.best), N, 0, s);
   if (C > 0) {
-    k_cand_best<<<div_up(C, 256), 256, 0, s>>>(B.cnm, B.cs, C, idbits, B.best);
+    k_cand_best<<<div_up(C, 256), 256, 0, s>>>(B.cnm, B.cs, C, B.cdev, idbits, B.best);
     HGP_LAUNCH_CHECK();
   }
   k_cand_pick<<<div_up(N, 256), 256, 0, s>>>(B.best, N, B.ck, B.ccnt, B.pair, B.score, B.ppair, B.pscore);

@@ -35,6 +35,9 @@ struct CandBufs {
   int64_t *pscore = nullptr; // [N] its hist
   unsigned long long *best = nullptr;  // [N] selection scratch: best packed (score, id) per node
   int64_t *hbox = nullptr;             // pinned host words for read-backs
+  // with device counts (candidate_sets_dev): the number of entries C on the
+  // device; the host then knows a bound only
+  const int32_t *cdev = nullptr;
 };
 
 // Validates a network (HGP_EINVAL / HGP_EUNSUPPORTED) and copies it to buf.
@@ -56,7 +59,12 @@ int64_t build_candidates(const LevelView &L, const int32_t *total, int32_t omega
 // Symmetric candidate sets, deduplicated pairs and offsets from ck / cc / ccnt
 // (the second half of build_candidates); returns the number of pairs.
 int64_t candidate_sets(const LevelView &L, CandBufs &B, DevBuf &scan_tmp, DevBuf &sort_tmp, hipStream_t s);
-// Steps 3-4 on C entries built by build_candidates.
+// As candidate_sets without a host round trip: the arrays are built for the
+// bound of 2 N keep mirrored entries (keep: the most candidates of a node),
+// the exact counts stay on the device (B.cdev), and the bound is returned.
+int64_t candidate_sets_dev(const LevelView &L, CandBufs &B, int keep, DevBuf &scan_tmp, DevBuf &sort_tmp,
+                           hipStream_t s);
+// Steps 3-4 on C entries built by build_candidates (C a bound when B.cdev is set).
 void score_and_select(const LevelView &L, int32_t omega, int32_t delta, int level, const int32_t *params,
                       CandBufs &B, int64_t C, hipStream_t s);
 // Input codes of the C entries of B ([C*16]).

@@ -459,12 +459,11 @@ int64_t build_sequence(const LevelView &L, RoundBufs &B, DevBuf &scan_tmp, DevBu
                                               reinterpret_cast<unsigned long long *>(B.scal + SC_GMAX));
   HGP_LAUNCH_CHECK();
   scan_i32(B.flag, B.flag, N, reinterpret_cast<int32_t *>(B.scal + SC_S), scan_tmp, s);
-  // |S| and the largest gain in one round trip
-  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_S, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HGP_HIP(hipMemcpyAsync(B.hbox + 1, B.scal + SC_GMAX, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  // |S| and the largest gain in one copy (scal[SC_S .. SC_GMAX])
+  HGP_HIP(hipMemcpyAsync(B.hbox, B.scal + SC_S, (SC_GMAX - SC_S + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HGP_HIP(hipStreamSynchronize(s));
-  const int64_t S = *reinterpret_cast<const int32_t *>(B.hbox);
-  const int64_t gmax = B.hbox[1];
+  const int64_t S = *reinterpret_cast<const int32_t *>(B.hbox + SC_S);
+  const int64_t gmax = B.hbox[SC_GMAX];
   if (S == 0) return 0;
   const int idbits = bits_for(N - 1) > 0 ? bits_for(N - 1) : 1;
   const int gbits = bits_for(gmax);
