@@ -131,8 +131,10 @@ def cpu_baseline(w, mlp, threads_multi: int):
 def bench_batch(args):
     """256 random SNNs (node counts log-uniform in [2048, 32768], |T_v| ~
     Poisson(mu)+1 with mu uniform in [32, 256], w in [1,16], seeds 4000+g),
-    partitioned as one batch; the schedule is tuned once, on a 16-graph
-    sample, before timing."""
+    partitioned as one batch with the learned proposal (--plain: the plain
+    method); the schedule is tuned once, on a 16-graph sample, before timing.
+    --plain-steps > 0 adds one plain batch under its own tuned schedule, as
+    the judge of the learned connectivity."""
     import numpy as np
     import torch
 
@@ -148,38 +150,59 @@ def bench_batch(args):
             log(f"[bench] generated {i + 1} graphs")
     pins = sum(g.n_pins for g in gs)
     log(f"[bench] batch of {len(gs)} graphs, {pins} pins, generated in {time.perf_counter() - t:.1f} s")
+    mlp = None
+    if not args.plain:
+        from paper_2604_14411_amd.learn import load_checkpoint
+
+        mlp, _, _ = load_checkpoint(args.mlp)
     ctx = hgp.Context(0)
     dgs = [hgp.DeviceHypergraph(g, "cuda:0") for g in gs]
     outs = [torch.empty(max(g.n_nodes, 1), dtype=torch.int32, device="cuda:0") for g in gs]
     om, de = [1024] * len(gs), [4096] * len(gs)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
     # tune on every 16th graph (16 graphs spanning the size range)
     sample = list(range(0, len(gs), 16))
-    sched, tune_ms = hgp.batch_tune(ctx, [dgs[i] for i in sample], [om[i] for i in sample], [de[i] for i in sample],
-                                    outs=[outs[i] for i in sample])
-    log(f"[bench] tuned schedule {sched} ({tune_ms:.0f} ms for the 16-graph sample) in "
-        f"{time.perf_counter() - t:.1f} s")
-    lat, done = [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        _, res, ts, te = hgp.partition_batch_device(ctx, dgs, om, de, outs=outs)
-        lat.append(te - ts)
-        done.append(te)
-        log(f"[bench] batch step {i}: {te.max():.0f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    lat = np.concatenate(lat)
-    done = np.concatenate(done)
+
+    def tune(q):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sched, tune_ms = hgp.batch_tune(ctx, [dgs[i] for i in sample], [om[i] for i in sample],
+                                        [de[i] for i in sample], outs=[outs[i] for i in sample], mlp=q)
+        log(f"[bench] tuned schedule {sched} ({tune_ms:.0f} ms for the 16-graph sample) in "
+            f"{time.perf_counter() - t:.1f} s")
+        return sched
+
+    def timed(q, steps, tag):
+        lat, done = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            _, res, ts, te = hgp.partition_batch_device(ctx, dgs, om, de, outs=outs, mlp=q)
+            lat.append(te - ts)
+            done.append(te)
+            log(f"[bench] {tag} batch step {i}: {te.max():.0f} ms")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, res, np.concatenate(lat), np.concatenate(done)
+
+    sched = tune(mlp)
+    elapsed, res, lat, done = timed(mlp, args.steps, "plain" if mlp is None else "learned")
     line = dict(metric="pins/s (sum |e| per second), batch of independent partitions", value=pins * args.steps / elapsed,
                 unit="pins/s", n_gpus=1, steps=args.steps, warmup=0, ms_per_step=1e3 * elapsed / args.steps,
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
                 config=dict(workload="batch256", graphs=len(gs), pins=pins, omega=1024, delta=4096,
-                            schedule=sched, conn_sum=int(sum(r["connectivity"] for r in res))),
+                            proposal="plain" if mlp is None else "learned", schedule=sched,
+                            conn_sum=int(sum(r["connectivity"] for r in res)),
+                            n_fallback=int(sum(r["n_fallback"] for r in res))),
                 latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
                                 completion_p50=float(np.percentile(done, 50)),
                                 completion_p99=float(np.percentile(done, 99))))
+    if mlp is not None and args.plain_steps > 0:
+        psched = tune(None)
+        pel, pres, _, _ = timed(None, 1, "plain")
+        pconn = int(sum(r["connectivity"] for r in pres))
+        line["learned_vs_plain"] = dict(plain=dict(value=pins / pel, ms_per_step=1e3 * pel, schedule=psched,
+                                                   conn_sum=pconn),
+                                        conn_ratio=line["config"]["conn_sum"] / pconn,
+                                        speed_ratio=line["value"] / (pins / pel))
     print(json.dumps(line), flush=True)
 
 

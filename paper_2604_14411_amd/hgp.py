@@ -633,11 +633,12 @@ def partition_batch_device(ctx: Context, dgs, omegas, deltas, sched=None, outs=N
             np.array(t0[:n]), np.array(t1[:n]))
 
 
-def batch_tune(ctx: Context, dgs, omegas, deltas, outs=None, flags: int = 0):
-    """hgp_batch_tune; returns (schedule dict, wall ms of the best schedule)."""
+def batch_tune(ctx: Context, dgs, omegas, deltas, outs=None, flags: int = 0, mlp=None):
+    """hgp_batch_tune (with the learned proposal when an integer network
+    `mlp` is given); returns (schedule dict, wall ms of the best schedule)."""
     lib = load()
     n, hg, om, de, outs, po = _batch_args(dgs, omegas, deltas, outs)
-    o, _keep = options(0, 8, 0, flags)
+    o, _keep = options(0, 8, 0, flags, mlp=mlp)
     best = BatchSched_t()
     ms = ctypes.c_double()
     _check(lib.hgp_batch_tune(ctx.handle, n, hg, om.ctypes.data, de.ctypes.data, ctypes.byref(o), _stream(), po,

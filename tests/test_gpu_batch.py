@@ -102,6 +102,37 @@ def test_autotuner_picks_a_valid_schedule(ctx, singles):
         assert np.array_equal(parts[i].cpu().numpy(), ref[i][0]), i
 
 
+def test_learned_batch_matches_single_calls_and_oracle(ctx, singles):
+    """The learned proposal in a batch: every graph gets the result of a
+    single learned call, under two schedules and the tuned one, and the
+    oracle's on three of them."""
+    import os
+
+    from paper_2604_14411_amd import hgp
+    from paper_2604_14411_amd.learn import load_checkpoint
+
+    q, _, _ = load_checkpoint(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                           "paper_2604_14411_amd", "mlp_v2.json"))
+    gs, om, de, dgs, _ = singles
+    ref = []
+    for i, d in enumerate(dgs):
+        p, r = hgp.partition_device(ctx, d, om[i], de[i], mlp=q)
+        ref.append((p.cpu().numpy().copy(), r["connectivity"], r["n_parts"], r["n_levels"]))
+    for i in (0, 9, 10):
+        rc, p, r, _ = oracle.partition_learned(gs[i], om[i], de[i], q)
+        assert rc == 0 and np.array_equal(p, ref[i][0]) and r["connectivity"] == ref[i][1], i
+    say("[batch] learned tune")
+    best, ms = hgp.batch_tune(ctx, dgs, om, de, mlp=q)
+    assert best["workers"] in (1, 2, 4, 8, 16) and ms > 0
+    for sched in (dict(workers=1, order=2), dict(workers=4, order=1), None):
+        say(f"[batch] learned schedule {sched}")
+        parts, res, t0, t1 = hgp.partition_batch_device(ctx, dgs, om, de, sched=sched, mlp=q)
+        for i in range(len(gs)):
+            assert np.array_equal(parts[i].cpu().numpy(), ref[i][0]), (sched, i)
+            assert res[i]["connectivity"] == ref[i][1] and res[i]["n_levels"] == ref[i][3], (sched, i)
+        assert np.all(t1 > t0)
+
+
 def test_batch_rejects_bad_member(ctx, singles):
     from paper_2604_14411_amd import hgp
 
