@@ -227,6 +227,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // each segment is first narrowed by binary search to the entries whose id
 // lies in [clip_lo, clip_hi): a rating over several LDS windows then streams
 // each pin once instead of once per window.
+// ROLE 1 streams only the incidences with the destination bit (the hedges
+// whose destination the node is), ROLE 2 only the others, ROLE 0 all.
 // With PASS_OK, apply(v, info, ok) is called for every lane of every round,
 // ok false for the lanes past the end (their v and info repeat the last
 // entry), so that a caller can fold the mask into its update instead of
@@ -236,7 +238,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // of a latency-bound stream grows with U.
 constexpr int kRateU = 16;
 
-template <int NW, int U, bool LEN_FROM_END, class V, bool PASS_OK = false, class Load, class Apply>
+template <int NW, int U, bool LEN_FROM_END, class V, bool PASS_OK = false, int ROLE = 0, class Load, class Apply>
 __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_t *__restrict__ inc,
                                                    const int32_t *__restrict__ soff, const int32_t *__restrict__ slen,
                                                    const int32_t *__restrict__ hw, int32_t *tbl, Load load,
@@ -251,8 +253,14 @@ __device__ __forceinline__ int64_t stream_segments(int i0, int i1, const uint32_
     const int idx = base + l;
     int b = 0, len = 0;
     uint32_t info = 0;
-    if (idx < i1) {
-      const uint32_t x = inc[idx];
+    uint32_t x = 0;
+    bool take = idx < i1;
+    if (take) {
+      x = inc[idx];
+      if constexpr (ROLE == 1) take = (x & kDst) != 0u;
+      if constexpr (ROLE == 2) take = (x & kDst) == 0u;
+    }
+    if (take) {
       const int e = (int)(x & kIdMask);
       b = soff[e];
       len = LEN_FROM_END ? soff[e + 1] - b : slen[e];

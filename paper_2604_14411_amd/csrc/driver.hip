@@ -103,6 +103,9 @@ struct Workspace {
   DevBuf tkA_key, tkA_c, tkA_cnt, tkA_kap, tkB_key, tkB_c, tkB_cnt, tkB_kap, newc, row_slot, nflag, rerate, dev_cnt;
   DevBuf split, cdest, cgain, maxbits, biglist, midlist, longlist, huge_k, huge_i, tail_acc;
   DevBuf dp_nchild, dp_arrived, dp_g, dp_key, dp_f, dp_root;  // exact matching
+  DevBuf gk, gka, gv, gva, gpos, goff, gcnt, gscr;             // grouped ratings
+  bool group_on = true;        // grouped ratings still pay in this run
+  bool group_pending = false;  // a grouped rating's counts await the next read-back
   // learned proposal
   hgp_trace *trace = nullptr;  // set for the duration of a traced run
   // coarse levels kept for refinement: the most recent, within the budget
@@ -145,7 +148,7 @@ struct Workspace {
     hbox.release();
     release_level_cache();
     DevBuf *inc_bufs[] = {&tkA_key, &tkA_c, &tkA_cnt, &tkA_kap, &tkB_key, &tkB_c, &tkB_cnt, &tkB_kap, &newc, &row_slot,
-                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &huge_k, &huge_i, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
+                          &nflag, &rerate, &dev_cnt, &split, &cdest, &cgain, &maxbits, &biglist, &midlist, &longlist, &huge_k, &huge_i, &dp_nchild, &dp_arrived, &dp_g, &dp_key, &dp_f, &dp_root, &gk, &gka, &gv, &gva, &gpos, &goff, &gcnt, &gscr, &tr_xq, &tr_prm, &tr_mom, &tr_part, &tr_perm, &tr_loss, &tr_grad, &mlp, &ck, &cc, &ccnt, &coff32, &ctot, &ckey, &ckey2, &cval, &cval2, &cflag, &cnm, &csrc, &cs, &ccoff, &ppair, &pscore, &pmatch, &pgam, &tail_acc};
     for (DevBuf *b : inc_bufs) b->release();
     timer.destroy();
     release_levels();
@@ -247,6 +250,7 @@ static void check_err(Workspace &W, hipStream_t s, int32_t mask = -1) {
 constexpr int kErrWords = 16;
 constexpr int kErrNnext = 4;     // matching: nodes of the next level (learned, plain pairs)
 constexpr int kErrContract = 8;  // contraction: pins of the next level, long hedges
+constexpr int kErrGroups = 12;   // grouped rating: groups, rated nodes
 
 // err[0 .. n) in one round trip; throws on an error.
 static const int32_t *read_err_words(Workspace &W, int n, hipStream_t s) {
@@ -418,6 +422,75 @@ static LevelView make_view(Workspace &W, int32_t n, int32_t E, const int32_t *ho
   L.hw = hw;
   L.big = big;
   return L;
+}
+
+// Grouped ratings (launch_rate_topk_grouped) for levels of at least
+// HGP_GROUP_MIN nodes (default 16384; negative: never), until one of at
+// least 4096 rated nodes finds groups of fewer than two nodes on average:
+// then the rest of the run rates node by node (the groups of a level only
+// ever shrink as clusters merge).
+static int64_t group_min() {
+  const char *e = std::getenv("HGP_GROUP_MIN");
+  return e && e[0] ? std::atoll(e) : 16384;
+}
+
+// Re-rating lists are grouped only with HGP_GROUP_LISTS=1: their groups are
+// small, and grouping them measured slower on conv302k than rating node by
+// node; full ratings are grouped by default.
+static bool group_lists() {
+  const char *e = std::getenv("HGP_GROUP_LISTS");
+  return e && e[0] == '1';
+}
+
+static bool grouping(Workspace &W, int32_t n) {
+  const int64_t m = group_min();
+  return W.group_on && m >= 0 && n >= m;
+}
+
+// Top-K rating of list[0 .. *count) (every node when list is null; bound: a
+// host bound of the count), grouped when grouping(W, n).
+static void rate_topk(Workspace &W, const LevelView &L, int32_t omega, int32_t delta, const int32_t *list,
+                      const int64_t *count, int64_t bound, int32_t *pair, int64_t *score, TopK &tk, hipStream_t s) {
+  if (!grouping(W, L.n) || bound <= 0 || (list && !group_lists())) {
+    launch_rate_topk(L, L.total, omega, delta, list, count, bound, pair, score, tk, s);
+    return;
+  }
+  GroupBufs G;
+  G.keys = need<uint32_t>(W.gk, bound);
+  G.alt = need<uint32_t>(W.gka, bound);
+  G.vals = need<uint32_t>(W.gv, bound);
+  G.valt = need<uint32_t>(W.gva, bound);
+  G.pos = need<int32_t>(W.gpos, bound);
+  G.goff = need<int32_t>(W.goff, bound + 1);
+  G.groups = need<int32_t>(W.gcnt, 1);
+  G.scratch = need<uint32_t>(W.gscr, group_scratch_words(L.n));
+  G.tmp = &W.sort_tmp;
+  G.scan_tmp = &W.scan_tmp;
+  launch_group_order(L, list, count, bound, G, s);
+  if (!list) {
+    // a full rating reads the group count first: without groups (random
+    // networks) it rates node by node, and the run stops grouping
+    int32_t *h = reinterpret_cast<int32_t *>(W.hbox.get());
+    HGP_HIP(hipMemcpyAsync(h, G.groups, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HGP_HIP(hipStreamSynchronize(s));
+    if (2 * (int64_t)h[0] > bound) {
+      W.group_on = false;
+      launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, bound, pair, score, tk, s);
+      return;
+    }
+  }
+  launch_rate_topk_grouped(L, L.total, omega, delta, count, bound, pair, score, tk, G,
+                           need<int32_t>(W.err, kErrWords) + kErrGroups, s);
+  W.group_pending = true;
+}
+
+// After a read-back of the error words: a grouped rating of at least 4096
+// nodes with groups of fewer than two nodes on average ends grouping.
+static void group_verdict(Workspace &W, const int32_t *v) {
+  if (!W.group_pending) return;
+  W.group_pending = false;
+  const int64_t groups = v[kErrGroups], rated = v[kErrGroups + 1];
+  if (rated >= 4096 && 2 * groups > rated) W.group_on = false;
 }
 
 static RoundBufs round_bufs(Workspace &W, int32_t n, int32_t E, int64_t P, int32_t n_parts) {
@@ -737,6 +810,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
   const int32_t *hw = I.hw;
   const int32_t *mlp_params = learned ? upload_mlp(W.mlp, opt.mlp, s) : nullptr;
   W.clear_levels();
+  W.group_on = true;
+  W.group_pending = false;
   level_slot(W.lv_size, 0);
   W.lv_n.push_back(N);
   int32_t *size0 = need<int32_t>(W.lv_size[0], N);
@@ -819,7 +894,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
           // rating of k_rate_cand: conv302k 3.65 to 3.27 s per partition)
           if (!lists_fresh) {
             path = "learned, topk";
-            launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
+            rate_topk(W, L, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
             lists_ok = true;
           } else {
             path = "learned, incremental";
@@ -838,7 +913,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
         lists_fresh = false;
       } else if (incremental && tail) {
         path = "topk";
-        launch_rate_topk(L, L.total, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
+        rate_topk(W, L, omega, delta, nullptr, nullptr, n, pair, score, tk_cur, s);
         lists_ok = true;
       } else {
         launch_rate(L, L.total, omega, delta, pair, score, need<int32_t>(W.maxin, 1), s,
@@ -859,7 +934,9 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       launch_match(pair, score, n, best, up, lmatch, gam, rep, nnext_dev, W.err.as<int32_t>(), W.scan_tmp, s);
     int32_t n_next = 0;
     if (!learned) {
-      n_next = read_err_words(W, kErrNnext + 1, s)[kErrNnext];
+      const int32_t *v = read_err_words(W, kErrWords, s);
+      group_verdict(W, v);
+      n_next = v[kErrNnext];
     } else {
       // fallback: the plain pairs' matching, used if it merges over twice as
       // many pairs (both counts read back together)
@@ -867,7 +944,8 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       int32_t *pg = need<int32_t>(W.pgam, n);
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
-      const int32_t *v = read_err_words(W, kErrNnext + 2, s);
+      const int32_t *v = read_err_words(W, kErrWords, s);
+      group_verdict(W, v);
       n_next = v[kErrNnext];
       const int32_t n_next_p = v[kErrNnext + 1];
       if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
@@ -951,7 +1029,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       launch_rate_update(n, lmatch, gam, tk_cur, M, newc, rows, n_next, L.size, L.indeg, omega, delta,
                          learned ? opt.mlp->k : 1, tk_nxt, pair,
                          score, nflag, rerate, dcnt + 1, W.scan_tmp, s, log_on() ? dcnt + 4 : nullptr);
-      launch_rate_topk(L, L.total, omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
+      rate_topk(W, L, omega, delta, rerate, dcnt + 1, n_next, pair, score, tk_nxt, s);
       have_pairs = !learned;
       lists_fresh = learned;
       lists_ok = true;

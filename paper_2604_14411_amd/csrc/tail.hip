@@ -30,6 +30,7 @@
 // wider than the window is covered by several windows, each streaming only
 // the pins inside it (binary search per hedge).
 #include <algorithm>
+#include <cstdlib>
 
 #include "../../include/hgp.h"
 #include "coarsen.hpp"
@@ -88,6 +89,63 @@ __device__ __forceinline__ void window_clear_self(uint32_t *lds, uint64_t *lds64
       lds64[rn] = 0ull;
   }
   __syncthreads();
+}
+
+// Groups of nodes with the same inbound hedges (the nodes of one position
+// across the channels of a layered network) share the part of their
+// histograms that those hedges give: hist(n, m) is the sum over n's inbound
+// hedges plus the sum over its other (outbound) hedges, and c(n, m) counts
+// inbound hedges only.  A workgroup rating such a group streams the inbound
+// hedges once per window into a scratch slot of its own, and every member
+// then reloads the window and adds only its outbound hedges.
+constexpr int kGroupCap = 64;   // members per group at most
+constexpr int kGroupWins = 4;   // windows of a shared histogram at most
+
+// Block-wide set-up of group list[m0 .. m1): whether every member has the
+// leader's inbound hedges (checked exactly: equal |in|, and each inbound hedge
+// of a member found as an inbound hedge in the leader's incidence, which is
+// sorted by hedge id), the union of the members' neighbour ranges, and the
+// largest total(n).  The result is uniform across the block.
+template <int NT>
+__device__ bool group_setup(const int32_t *__restrict__ list, int64_t m0, int64_t m1,
+                            const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc,
+                            const int32_t *__restrict__ hoff, const uint32_t *__restrict__ hpin,
+                            const int32_t *__restrict__ indeg, const int32_t *__restrict__ total, int2 *rng_s,
+                            int *bad, int2 &range, uint32_t &max_total) {
+  const int tid = threadIdx.x;
+  const int leader = list[m0];
+  const int li0 = ioff[leader], li1 = ioff[leader + 1];
+  const int32_t ldin = indeg[leader];
+  if (tid == 0) *bad = 0;
+  __syncthreads();
+  int lo = 0x7fffffff, hi = -1;
+  uint32_t mt = 0;
+  for (int64_t t = m0; t < m1; ++t) {
+    const int v = list[t];
+    mt = max(mt, (uint32_t)total[v]);
+    if (t > m0) {
+      if (tid == 0 && indeg[v] != ldin) *bad = 1;
+      for (int i = ioff[v] + tid; i < ioff[v + 1]; i += NT) {
+        const uint32_t x = inc[i];
+        if (!(x & kDst)) continue;
+        const uint32_t e = x & kIdMask;
+        int a = li0, z = li1;
+        while (a < z) {
+          const int mid = (a + z) >> 1;
+          if ((inc[mid] & kIdMask) < e) a = mid + 1;
+          else z = mid;
+        }
+        if (a == li1 || (inc[a] & kIdMask) != e || !(inc[a] & kDst)) *bad = 1;
+      }
+    }
+    const int2 r = neighbour_range<NT>(ioff[v], ioff[v + 1], inc, hoff, hpin, rng_s);
+    lo = min(lo, r.x);
+    hi = max(hi, r.y);
+  }
+  __syncthreads();
+  range = make_int2(lo, hi);
+  max_total = mt;
+  return *bad == 0;
 }
 
 // Full rating with top-(TK+1) selection of the nodes in list[0 .. *count)
@@ -266,6 +324,233 @@ __global__ __launch_bounds__(NT) void k_rate_topk(int32_t N, const int32_t *__re
       score[n] = keep ? (int64_t)(found[0] >> 32) : 0;
     }
     __syncthreads();
+  }
+  add_wave_units(units, streamed);
+}
+
+// k_rate_topk over the groups list[goff[g] .. goff[g+1]) for g < *gcount
+// (groups of equal inbound hedge sets, kGroupCap members at most; launched
+// with GROUPED = true and pre null): every member's rating is that of
+// k_rate_topk.  Members of a checked group share the windows of their
+// inbound hedges through the workgroup's slot of gscratch (kGroupWins windows
+// of `words` words).  A kernel of its own, so that k_rate_topk keeps its
+// registers.
+template <int NT, bool GROUPED>
+__global__ __launch_bounds__(NT) void k_rate_topk_groups(int32_t N, const int32_t *__restrict__ list,
+                                                  const int64_t *__restrict__ count, const int32_t *__restrict__ ioff,
+                                                  const uint32_t *__restrict__ inc, const int32_t *__restrict__ hoff,
+                                                  const uint32_t *__restrict__ hpin, const int32_t *__restrict__ hw,
+                                                  const int32_t *__restrict__ size, const int32_t *__restrict__ indeg,
+                                                  const int32_t *__restrict__ total, const int32_t *__restrict__ maxin,
+                                                  int32_t omega, int32_t delta,
+                                                  const int32_t *__restrict__ row_slot, uint64_t *rows,
+                                                  int32_t *__restrict__ pair, int64_t *__restrict__ score,
+                                                  uint64_t *__restrict__ tk_key, int32_t *__restrict__ tk_c,
+                                                  int32_t *__restrict__ tk_cnt, uint64_t *__restrict__ tk_kappa,
+                                                  int32_t words, const uint64_t *pre,
+                                                  const int32_t *__restrict__ goff, const int32_t *__restrict__ gcount,
+                                                  uint32_t *__restrict__ gscratch,
+                                                  unsigned long long *__restrict__ units) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ int32_t tbl[NT / 64 * 192];
+  __shared__ int2 rng_s[NT / 64];
+  __shared__ int s_bad;
+  __shared__ unsigned long long s_basecnt[kGroupWins];  // pin visits of the shared windows
+  __shared__ uint64_t red[NT / 64];
+  __shared__ uint64_t found[kTopK + 1];
+  __shared__ int32_t foundc[kTopK + 1];
+  const int tid = threadIdx.x, w = tid >> 6, l = lane_id();
+  uint64_t *lds64 = reinterpret_cast<uint64_t *>(lds);
+  const int64_t n_items = GROUPED ? (int64_t)*gcount : (list ? *count : (int64_t)N);
+  int64_t streamed = 0;
+  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const int64_t m0 = GROUPED ? goff[item] : item, m1 = GROUPED ? goff[item + 1] : item + 1;
+  bool shared = false;
+  int2 grg = make_int2(0x7fffffff, -1);
+  uint32_t gtot = 0, gdin = 0;
+  if (GROUPED && m1 - m0 > 1) {
+    if (tid < kGroupWins) s_basecnt[tid] = 0ull;  // group_setup's barriers publish it
+    shared = group_setup<NT>(list, m0, m1, ioff, inc, hoff, hpin, indeg, total, rng_s, &s_bad, grg, gtot);
+    gdin = (uint32_t)indeg[list[m0]];
+    // the group's layout must hold every member's counters; more windows
+    // than the scratch slot holds rate the members one by one
+    const int hb = gtot ? 32 - __clz(gtot) : 0, cb = gdin ? 32 - __clz(gdin) : 0;
+    const bool half = maxin && hb <= 16 && (int64_t)gdin + (int64_t)(*maxin) <= (int64_t)delta &&
+                      inbound_slots(gdin) <= words;
+    const int R = half ? 2 * words : (hb + cb <= 32 ? words : (words >> 1));
+    if (grg.y >= grg.x && ((int64_t)grg.y - grg.x) / R + 1 > kGroupWins) shared = false;
+  }
+  bool have_base = false;  // the shared windows are in the scratch slot
+  for (int64_t t = m0; t < m1; ++t) {
+    const int n = list ? list[t] : (int)t;
+    const int64_t sn = size[n];
+    const uint32_t tot = shared ? gtot : (uint32_t)total[n];
+    const uint32_t din = shared ? gdin : (uint32_t)indeg[n];
+    const int hb = tot ? 32 - __clz(tot) : 0;
+    const int cb = din ? 32 - __clz(din) : 0;
+    const bool packed = hb + cb <= 32;
+    // hist alone in 16-bit halves when it fits and no candidate can break
+    // Delta (then c is not needed to select; it is counted afterwards for
+    // the listed candidates only)
+    const bool half = !pre && maxin && hb <= 16 && (int64_t)din + (int64_t)(*maxin) <= (int64_t)delta &&
+                      inbound_slots(din) <= words;
+    const uint64_t hmask = (hb >= 32) ? 0xffffffffull : ((1ull << hb) - 1ull);
+    // each thread keeps the TK+1 largest valid keys of its counters, descending
+    uint64_t top[kTopK + 1];
+    int32_t topc[kTopK + 1];
+#pragma unroll
+    for (int z = 0; z <= kTopK; ++z) {
+      top[z] = 0ull;
+      topc[z] = 0;
+    }
+    auto offer = [&](uint64_t h, uint64_t c, int m) {
+      bool ok = false;
+      if (h) {
+        const int64_t un = (int64_t)din + indeg[m] - (int64_t)c;
+        ok = sn + size[m] <= omega && un <= delta;
+      }
+      if (ok) {
+        uint64_t x = cand_key(h, (uint32_t)m);
+        int32_t xc = (int32_t)c;
+        if (x > top[kTopK]) list_insert<kTopK + 1>(top, topc, x, xc);
+      }
+      return ok;
+    };
+    if (pre) {
+      const uint64_t *row = pre + t * (int64_t)N;
+      const int slot = row_slot ? row_slot[n] : -1;
+      for (int i = tid; i < N; i += NT) {
+        const uint64_t v = row[i];
+        const bool ok = offer(v & 0xffffffffull, v >> 32, i);
+        if (slot >= 0) rows[(int64_t)slot * N + i] = ok ? v : 0ull;
+      }
+    } else if (sn < omega) {
+      const int i0 = ioff[n], i1 = ioff[n + 1];
+      const int R = half ? 2 * words : (packed ? words : (words >> 1));
+      const int2 rg = shared ? grg : neighbour_range<NT>(i0, i1, inc, hoff, hpin, rng_s);
+      const uint32_t *clip = ((int64_t)rg.y - rg.x >= R) ? hpin : nullptr;  // several windows
+      int wi = 0;
+      for (int lo = rg.x; lo <= rg.y; lo += R, ++wi) {
+        const int span = min(R, rg.y + 1 - lo);
+        const int zw = half ? (span + 1) >> 1 : (packed ? span : 2 * span);
+        uint32_t *slot = shared ? gscratch + ((int64_t)blockIdx.x * kGroupWins + wi) * words : nullptr;
+        if (GROUPED && have_base) {
+          for (int i = tid; i < zw; i += NT) lds[i] = slot[i];
+          // the method's pin visits for this member include the shared ones
+          if (w == 0) streamed += (int64_t)s_basecnt[wi];
+        } else {
+          for (int i = tid; i < zw; i += NT) lds[i] = 0u;
+        }
+        __syncthreads();
+        // counter layout: 0 = hist in 16-bit halves, 1 = packed 32-bit, 2 = 64-bit
+        streamed += with_mode(half ? 0 : (packed ? 1 : 2), [&](auto mode) {
+          constexpr int MODE = decltype(mode)::value;
+          auto add = [&](uint32_t y, uint32_t info, bool ok) {
+            window_add<MODE>(lds, lds64, (y & kIdMask) - (uint32_t)lo, ok ? info & kIdMask : 0u,
+                             ok ? (info & y) >> 31 : 0u, hb);
+          };
+          auto ld = [&](int j) { return hpin[j]; };
+          if (!GROUPED || !shared)
+            return stream_segments<NT / 64, kRateU, true, uint32_t, true>(i0, i1, inc, hoff, nullptr, hw, tbl, ld,
+                                                                           add, clip, lo, lo + span);
+          int64_t s = 0;
+          if (!have_base) {
+            // the group's inbound hedges (this member's equal the leader's),
+            // kept in the slot for the other members
+            s = stream_segments<NT / 64, kRateU, true, uint32_t, true, 1>(i0, i1, inc, hoff, nullptr, hw, tbl, ld,
+                                                                           add, clip, lo, lo + span);
+            if (l == 0 && s) atomicAdd(&s_basecnt[wi], (unsigned long long)s);
+            __syncthreads();
+            for (int i = tid; i < zw; i += NT) slot[i] = lds[i];
+            __syncthreads();
+          }
+          return s + stream_segments<NT / 64, kRateU, true, uint32_t, true, 2>(i0, i1, inc, hoff, nullptr, hw, tbl,
+                                                                                ld, add, clip, lo, lo + span);
+        });
+        __syncthreads();
+        window_clear_self(lds, lds64, half ? 0 : (packed ? 1 : 2), n - lo, span);
+        if (half) {
+          // Delta holds for every candidate here, whatever c is
+          for (int i = tid; i < zw; i += NT) {
+            const uint32_t v = lds[i];
+            if (!v) continue;
+            offer(v & 0xffffu, 0, lo + 2 * i);
+            offer(v >> 16, 0, lo + 2 * i + 1);
+          }
+          __syncthreads();
+          continue;
+        }
+        for (int i = tid; i < span; i += NT) {
+          uint64_t h, c;
+          if (packed) {
+            const uint32_t v = lds[i];
+            if (!v) continue;
+            h = v & hmask;
+            c = (hb >= 32) ? 0 : (v >> hb);
+          } else {
+            const uint64_t v = lds64[i];
+            if (!v) continue;
+            h = v & 0xffffffffull;
+            c = v >> 32;
+          }
+          offer(h, c, lo + i);
+        }
+        __syncthreads();
+      }
+      if (GROUPED && shared) have_base = true;
+    }
+    // merge of the per-thread lists: TK+1 rounds of a block max over the
+    // heads; keys are distinct (the id is in the low bits), so exactly one
+    // thread owns each winner and drops it from its list
+    int nf = 0;
+    for (int r = 0; r <= kTopK; ++r) {
+      uint64_t best = top[0];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t x = __shfl_xor(best, o, 64);
+        best = x > best ? x : best;
+      }
+      if (l == 0) red[w] = best;
+      __syncthreads();
+      if (tid == 0) {
+        uint64_t b = red[0];
+        for (int q = 1; q < NT / 64; ++q) b = red[q] > b ? red[q] : b;
+        found[r] = b;
+      }
+      __syncthreads();
+      const uint64_t win = found[r];
+      if (win == 0) break;
+      nf = r + 1;
+      if (top[0] == win) {
+        foundc[r] = topc[0];
+#pragma unroll
+        for (int z = 0; z < kTopK; ++z) {
+          top[z] = top[z + 1];
+          topc[z] = topc[z + 1];
+        }
+        top[kTopK] = 0ull;
+        topc[kTopK] = 0;
+      }
+    }
+    __syncthreads();
+    if (half) {
+      // c(n, m) of the listed candidates (the window's LDS is free now)
+      inbound_common<NT>(n, ioff, inc, lds, inbound_slots(din), found, foundc, nf < kTopK ? nf : kTopK);
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int keep = nf < kTopK ? nf : kTopK;
+      for (int q = 0; q < kTopK; ++q) {
+        tk_key[(int64_t)n * kTopK + q] = q < keep ? found[q] : 0ull;
+        tk_c[(int64_t)n * kTopK + q] = q < keep ? foundc[q] : 0;
+      }
+      tk_cnt[n] = keep;
+      tk_kappa[n] = nf > kTopK ? found[kTopK] : 0ull;
+      pair[n] = keep ? (int32_t)(found[0] & 0xffffffffull) : -1;
+      score[n] = keep ? (int64_t)(found[0] >> 32) : 0;
+    }
+    __syncthreads();
+  }
   }
   add_wave_units(units, streamed);
 }
@@ -526,6 +811,8 @@ static void topk_attr() {
   static const bool attr_set = [] {
     HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kTopKWideMaxWords * 4));
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk_groups<TOPK_NT, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kTopKWideMaxWords * 4));
     HGP_HIP(hipFuncSetAttribute((const void *)k_tail_hist<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kTopKWideMaxWords * 4));
     return true;
@@ -552,6 +839,119 @@ void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, i
       nullptr,
       pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr, units_ptr(8));
   HGP_LAUNCH_CHECK();
+}
+
+// splitmix64's finaliser (a bijection of 64-bit words)
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// keys[t] = a 32-bit hash (masked by `mask`) of the set of inbound hedges of
+// node list[t] (t < *count; one wave per entry), vals[t] = the node; entries
+// from *count up to the bound get the key 0xffffffff, which no node's key
+// has, so that they sort last.
+__global__ void k_group_keys(const int32_t *__restrict__ list, const int64_t *__restrict__ count, int64_t bound,
+                             const int32_t *__restrict__ ioff, const uint32_t *__restrict__ inc, uint32_t mask,
+                             uint32_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int l = lane_id();
+  if (t >= bound) return;  // uniform per wave
+  const int64_t cnt = count ? *count : bound;
+  if (t >= cnt) {
+    if (l == 0) {
+      keys[t] = 0xffffffffu;
+      vals[t] = 0xffffffffu;
+    }
+    return;
+  }
+  const int n = list ? list[t] : (int)t;
+  uint64_t h = 0;  // a sum of mixed hedge ids: independent of their order
+  for (int i = ioff[n] + l; i < ioff[n + 1]; i += 64) {
+    const uint32_t x = inc[i];
+    if (x & kDst) h += mix64((uint64_t)(x & kIdMask) + 1ull);
+  }
+  h = wave_sum(h);
+  if (l == 0) {
+    const uint32_t k = (uint32_t)(mix64(h) >> 32) & mask;
+    keys[t] = k == 0xffffffffu ? 0xfffffffeu : k;
+    vals[t] = (uint32_t)n;
+  }
+}
+
+// A group starts at every change of key and at every multiple of kGroupCap.
+__device__ __forceinline__ bool group_start(const uint32_t *__restrict__ keys, int64_t i) {
+  return i == 0 || keys[i] != keys[i - 1] || i % kGroupCap == 0;
+}
+__global__ void k_group_flags(const uint32_t *__restrict__ keys, int64_t bound, const int64_t *__restrict__ count,
+                              int32_t *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bound) return;
+  const int64_t cnt = count ? *count : bound;
+  flags[i] = (i < cnt && group_start(keys, i)) ? 1 : 0;
+}
+// goff[pos[i]] = i for the group starts; goff[*groups] = the entry count.
+__global__ void k_group_offsets(const uint32_t *__restrict__ keys, const int32_t *__restrict__ pos, int64_t bound,
+                                const int64_t *__restrict__ count, const int32_t *__restrict__ groups,
+                                int32_t *__restrict__ goff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bound) return;
+  const int64_t cnt = count ? *count : bound;
+  if (i < cnt && group_start(keys, i)) goff[pos[i]] = (int32_t)i;
+  if (i == 0) goff[*groups] = (int32_t)cnt;
+}
+
+static uint32_t group_hash_mask() {
+  // tests narrow the key to force collisions, which the exact check catches
+  const char *e = std::getenv("HGP_GROUP_HASH_BITS");
+  const int b = e && e[0] ? std::atoi(e) : 32;
+  return b >= 32 ? 0xffffffffu : (b <= 0 ? 0u : ((1u << b) - 1u));
+}
+
+int64_t group_scratch_words(int32_t n) { return (int64_t)TOPK_GRID * kGroupWins * topk_words(n); }
+
+// stat[0] = the number of groups, stat[1] = the number of rated nodes
+__global__ void k_group_stat(int32_t *__restrict__ stat, const int32_t *__restrict__ groups,
+                             const int64_t *__restrict__ count, int32_t n) {
+  if (threadIdx.x == 0) {
+    stat[0] = *groups;
+    stat[1] = count ? (int32_t)*count : n;
+  }
+}
+
+void launch_group_order(const LevelView &L, const int32_t *list, const int64_t *count, int64_t bound,
+                        const GroupBufs &G, hipStream_t s) {
+  if (L.n <= 0 || bound <= 0) return;
+  KScope ks(8, s);
+  k_group_keys<<<div_up(bound * 64, 256), 256, 0, s>>>(list, count, bound, L.ioff, L.inc, group_hash_mask(), G.keys,
+                                                       G.vals);
+  HGP_LAUNCH_CHECK();
+  radix_sort_u32(G.keys, G.alt, G.vals, G.valt, bound, 32, *G.tmp, s);
+  k_group_flags<<<div_up(bound, 256), 256, 0, s>>>(G.keys, bound, count, G.pos);
+  HGP_LAUNCH_CHECK();
+  scan_i32(G.pos, G.pos, bound, G.groups, *G.scan_tmp, s);
+  k_group_offsets<<<div_up(bound, 256), 256, 0, s>>>(G.keys, G.pos, bound, count, G.groups, G.goff);
+  HGP_LAUNCH_CHECK();
+}
+
+void launch_rate_topk_grouped(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta,
+                              const int64_t *count, int64_t bound, int32_t *pair, int64_t *score, TopK &tk,
+                              const GroupBufs &G, int32_t *stat, hipStream_t s) {
+  if (L.n <= 0 || bound <= 0) return;
+  KScope ks(8, s);
+  topk_attr();
+  const int words = topk_words(L.n);
+  const int grid = (int)std::min<int64_t>(TOPK_GRID, xcd_grid((int)std::min<int64_t>(bound, TOPK_GRID)));
+  k_rate_topk_groups<TOPK_NT, true><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
+      L.n, reinterpret_cast<const int32_t *>(G.vals), nullptr, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg,
+      total, L.maxin, omega, delta, nullptr, nullptr, pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr,
+      G.goff, G.groups, G.scratch, units_ptr(8));
+  HGP_LAUNCH_CHECK();
+  if (stat) {
+    k_group_stat<<<1, 64, 0, s>>>(stat, G.groups, count, (int32_t)bound);
+    HGP_LAUNCH_CHECK();
+  }
 }
 
 uint64_t *launch_rate_topk_rows(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta,

@@ -21,6 +21,28 @@ struct TopK {
 void launch_rate_topk(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta, const int32_t *list,
                       const int64_t *count, int64_t grid_nodes, int32_t *pair, int64_t *score, TopK &tk,
                       hipStream_t s);
+// Work buffers of the grouped rating: keys, alt, vals, valt, pos, goff of
+// `bound` (+1 for goff) entries, the device group count, and the scratch
+// windows (group_scratch_words(n) words).
+struct GroupBufs {
+  uint32_t *keys = nullptr, *alt = nullptr, *vals = nullptr, *valt = nullptr;
+  int32_t *pos = nullptr, *goff = nullptr, *groups = nullptr;
+  uint32_t *scratch = nullptr;
+  DevBuf *tmp = nullptr, *scan_tmp = nullptr;
+};
+int64_t group_scratch_words(int32_t n);
+// The listed nodes (list null: every node; *count of them, count null:
+// bound, a host bound of the count) sorted by a hash of their inbound hedge
+// sets into G.vals and cut into groups of equal keys (at most kGroupCap
+// nodes): G.goff, and their number in *G.groups.
+void launch_group_order(const LevelView &L, const int32_t *list, const int64_t *count, int64_t bound,
+                        const GroupBufs &G, hipStream_t s);
+// As launch_rate_topk over the groups of launch_group_order: groups of equal
+// inbound hedge sets share those hedges' histogram (results exactly equal).
+// stat (device, may be null) receives the number of groups and of rated nodes.
+void launch_rate_topk_grouped(const LevelView &L, const int32_t *total, int32_t omega, int32_t delta,
+                              const int64_t *count, int64_t bound, int32_t *pair, int64_t *score, TopK &tk,
+                              const GroupBufs &G, int32_t *stat, hipStream_t s);
 // As launch_rate_topk for the n_rows (host) nodes of list, with each row's
 // pin stream split over many workgroups.  Returns the rows (in acc): row
 // row_slot[list[j]] = j holds hist | c << 32 of every valid pair, 0 elsewhere.

@@ -191,6 +191,15 @@ def test_medium_learned_end_to_end(ctx, name, make, omega, delta):
     _compare(ctx, make(), omega, delta, random_int_mlp(77), label=name)
 
 
+@pytest.mark.parametrize("name,make,omega,delta", MEDIUM, ids=[m[0] for m in MEDIUM])
+def test_medium_learned_grouped_ratings(ctx, monkeypatch, name, make, omega, delta):
+    """The learned proposal with every top-K rating grouped by inbound hedge
+    set (HGP_GROUP_MIN=1 and HGP_GROUP_LISTS=1): id-by-id equal to the oracle."""
+    monkeypatch.setenv("HGP_GROUP_MIN", "1")
+    monkeypatch.setenv("HGP_GROUP_LISTS", "1")
+    _compare(ctx, make(), omega, delta, random_int_mlp(77), label=f"{name} grouped")
+
+
 def test_constant_network_exercises_fallback(ctx):
     total = 0
     for i, (name, make, omega, delta) in enumerate(MEDIUM[:2]):

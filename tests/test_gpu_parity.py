@@ -114,6 +114,15 @@ INCR = [
 ]
 
 
+@pytest.mark.parametrize("name,make,omega,delta", INCR + MEDIUM[4:], ids=[c[0] for c in INCR + MEDIUM[4:]])
+def test_grouped_ratings_match_oracle(ctx, monkeypatch, name, make, omega, delta):
+    """Every top-K rating grouped by inbound hedge set (HGP_GROUP_MIN=1 and HGP_GROUP_LISTS=1; by
+    default only levels of 16384 nodes or more): id-by-id equal to the oracle."""
+    monkeypatch.setenv("HGP_GROUP_MIN", "1")
+    monkeypatch.setenv("HGP_GROUP_LISTS", "1")
+    _compare(ctx, make(), omega, delta, label=f"{name} grouped")
+
+
 @pytest.mark.parametrize("name,make,omega,delta", INCR, ids=[c[0] for c in INCR])
 def test_incremental_late_levels_match_full_recompute(ctx, name, make, omega, delta):
     from paper_2604_14411_amd import hgp

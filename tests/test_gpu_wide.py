@@ -114,3 +114,19 @@ def test_layered_at_large_bounds_matches_oracle_golden(ctx, name):
         assert res[key] == gold[key], (key, res[key], gold[key])
     if q is not None:
         assert res["n_fallback"] == gold["n_fallback"]
+
+
+@pytest.mark.parametrize("name,hash_bits", [(n, 32) for n in LAYERED] + [("conv12k_3x3_learned", 3)],
+                         ids=[n for n in LAYERED] + ["conv12k_3x3_learned_colliding_keys"])
+def test_layered_grouped_ratings_match_oracle_golden(ctx, monkeypatch, name, hash_bits):
+    """The same goldens with every top-K rating grouped (HGP_GROUP_MIN=1, and
+    HGP_GROUP_LISTS=1 for the re-rating lists):
+    the nodes of one position across the channels share their inbound
+    hedges, so they are rated in groups that share those hedges' histogram.
+    With 3-bit keys nodes of different inbound sets collide into one group,
+    which the exact set check must catch (its members are then rated one by
+    one)."""
+    monkeypatch.setenv("HGP_GROUP_MIN", "1")
+    monkeypatch.setenv("HGP_GROUP_LISTS", "1")
+    monkeypatch.setenv("HGP_GROUP_HASH_BITS", str(hash_bits))
+    test_layered_at_large_bounds_matches_oracle_golden(ctx, name)
