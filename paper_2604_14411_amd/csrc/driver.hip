@@ -486,7 +486,7 @@ static void rate_topk(Workspace &W, const LevelView &L, int32_t omega, int32_t d
 
 // After a read-back of the error words: a grouped rating of at least 4096
 // nodes with groups of fewer than two nodes on average ends grouping.
-static void group_verdict(Workspace &W, const int32_t *v) {
+static void group_decide(Workspace &W, const int32_t *v) {
   if (!W.group_pending) return;
   W.group_pending = false;
   const int64_t groups = v[kErrGroups], rated = v[kErrGroups + 1];
@@ -935,7 +935,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
     int32_t n_next = 0;
     if (!learned) {
       const int32_t *v = read_err_words(W, kErrWords, s);
-      group_verdict(W, v);
+      group_decide(W, v);
       n_next = v[kErrNnext];
     } else {
       // fallback: the plain pairs' matching, used if it merges over twice as
@@ -945,7 +945,7 @@ static RunStats run_partition(Workspace &W, const hgp_hypergraph *g, int32_t ome
       launch_match(W.ppair.as<int32_t>(), W.pscore.as<int64_t>(), n, best, up, pm, pg, rep, nnext_dev + 1,
                    W.err.as<int32_t>(), W.scan_tmp, s);
       const int32_t *v = read_err_words(W, kErrWords, s);
-      group_verdict(W, v);
+      group_decide(W, v);
       n_next = v[kErrNnext];
       const int32_t n_next_p = v[kErrNnext + 1];
       if (2 * (int64_t)(n - n_next) < (int64_t)(n - n_next_p)) {
