@@ -463,7 +463,6 @@ static void rate_topk(Workspace &W, const LevelView &L, int32_t omega, int32_t d
   G.pos = need<int32_t>(W.gpos, bound);
   G.goff = need<int32_t>(W.goff, bound + 1);
   G.groups = need<int32_t>(W.gcnt, 1);
-  G.scratch = need<uint32_t>(W.gscr, group_scratch_words(L.n));
   G.tmp = &W.sort_tmp;
   G.scan_tmp = &W.scan_tmp;
   launch_group_order(L, list, count, bound, G, s);
@@ -479,6 +478,7 @@ static void rate_topk(Workspace &W, const LevelView &L, int32_t omega, int32_t d
       return;
     }
   }
+  G.scratch = need<uint32_t>(W.gscr, group_scratch_words(L.n));  // only once groups pay
   launch_rate_topk_grouped(L, L.total, omega, delta, count, bound, pair, score, tk, G,
                            need<int32_t>(W.err, kErrWords) + kErrGroups, s);
   W.group_pending = true;
