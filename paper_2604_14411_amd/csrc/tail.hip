@@ -803,6 +803,10 @@ __global__ __launch_bounds__(NT) void k_tail_hist(int32_t N, const int32_t *__re
 // streams (4 waves per CU with 256 threads).  Their static LDS (12.5 KB of
 // stream tables and reductions) and the window share the CU's 160 KB.
 constexpr int TOPK_NT = 1024;
+// The grouped rating runs 512-thread workgroups: its per-member selection
+// keeps its lists in registers there (205 registers, none spilled, against
+// 131 spilled at 1024 threads; rate_tail 1342 to 1329 ms on conv302k).
+constexpr int GROUP_NT = 512;
 constexpr int TOPK_GRID = 512;
 constexpr int kTopKWideMaxWords = 37376;
 
@@ -811,7 +815,7 @@ static void topk_attr() {
   static const bool attr_set = [] {
     HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kTopKWideMaxWords * 4));
-    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk_groups<TOPK_NT, true>,
+    HGP_HIP(hipFuncSetAttribute((const void *)k_rate_topk_groups<GROUP_NT, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, kTopKWideMaxWords * 4));
     HGP_HIP(hipFuncSetAttribute((const void *)k_tail_hist<TOPK_NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 kTopKWideMaxWords * 4));
@@ -943,7 +947,7 @@ void launch_rate_topk_grouped(const LevelView &L, const int32_t *total, int32_t 
   topk_attr();
   const int words = topk_words(L.n);
   const int grid = (int)std::min<int64_t>(TOPK_GRID, xcd_grid((int)std::min<int64_t>(bound, TOPK_GRID)));
-  k_rate_topk_groups<TOPK_NT, true><<<grid, TOPK_NT, (size_t)words * 4, s>>>(
+  k_rate_topk_groups<GROUP_NT, true><<<grid, GROUP_NT, (size_t)words * 4, s>>>(
       L.n, reinterpret_cast<const int32_t *>(G.vals), nullptr, L.ioff, L.inc, L.hoff, L.hpin, L.hw, L.size, L.indeg,
       total, L.maxin, omega, delta, nullptr, nullptr, pair, score, tk.key, tk.c, tk.cnt, tk.kappa, words, nullptr,
       G.goff, G.groups, G.scratch, units_ptr(8));
